@@ -1,0 +1,97 @@
+/*
+ * cgks_oracle.h -- plain FP64 CPU oracle of the compact 8th-order gas-kinetic
+ * scheme (Zhao, Ji, Shyy, Xu, "An acoustic and shock wave capturing compact
+ * high-order gas-kinetic scheme with spectral-like resolution", arXiv 2001.01570).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP path: only
+ * the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * may load it.  It shares no code, header, table or constant with the GPU
+ * library, and the GPU library never calls it.
+ *
+ * Field layout (structure of arrays, x fastest): 1D has 6 fields
+ *   [rho, rhoU, rhoE, (rho)_x, (rhoU)_x, (rhoE)_x]  each of length nx,
+ * 2D has 12 fields
+ *   [W(4), W_x(4), W_y(4)],  W = (rho, rhoU, rhoV, rhoE), each ny*nx.
+ * W are cell averages, W_x / W_y cell-averaged gradients (Sec. 3.1).
+ *
+ * All arithmetic is IEEE double, compiled without contraction or fast-math.
+ */
+#ifndef CGKS_ORACLE_H
+#define CGKS_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_PERIODIC = 0, ORC_FREE = 1, ORC_WALL = 2, ORC_INFLOW = 3 };
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ENONPHYS = -4 };
+
+typedef struct {
+  int dim, nx, ny;
+  double x0, x1, y0, y1, gamma, cfl;
+  int bc[4];                 /* xlo, xhi, ylo, yhi */
+  double inflow_prim[4][4];  /* (rho, U, V, p) per side with ORC_INFLOW */
+  double weno_eps, tau_eps, tau_C;
+  double fixed_dt;           /* 0 -> CFL rule, >0 -> fixed step */
+} orc_config;
+
+typedef struct orc_ctx orc_ctx;
+
+typedef struct {
+  long steps;
+  long guard_w0;     /* linear equilibrium state inadmissible -> kinetic state */
+  long guard_weno;   /* WENO point state inadmissible -> adjacent cell average */
+  double last_dt;
+} orc_counters;
+
+int  orc_create(const orc_config *cfg, orc_ctx **out);
+void orc_destroy(orc_ctx *c);
+int  orc_set_state(orc_ctx *c, const double *fields, double t0);
+int  orc_get_state(const orc_ctx *c, double *fields, double *t, long *step);
+double orc_cfl_dt(const orc_ctx *c);      /* CFL step of the current state (unclamped) */
+int  orc_step(orc_ctx *c, double dt, double *dt_used);   /* dt<=0 -> rule in cfg */
+int  orc_advance_to(orc_ctx *c, double t_end, long max_steps, long *steps_taken);
+int  orc_counters_get(const orc_ctx *c, orc_counters *out);
+long orc_last_bad_cell(const orc_ctx *c);
+void orc_set_threads(int n);
+
+/* ---- building blocks exposed for unit tests (scaled cell width h = 1) ---- */
+/* Linear compact reconstruction at x_{i+1/2}, eq. (recons-8th-val):
+ * Q[0..3] = Q_{i-1..i+2}, D[0..3] = h Q'_{i-1..i+2}; out = (P7, h P7_x, h^2 P7_xx). */
+void orc_p7(const double *Q, const double *D, double *out);
+/* Left WENO-Z value at x_{i+1/2} (Sec. 3.3): returns value; cand[7], beta[7],
+ * weights[7] receive the candidate values, smoothness indicators and weights. */
+double orc_weno_left(const double *Q, const double *D, double eps,
+                     double *cand, double *beta, double *weights);
+double orc_weno_right(const double *Q, const double *D, double eps);
+/* Moments <u^n v^m xi^(2k)> of a (half-)Maxwellian; half = 0 full, +1 u>0, -1 u<0. */
+double orc_moment(int dim, double gamma, double U, double V, double lambda,
+                  int half, int n, int m, int k);
+/* Solve <psi a>_g = b for the expansion coefficients a of g (dim+2 unknowns). */
+void orc_slope(int dim, double gamma, const double *W, const double *b, double *a);
+/* Exact Euler second time derivative at a point (Cauchy-Kowalewski), 2D form:
+ * inputs are conservative W and its first and second derivatives. */
+void orc_euler_wtt(double gamma, const double *W, const double *Wx, const double *Wy,
+                   const double *Wxx, const double *Wxy, const double *Wyy, double *Wtt);
+/* One interface point of the gas-kinetic evolution (Sec. 2.1-2.2).
+ * in: W0, W0_n, W0_t, W0_nn, W0_nt, W0_tt, Wl, Wr (dim+2 each, normal = x);
+ * out: F[nc], Ft[nc], Wt[nc], Wtt[nc], N_half[nc], N_full[nc], tau. */
+void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double dt,
+                   const double *W0, const double *W0n, const double *W0t,
+                   const double *W0nn, const double *W0nt, const double *W0tt,
+                   const double *Wl, const double *Wr,
+                   double *F, double *Ft, double *Wt, double *Wtt,
+                   double *Nh, double *Nf, double *tau);
+/* The same evolution evaluated as the time integral of the interface flux over
+ * [0, delta]: Fhat(delta) (exposed for the extraction tests). */
+void orc_flux_integral(int dim, double gamma, double tau, double delta,
+                       const double *W0, const double *W0n, const double *W0t,
+                       const double *Wl, const double *Wr, double *Fhat);
+/* Tangential quartic through 5 segment averages s[0..4] (segments -2..2):
+ * value, first and second derivative (unit width) at eta. */
+void orc_quartic(const double *s, double eta, double *out3);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,384 @@
+/* Gas-kinetic interface evolution of Sec. 2 (test infrastructure only, see
+ * cgks_oracle.h).  Everything here follows the definitions directly: the
+ * Maxwellian and its moments (Sec. 2.1), the slope expansions obtained by
+ * solving the moment systems, the time-dependent interface distribution of
+ * eq. (3rd-simplify-flux) integrated in time, and the flux extraction of
+ * Sec. 2.2.  No closed-form shortcuts are used. */
+#include <math.h>
+#include <string.h>
+#include "oracle_internal.h"
+#include "cgks_oracle.h"
+
+static double internal_dof(int dim, double gamma) {
+  /* K = (4-2 gamma)/(gamma-1) in 2D (Sec. 2.1); the 1D value follows from
+   * gamma = (K+3)/(K+1), i.e. K = (3-gamma)/(gamma-1). */
+  return dim == 2 ? (4.0 - 2.0 * gamma) / (gamma - 1.0) : (3.0 - gamma) / (gamma - 1.0);
+}
+
+double orc_pressure(int dim, double gamma, const double *W) {
+  const double rho = W[0];
+  double ke = 0.5 * W[1] * W[1] / rho;
+  if (dim == 2) ke += 0.5 * W[2] * W[2] / rho;
+  return (gamma - 1.0) * (W[dim + 1] - ke);
+}
+
+int orc_admissible(int dim, double gamma, const double *W) {
+  for (int c = 0; c < dim + 2; ++c) if (!isfinite(W[c])) return 0;
+  if (!(W[0] > 0.0)) return 0;
+  const double p = orc_pressure(dim, gamma, W);
+  return p > 0.0 && isfinite(p);
+}
+
+int orc_maxw_init(int dim, double gamma, const double *W, int half, orc_maxw *g) {
+  memset(g, 0, sizeof *g);
+  g->dim = dim;
+  g->K = internal_dof(dim, gamma);
+  if (!orc_admissible(dim, gamma, W)) return -1;
+  g->rho = W[0];
+  g->U = W[1] / W[0];
+  g->V = dim == 2 ? W[2] / W[0] : 0.0;
+  const double p = orc_pressure(dim, gamma, W);
+  g->lam = g->rho / (2.0 * p);                      /* lambda = m/(2kT) = rho/(2p) */
+  const double lam = g->lam, U = g->U, V = g->V;
+  if (half == 0) {
+    g->mu[0] = 1.0;
+    g->mu[1] = U;
+  } else {
+    const double s = half > 0 ? 1.0 : -1.0;
+    g->mu[0] = 0.5 * erfc(-s * sqrt(lam) * U);
+    g->mu[1] = U * g->mu[0] + s * exp(-lam * U * U) / (2.0 * sqrt(M_PI * lam));
+  }
+  for (int n = 1; n < 8; ++n) g->mu[n + 1] = U * g->mu[n] + n / (2.0 * lam) * g->mu[n - 1];
+  g->mv[0] = 1.0;
+  if (dim == 2) {
+    g->mv[1] = V;
+    for (int n = 1; n < 8; ++n) g->mv[n + 1] = V * g->mv[n] + n / (2.0 * lam) * g->mv[n - 1];
+  }
+  g->mx[0] = 1.0;
+  g->mx[1] = g->K / (2.0 * lam);
+  g->mx[2] = (g->K * g->K + 2.0 * g->K) / (4.0 * lam * lam);
+  return 0;
+}
+
+/* psi = (1, u, [v,] (u^2 [+ v^2] + xi^2)/2) written as monomials c u^pu v^pv (xi^2)^px */
+typedef struct { double c; int pu, pv, px; } mono_t;
+typedef struct { int n; mono_t m[3]; } psi_t;
+static const psi_t PSI1[3] = {
+  {1, {{1.0, 0, 0, 0}}},
+  {1, {{1.0, 1, 0, 0}}},
+  {2, {{0.5, 2, 0, 0}, {0.5, 0, 0, 1}}},
+};
+static const psi_t PSI2[4] = {
+  {1, {{1.0, 0, 0, 0}}},
+  {1, {{1.0, 1, 0, 0}}},
+  {1, {{1.0, 0, 1, 0}}},
+  {3, {{0.5, 2, 0, 0}, {0.5, 0, 2, 0}, {0.5, 0, 0, 1}}},
+};
+
+static double E(const orc_maxw *g, int n, int m, int k) { return g->mu[n] * g->mv[m] * g->mx[k]; }
+
+/* <u^n v^m psi_al psi_be> */
+static double m_pp(const orc_maxw *g, int n, int m, int al, int be) {
+  const psi_t *P = g->dim == 2 ? PSI2 : PSI1;
+  double s = 0.0;
+  for (int i = 0; i < P[al].n; ++i)
+    for (int j = 0; j < P[be].n; ++j) {
+      const mono_t *x = &P[al].m[i], *y = &P[be].m[j];
+      s += x->c * y->c * E(g, n + x->pu + y->pu, m + x->pv + y->pv, x->px + y->px);
+    }
+  return s;
+}
+
+/* out_al = <u^n v^m psi_al> */
+static void m_p(const orc_maxw *g, int n, int m, double *out) {
+  const int nc = g->dim + 2;
+  for (int al = 0; al < nc; ++al) out[al] = m_pp(g, n, m, al, 0);   /* psi_0 = 1 */
+}
+
+/* out_al = <u^n v^m psi_al a>, a = sum_be a_be psi_be */
+static void m_pa(const orc_maxw *g, int n, int m, const double *a, double *out) {
+  const int nc = g->dim + 2;
+  for (int al = 0; al < nc; ++al) {
+    double s = 0.0;
+    for (int be = 0; be < nc; ++be) s += a[be] * m_pp(g, n, m, al, be);
+    out[al] = s;
+  }
+}
+
+/* Solve <psi a>_g = b (full-space moments of g). */
+static void solve_slope(const orc_maxw *g, const double *b, double *a) {
+  const int nc = g->dim + 2;
+  double M[16];
+  for (int al = 0; al < nc; ++al)
+    for (int be = 0; be < nc; ++be) M[al * nc + be] = m_pp(g, 0, 0, al, be);
+  for (int al = 0; al < nc; ++al) a[al] = b[al];
+  orc_solve(nc, M, a);
+}
+
+void orc_slope(int dim, double gamma, const double *W, const double *b, double *a) {
+  orc_maxw g;
+  orc_maxw_init(dim, gamma, W, 0, &g);
+  solve_slope(&g, b, a);
+}
+
+double orc_moment(int dim, double gamma, double U, double V, double lambda,
+                  int half, int n, int m, int k) {
+  /* state with unit density, velocity (U,V) and temperature 1/(2 lambda) */
+  double W[4];
+  const double p = 1.0 / (2.0 * lambda);
+  W[0] = 1.0; W[1] = U;
+  if (dim == 2) { W[2] = V; W[3] = p / (gamma - 1.0) + 0.5 * (U * U + V * V); }
+  else W[2] = p / (gamma - 1.0) + 0.5 * U * U;
+  orc_maxw g;
+  orc_maxw_init(dim, gamma, W, half, &g);
+  return E(&g, n, m, k);
+}
+
+/* Exact second time derivative of the Euler solution at a point, from the
+ * value and first/second spatial derivatives (Cauchy-Kowalewski procedure in
+ * primitive variables rho, U, V, p).  Used for the a_tt part of the
+ * third-order interface distribution (Sec. 2.1, 2.2). */
+void orc_euler_wtt(double gamma, const double *W, const double *Wx, const double *Wy,
+                   const double *Wxx, const double *Wxy, const double *Wyy, double *Wtt) {
+  const double g1 = gamma - 1.0;
+  const double r = W[0], U = W[1] / r, V = W[2] / r;
+  const double p = g1 * (W[3] - 0.5 * r * (U * U + V * V));
+  const double *D1[2] = {Wx, Wy};
+  double r1[2], U1[2], V1[2], p1[2];
+  for (int a = 0; a < 2; ++a) {
+    const double *d = D1[a];
+    r1[a] = d[0];
+    U1[a] = (d[1] - U * r1[a]) / r;
+    V1[a] = (d[2] - V * r1[a]) / r;
+    p1[a] = g1 * (d[3] - 0.5 * r1[a] * (U * U + V * V) - r * (U * U1[a] + V * V1[a]));
+  }
+  const double *D2[2][2] = {{Wxx, Wxy}, {Wxy, Wyy}};
+  double r2[2][2], U2[2][2], V2[2][2], p2[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const double *d = D2[a][b];
+      r2[a][b] = d[0];
+      U2[a][b] = (d[1] - r2[a][b] * U - r1[a] * U1[b] - r1[b] * U1[a]) / r;
+      V2[a][b] = (d[2] - r2[a][b] * V - r1[a] * V1[b] - r1[b] * V1[a]) / r;
+      p2[a][b] = g1 * (d[3] - 0.5 * r2[a][b] * (U * U + V * V)
+                       - r1[a] * (U * U1[b] + V * V1[b]) - r1[b] * (U * U1[a] + V * V1[a])
+                       - r * (U1[a] * U1[b] + V1[a] * V1[b]) - r * (U * U2[a][b] + V * V2[a][b]));
+    }
+  /* first time derivatives */
+  const double div = U1[0] + V1[1];
+  const double rt = -(U * r1[0] + V * r1[1] + r * div);
+  const double Ut = -(U * U1[0] + V * U1[1] + p1[0] / r);
+  const double Vt = -(U * V1[0] + V * V1[1] + p1[1] / r);
+  const double pt = -(U * p1[0] + V * p1[1] + gamma * p * div);
+  /* mixed derivatives q_{ta} */
+  double rta[2], Uta[2], Vta[2], pta[2];
+  for (int a = 0; a < 2; ++a) {
+    const double diva = U2[0][a] + V2[1][a];
+    rta[a] = -(U1[a] * r1[0] + U * r2[0][a] + V1[a] * r1[1] + V * r2[1][a] + r1[a] * div + r * diva);
+    Uta[a] = -(U1[a] * U1[0] + U * U2[0][a] + V1[a] * U1[1] + V * U2[1][a] + p2[0][a] / r - p1[0] * r1[a] / (r * r));
+    Vta[a] = -(U1[a] * V1[0] + U * V2[0][a] + V1[a] * V1[1] + V * V2[1][a] + p2[1][a] / r - p1[1] * r1[a] / (r * r));
+    pta[a] = -(U1[a] * p1[0] + U * p2[0][a] + V1[a] * p1[1] + V * p2[1][a] + gamma * p1[a] * div + gamma * p * diva);
+  }
+  const double divt = Uta[0] + Vta[1];
+  const double rtt = -(Ut * r1[0] + U * rta[0] + Vt * r1[1] + V * rta[1] + rt * div + r * divt);
+  const double Utt = -(Ut * U1[0] + U * Uta[0] + Vt * U1[1] + V * Uta[1] + pta[0] / r - p1[0] * rt / (r * r));
+  const double Vtt = -(Ut * V1[0] + U * Vta[0] + Vt * V1[1] + V * Vta[1] + pta[1] / r - p1[1] * rt / (r * r));
+  const double ptt = -(Ut * p1[0] + U * pta[0] + Vt * p1[1] + V * pta[1] + gamma * pt * div + gamma * p * divt);
+  Wtt[0] = rtt;
+  Wtt[1] = rtt * U + 2.0 * rt * Ut + r * Utt;
+  Wtt[2] = rtt * V + 2.0 * rt * Vt + r * Vtt;
+  Wtt[3] = ptt / g1 + 0.5 * rtt * (U * U + V * V) + 2.0 * rt * (U * Ut + V * Vt)
+           + r * (Ut * Ut + Vt * Vt) + r * (U * Utt + V * Vtt);
+}
+
+/* ---- the interface evolution ------------------------------------------- */
+
+typedef struct {
+  int dim, nc;
+  orc_maxw g0, gl_full, gl_half, gr_full, gr_half;
+  double an0[4], at0[4], A0[4], anl[4], atl[4], anr[4], atr[4];
+} iface_t;
+
+/* Maxwellians and slopes of one interface point.  The equilibrium g0 comes
+ * from the linear reconstruction, g_l / g_r from the nonlinear one (Sec. 2.1);
+ * all slopes use the linear reconstruction's derivatives expressed in each
+ * state's own Maxwellian; A0 follows from the compatibility condition
+ * <psi (a_n u + a_t v + A)>_g0 = 0, eq. (compatibility). */
+static void iface_setup(int dim, double gamma, const double *W0, const double *W0n,
+                        const double *W0t, const double *Wl, const double *Wr, iface_t *s) {
+  const int nc = dim + 2;
+  s->dim = dim; s->nc = nc;
+  double b[4] = {0.0, 0.0, 0.0, 0.0};
+  orc_maxw_init(dim, gamma, W0, 0, &s->g0);
+  orc_maxw_init(dim, gamma, Wl, 0, &s->gl_full);
+  orc_maxw_init(dim, gamma, Wl, +1, &s->gl_half);
+  orc_maxw_init(dim, gamma, Wr, 0, &s->gr_full);
+  orc_maxw_init(dim, gamma, Wr, -1, &s->gr_half);
+  for (int c = 0; c < nc; ++c) b[c] = W0n[c] / W0[0];
+  solve_slope(&s->g0, b, s->an0);
+  for (int c = 0; c < nc; ++c) b[c] = W0n[c] / Wl[0];
+  solve_slope(&s->gl_full, b, s->anl);
+  for (int c = 0; c < nc; ++c) b[c] = W0n[c] / Wr[0];
+  solve_slope(&s->gr_full, b, s->anr);
+  if (dim == 2) {
+    for (int c = 0; c < nc; ++c) b[c] = W0t[c] / W0[0];
+    solve_slope(&s->g0, b, s->at0);
+    for (int c = 0; c < nc; ++c) b[c] = W0t[c] / Wl[0];
+    solve_slope(&s->gl_full, b, s->atl);
+    for (int c = 0; c < nc; ++c) b[c] = W0t[c] / Wr[0];
+    solve_slope(&s->gr_full, b, s->atr);
+  } else {
+    memset(s->at0, 0, sizeof s->at0);
+    memset(s->atl, 0, sizeof s->atl);
+    memset(s->atr, 0, sizeof s->atr);
+  }
+  double t1[4], t2[4];
+  m_pa(&s->g0, 1, 0, s->an0, t1);
+  if (dim == 2) m_pa(&s->g0, 0, 1, s->at0, t2); else memset(t2, 0, sizeof t2);
+  for (int c = 0; c < nc; ++c) b[c] = -(t1[c] + t2[c]);
+  solve_slope(&s->g0, b, s->A0);
+}
+
+/* rho <u^n v^m psi (a_n u + a_t v)>_g  (the slope term of one Maxwellian) */
+static void slope_term(const orc_maxw *g, int n, int m, const double *an, const double *at, double *out) {
+  double t1[4], t2[4];
+  const int nc = g->dim + 2;
+  m_pa(g, n + 1, m, an, t1);
+  if (g->dim == 2) m_pa(g, n, m + 1, at, t2); else memset(t2, 0, sizeof t2);
+  for (int c = 0; c < nc; ++c) out[c] = g->rho * (t1[c] + t2[c]);
+}
+
+/* Time integral over [0, delta] of the flux of the second-order distribution:
+ * eq. (3rd-simplify-flux) without the a_tt, a_xt, a_yt terms.  For the Euler
+ * equations the Chapman-Enskog terms carry the physical collision time, zero
+ * here, and the numerical collision time tau enters through exp(-t/tau). */
+static void fhat(const iface_t *s, double tau, double delta, double *out) {
+  const int nc = s->nc;
+  const double Ed = exp(-delta / tau);
+  const double c1 = delta - tau * (1.0 - Ed);                    /* g0 (1 - e^{-t/tau})            */
+  const double c2 = 0.5 * delta * delta;                          /* A g0 t                          */
+  const double c3 = tau * tau * (1.0 - Ed) - tau * delta * Ed;    /* e^{-t/tau} t (a.u) g0           */
+  const double c4 = tau * (1.0 - Ed);                             /* e^{-t/tau} g_{l,r} H            */
+  const double c5 = -c3;                                          /* -e^{-t/tau} t (a_{l,r}.u) g_{l,r} H */
+  double f0[4], fA[4], fs0[4], flr[4], fslr[4], tmp[4];
+  m_p(&s->g0, 1, 0, f0);
+  m_pa(&s->g0, 1, 0, s->A0, fA);
+  slope_term(&s->g0, 1, 0, s->an0, s->at0, fs0);
+  m_p(&s->gl_half, 1, 0, flr);
+  m_p(&s->gr_half, 1, 0, tmp);
+  for (int c = 0; c < nc; ++c) flr[c] = s->gl_half.rho * flr[c] + s->gr_half.rho * tmp[c];
+  slope_term(&s->gl_half, 1, 0, s->anl, s->atl, fslr);
+  slope_term(&s->gr_half, 1, 0, s->anr, s->atr, tmp);
+  for (int c = 0; c < nc; ++c) fslr[c] += tmp[c];
+  for (int c = 0; c < nc; ++c)
+    out[c] = c1 * s->g0.rho * f0[c] + c2 * s->g0.rho * fA[c] + c3 * fs0[c]
+             + c4 * flr[c] + c5 * fslr[c];
+}
+
+static double collision_time(int dim, double gamma, double tau_eps, double tau_C, double dt,
+                             const double *Wl, const double *Wr) {
+  /* tau = eps dt + C |(p_l - p_r)/(p_l + p_r)| dt  (Sec. 4, inviscid flow) */
+  const double pl = orc_pressure(dim, gamma, Wl), pr = orc_pressure(dim, gamma, Wr);
+  return tau_eps * dt + tau_C * fabs((pl - pr) / (pl + pr)) * dt;
+}
+
+void orc_flux_integral(int dim, double gamma, double tau, double delta,
+                       const double *W0, const double *W0n, const double *W0t,
+                       const double *Wl, const double *Wr, double *Fhat) {
+  iface_t s;
+  iface_setup(dim, gamma, W0, W0n, W0t, Wl, Wr, &s);
+  fhat(&s, tau, delta, Fhat);
+}
+
+int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double dt,
+                    const double *W0in, const double *W0n, const double *W0t,
+                    const double *W0nn, const double *W0nt, const double *W0tt,
+                    const double *Wl, const double *Wr,
+                    double *F, double *Ft, double *Wt, double *Wtt,
+                    double *Nh, double *Nf, double *tau_out, double *W0used) {
+  const int nc = dim + 2;
+  double W0[4];
+  int fired = 0;
+  for (int c = 0; c < nc; ++c) W0[c] = W0in[c];
+  const double tau = collision_time(dim, gamma, tau_eps, tau_C, dt, Wl, Wr);
+
+  /* S_lr = rho_l <psi>_{l,u>0} + rho_r <psi>_{r,u<0}: the state the two
+   * nonlinear distributions carry to the interface. */
+  orc_maxw glh, grh;
+  orc_maxw_init(dim, gamma, Wl, +1, &glh);
+  orc_maxw_init(dim, gamma, Wr, -1, &grh);
+  double Slr[4], tl[4], tr[4];
+  m_p(&glh, 0, 0, tl);
+  m_p(&grh, 0, 0, tr);
+  for (int c = 0; c < nc; ++c) Slr[c] = glh.rho * tl[c] + grh.rho * tr[c];
+  if (!orc_admissible(dim, gamma, W0)) {          /* positivity guard of the equilibrium */
+    for (int c = 0; c < nc; ++c) W0[c] = Slr[c];
+    fired = 1;
+  }
+  if (W0used) for (int c = 0; c < nc; ++c) W0used[c] = W0[c];
+
+  iface_t s;
+  double zero[4] = {0, 0, 0, 0};
+  iface_setup(dim, gamma, W0, W0n, dim == 2 ? W0t : zero, Wl, Wr, &s);
+
+  /* flux extraction (Sec. 2.2): F(t) ~ F + Ft t fitted to the time integrals
+   * over [0, dt/2] and [0, dt] */
+  double Fh[4], Ff[4];
+  fhat(&s, tau, 0.5 * dt, Fh);
+  fhat(&s, tau, dt, Ff);
+  for (int c = 0; c < nc; ++c) {
+    F[c] = (4.0 * Fh[c] - Ff[c]) / dt;
+    Ft[c] = 4.0 * (Ff[c] - 2.0 * Fh[c]) / (dt * dt);
+  }
+
+  /* time derivative of the equilibrium state: W_t = rho0 <psi A>_g0 */
+  double tA[4];
+  m_pa(&s.g0, 0, 0, s.A0, tA);
+  for (int c = 0; c < nc; ++c) Wt[c] = s.g0.rho * tA[c];
+
+  /* W_tt: exact Euler second time derivative at the point */
+  {
+    double W4[4], x4[4], y4[4], xx4[4], xy4[4], yy4[4], o4[4];
+    if (dim == 2) {
+      for (int c = 0; c < 4; ++c) {
+        W4[c] = W0[c]; x4[c] = W0n[c]; y4[c] = W0t[c];
+        xx4[c] = W0nn[c]; xy4[c] = W0nt[c]; yy4[c] = W0tt[c];
+      }
+    } else {  /* 1D embedded as V = 0 with no y dependence */
+      const int map[4] = {0, 1, -1, 2};
+      for (int c = 0; c < 4; ++c) {
+        const int k = map[c];
+        W4[c] = k < 0 ? 0.0 : W0[k]; x4[c] = k < 0 ? 0.0 : W0n[k];
+        xx4[c] = k < 0 ? 0.0 : W0nn[k];
+        y4[c] = xy4[c] = yy4[c] = 0.0;
+      }
+    }
+    orc_euler_wtt(gamma, W4, x4, y4, xx4, xy4, yy4, o4);
+    if (dim == 2) for (int c = 0; c < 4; ++c) Wtt[c] = o4[c];
+    else { Wtt[0] = o4[0]; Wtt[1] = o4[1]; Wtt[2] = o4[3]; }
+  }
+
+  /* non-equilibrium part of the interface state:
+   * e^{-t/tau} [ -W0 - t W_t + S_lr - t S_alr ] */
+  double Salr[4], sl[4], sr[4];
+  slope_term(&s.gl_half, 0, 0, s.anl, s.atl, sl);
+  slope_term(&s.gr_half, 0, 0, s.anr, s.atr, sr);
+  for (int c = 0; c < nc; ++c) Salr[c] = sl[c] + sr[c];
+  const double eh = exp(-0.5 * dt / tau), ef = exp(-dt / tau);
+  for (int c = 0; c < nc; ++c) {
+    Nh[c] = eh * (-W0[c] - 0.5 * dt * Wt[c] + Slr[c] - 0.5 * dt * Salr[c]);
+    Nf[c] = ef * (-W0[c] - dt * Wt[c] + Slr[c] - dt * Salr[c]);
+  }
+  if (tau_out) *tau_out = tau;
+  return fired;
+}
+
+void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double dt,
+                   const double *W0, const double *W0n, const double *W0t,
+                   const double *W0nn, const double *W0nt, const double *W0tt,
+                   const double *Wl, const double *Wr,
+                   double *F, double *Ft, double *Wt, double *Wtt,
+                   double *Nh, double *Nf, double *tau) {
+  orc_gks_point_g(dim, gamma, tau_eps, tau_C, dt, W0, W0n, W0t, W0nn, W0nt, W0tt, Wl, Wr,
+                  F, Ft, Wt, Wtt, Nh, Nf, tau, 0);
+}

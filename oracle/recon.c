@@ -1,0 +1,157 @@
+/* Compact reconstructions of Sec. 3 (test infrastructure only, see cgks_oracle.h).
+ *
+ * Coordinates are scaled by the cell width h: cell I_i is [-1/2, 1/2], the
+ * stencil cells I_{i-1}, I_i, I_{i+1}, I_{i+2} are indexed 0..3, the interface
+ * x_{i+1/2} sits at 1/2.  Q[m] are cell averages, D[m] = h Q'_m cell-averaged
+ * slopes times h (so D[m] = q(right edge) - q(left edge) for the cell's
+ * polynomial).
+ */
+#include <math.h>
+#include <string.h>
+#include "oracle_internal.h"
+#include "cgks_oracle.h"
+
+/* Eq. (recons-8th-val): value, h*d/dx and h^2*d2/dx2 of P^7 at x_{i+1/2}. */
+void orc_p7(const double *Q, const double *D, double *out) {
+  out[0] = (25.0 * Q[0] + 185.0 * Q[1] + 185.0 * Q[2] + 25.0 * Q[3]
+            + 6.0 * D[0] + 102.0 * D[1] - 102.0 * D[2] - 6.0 * D[3]) / 420.0;
+  out[1] = (-14.0 * Q[0] - 270.0 * Q[1] + 270.0 * Q[2] + 14.0 * Q[3]
+            - 3.0 * D[0] - 99.0 * D[1] - 99.0 * D[2] - 3.0 * D[3]) / 108.0;
+  out[2] = (-4.0 * Q[0] + 4.0 * Q[1] + 4.0 * Q[2] - 4.0 * Q[3]
+            - D[0] - 9.0 * D[1] + 9.0 * D[2] + D[3]) / 4.0;
+}
+
+/* Candidate values q_k(x_{i+1/2}) of eq. (sub-stencil). */
+static void candidates(const double *Q, const double *D, double *q) {
+  q[0] = (-7.0 * Q[0] + 13.0 * Q[1] - 4.0 * D[0]) / 6.0;
+  q[1] = (-Q[0] + 5.0 * Q[1] + 2.0 * Q[2]) / 6.0;
+  q[2] = (5.0 * Q[1] + 32.0 * Q[2] - 13.0 * Q[3] + 6.0 * D[3]) / 24.0;
+  q[3] = (-Q[0] + 5.0 * Q[1] + 2.0 * Q[2]) / 6.0;
+  q[4] = (2.0 * Q[1] + 5.0 * Q[2] - Q[3]) / 6.0;
+  q[5] = (10.0 * Q[0] + 19.0 * Q[1] + Q[2] + 3.0 * D[0] + 21.0 * D[1]) / 30.0;
+  q[6] = (Q[1] + 19.0 * Q[2] + 10.0 * Q[3] - 21.0 * D[2] - 3.0 * D[3]) / 30.0;
+}
+
+/* Linear weights d_k of the 8th-order reconstruction (Sec. 3.3). */
+static const double DK[7] = {3.0 / 98.0, 5.0 / 98.0, 4.0 / 49.0, 7.0 / 98.0,
+                             7.0 / 98.0, 17.0 / 49.0, 17.0 / 49.0};
+
+/* ---- smoothness indicators from their definition, eq. (smooth-indicator) ----
+ * Each sub-stencil polynomial is built explicitly: its monomial coefficients on
+ * I_i are the solution of the stencil's averaging/slope conditions (inverted
+ * once), and beta = sum_r int_{I_i} (q^(r))^2 (h = 1 after scaling). */
+typedef struct { int kind; int cell; } cond_t;   /* kind 0: average, 1: slope */
+typedef struct { int deg; int n; cond_t c[5]; } stencil_t;
+
+/* beta_0..beta_6 use S_0, S~_1 (cubic on Q_{i-1},Q_i,Q_{i+1},Q'_{i-1}, the
+ * symmetric replacement of Sec. 3.3), S_2, S_3, S_4, S_5, S_6. */
+static const stencil_t STENCIL[7] = {
+  {2, 3, {{0, 0}, {0, 1}, {1, 0}}},
+  {3, 4, {{0, 0}, {0, 1}, {0, 2}, {1, 0}}},
+  {3, 4, {{0, 1}, {0, 2}, {0, 3}, {1, 3}}},
+  {2, 3, {{0, 0}, {0, 1}, {0, 2}}},
+  {2, 3, {{0, 1}, {0, 2}, {0, 3}}},
+  {4, 5, {{0, 0}, {0, 1}, {0, 2}, {1, 0}, {1, 1}}},
+  {4, 5, {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}}},
+};
+static double STENCIL_INV[7][25];
+static double QUARTIC_INV[25];
+static int recon_ready = 0;
+
+static double ipow(double x, int p) { double r = 1.0; for (int i = 0; i < p; ++i) r *= x; return r; }
+
+static double cell_lo(int m) { return (double)m - 1.5; }   /* cell m spans [m-3/2, m-1/2] */
+
+__attribute__((constructor)) void orc_recon_init(void) {
+  if (recon_ready) return;
+  for (int k = 0; k < 7; ++k) {
+    const stencil_t *s = &STENCIL[k];
+    double A[25];
+    for (int r = 0; r < s->n; ++r) {
+      double lo = cell_lo(s->c[r].cell), hi = lo + 1.0;
+      for (int p = 0; p < s->n; ++p) {
+        if (s->c[r].kind == 0) A[r * s->n + p] = (ipow(hi, p + 1) - ipow(lo, p + 1)) / (p + 1);
+        else A[r * s->n + p] = ipow(hi, p) - ipow(lo, p);
+      }
+    }
+    orc_invert(s->n, A, STENCIL_INV[k]);
+  }
+  /* quartic through 5 averages on segments [m-2-1/2, m-2+1/2], m = 0..4 */
+  double B[25];
+  for (int r = 0; r < 5; ++r) {
+    double lo = r - 2.5, hi = r - 1.5;
+    for (int p = 0; p < 5; ++p) B[r * 5 + p] = (ipow(hi, p + 1) - ipow(lo, p + 1)) / (p + 1);
+  }
+  orc_invert(5, B, QUARTIC_INV);
+  recon_ready = 1;
+}
+
+/* int_{-1/2}^{1/2} xi^p dxi */
+static double mono_int(int p) {
+  if (p % 2) return 0.0;
+  return 2.0 * ipow(0.5, p + 1) / (p + 1);
+}
+
+static double falling(int m, int r) { double f = 1.0; for (int i = 0; i < r; ++i) f *= (m - i); return f; }
+
+static double beta_of(int k, const double *Q, const double *D) {
+  const stencil_t *s = &STENCIL[k];
+  double rhs[5], coef[5];
+  for (int r = 0; r < s->n; ++r) rhs[r] = s->c[r].kind == 0 ? Q[s->c[r].cell] : D[s->c[r].cell];
+  for (int p = 0; p < s->n; ++p) {
+    double acc = 0.0;
+    for (int r = 0; r < s->n; ++r) acc += STENCIL_INV[k][p * s->n + r] * rhs[r];
+    coef[p] = acc;
+  }
+  double beta = 0.0;
+  for (int r = 1; r <= s->deg; ++r)
+    for (int m = r; m <= s->deg; ++m)
+      for (int mm = r; mm <= s->deg; ++mm)
+        beta += coef[m] * coef[mm] * falling(m, r) * falling(mm, r) * mono_int(m + mm - 2 * r);
+  return beta;
+}
+
+/* Left value of the WENO-Z reconstruction, eqs. (right-left), (WENO-Z-w), (tau).
+ * The data are first shifted by Q_i: the reconstruction commutes with adding a
+ * constant, and the shift keeps the indicators free of cancellation. */
+double orc_weno_left(const double *Qin, const double *D, double eps,
+                     double *cand, double *beta, double *weights) {
+  double Q[4], q[7], b[7], w[7];
+  const double ref = Qin[1];
+  for (int m = 0; m < 4; ++m) Q[m] = Qin[m] - ref;
+  candidates(Q, D, q);
+  for (int k = 0; k < 7; ++k) b[k] = beta_of(k, Q, D);
+  const double zref = fabs(3.0 * (b[0] - b[4]) + (b[4] - b[3]));
+  double asum = 0.0;
+  for (int k = 0; k < 7; ++k) { w[k] = DK[k] * (1.0 + zref / (b[k] + eps)); asum += w[k]; }
+  double val = 0.0;
+  for (int k = 0; k < 7; ++k) { w[k] /= asum; val += w[k] * q[k]; }
+  if (cand) for (int k = 0; k < 7; ++k) cand[k] = q[k] + ref;
+  if (beta) memcpy(beta, b, sizeof b);
+  if (weights) memcpy(weights, w, sizeof w);
+  return val + ref;
+}
+
+/* Right value at x_{i+1/2}: the left procedure applied to the stencil mirrored
+ * about the interface (cells reversed, slopes negated). */
+double orc_weno_right(const double *Q, const double *D, double eps) {
+  double Qm[4], Dm[4];
+  for (int m = 0; m < 4; ++m) { Qm[m] = Q[3 - m]; Dm[m] = -D[3 - m]; }
+  return orc_weno_left(Qm, Dm, eps, 0, 0, 0);
+}
+
+void orc_quartic(const double *s, double eta, double *out3) {
+  double c[5];
+  for (int p = 0; p < 5; ++p) {
+    double acc = 0.0;
+    for (int r = 0; r < 5; ++r) acc += QUARTIC_INV[p * 5 + r] * s[r];
+    c[p] = acc;
+  }
+  double v = 0.0, d1 = 0.0, d2 = 0.0;
+  for (int p = 0; p < 5; ++p) {
+    v += c[p] * ipow(eta, p);
+    if (p >= 1) d1 += c[p] * p * ipow(eta, p - 1);
+    if (p >= 2) d2 += c[p] * p * (p - 1) * ipow(eta, p - 2);
+  }
+  out3[0] = v; out3[1] = d1; out3[2] = d2;
+}

@@ -1,0 +1,476 @@
+/* The compact GKS time step in 1D and 2D (test infrastructure only, see
+ * cgks_oracle.h): ghost cells, the two stages of the two-stage fourth-order
+ * method for the cell averages (eq. step-hyper-1) and, along the same line,
+ * for the interface states that update the cell-averaged gradients through
+ * the Gauss theorem (eq. compact-deriv-1), and the CFL time step. */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+#include "oracle_internal.h"
+#include "cgks_oracle.h"
+
+struct orc_ctx {
+  orc_config cfg;
+  int nc, nf, gx, gy;
+  double dx, dy;
+  double *U, *Us, *Un;   /* ghosted state, ghosted intermediate state, next state */
+  double *P;             /* W + dt L + dt^2/6 L_t and the matching gradient part */
+  double *xf, *yf;       /* per-face results, 4 blocks of nc */
+  double t;
+  long step, bad_cell;
+  orc_counters cnt;
+};
+
+#define NF_FACE 4  /* blocks per face: F, Ft, A, B */
+
+static int nthreads_req = 0;
+void orc_set_threads(int n) { nthreads_req = n; }
+
+static size_t fsize(const orc_ctx *c) { return (size_t)c->gx * c->gy; }
+static double *fld(const orc_ctx *c, double *base, int f) { return base + (size_t)f * fsize(c); }
+static size_t gidx(const orc_ctx *c, int i, int j) {
+  return c->cfg.dim == 2 ? (size_t)(j + 2) * c->gx + (i + 2) : (size_t)(i + 2);
+}
+
+int orc_create(const orc_config *cfg, orc_ctx **out) {
+  if (!cfg || !out) return ORC_EINVAL;
+  if (cfg->dim != 1 && cfg->dim != 2) return ORC_EINVAL;
+  if (cfg->nx < 1 || (cfg->dim == 2 && cfg->ny < 1)) return ORC_EINVAL;
+  if (!(cfg->gamma > 1.0) || !(cfg->x1 > cfg->x0)) return ORC_EINVAL;
+  if (cfg->dim == 2 && !(cfg->y1 > cfg->y0)) return ORC_EINVAL;
+  for (int s = 0; s < 2 * cfg->dim; ++s) if (cfg->bc[s] < 0 || cfg->bc[s] > 3) return ORC_EINVAL;
+  if ((cfg->bc[0] == ORC_PERIODIC) != (cfg->bc[1] == ORC_PERIODIC)) return ORC_EINVAL;
+  if (cfg->dim == 2 && (cfg->bc[2] == ORC_PERIODIC) != (cfg->bc[3] == ORC_PERIODIC)) return ORC_EINVAL;
+  orc_recon_init();
+  orc_ctx *c = (orc_ctx *)calloc(1, sizeof *c);
+  if (!c) return ORC_ENOMEM;
+  c->cfg = *cfg;
+  if (cfg->dim == 1) c->cfg.ny = 1;
+  c->nc = cfg->dim + 2;
+  c->nf = cfg->dim == 2 ? 12 : 6;
+  c->gx = c->cfg.nx + 4;
+  c->gy = cfg->dim == 2 ? c->cfg.ny + 4 : 1;
+  c->dx = (cfg->x1 - cfg->x0) / cfg->nx;
+  c->dy = cfg->dim == 2 ? (cfg->y1 - cfg->y0) / cfg->ny : 1.0;
+  const size_t n = (size_t)c->nf * fsize(c);
+  c->U = (double *)calloc(n, sizeof(double));
+  c->Us = (double *)calloc(n, sizeof(double));
+  c->Un = (double *)calloc(n, sizeof(double));
+  c->P = (double *)calloc(n, sizeof(double));
+  const size_t nxf = (size_t)(c->cfg.nx + 1) * c->cfg.ny * NF_FACE * c->nc;
+  const size_t nyf = (size_t)c->cfg.nx * (c->cfg.ny + 1) * NF_FACE * c->nc;
+  c->xf = (double *)calloc(nxf, sizeof(double));
+  c->yf = cfg->dim == 2 ? (double *)calloc(nyf, sizeof(double)) : NULL;
+  if (!c->U || !c->Us || !c->Un || !c->P || !c->xf || (cfg->dim == 2 && !c->yf)) {
+    orc_destroy(c);
+    return ORC_ENOMEM;
+  }
+  c->bad_cell = -1;
+  *out = c;
+  return ORC_OK;
+}
+
+void orc_destroy(orc_ctx *c) {
+  if (!c) return;
+  free(c->U); free(c->Us); free(c->Un); free(c->P); free(c->xf); free(c->yf);
+  free(c);
+}
+
+int orc_set_state(orc_ctx *c, const double *fields, double t0) {
+  const int nx = c->cfg.nx, ny = c->cfg.ny;
+  for (int f = 0; f < c->nf; ++f)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
+        fld(c, c->U, f)[gidx(c, i, j)] = fields[((size_t)f * ny + j) * nx + i];
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double W[4];
+      for (int k = 0; k < c->nc; ++k) W[k] = fld(c, c->U, k)[gidx(c, i, j)];
+      if (!orc_admissible(c->cfg.dim, c->cfg.gamma, W)) { c->bad_cell = (long)j * nx + i; return ORC_ENONPHYS; }
+    }
+  c->t = t0;
+  c->step = 0;
+  return ORC_OK;
+}
+
+int orc_get_state(const orc_ctx *c, double *fields, double *t, long *step) {
+  const int nx = c->cfg.nx, ny = c->cfg.ny;
+  if (fields)
+    for (int f = 0; f < c->nf; ++f)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+          fields[((size_t)f * ny + j) * nx + i] = fld(c, c->U, f)[gidx(c, i, j)];
+  if (t) *t = c->t;
+  if (step) *step = c->step;
+  return ORC_OK;
+}
+
+int orc_counters_get(const orc_ctx *c, orc_counters *out) { *out = c->cnt; out->steps = c->step; return ORC_OK; }
+long orc_last_bad_cell(const orc_ctx *c) { return c->bad_cell; }
+
+/* ---- ghost cells (two layers) -------------------------------------------
+ * periodic: wrap; free: copy the boundary cell average, zero gradients;
+ * wall: mirror (normal momentum odd; the normal gradient has the opposite
+ * parity of its variable, the tangential gradient the same); inflow: fixed
+ * state with zero gradients.  x ghosts first, then y ghosts over all columns. */
+static void inflow_state(const orc_ctx *c, int side, double *W) {
+  const double *q = c->cfg.inflow_prim[side];
+  const double g1 = c->cfg.gamma - 1.0;
+  if (c->cfg.dim == 2) {
+    W[0] = q[0]; W[1] = q[0] * q[1]; W[2] = q[0] * q[2];
+    W[3] = q[3] / g1 + 0.5 * q[0] * (q[1] * q[1] + q[2] * q[2]);
+  } else {
+    W[0] = q[0]; W[1] = q[0] * q[1]; W[2] = q[3] / g1 + 0.5 * q[0] * q[1] * q[1];
+  }
+}
+
+/* copy one ghost cell dst from src following the side's rule; axis 0 = x, 1 = y */
+static void ghost_copy(orc_ctx *c, double *G, size_t dst, size_t src, int side, int axis) {
+  const int nc = c->nc, bc = c->cfg.bc[side];
+  if (bc == ORC_PERIODIC) {
+    for (int f = 0; f < c->nf; ++f) fld(c, G, f)[dst] = fld(c, G, f)[src];
+  } else if (bc == ORC_FREE) {
+    for (int k = 0; k < nc; ++k) fld(c, G, k)[dst] = fld(c, G, k)[src];
+    for (int f = nc; f < c->nf; ++f) fld(c, G, f)[dst] = 0.0;
+  } else if (bc == ORC_INFLOW) {
+    double W[4];
+    inflow_state(c, side, W);
+    for (int k = 0; k < nc; ++k) fld(c, G, k)[dst] = W[k];
+    for (int f = nc; f < c->nf; ++f) fld(c, G, f)[dst] = 0.0;
+  } else {  /* wall */
+    const int vel = 1 + axis;     /* momentum component normal to the wall */
+    for (int k = 0; k < nc; ++k) {
+      const double par = (k == vel) ? -1.0 : 1.0;
+      fld(c, G, k)[dst] = par * fld(c, G, k)[src];
+      for (int a = 0; a < c->cfg.dim; ++a) {
+        const double gpar = (a == axis) ? -par : par;
+        fld(c, G, c->nc * (1 + a) + k)[dst] = gpar * fld(c, G, c->nc * (1 + a) + k)[src];
+      }
+    }
+  }
+}
+
+static void fill_ghosts(orc_ctx *c, double *G) {
+  const int nx = c->cfg.nx, ny = c->cfg.ny;
+  for (int j = 0; j < ny; ++j)
+    for (int k = 1; k <= 2; ++k) {
+      int src_lo, src_hi;
+      switch (c->cfg.bc[0]) {
+        case ORC_PERIODIC: src_lo = ((-k) % nx + nx) % nx; break;
+        case ORC_WALL: src_lo = k - 1 < nx ? k - 1 : nx - 1; break;
+        default: src_lo = 0;
+      }
+      switch (c->cfg.bc[1]) {
+        case ORC_PERIODIC: src_hi = (nx - 1 + k) % nx; break;
+        case ORC_WALL: src_hi = nx - k >= 0 ? nx - k : 0; break;
+        default: src_hi = nx - 1;
+      }
+      ghost_copy(c, G, gidx(c, -k, j), gidx(c, src_lo, j), 0, 0);
+      ghost_copy(c, G, gidx(c, nx - 1 + k, j), gidx(c, src_hi, j), 1, 0);
+    }
+  if (c->cfg.dim == 1) return;
+  for (int i = -2; i < nx + 2; ++i)
+    for (int k = 1; k <= 2; ++k) {
+      int src_lo, src_hi;
+      switch (c->cfg.bc[2]) {
+        case ORC_PERIODIC: src_lo = ((-k) % ny + ny) % ny; break;
+        case ORC_WALL: src_lo = k - 1 < ny ? k - 1 : ny - 1; break;
+        default: src_lo = 0;
+      }
+      switch (c->cfg.bc[3]) {
+        case ORC_PERIODIC: src_hi = (ny - 1 + k) % ny; break;
+        case ORC_WALL: src_hi = ny - k >= 0 ? ny - k : 0; break;
+        default: src_hi = ny - 1;
+      }
+      ghost_copy(c, G, gidx(c, i, -k), gidx(c, i, src_lo), 2, 1);
+      ghost_copy(c, G, gidx(c, i, ny - 1 + k), gidx(c, i, src_hi), 3, 1);
+    }
+}
+
+/* ---- CFL (Sec. 4): dt = CFL * min over cells of min(dx/(|U|+c), dy/(|V|+c)) */
+double orc_cfl_dt(const orc_ctx *c) {
+  const int nx = c->cfg.nx, ny = c->cfg.ny, dim = c->cfg.dim;
+  double lmax = 0.0;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double W[4];
+      for (int k = 0; k < c->nc; ++k) W[k] = fld(c, c->U, k)[gidx(c, i, j)];
+      const double p = orc_pressure(dim, c->cfg.gamma, W);
+      const double snd = sqrt(c->cfg.gamma * p / W[0]);
+      double l = (fabs(W[1] / W[0]) + snd) / c->dx;
+      if (dim == 2) {
+        const double ly = (fabs(W[2] / W[0]) + snd) / c->dy;
+        if (ly > l) l = ly;
+      }
+      if (l > lmax) lmax = l;
+    }
+  return c->cfg.cfl / lmax;
+}
+
+/* ---- one face: normal reconstruction of 5 stencil lines, tangential
+ * quartic to the Gauss points, gas-kinetic evolution at each point ---------- */
+
+/* Normal reconstruction on one line (Sec. 3.2, 3.3): Q shifted by the face's
+ * reference state, D = h Q'.  Output: P7, P7_n, P7_nn, left and right values. */
+static void normal_line(const double *Q, const double *D, double h, double eps, double *o5) {
+  double p[3];
+  orc_p7(Q, D, p);
+  o5[0] = p[0];
+  o5[1] = p[1] / h;
+  o5[2] = p[2] / (h * h);
+  o5[3] = orc_weno_left(Q, D, eps, 0, 0, 0);
+  o5[4] = orc_weno_right(Q, D, eps);
+}
+
+static void swap12(double *v) { double t = v[1]; v[1] = v[2]; v[2] = t; }
+
+typedef struct { long w0, weno; } guards_t;
+
+/* Evaluate one face.  lines[l][q][c]: stencil line l (tangential offset l-2,
+ * only l=0 used in 1D), quantity q (P7, P7_n, P7_nn, W_l, W_r), component c;
+ * the value quantities are deviations from ref.  rot: y-face (swap momenta).
+ * Writes F, Ft, A, B (blocks of nc) averaged over the Gauss points. */
+static void face_eval(orc_ctx *c, double lines[5][5][4], const double *ref, const double *Wleft,
+                      const double *Wright, double dt, int final, int rot, double ht,
+                      double *out, guards_t *gd) {
+  const int dim = c->cfg.dim, nc = c->nc;
+  const double gam = c->cfg.gamma;
+  const int npts = dim == 2 ? 2 : 1;
+  const double eta[2] = {-0.5 / sqrt(3.0), 0.5 / sqrt(3.0)};   /* 2-point Gauss-Legendre */
+  for (int k = 0; k < NF_FACE * nc; ++k) out[k] = 0.0;
+  for (int g = 0; g < npts; ++g) {
+    double W0d[4], W0[4], Wn[4], Wt_[4], Wnn[4], Wnt[4], Wtt_[4], Wl[4], Wr[4];
+    for (int k = 0; k < nc; ++k) {
+      if (dim == 2) {
+        double s[5], r3[3];
+        for (int l = 0; l < 5; ++l) s[l] = lines[l][0][k];
+        orc_quartic(s, eta[g], r3);
+        W0d[k] = r3[0]; Wt_[k] = r3[1] / ht; Wtt_[k] = r3[2] / (ht * ht);
+        for (int l = 0; l < 5; ++l) s[l] = lines[l][1][k];
+        orc_quartic(s, eta[g], r3);
+        Wn[k] = r3[0]; Wnt[k] = r3[1] / ht;
+        for (int l = 0; l < 5; ++l) s[l] = lines[l][2][k];
+        orc_quartic(s, eta[g], r3);
+        Wnn[k] = r3[0];
+        for (int l = 0; l < 5; ++l) s[l] = lines[l][3][k];
+        orc_quartic(s, eta[g], r3);
+        Wl[k] = ref[k] + r3[0];
+        for (int l = 0; l < 5; ++l) s[l] = lines[l][4][k];
+        orc_quartic(s, eta[g], r3);
+        Wr[k] = ref[k] + r3[0];
+      } else {
+        W0d[k] = lines[0][0][k]; Wn[k] = lines[0][1][k]; Wnn[k] = lines[0][2][k];
+        Wl[k] = ref[k] + lines[0][3][k]; Wr[k] = ref[k] + lines[0][4][k];
+        Wt_[k] = Wnt[k] = Wtt_[k] = 0.0;
+      }
+      W0[k] = ref[k] + W0d[k];
+    }
+    /* inadmissible nonlinear states fall back to the adjacent cell average */
+    if (!orc_admissible(dim, gam, Wl)) { for (int k = 0; k < nc; ++k) Wl[k] = Wleft[k]; gd->weno++; }
+    if (!orc_admissible(dim, gam, Wr)) { for (int k = 0; k < nc; ++k) Wr[k] = Wright[k]; gd->weno++; }
+    if (rot) {
+      swap12(W0); swap12(Wn); swap12(Wt_); swap12(Wnn); swap12(Wnt); swap12(Wtt_);
+      swap12(Wl); swap12(Wr);
+    }
+    double F[4], Ft[4], Wt[4], Wtt[4], Nh[4], Nf[4], tau, W0u[4];
+    const int fired = orc_gks_point_g(dim, gam, c->cfg.tau_eps, c->cfg.tau_C, dt, W0, Wn, Wt_, Wnn,
+                                      Wnt, Wtt_, Wl, Wr, F, Ft, Wt, Wtt, Nh, Nf, &tau, W0u);
+    if (rot) { swap12(F); swap12(Ft); swap12(Wt); swap12(Wtt); swap12(Nh); swap12(Nf); swap12(W0u); }
+    if (fired) { gd->w0++; for (int k = 0; k < nc; ++k) W0d[k] = W0u[k] - ref[k]; }
+    const double wg = 1.0 / npts;
+    for (int k = 0; k < nc; ++k) {
+      double A, B;
+      if (!final) {
+        /* interface state at t + dt/2 and the stage-n part of the state at t + dt (Sec. 2.2) */
+        A = W0d[k] + 0.5 * dt * Wt[k] + dt * dt / 8.0 * Wtt[k] + Nh[k];
+        B = W0d[k] + dt * Wt[k] + dt * dt / 6.0 * Wtt[k] + Nf[k];
+      } else {
+        A = Wtt[k];
+        B = 0.0;
+      }
+      out[k] += wg * F[k];
+      out[nc + k] += wg * Ft[k];
+      out[2 * nc + k] += wg * A;
+      out[3 * nc + k] += wg * B;
+    }
+  }
+}
+
+/* all faces of one stage on the ghosted state G */
+static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guards_t *gd_total) {
+  const int nx = c->cfg.nx, ny = c->cfg.ny, nc = c->nc, dim = c->cfg.dim;
+  const double eps = c->cfg.weno_eps;
+  long gw0 = 0, gwe = 0;
+  /* x faces: face f between cells f-1 and f, reference = cell f-1 of the same row */
+#pragma omp parallel for schedule(dynamic) reduction(+ : gw0, gwe) if (nthreads_req != 1)
+  for (int j = 0; j < ny; ++j) {
+    guards_t gd = {0, 0};
+    for (int f = 0; f <= nx; ++f) {
+      double ref[4], Wlc[4], Wrc[4], lines[5][5][4];
+      for (int k = 0; k < nc; ++k) {
+        ref[k] = fld(c, (double *)G, k)[gidx(c, f - 1, j)];
+        Wlc[k] = ref[k];
+        Wrc[k] = fld(c, (double *)G, k)[gidx(c, f, j)];
+      }
+      const int nl = dim == 2 ? 5 : 1;
+      for (int l = 0; l < nl; ++l) {
+        const int jj = dim == 2 ? j + l - 2 : 0;
+        for (int k = 0; k < nc; ++k) {
+          double Q[4], D[4];
+          for (int m = 0; m < 4; ++m) {
+            Q[m] = fld(c, (double *)G, k)[gidx(c, f - 2 + m, jj)] - ref[k];
+            D[m] = c->dx * fld(c, (double *)G, nc + k)[gidx(c, f - 2 + m, jj)];
+          }
+          double o5[5];
+          normal_line(Q, D, c->dx, eps, o5);
+          for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q];
+        }
+      }
+      double *out = c->xf + ((size_t)j * (nx + 1) + f) * NF_FACE * nc;
+      face_eval(c, lines, ref, Wlc, Wrc, dt, final, 0, c->dy, out, &gd);
+    }
+    gw0 += gd.w0; gwe += gd.weno;
+  }
+  if (dim == 2) {
+    /* y faces: face f between cells (i, f-1) and (i, f), reference = cell (i, f-1) */
+#pragma omp parallel for schedule(dynamic) reduction(+ : gw0, gwe) if (nthreads_req != 1)
+    for (int f = 0; f <= ny; ++f) {
+      guards_t gd = {0, 0};
+      for (int i = 0; i < nx; ++i) {
+        double ref[4], Wlc[4], Wrc[4], lines[5][5][4];
+        for (int k = 0; k < nc; ++k) {
+          ref[k] = fld(c, (double *)G, k)[gidx(c, i, f - 1)];
+          Wlc[k] = ref[k];
+          Wrc[k] = fld(c, (double *)G, k)[gidx(c, i, f)];
+        }
+        for (int l = 0; l < 5; ++l) {
+          const int ii = i + l - 2;
+          for (int k = 0; k < nc; ++k) {
+            double Q[4], D[4];
+            for (int m = 0; m < 4; ++m) {
+              Q[m] = fld(c, (double *)G, k)[gidx(c, ii, f - 2 + m)] - ref[k];
+              D[m] = c->dy * fld(c, (double *)G, 2 * nc + k)[gidx(c, ii, f - 2 + m)];
+            }
+            double o5[5];
+            normal_line(Q, D, c->dy, eps, o5);
+            for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q];
+          }
+        }
+        double *out = c->yf + ((size_t)f * nx + i) * NF_FACE * nc;
+        face_eval(c, lines, ref, Wlc, Wrc, dt, final, 1, c->dx, out, &gd);
+      }
+      gw0 += gd.w0; gwe += gd.weno;
+    }
+  }
+  gd_total->w0 += gw0;
+  gd_total->weno += gwe;
+}
+
+/* Cell updates.  Stage 1 (final = 0): W* = W + dt/2 L + dt^2/8 L_t and the
+ * partial P = W + dt L + dt^2/6 L_t (eq. step-hyper-1); gradients of the
+ * intermediate state from the interface states at t + dt/2 by the Gauss
+ * theorem (eq. compact-deriv-1), and their stage-n partial.
+ * Stage 2 (final = 1): W^{n+1} = P + dt^2/3 L_t*, gradients likewise with
+ * the second time derivative of the interface state at t*. */
+static void stage_update(orc_ctx *c, const double *G, double dt, int final, double *dst) {
+  const int nx = c->cfg.nx, ny = c->cfg.ny, nc = c->nc, dim = c->cfg.dim;
+  const int B = NF_FACE * nc;
+#pragma omp parallel for if (nthreads_req != 1)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double *xl = c->xf + ((size_t)j * (nx + 1) + i) * B;
+      const double *xr = xl + B;
+      const double *yl = dim == 2 ? c->yf + ((size_t)j * nx + i) * B : NULL;
+      const double *yr = dim == 2 ? c->yf + ((size_t)(j + 1) * nx + i) * B : NULL;
+      const size_t id = gidx(c, i, j);
+      for (int k = 0; k < nc; ++k) {
+        double L = -(xr[k] - xl[k]) / c->dx;
+        double Lt = -(xr[nc + k] - xl[nc + k]) / c->dx;
+        if (dim == 2) {
+          L += -(yr[k] - yl[k]) / c->dy;
+          Lt += -(yr[nc + k] - yl[nc + k]) / c->dy;
+        }
+        const double W = fld(c, (double *)G, k)[id];
+        /* the x-face values carry deviations from their left cells:
+         * W(x_{i+1/2}) - W(x_{i-1/2}) = dev_{i+1/2} - dev_{i-1/2} + (W_i - W_{i-1}) */
+        const double jx = W - fld(c, (double *)G, k)[gidx(c, i - 1, j)];
+        const double jy = dim == 2 ? W - fld(c, (double *)G, k)[gidx(c, i, j - 1)] : 0.0;
+        if (!final) {
+          fld(c, dst, k)[id] = W + 0.5 * dt * L + dt * dt / 8.0 * Lt;
+          fld(c, c->P, k)[id] = W + dt * L + dt * dt / 6.0 * Lt;
+          fld(c, dst, nc + k)[id] = ((xr[2 * nc + k] - xl[2 * nc + k]) + jx) / c->dx;
+          fld(c, c->P, nc + k)[id] = ((xr[3 * nc + k] - xl[3 * nc + k]) + jx) / c->dx;
+          if (dim == 2) {
+            fld(c, dst, 2 * nc + k)[id] = ((yr[2 * nc + k] - yl[2 * nc + k]) + jy) / c->dy;
+            fld(c, c->P, 2 * nc + k)[id] = ((yr[3 * nc + k] - yl[3 * nc + k]) + jy) / c->dy;
+          }
+        } else {
+          fld(c, dst, k)[id] = fld(c, c->P, k)[id] + dt * dt / 3.0 * Lt;
+          fld(c, dst, nc + k)[id] = fld(c, c->P, nc + k)[id]
+                                    + dt * dt / 3.0 * (xr[2 * nc + k] - xl[2 * nc + k]) / c->dx;
+          if (dim == 2)
+            fld(c, dst, 2 * nc + k)[id] = fld(c, c->P, 2 * nc + k)[id]
+                                          + dt * dt / 3.0 * (yr[2 * nc + k] - yl[2 * nc + k]) / c->dy;
+        }
+      }
+    }
+}
+
+static long first_bad(const orc_ctx *c, const double *G) {
+  for (int j = 0; j < c->cfg.ny; ++j)
+    for (int i = 0; i < c->cfg.nx; ++i) {
+      double W[4];
+      for (int k = 0; k < c->nc; ++k) W[k] = fld(c, (double *)G, k)[gidx(c, i, j)];
+      if (!orc_admissible(c->cfg.dim, c->cfg.gamma, W)) return (long)j * c->cfg.nx + i;
+    }
+  return -1;
+}
+
+int orc_step(orc_ctx *c, double dt, double *dt_used) {
+#ifdef _OPENMP
+  if (nthreads_req > 0) omp_set_num_threads(nthreads_req);
+#endif
+  if (!(dt > 0.0)) dt = c->cfg.fixed_dt > 0.0 ? c->cfg.fixed_dt : orc_cfl_dt(c);
+  if (!(dt > 0.0) || !isfinite(dt)) return ORC_EINVAL;
+  guards_t gd = {0, 0};
+  fill_ghosts(c, c->U);
+  stage_faces(c, c->U, dt, 0, &gd);
+  stage_update(c, c->U, dt, 0, c->Us);
+  long bad = first_bad(c, c->Us);
+  if (bad >= 0) { c->bad_cell = bad; return ORC_ENONPHYS; }
+  fill_ghosts(c, c->Us);
+  stage_faces(c, c->Us, dt, 1, &gd);
+  stage_update(c, c->Us, dt, 1, c->Un);
+  bad = first_bad(c, c->Un);
+  if (bad >= 0) { c->bad_cell = bad; return ORC_ENONPHYS; }
+  double *t = c->U; c->U = c->Un; c->Un = t;
+  c->t += dt;
+  c->step += 1;
+  c->cnt.guard_w0 += gd.w0;
+  c->cnt.guard_weno += gd.weno;
+  c->cnt.last_dt = dt;
+  if (dt_used) *dt_used = dt;
+  return ORC_OK;
+}
+
+/* Advance to t_end: each step uses the CFL (or fixed) step, the last one is
+ * clamped so that the run lands on t_end exactly. */
+int orc_advance_to(orc_ctx *c, double t_end, long max_steps, long *steps_taken) {
+  long n = 0;
+  int rc = ORC_OK;
+  while (c->t < t_end && (max_steps <= 0 || n < max_steps)) {
+    double dt = c->cfg.fixed_dt > 0.0 ? c->cfg.fixed_dt : orc_cfl_dt(c);
+    int last = 0;
+    /* a step that reaches t_end to within round-off of the time sum is the last */
+    if (dt * (1.0 + 1e-9) >= t_end - c->t) { dt = t_end - c->t; last = 1; }
+    rc = orc_step(c, dt, NULL);
+    if (rc) break;
+    if (last) c->t = t_end;
+    ++n;
+  }
+  if (steps_taken) *steps_taken = n;
+  return rc;
+}
