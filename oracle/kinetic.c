@@ -248,31 +248,49 @@ static void slope_term(const orc_maxw *g, int n, int m, const double *an, const 
   for (int c = 0; c < nc; ++c) out[c] = g->rho * (t1[c] + t2[c]);
 }
 
-/* Time integral over [0, delta] of the flux of the second-order distribution:
- * eq. (3rd-simplify-flux) without the a_tt, a_xt, a_yt terms.  For the Euler
- * equations the Chapman-Enskog terms carry the physical collision time, zero
- * here, and the numerical collision time tau enters through exp(-t/tau). */
-static void fhat(const iface_t *s, double tau, double delta, double *out) {
+/* The flux of the second-order distribution is linear in five moment vectors,
+ * one per term of eq. (3rd-simplify-flux) without a_tt, a_xt, a_yt:
+ *   M1 = rho0 <u psi>_0                 (g0)
+ *   M2 = rho0 <u psi A>_0               (A g0 t)
+ *   M3 = rho0 <u psi (a_n u + a_t v)>_0 (slope part of the equilibrium)
+ *   M4 = rho_l <u psi>_{l,u>0} + rho_r <u psi>_{r,u<0}
+ *   M5 = rho_l <u psi (a_l.u)>_{l,u>0} + rho_r <u psi (a_r.u)>_{r,u<0}  */
+static void moment_vectors(const iface_t *s, double M[5][4]) {
   const int nc = s->nc;
-  const double Ed = exp(-delta / tau);
-  const double c1 = delta - tau * (1.0 - Ed);                    /* g0 (1 - e^{-t/tau})            */
-  const double c2 = 0.5 * delta * delta;                          /* A g0 t                          */
-  const double c3 = tau * tau * (1.0 - Ed) - tau * delta * Ed;    /* e^{-t/tau} t (a.u) g0           */
-  const double c4 = tau * (1.0 - Ed);                             /* e^{-t/tau} g_{l,r} H            */
-  const double c5 = -c3;                                          /* -e^{-t/tau} t (a_{l,r}.u) g_{l,r} H */
-  double f0[4], fA[4], fs0[4], flr[4], fslr[4], tmp[4];
-  m_p(&s->g0, 1, 0, f0);
-  m_pa(&s->g0, 1, 0, s->A0, fA);
-  slope_term(&s->g0, 1, 0, s->an0, s->at0, fs0);
-  m_p(&s->gl_half, 1, 0, flr);
+  double tmp[4];
+  m_p(&s->g0, 1, 0, M[0]);
+  m_pa(&s->g0, 1, 0, s->A0, M[1]);
+  for (int c = 0; c < nc; ++c) { M[0][c] *= s->g0.rho; M[1][c] *= s->g0.rho; }
+  slope_term(&s->g0, 1, 0, s->an0, s->at0, M[2]);
+  m_p(&s->gl_half, 1, 0, M[3]);
   m_p(&s->gr_half, 1, 0, tmp);
-  for (int c = 0; c < nc; ++c) flr[c] = s->gl_half.rho * flr[c] + s->gr_half.rho * tmp[c];
-  slope_term(&s->gl_half, 1, 0, s->anl, s->atl, fslr);
+  for (int c = 0; c < nc; ++c) M[3][c] = s->gl_half.rho * M[3][c] + s->gr_half.rho * tmp[c];
+  slope_term(&s->gl_half, 1, 0, s->anl, s->atl, M[4]);
   slope_term(&s->gr_half, 1, 0, s->anr, s->atr, tmp);
-  for (int c = 0; c < nc; ++c) fslr[c] += tmp[c];
-  for (int c = 0; c < nc; ++c)
-    out[c] = c1 * s->g0.rho * f0[c] + c2 * s->g0.rho * fA[c] + c3 * fs0[c]
-             + c4 * flr[c] + c5 * fslr[c];
+  for (int c = 0; c < nc; ++c) M[4][c] += tmp[c];
+}
+
+/* Time coefficients of the five terms integrated over [0, delta].  For the
+ * Euler equations the Chapman-Enskog terms carry the physical collision time,
+ * zero here; the numerical collision time tau enters through exp(-t/tau):
+ *   c1 = int (1 - e^{-t/tau}),  c2 = int t,  c3 = int e^{-t/tau} t,
+ *   c4 = int e^{-t/tau},        c5 = -c3. */
+static void time_coefs(double tau, double delta, double c[5]) {
+  const double Ed = exp(-delta / tau);
+  c[0] = delta - tau * (1.0 - Ed);
+  c[1] = 0.5 * delta * delta;
+  c[2] = tau * tau * (1.0 - Ed) - tau * delta * Ed;
+  c[3] = tau * (1.0 - Ed);
+  c[4] = -c[2];
+}
+
+/* Time integral over [0, delta] of the interface flux: sum_k c_k M_k. */
+static void fhat(const iface_t *s, double tau, double delta, double *out) {
+  double M[5][4], c[5];
+  moment_vectors(s, M);
+  time_coefs(tau, delta, c);
+  for (int k = 0; k < s->nc; ++k)
+    out[k] = c[0] * M[0][k] + c[1] * M[1][k] + c[2] * M[2][k] + c[3] * M[3][k] + c[4] * M[4][k];
 }
 
 static double collision_time(int dim, double gamma, double tau_eps, double tau_C, double dt,
@@ -322,13 +340,22 @@ int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double 
   iface_setup(dim, gamma, W0, W0n, dim == 2 ? W0t : zero, Wl, Wr, &s);
 
   /* flux extraction (Sec. 2.2): F(t) ~ F + Ft t fitted to the time integrals
-   * over [0, dt/2] and [0, dt] */
-  double Fh[4], Ff[4];
-  fhat(&s, tau, 0.5 * dt, Fh);
-  fhat(&s, tau, dt, Ff);
+   * over [0, dt/2] and [0, dt], Fhat(dt/2) = F dt/2 + Ft dt^2/8 and
+   * Fhat(dt) = F dt + Ft dt^2/2.  Fhat is linear in the moment vectors, so the
+   * fit is applied to each scalar time coefficient (fitting the vectors would
+   * subtract F dt from 2 F dt/2 and lose the small Ft).  With c1 = delta - c4
+   * and c5 = -c3 the integral reads delta M1 + c2 M2 + c4 (M4 - M1) + c3 (M3 - M5);
+   * delta fits to (1, 0) and c2 = delta^2/2 to (0, 1). */
+  double M[5][4], ch[5], cf[5];
+  moment_vectors(&s, M);
+  time_coefs(tau, 0.5 * dt, ch);
+  time_coefs(tau, dt, cf);
+  const double e4 = (4.0 * ch[3] - cf[3]) / dt, e4t = 4.0 * (cf[3] - 2.0 * ch[3]) / (dt * dt);
+  const double e3 = (4.0 * ch[2] - cf[2]) / dt, e3t = 4.0 * (cf[2] - 2.0 * ch[2]) / (dt * dt);
   for (int c = 0; c < nc; ++c) {
-    F[c] = (4.0 * Fh[c] - Ff[c]) / dt;
-    Ft[c] = 4.0 * (Ff[c] - 2.0 * Fh[c]) / (dt * dt);
+    const double d41 = M[3][c] - M[0][c], d35 = M[2][c] - M[4][c];
+    F[c] = M[0][c] + e4 * d41 + e3 * d35;
+    Ft[c] = M[1][c] + e4t * d41 + e3t * d35;
   }
 
   /* time derivative of the equilibrium state: W_t = rho0 <psi A>_g0 */
