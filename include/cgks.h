@@ -1,0 +1,113 @@
+/*
+ * cgks.h -- C ABI of the compact 8th-order gas-kinetic scheme on MI355X.
+ *
+ * The library advances the Euler equations on structured 1D and 2D grids by
+ * the compact gas-kinetic scheme of Zhao, Ji, Shyy, Xu (arXiv 2001.01570):
+ * given cell averages W and cell-averaged gradients W' (Sec. 3.1, eqs.
+ * compact-deriv-1 / compact-deriv), one step performs the compact linear and
+ * WENO-Z reconstruction (Sec. 3.2-3.3), the gas-kinetic interface evolution
+ * (Sec. 2.1, eq. 3rd-simplify-flux) and the two-stage fourth-order update of
+ * both W and W' (Sec. 2.2, eq. step-hyper-1 and the interface-state update).
+ * Every step runs in HIP kernels on the device; all arithmetic is FP64.
+ *
+ * Field layout (structure of arrays, x fastest, row-major in y):
+ *   1D: 6 fields  [rho, rhoU, rhoE, (rho)_x, (rhoU)_x, (rhoE)_x], each nx
+ *   2D: 12 fields [W(4), W_x(4), W_y(4)], W = (rho, rhoU, rhoV, rhoE), each ny*nx
+ * Field f, cell (i, j) lives at fields[(f*ny + j)*nx + i].
+ *
+ * Error behaviour: every call returns CGKS_OK (0) or a negative code; nothing
+ * aborts.  A step that produces a non-physical cell (rho <= 0, p <= 0 or
+ * NaN) is not committed: the state stays at the last good step and the call
+ * returns CGKS_ENONPHYS (cgks_last_bad_cell names the first bad cell).
+ * Threading: one host thread per context at a time.
+ */
+#ifndef CGKS_H
+#define CGKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGKS_OK 0
+#define CGKS_EINVAL (-1)     /* bad argument or configuration                      */
+#define CGKS_ENOMEM (-2)     /* device or host allocation failed                    */
+#define CGKS_EDEVICE (-3)    /* a HIP call failed                                   */
+#define CGKS_ENONPHYS (-4)   /* non-physical state; step not committed              */
+#define CGKS_EBUSY (-5)      /* batch: no free slot or memory budget exhausted      */
+#define CGKS_ESTATE (-6)     /* call not valid in the current state (e.g. no state) */
+
+enum { CGKS_PERIODIC = 0, CGKS_FREE = 1, CGKS_WALL = 2, CGKS_INFLOW = 3 };
+enum { CGKS_FP64 = 0 };
+
+typedef struct cgks_ctx cgks_ctx;
+
+typedef struct {
+  int dim;                   /* 1 or 2                                                  */
+  int nx, ny;                /* cells; ny ignored in 1D; wall sides need >= 2 cells      */
+  double x0, x1, y0, y1;     /* domain                                                   */
+  double gamma;              /* ratio of specific heats (> 1)                            */
+  double cfl;                /* CFL number of the time step rule (Sec. 4)                */
+  int bc[4];                 /* xlo, xhi, ylo, yhi: CGKS_PERIODIC|FREE|WALL|INFLOW;
+                                periodic must be paired on both sides of an axis         */
+  double inflow_prim[4][4];  /* (rho, U, V, p) of each CGKS_INFLOW side                  */
+  double weno_eps;           /* epsilon of the WENO-Z weights (eq. WENO-Z-w), e.g. 1e-6  */
+  double tau_eps, tau_C;     /* collision time eps*dt + C|dp/sum p|*dt (Sec. 4): 0.01, 1 */
+  double fixed_dt;           /* 0: CFL rule; > 0: fixed step (accuracy tests, Sec. 4.1) */
+  int storage;               /* CGKS_FP64                                                */
+} cgks_config;
+
+typedef struct {
+  long steps;                /* committed steps since set_state                         */
+  long guard_w0;             /* points where the linear equilibrium state was replaced  */
+  long guard_weno;           /* points where a WENO state fell back to a cell average   */
+  double last_dt;            /* step size of the last committed step                    */
+  double t;                  /* current time                                            */
+} cgks_counters_t;
+
+/* Create a solver context.  hip_stream (a hipStream_t, may be NULL for the
+ * null stream) is borrowed: all work is queued on it and it must outlive the
+ * context.  The context owns every device buffer it allocates. */
+int cgks_create(const cgks_config *cfg, void *hip_stream, cgks_ctx **out);
+
+/* Load a state (layout above).  fields is a host pointer (on_device = 0) or a
+ * device pointer (on_device = 1); it is copied, never retained.  Rejects a
+ * non-physical cell with CGKS_ENONPHYS. */
+int cgks_set_state(cgks_ctx *ctx, const double *fields, int on_device, double t0);
+
+/* One step of the rule in the configuration (CFL or fixed_dt). */
+int cgks_step(cgks_ctx *ctx, double *dt_used);
+
+/* One step of the given size dt > 0 (dt <= 0 falls back to the rule). */
+int cgks_step_dt(cgks_ctx *ctx, double dt, double *dt_used);
+
+/* Advance until t_end: every step uses the rule; the step that reaches t_end
+ * to within (1 + 1e-9) of its size is the last and lands on t_end exactly.
+ * max_steps > 0 bounds the number of steps of this call. */
+int cgks_advance_to(cgks_ctx *ctx, double t_end, long max_steps, long *steps_taken);
+
+/* Exactly n steps of the rule (no end time); used to time fixed step counts. */
+int cgks_run_steps(cgks_ctx *ctx, long n);
+
+/* Copy the current state out (host or device pointer); t and step may be NULL. */
+int cgks_get_state(cgks_ctx *ctx, double *fields_out, int on_device, double *t, long *step);
+
+int cgks_last_bad_cell(const cgks_ctx *ctx, long *cell);
+
+/* Measurement: while profiling is on, every hot kernel launch of a step is
+ * bracketed by HIP events on the context's stream.  cgks_kernel_times fills
+ * ms[k] (accumulated device milliseconds) and calls[k] for kernel kind k
+ * (2D: xfaces1, yfaces1, update1, xfaces2, yfaces2, update2; 1D: faces1,
+ * update1, faces2, update2) and returns the number of kinds, or an error.
+ * Turning profiling on clears the accumulators. */
+int cgks_set_profiling(cgks_ctx *ctx, int on);
+int cgks_kernel_times(cgks_ctx *ctx, double *ms, long *calls, int n);
+int cgks_counters(cgks_ctx *ctx, cgks_counters_t *out);
+void cgks_destroy(cgks_ctx *ctx);
+const char *cgks_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

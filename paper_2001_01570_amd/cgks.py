@@ -1,0 +1,209 @@
+"""Python binding of libcgks (the HIP implementation behind include/cgks.h).
+
+Argument marshalling only: every step of the scheme runs in the library's
+HIP kernels.  PyTorch supplies device memory (state tensors on the GPU) and
+the stream the library queues its work on.  There is no fallback: without
+the built library or without a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import build as _build
+
+CGKS_OK, CGKS_EINVAL, CGKS_ENOMEM, CGKS_EDEVICE, CGKS_ENONPHYS, CGKS_EBUSY, CGKS_ESTATE = 0, -1, -2, -3, -4, -5, -6
+PERIODIC, FREE, WALL, INFLOW = 0, 1, 2, 3
+
+
+class cgks_config(C.Structure):
+    _fields_ = [('dim', C.c_int), ('nx', C.c_int), ('ny', C.c_int),
+                ('x0', C.c_double), ('x1', C.c_double), ('y0', C.c_double), ('y1', C.c_double),
+                ('gamma', C.c_double), ('cfl', C.c_double),
+                ('bc', C.c_int * 4), ('inflow_prim', (C.c_double * 4) * 4),
+                ('weno_eps', C.c_double), ('tau_eps', C.c_double), ('tau_C', C.c_double),
+                ('fixed_dt', C.c_double), ('storage', C.c_int)]
+
+
+class cgks_counters_t(C.Structure):
+    _fields_ = [('steps', C.c_long), ('guard_w0', C.c_long), ('guard_weno', C.c_long),
+                ('last_dt', C.c_double), ('t', C.c_double)]
+
+
+class CgksError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        msg = _lib.cgks_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__('%s: %s (code %d)' % (what, msg, code))
+
+
+_lib = None
+_D = C.POINTER(C.c_double)
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def load():
+    """Load libcgks.so (building it first only if it does not exist)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    L = C.CDLL(_build.LIB)
+    L.cgks_create.argtypes = [C.POINTER(cgks_config), C.c_void_p, C.POINTER(C.c_void_p)]
+    L.cgks_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_double]
+    L.cgks_step.argtypes = [C.c_void_p, _D]
+    L.cgks_step_dt.argtypes = [C.c_void_p, C.c_double, _D]
+    L.cgks_advance_to.argtypes = [C.c_void_p, C.c_double, C.c_long, C.POINTER(C.c_long)]
+    L.cgks_run_steps.argtypes = [C.c_void_p, C.c_long]
+    L.cgks_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_int, _D, C.POINTER(C.c_long)]
+    L.cgks_last_bad_cell.argtypes = [C.c_void_p, C.POINTER(C.c_long)]
+    L.cgks_counters.argtypes = [C.c_void_p, C.POINTER(cgks_counters_t)]
+    L.cgks_destroy.argtypes = [C.c_void_p]
+    L.cgks_destroy.restype = None
+    L.cgks_strerror.argtypes = [C.c_int]
+    L.cgks_strerror.restype = C.c_char_p
+    L.cgks_set_profiling.argtypes = [C.c_void_p, C.c_int]
+    L.cgks_kernel_times.argtypes = [C.c_void_p, _D, C.POINTER(C.c_long), C.c_int]
+    L.cgks_kernel_times.restype = C.c_int
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError('the HIP path needs a GPU (torch.cuda.is_available() is False)')
+    return torch
+
+
+def make_config(prob) -> cgks_config:
+    d = prob.config_dict()
+    cfg = cgks_config()
+    for k in ('dim', 'nx', 'ny'):
+        setattr(cfg, k, int(d[k]))
+    for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt'):
+        setattr(cfg, k, float(d[k]))
+    for s in range(4):
+        cfg.bc[s] = int(d['bc'][s])
+        for q in range(4):
+            cfg.inflow_prim[s][q] = float(d['inflow_prim'][s][q])
+    cfg.storage = 0
+    return cfg
+
+
+KERNEL_NAMES_2D = ['xfaces1', 'yfaces1', 'update1', 'xfaces2', 'yfaces2', 'update2']
+KERNEL_NAMES_1D = ['faces1', 'update1', 'faces2', 'update2']
+
+
+class Solver:
+    """One simulation on the GPU (see paper_2001_01570_amd.inputs.Problem)."""
+
+    def __init__(self, prob, stream=None, load_state: bool = True):
+        torch = _torch()
+        L = load()
+        self.prob = prob
+        self.dim = prob.dim
+        self.shape = (6, prob.nx) if prob.dim == 1 else (12, prob.ny, prob.nx)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        rc = L.cgks_create(C.byref(make_config(prob)), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc:
+            raise CgksError(rc, 'cgks_create')
+        self.h = h
+        if load_state:
+            self.set_state(prob.fields, 0.0)
+
+    def close(self):
+        if getattr(self, 'h', None):
+            load().cgks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc:
+            raise CgksError(rc, what)
+
+    def set_state(self, fields, t0: float = 0.0):
+        torch = _torch()
+        if isinstance(fields, torch.Tensor) and fields.is_cuda:
+            assert tuple(fields.shape) == self.shape and fields.dtype == torch.float64
+            f = fields.contiguous()
+            self._check(load().cgks_set_state(self.h, C.c_void_p(f.data_ptr()), 1, float(t0)), 'cgks_set_state')
+        else:
+            a = np.ascontiguousarray(np.asarray(fields, dtype=np.float64))
+            assert a.shape == self.shape, (a.shape, self.shape)
+            self._check(load().cgks_set_state(self.h, C.c_void_p(a.ctypes.data), 0, float(t0)), 'cgks_set_state')
+
+    def step(self, dt: float = 0.0) -> float:
+        used = C.c_double()
+        self._check(load().cgks_step_dt(self.h, float(dt), C.byref(used)), 'cgks_step')
+        return used.value
+
+    def run_steps(self, n: int):
+        self._check(load().cgks_run_steps(self.h, int(n)), 'cgks_run_steps')
+
+    def advance_to(self, t_end: float, max_steps: int = 0) -> int:
+        n = C.c_long()
+        self._check(load().cgks_advance_to(self.h, float(t_end), int(max_steps), C.byref(n)), 'cgks_advance_to')
+        return n.value
+
+    def get_state(self, device: bool = False):
+        t = C.c_double()
+        s = C.c_long()
+        if device:
+            torch = _torch()
+            out = torch.empty(self.shape, dtype=torch.float64, device='cuda')
+            self._check(load().cgks_get_state(self.h, C.c_void_p(out.data_ptr()), 1, C.byref(t), C.byref(s)),
+                        'cgks_get_state')
+        else:
+            out = np.empty(self.shape)
+            self._check(load().cgks_get_state(self.h, C.c_void_p(out.ctypes.data), 0, C.byref(t), C.byref(s)),
+                        'cgks_get_state')
+        return out, t.value, s.value
+
+    @property
+    def state(self):
+        return self.get_state()[0]
+
+    @property
+    def t(self):
+        return self.get_state()[1]
+
+    def counters(self) -> dict:
+        c = cgks_counters_t()
+        self._check(load().cgks_counters(self.h, C.byref(c)), 'cgks_counters')
+        return dict(steps=c.steps, guard_w0=c.guard_w0, guard_weno=c.guard_weno, last_dt=c.last_dt, t=c.t)
+
+    def last_bad_cell(self) -> int:
+        c = C.c_long()
+        load().cgks_last_bad_cell(self.h, C.byref(c))
+        return c.value
+
+    def set_profiling(self, on: bool):
+        self._check(load().cgks_set_profiling(self.h, 1 if on else 0), 'cgks_set_profiling')
+
+    def kernel_times(self) -> dict:
+        """Per-kernel accumulated device time (ms) and launch counts recorded with
+        HIP events on the solver's stream while profiling was on."""
+        n = 8
+        ms = (C.c_double * n)()
+        calls = (C.c_long * n)()
+        k = load().cgks_kernel_times(self.h, ms, calls, n)
+        if k < 0:
+            raise CgksError(k, 'cgks_kernel_times')
+        names = KERNEL_NAMES_2D if self.dim == 2 else KERNEL_NAMES_1D
+        return {names[i]: (ms[i], calls[i]) for i in range(min(k, len(names)))}

@@ -1,0 +1,886 @@
+// Kernels and C ABI of the compact 8th-order gas-kinetic scheme on gfx950.
+//
+// One time step (two-stage fourth-order method, eq. step-hyper-1) is eight
+// launches on the context's stream:
+//   begin   (1 thread)   step size from the CFL maximum of the previous step
+//   xfaces1, yfaces1     normal reconstruction of line segments into LDS, tangential
+//                        quartic to 2 Gauss points, gas-kinetic evolution per point
+//   update1              W*, P (partial sums of the final update), gradients of W*
+//   xfaces2, yfaces2     same on W*, only F_t and W_tt
+//   update2              W^{n+1}, its gradients, CFL maximum and admissibility
+//   end     (1 thread)   commit (or keep the old state after a non-physical one)
+// The step size, time and status live in device memory so that consecutive
+// steps need no host round trip.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cgks.h"
+#include "cgks_device.h"
+
+namespace cgks {
+
+constexpr int TF = 16;          // faces per tile along the normal direction
+constexpr int TT = 16;          // face segments per tile along the tangential direction
+constexpr int TH = TT + 4;      // tangential extent including the 2+2 halo
+constexpr int NSEG = TF * TH;   // reconstructed line segments per tile (320)
+constexpr int NQ = 24;          // per segment: 5 quantities x 4 components + 4 reference values
+
+struct Geom {
+  int dim, nx, ny;
+  double dx, dy, eps;
+  int bc[4];
+  double inflow[4][4];   // conservative inflow state per side
+  Gas gas;
+};
+
+struct Params {          // written by the host before a batch of steps
+  double t_end;          // +inf: no end time
+  double dt_override;    // > 0: use this step size
+};
+
+struct Scalars {
+  Params prm;
+  double t, dt, cfl, fixed_dt, last_dt;
+  unsigned long long lam_bits, lam_next;   // bits of the positive CFL maximum
+  unsigned long long bad_cell;
+  unsigned long long guard_w0, guard_weno;
+  long long step;
+  int status, active, last, cur;
+};
+
+struct Bufs {
+  double* S[2];    // state double buffer
+  double* Ws;      // intermediate state W*
+  double* P;       // W + dt L + dt^2/6 L_t and the gradient counterpart
+  double* FX;      // x-face results
+  double* FY;      // y-face results
+  Scalars* sc;
+};
+
+// ---------------------------------------------------------------- boundaries
+// Ghost cells are never stored: a cell index outside the grid is mapped to its
+// source cell and the boundary rule is applied on load (x rule, then y rule,
+// i.e. x ghosts first and y ghosts over all columns).
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ int src_index(int i, int n, int bclo, int bchi, int& kind, int& side) {
+  if (i >= 0 && i < n) { kind = -1; return i; }
+  if (i < 0) {
+    kind = bclo; side = 0;
+    if (bclo == CGKS_PERIODIC) return wrap(i, n);
+    if (bclo == CGKS_WALL) return -i - 1;
+    return 0;
+  }
+  kind = bchi; side = 1;
+  if (bchi == CGKS_PERIODIC) return wrap(i, n);
+  if (bchi == CGKS_WALL) return 2 * n - 1 - i;
+  return n - 1;
+}
+
+// rule of one side on (W, gradient along dir): free -> zero gradients,
+// inflow -> fixed state and zero gradients, wall -> mirror
+template <int NC>
+__device__ __forceinline__ void apply_rule(const Geom& G, int kind, int side, int axis, int dir,
+                                           double* W, double* Gd) {
+  if (kind < 0 || kind == CGKS_PERIODIC) return;
+  if (kind == CGKS_FREE) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) Gd[k] = 0.0;
+  } else if (kind == CGKS_INFLOW) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) { W[k] = G.inflow[side][k]; Gd[k] = 0.0; }
+  } else {  // wall: normal momentum odd; normal gradient opposite parity, tangential same
+    const int vel = 1 + axis;
+    W[vel] = -W[vel];
+    if (dir == axis) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) if (k != vel) Gd[k] = -Gd[k];
+    } else {
+      Gd[vel] = -Gd[vel];
+    }
+  }
+}
+
+// W and its gradient along dir (0: x, 1: y) of cell (i, j), ghosts included
+template <int NC>
+__device__ __forceinline__ void load_cell(const double* S, const Geom& G, int i, int j, int dir,
+                                          double* W, double* Gd) {
+  int kx, sx = 0, ky = -1, sy = 0;
+  const int si = src_index(i, G.nx, G.bc[0], G.bc[1], kx, sx);
+  int sj = 0;
+  if constexpr (NC == 4) sj = src_index(j, G.ny, G.bc[2], G.bc[3], ky, sy);
+  const size_t N = (size_t)G.nx * (NC == 4 ? G.ny : 1);
+  const size_t id = (size_t)sj * G.nx + si;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    W[k] = S[k * N + id];
+    Gd[k] = S[(NC + NC * dir + k) * N + id];
+  }
+  apply_rule<NC>(G, kx, sx, 0, dir, W, Gd);
+  if constexpr (NC == 4) apply_rule<NC>(G, ky, 2 + sy, 1, dir, W, Gd);
+}
+
+template <int NC>
+__device__ __forceinline__ void load_avg(const double* S, const Geom& G, int i, int j, double* W) {
+  double Gd[NC];
+  load_cell<NC>(S, G, i, j, 0, W, Gd);
+}
+
+// ---------------------------------------------------------------- step control
+
+__global__ void k_begin(Scalars* sc) {
+  if (threadIdx.x != 0) return;
+  sc->active = 0;
+  if (sc->status != 0) return;
+  const double rem = sc->prm.t_end - sc->t;
+  if (!(rem > 0.0)) { sc->dt = 0.0; return; }
+  double dt = sc->prm.dt_override;
+  if (!(dt > 0.0)) dt = sc->fixed_dt > 0.0 ? sc->fixed_dt : sc->cfl / __longlong_as_double((long long)sc->lam_bits);
+  int last = 0;
+  if (dt * (1.0 + 1e-9) >= rem) { dt = rem; last = 1; }
+  if (!(dt > 0.0) || !(dt < INFINITY)) { sc->status = CGKS_ENONPHYS; return; }
+  sc->dt = dt;
+  sc->last = last;
+  sc->lam_next = 0ull;
+  sc->active = 1;
+}
+
+__global__ void k_end(Scalars* sc) {
+  if (threadIdx.x != 0 || !sc->active) return;
+  if (sc->status == 0) {
+    sc->t = sc->last ? sc->prm.t_end : sc->t + sc->dt;
+    sc->step += 1;
+    sc->cur ^= 1;
+    sc->lam_bits = sc->lam_next;
+    sc->last_dt = sc->dt;
+  }
+  sc->active = 0;
+}
+
+__device__ __forceinline__ void reduce_lambda(Scalars* sc, double lam) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) lam = fmax(lam, __shfl_xor(lam, o, 64));
+  if ((threadIdx.x & 63) == 0 && lam > 0.0) atomicMax(&sc->lam_next, (unsigned long long)__double_as_longlong(lam));
+}
+
+template <int NC>
+__device__ __forceinline__ double cell_lambda(const double* W, const Geom& G) {
+  const double ir = 1.0 / W[0];
+  const double p = pressure<NC>(W, G.gas.gamma);
+  const double c = sqrt(G.gas.gamma * p * ir);
+  double l = (fabs(W[1] * ir) + c) / G.dx;
+  if constexpr (NC == 4) l = fmax(l, (fabs(W[2] * ir) + c) / G.dy);
+  return l;
+}
+
+__device__ __forceinline__ void flag_bad(Scalars* sc, unsigned long long cell) {
+  atomicMin(&sc->bad_cell, cell);
+  atomicMin(&sc->status, CGKS_ENONPHYS);
+}
+
+// admissibility and CFL maximum of the current state (after set_state)
+template <int NC>
+__global__ __launch_bounds__(256) void k_scan(Geom G, Bufs B) {
+  Scalars* sc = B.sc;
+  const double* S = B.S[sc->cur];
+  const size_t N = (size_t)G.nx * (NC == 4 ? G.ny : 1);
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double lam = 0.0;
+  if (id < N) {
+    double W[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) W[k] = S[k * N + id];
+    if (!admissible<NC>(W, G.gas.gamma)) flag_bad(sc, id);
+    else lam = cell_lambda<NC>(W, G);
+  }
+  reduce_lambda(sc, lam);
+}
+
+__global__ void k_scan_begin(Scalars* sc) { if (threadIdx.x == 0) sc->lam_next = 0ull; }
+__global__ void k_scan_end(Scalars* sc) { if (threadIdx.x == 0) sc->lam_bits = sc->lam_next; }
+
+// ---------------------------------------------------------------- 2D faces
+
+// Face kernel of one direction.  DIR 0: x faces (normal x, tangential y);
+// DIR 1: y faces (normal y, tangential x, momenta swapped for the evolution).
+// Tile: TF faces x TT segments.  Phase 1 reconstructs TF x (TT+4) line
+// segments (each shifted by its own reference cell) into LDS; phase 2 runs one
+// face segment per thread: tangential quartic to each Gauss point, the
+// gas-kinetic evolution, and the Gauss average.
+template <int DIR, int STAGE>
+__global__ __launch_bounds__(256) void k_faces2(Geom G, Bufs B) {
+  Scalars* sc = B.sc;
+  if (!sc->active || sc->status != 0) return;
+  const double dt = sc->dt;
+  const double* S = STAGE == 1 ? B.S[sc->cur] : B.Ws;
+  __shared__ double lds[NQ][NSEG];
+
+  const int nn = DIR == 0 ? G.nx : G.ny;     // cells along the normal
+  const int nt = DIR == 0 ? G.ny : G.nx;     // cells along the tangential
+  const double hn = DIR == 0 ? G.dx : G.dy;
+  const double ht = DIR == 0 ? G.dy : G.dx;
+  // DIR 0: blockIdx.x over faces, blockIdx.y over rows; DIR 1: blockIdx.x over columns, blockIdx.y over faces
+  const int f0 = (DIR == 0 ? blockIdx.x : blockIdx.y) * TF;
+  const int t0 = (DIR == 0 ? blockIdx.y : blockIdx.x) * TT;
+
+  // phase 1: line segments (face f, tangential index tt)
+  for (int s = threadIdx.x; s < NSEG; s += blockDim.x) {
+    int fl, tl, pos;
+    if (DIR == 0) { tl = s / TF; fl = s % TF; pos = tl * TF + fl; }
+    else { fl = s / TH; tl = s % TH; pos = fl * TH + tl; }
+    const int f = f0 + fl, tt = t0 - 2 + tl;
+    if (f > nn || tt > nt + 1) continue;
+    double Wc[4][4], Dc[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if (DIR == 0) load_cell<4>(S, G, f - 2 + m, tt, 0, Wc[m], Dc[m]);
+      else load_cell<4>(S, G, tt, f - 2 + m, 1, Wc[m], Dc[m]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double ref = Wc[1][k];
+      const Line5 L = normal_line(Wc[0][k] - ref, Wc[2][k] - ref, Wc[3][k] - ref, hn * Dc[0][k],
+                                  hn * Dc[1][k], hn * Dc[2][k], hn * Dc[3][k], G.eps);
+      lds[0 * 4 + k][pos] = L.v;
+      lds[1 * 4 + k][pos] = L.vn;
+      lds[2 * 4 + k][pos] = L.vnn;
+      lds[3 * 4 + k][pos] = L.wl;
+      lds[4 * 4 + k][pos] = L.wr;
+      lds[20 + k][pos] = ref;
+    }
+  }
+  __syncthreads();
+
+  // phase 2: one face segment per thread, lanes along the contiguous index
+  const int lane16 = threadIdx.x % 16, row16 = threadIdx.x / 16;
+  int fl, tl;
+  if (DIR == 0) { fl = lane16; tl = row16; } else { tl = lane16; fl = row16; }
+  const int f = f0 + fl, tt = t0 + tl;
+  if (f > nn || tt >= nt) return;
+  auto P = [&](int l) { return DIR == 0 ? (tl + l) * TF + fl : fl * TH + tl + l; };
+
+  constexpr int NO = STAGE == 1 ? 16 : 8;
+  double acc[NO];
+#pragma unroll
+  for (int q = 0; q < NO; ++q) acc[q] = 0.0;
+  int guards_w0 = 0, guards_weno = 0;
+  const double hn2 = hn * hn, inv_ht = 1.0 / ht;
+
+#pragma unroll 1
+  for (int g = 0; g < 2; ++g) {
+    PointIn<4> in;
+    double dev[4], ref[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double rj = lds[20 + k][P(2)];
+      double v = 0, vt = 0, vtt = 0, n = 0, nt_ = 0, n2 = 0, wl = 0, wr = 0;
+#pragma unroll
+      for (int l = 0; l < 5; ++l) {
+        const int p = P(l);
+        const double off = lds[20 + k][p] - rj;
+        const double vl = lds[k][p] + off;
+        const double vnl = lds[4 + k][p];
+        v += kTang[g].v[l] * vl;
+        vt += kTang[g].d1[l] * vl;
+        vtt += kTang[g].d2[l] * vl;
+        n += kTang[g].v[l] * vnl;
+        nt_ += kTang[g].d1[l] * vnl;
+        n2 += kTang[g].v[l] * lds[8 + k][p];
+        wl += kTang[g].v[l] * (lds[12 + k][p] + off);
+        wr += kTang[g].v[l] * (lds[16 + k][p] + off);
+      }
+      ref[k] = rj;
+      dev[k] = v;
+      in.W0[k] = rj + v;
+      in.Wn[k] = n / hn;
+      in.Wnn[k] = n2 / hn2;
+      in.Wt[k] = vt * inv_ht;
+      in.Wnt[k] = nt_ / hn * inv_ht;
+      in.Wtt[k] = vtt * inv_ht * inv_ht;
+      in.Wl[k] = rj + wl;
+      in.Wr[k] = rj + wr;
+    }
+    // inadmissible nonlinear states fall back to the adjacent cell average
+    if (!admissible<4>(in.Wl, G.gas.gamma)) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) in.Wl[k] = ref[k];
+      ++guards_weno;
+    }
+    if (!admissible<4>(in.Wr, G.gas.gamma)) {
+      double Wn_[4];
+      if (DIR == 0) load_avg<4>(S, G, f, tt, Wn_); else load_avg<4>(S, G, tt, f, Wn_);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) in.Wr[k] = Wn_[k];
+      ++guards_weno;
+    }
+    if (DIR == 1) {   // rotate: the normal momentum becomes the first velocity component
+      auto sw = [](double* v) { const double t = v[1]; v[1] = v[2]; v[2] = t; };
+      sw(in.W0); sw(in.Wn); sw(in.Wt); sw(in.Wnn); sw(in.Wnt); sw(in.Wtt); sw(in.Wl); sw(in.Wr);
+    }
+    PointOut<4> o;
+    gks_point<4, STAGE == 1>(in, G.gas, dt, o);
+    if (DIR == 1) {
+      auto sw = [](double* v) { const double t = v[1]; v[1] = v[2]; v[2] = t; };
+      sw(o.F); sw(o.Ft); sw(o.Wt); sw(o.Wtt); sw(o.Nh); sw(o.Nf); sw(o.W0);
+    }
+    guards_w0 += o.guard;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (STAGE == 1) {
+        const double d0 = o.guard ? o.W0[k] - ref[k] : dev[k];
+        acc[k] += 0.5 * o.F[k];
+        acc[4 + k] += 0.5 * o.Ft[k];
+        acc[8 + k] += 0.5 * (d0 + 0.5 * dt * o.Wt[k] + dt * dt / 8.0 * o.Wtt[k] + o.Nh[k]);
+        acc[12 + k] += 0.5 * (d0 + dt * o.Wt[k] + dt * dt / 6.0 * o.Wtt[k] + o.Nf[k]);
+      } else {
+        acc[k] += 0.5 * o.Ft[k];
+        acc[4 + k] += 0.5 * o.Wtt[k];
+      }
+    }
+  }
+  if (guards_w0) atomicAdd(&sc->guard_w0, (unsigned long long)guards_w0);
+  if (guards_weno) atomicAdd(&sc->guard_weno, (unsigned long long)guards_weno);
+  double* F = DIR == 0 ? B.FX : B.FY;
+  // x faces: [q][row][face] (nx+1 per row); y faces: [q][face][column] (nx per row)
+  const size_t plane = DIR == 0 ? (size_t)G.ny * (G.nx + 1) : (size_t)(G.ny + 1) * G.nx;
+  const size_t idx = DIR == 0 ? (size_t)tt * (G.nx + 1) + f : (size_t)f * G.nx + tt;
+#pragma unroll
+  for (int q = 0; q < NO; ++q) F[q * plane + idx] = acc[q];
+}
+
+// ---------------------------------------------------------------- 2D update
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_update2(Geom G, Bufs B) {
+  Scalars* sc = B.sc;
+  if (!sc->active || sc->status != 0) return;
+  const double dt = sc->dt;
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const bool in = i < G.nx && j < G.ny;
+  const size_t N = (size_t)G.nx * G.ny;
+  const size_t id = (size_t)j * G.nx + i;
+  const size_t px = (size_t)G.ny * (G.nx + 1), py = (size_t)(G.ny + 1) * G.nx;
+  const size_t xl = (size_t)j * (G.nx + 1) + i, xr = xl + 1;
+  const size_t yl = (size_t)j * G.nx + i, yr = yl + G.nx;
+  double lam = 0.0;
+  if (in) {
+    if (STAGE == 1) {
+      const double* S = B.S[sc->cur];
+      double W[4], Wm[4], Wb[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) W[k] = S[k * N + id];
+      load_avg<4>(S, G, i - 1, j, Wm);
+      load_avg<4>(S, G, i, j - 1, Wb);
+      double Wst[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double* FX = B.FX;
+        const double* FY = B.FY;
+        double L = -(FX[k * px + xr] - FX[k * px + xl]) / G.dx;
+        double Lt = -(FX[(4 + k) * px + xr] - FX[(4 + k) * px + xl]) / G.dx;
+        L += -(FY[k * py + yr] - FY[k * py + yl]) / G.dy;
+        Lt += -(FY[(4 + k) * py + yr] - FY[(4 + k) * py + yl]) / G.dy;
+        const double jx = W[k] - Wm[k], jy = W[k] - Wb[k];
+        Wst[k] = W[k] + 0.5 * dt * L + dt * dt / 8.0 * Lt;
+        B.Ws[k * N + id] = Wst[k];
+        B.P[k * N + id] = W[k] + dt * L + dt * dt / 6.0 * Lt;
+        B.Ws[(4 + k) * N + id] = ((FX[(8 + k) * px + xr] - FX[(8 + k) * px + xl]) + jx) / G.dx;
+        B.P[(4 + k) * N + id] = ((FX[(12 + k) * px + xr] - FX[(12 + k) * px + xl]) + jx) / G.dx;
+        B.Ws[(8 + k) * N + id] = ((FY[(8 + k) * py + yr] - FY[(8 + k) * py + yl]) + jy) / G.dy;
+        B.P[(8 + k) * N + id] = ((FY[(12 + k) * py + yr] - FY[(12 + k) * py + yl]) + jy) / G.dy;
+      }
+      if (!admissible<4>(Wst, G.gas.gamma)) flag_bad(sc, id);
+    } else {
+      double* So = B.S[sc->cur ^ 1];
+      const double c3 = dt * dt / 3.0;
+      double Wn[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double* FX = B.FX;
+        const double* FY = B.FY;
+        double Lt = -(FX[k * px + xr] - FX[k * px + xl]) / G.dx;
+        Lt += -(FY[k * py + yr] - FY[k * py + yl]) / G.dy;
+        Wn[k] = B.P[k * N + id] + c3 * Lt;
+        So[k * N + id] = Wn[k];
+        So[(4 + k) * N + id] = B.P[(4 + k) * N + id] + c3 * (FX[(4 + k) * px + xr] - FX[(4 + k) * px + xl]) / G.dx;
+        So[(8 + k) * N + id] = B.P[(8 + k) * N + id] + c3 * (FY[(4 + k) * py + yr] - FY[(4 + k) * py + yl]) / G.dy;
+      }
+      if (!admissible<4>(Wn, G.gas.gamma)) flag_bad(sc, id);
+      else lam = cell_lambda<4>(Wn, G);
+    }
+  }
+  if (STAGE == 2) reduce_lambda(sc, lam);
+}
+
+// ---------------------------------------------------------------- 1D
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_faces1(Geom G, Bufs B) {
+  Scalars* sc = B.sc;
+  if (!sc->active || sc->status != 0) return;
+  const double dt = sc->dt;
+  const double* S = STAGE == 1 ? B.S[sc->cur] : B.Ws;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f > G.nx) return;
+  const double h = G.dx;
+  double Wc[4][3], Dc[4][3];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) load_cell<3>(S, G, f - 2 + m, 0, 0, Wc[m], Dc[m]);
+  PointIn<3> in;
+  double dev[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double ref = Wc[1][k];
+    const Line5 L = normal_line(Wc[0][k] - ref, Wc[2][k] - ref, Wc[3][k] - ref, h * Dc[0][k], h * Dc[1][k],
+                                h * Dc[2][k], h * Dc[3][k], G.eps);
+    dev[k] = L.v;
+    in.W0[k] = ref + L.v;
+    in.Wn[k] = L.vn / h;
+    in.Wnn[k] = L.vnn / (h * h);
+    in.Wt[k] = 0.0; in.Wnt[k] = 0.0; in.Wtt[k] = 0.0;
+    in.Wl[k] = ref + L.wl;
+    in.Wr[k] = ref + L.wr;
+  }
+  int gweno = 0;
+  if (!admissible<3>(in.Wl, G.gas.gamma)) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) in.Wl[k] = Wc[1][k];
+    ++gweno;
+  }
+  if (!admissible<3>(in.Wr, G.gas.gamma)) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) in.Wr[k] = Wc[2][k];
+    ++gweno;
+  }
+  PointOut<3> o;
+  gks_point<3, STAGE == 1>(in, G.gas, dt, o);
+  if (o.guard) atomicAdd(&sc->guard_w0, 1ull);
+  if (gweno) atomicAdd(&sc->guard_weno, (unsigned long long)gweno);
+  const size_t plane = (size_t)G.nx + 1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (STAGE == 1) {
+      const double d0 = o.guard ? o.W0[k] - Wc[1][k] : dev[k];
+      B.FX[k * plane + f] = o.F[k];
+      B.FX[(3 + k) * plane + f] = o.Ft[k];
+      B.FX[(6 + k) * plane + f] = d0 + 0.5 * dt * o.Wt[k] + dt * dt / 8.0 * o.Wtt[k] + o.Nh[k];
+      B.FX[(9 + k) * plane + f] = d0 + dt * o.Wt[k] + dt * dt / 6.0 * o.Wtt[k] + o.Nf[k];
+    } else {
+      B.FX[k * plane + f] = o.Ft[k];
+      B.FX[(3 + k) * plane + f] = o.Wtt[k];
+    }
+  }
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_update1(Geom G, Bufs B) {
+  Scalars* sc = B.sc;
+  if (!sc->active || sc->status != 0) return;
+  const double dt = sc->dt;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t N = (size_t)G.nx;
+  const size_t plane = N + 1;
+  double lam = 0.0;
+  if (i < G.nx) {
+    if (STAGE == 1) {
+      const double* S = B.S[sc->cur];
+      double W[3], Wm[3], Wst[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) W[k] = S[k * N + i];
+      load_avg<3>(S, G, i - 1, 0, Wm);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double L = -(B.FX[k * plane + i + 1] - B.FX[k * plane + i]) / G.dx;
+        const double Lt = -(B.FX[(3 + k) * plane + i + 1] - B.FX[(3 + k) * plane + i]) / G.dx;
+        const double jx = W[k] - Wm[k];
+        Wst[k] = W[k] + 0.5 * dt * L + dt * dt / 8.0 * Lt;
+        B.Ws[k * N + i] = Wst[k];
+        B.P[k * N + i] = W[k] + dt * L + dt * dt / 6.0 * Lt;
+        B.Ws[(3 + k) * N + i] = ((B.FX[(6 + k) * plane + i + 1] - B.FX[(6 + k) * plane + i]) + jx) / G.dx;
+        B.P[(3 + k) * N + i] = ((B.FX[(9 + k) * plane + i + 1] - B.FX[(9 + k) * plane + i]) + jx) / G.dx;
+      }
+      if (!admissible<3>(Wst, G.gas.gamma)) flag_bad(sc, i);
+    } else {
+      double* So = B.S[sc->cur ^ 1];
+      const double c3 = dt * dt / 3.0;
+      double Wn[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double Lt = -(B.FX[k * plane + i + 1] - B.FX[k * plane + i]) / G.dx;
+        Wn[k] = B.P[k * N + i] + c3 * Lt;
+        So[k * N + i] = Wn[k];
+        So[(3 + k) * N + i] = B.P[(3 + k) * N + i] + c3 * (B.FX[(3 + k) * plane + i + 1] - B.FX[(3 + k) * plane + i]) / G.dx;
+      }
+      if (!admissible<3>(Wn, G.gas.gamma)) flag_bad(sc, i);
+      else lam = cell_lambda<3>(Wn, G);
+    }
+  }
+  if (STAGE == 2) reduce_lambda(sc, lam);
+}
+
+}  // namespace cgks
+
+// ================================================================ host side
+
+using namespace cgks;
+
+constexpr int kKinds = 8;
+constexpr size_t kEventPairs = 1024;
+
+struct cgks_ctx {
+  cgks_config cfg;
+  hipStream_t stream;
+  Geom G;
+  Bufs B;
+  Scalars* host_sc;     // pinned mirror
+  size_t N, nf;
+  int has_state;
+  // profiling: event pairs around hot kernel launches
+  int profiling;
+  std::vector<hipEvent_t>* events;
+  std::vector<int>* ev_kind;
+  size_t ev_used;
+  double ms[kKinds];
+  long calls[kKinds];
+};
+
+// resolve recorded event pairs into the per-kernel accumulators (synchronises)
+static int resolve_events(cgks_ctx* c) {
+  if (!c->events || c->ev_used == 0) return CGKS_OK;
+  if (hipEventSynchronize((*c->events)[2 * c->ev_used - 1]) != hipSuccess) return CGKS_EDEVICE;
+  for (size_t k = 0; k < c->ev_used; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, (*c->events)[2 * k], (*c->events)[2 * k + 1]) != hipSuccess) return CGKS_EDEVICE;
+    const int kind = (*c->ev_kind)[k];
+    c->ms[kind] += ms;
+    c->calls[kind] += 1;
+  }
+  c->ev_used = 0;
+  return CGKS_OK;
+}
+
+// launch helper: records an event pair around the launch while profiling
+template <class F>
+static void timed(cgks_ctx* c, int kind, F&& launch) {
+  if (!c->profiling) { launch(); return; }
+  if (c->ev_used == kEventPairs) resolve_events(c);
+  (void)hipEventRecord((*c->events)[2 * c->ev_used], c->stream);
+  launch();
+  (void)hipEventRecord((*c->events)[2 * c->ev_used + 1], c->stream);
+  (*c->ev_kind)[c->ev_used] = kind;
+  c->ev_used += 1;
+}
+
+#define HIPCHK(x)                              \
+  do {                                         \
+    if ((x) != hipSuccess) return CGKS_EDEVICE; \
+  } while (0)
+
+static int validate(const cgks_config* c) {
+  if (!c) return CGKS_EINVAL;
+  if (c->dim != 1 && c->dim != 2) return CGKS_EINVAL;
+  if (c->nx < 1 || (c->dim == 2 && c->ny < 1)) return CGKS_EINVAL;
+  if ((long long)c->nx * (c->dim == 2 ? c->ny : 1) > (1ll << 31) / 16) return CGKS_EINVAL;
+  if (!(c->gamma > 1.0) || !(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) return CGKS_EINVAL;
+  if (!(c->cfl > 0.0) && !(c->fixed_dt > 0.0)) return CGKS_EINVAL;
+  if (!(c->weno_eps > 0.0) || !(c->tau_eps > 0.0) || c->tau_C < 0.0) return CGKS_EINVAL;
+  if (c->storage != CGKS_FP64) return CGKS_EINVAL;
+  for (int s = 0; s < 2 * c->dim; ++s) {
+    if (c->bc[s] < 0 || c->bc[s] > 3) return CGKS_EINVAL;
+    const int n = s < 2 ? c->nx : c->ny;
+    if (c->bc[s] == CGKS_WALL && n < 2) return CGKS_EINVAL;
+    if (c->bc[s] == CGKS_INFLOW) {
+      const double* q = c->inflow_prim[s];
+      if (!(q[0] > 0.0) || !(q[3] > 0.0)) return CGKS_EINVAL;
+    }
+  }
+  if ((c->bc[0] == CGKS_PERIODIC) != (c->bc[1] == CGKS_PERIODIC)) return CGKS_EINVAL;
+  if (c->dim == 2 && (c->bc[2] == CGKS_PERIODIC) != (c->bc[3] == CGKS_PERIODIC)) return CGKS_EINVAL;
+  return CGKS_OK;
+}
+
+static void free_bufs(cgks_ctx* c) {
+  (void)hipFree(c->B.S[0]); (void)hipFree(c->B.S[1]); (void)hipFree(c->B.Ws); (void)hipFree(c->B.P);
+  (void)hipFree(c->B.FX); (void)hipFree(c->B.FY); (void)hipFree(c->B.sc);
+  if (c->host_sc) (void)hipHostFree(c->host_sc);
+}
+
+extern "C" int cgks_create(const cgks_config* cfg, void* hip_stream, cgks_ctx** out) {
+  if (!out) return CGKS_EINVAL;
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  cgks_ctx* c = new (std::nothrow) cgks_ctx();
+  if (!c) return CGKS_ENOMEM;
+  std::memset(c, 0, sizeof *c);
+  c->cfg = *cfg;
+  if (cfg->dim == 1) c->cfg.ny = 1;
+  c->stream = (hipStream_t)hip_stream;
+  Geom& G = c->G;
+  G.dim = cfg->dim;
+  G.nx = cfg->nx;
+  G.ny = c->cfg.ny;
+  G.dx = (cfg->x1 - cfg->x0) / cfg->nx;
+  G.dy = cfg->dim == 2 ? (cfg->y1 - cfg->y0) / cfg->ny : 1.0;
+  G.eps = cfg->weno_eps;
+  G.gas.gamma = cfg->gamma;
+  G.gas.K = 2.0 / (cfg->gamma - 1.0) - cfg->dim;
+  G.gas.tau_eps = cfg->tau_eps;
+  G.gas.tau_C = cfg->tau_C;
+  for (int s = 0; s < 4; ++s) {
+    G.bc[s] = s < 2 * cfg->dim ? cfg->bc[s] : CGKS_PERIODIC;
+    const double* q = cfg->inflow_prim[s];
+    const double g1 = cfg->gamma - 1.0;
+    if (cfg->dim == 2) {
+      G.inflow[s][0] = q[0]; G.inflow[s][1] = q[0] * q[1]; G.inflow[s][2] = q[0] * q[2];
+      G.inflow[s][3] = q[3] / g1 + 0.5 * q[0] * (q[1] * q[1] + q[2] * q[2]);
+    } else {
+      G.inflow[s][0] = q[0]; G.inflow[s][1] = q[0] * q[1];
+      G.inflow[s][2] = q[3] / g1 + 0.5 * q[0] * q[1] * q[1]; G.inflow[s][3] = 0.0;
+    }
+  }
+  c->N = (size_t)G.nx * G.ny;
+  c->nf = cfg->dim == 2 ? 12 : 6;
+  const size_t fbytes = c->nf * c->N * sizeof(double);
+  size_t fx = 0, fy = 0;
+  if (cfg->dim == 2) {
+    fx = (size_t)16 * G.ny * (G.nx + 1) * sizeof(double);
+    fy = (size_t)16 * (G.ny + 1) * G.nx * sizeof(double);
+  } else {
+    fx = (size_t)12 * (G.nx + 1) * sizeof(double);
+    fy = sizeof(double);
+  }
+  bool ok = hipMalloc(&c->B.S[0], fbytes) == hipSuccess && hipMalloc(&c->B.S[1], fbytes) == hipSuccess &&
+            hipMalloc(&c->B.Ws, fbytes) == hipSuccess && hipMalloc(&c->B.P, fbytes) == hipSuccess &&
+            hipMalloc(&c->B.FX, fx) == hipSuccess && hipMalloc(&c->B.FY, fy) == hipSuccess &&
+            hipMalloc(&c->B.sc, sizeof(Scalars)) == hipSuccess &&
+            hipHostMalloc(&c->host_sc, sizeof(Scalars), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    free_bufs(c);
+    delete c;
+    return CGKS_ENOMEM;
+  }
+  std::memset(c->host_sc, 0, sizeof(Scalars));
+  *out = c;
+  return CGKS_OK;
+}
+
+extern "C" void cgks_destroy(cgks_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->events) {
+    for (hipEvent_t e : *c->events) (void)hipEventDestroy(e);
+    delete c->events;
+    delete c->ev_kind;
+  }
+  free_bufs(c);
+  delete c;
+}
+
+extern "C" int cgks_set_profiling(cgks_ctx* c, int on) {
+  if (!c) return CGKS_EINVAL;
+  if (on && !c->events) {
+    c->events = new (std::nothrow) std::vector<hipEvent_t>(2 * kEventPairs);
+    c->ev_kind = new (std::nothrow) std::vector<int>(kEventPairs);
+    if (!c->events || !c->ev_kind) return CGKS_ENOMEM;
+    for (auto& e : *c->events) HIPCHK(hipEventCreate(&e));
+  }
+  if (on) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->ev_used = 0;
+    for (int k = 0; k < kKinds; ++k) { c->ms[k] = 0.0; c->calls[k] = 0; }
+  } else {
+    int rc = resolve_events(c);
+    if (rc) return rc;
+  }
+  c->profiling = on ? 1 : 0;
+  return CGKS_OK;
+}
+
+extern "C" int cgks_kernel_times(cgks_ctx* c, double* ms, long* calls, int n) {
+  if (!c || !ms || !calls) return CGKS_EINVAL;
+  int rc = resolve_events(c);
+  if (rc) return rc;
+  const int kinds = c->G.dim == 2 ? 6 : 4;
+  for (int k = 0; k < n && k < kinds; ++k) { ms[k] = c->ms[k]; calls[k] = c->calls[k]; }
+  return kinds;
+}
+
+static int pull_scalars(cgks_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->host_sc, c->B.sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CGKS_OK;
+}
+
+static int push_params(cgks_ctx* c, double t_end, double dt_override) {
+  // the pinned mirror holds the last pulled scalars; only the parameter block is sent
+  c->host_sc->prm.t_end = t_end;
+  c->host_sc->prm.dt_override = dt_override;
+  HIPCHK(hipMemcpyAsync(c->B.sc, c->host_sc, sizeof(Params), hipMemcpyHostToDevice, c->stream));
+  return CGKS_OK;
+}
+
+extern "C" int cgks_set_state(cgks_ctx* c, const double* fields, int on_device, double t0) {
+  if (!c || !fields) return CGKS_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  Scalars& h = *c->host_sc;
+  std::memset(&h, 0, sizeof h);
+  h.prm.t_end = INFINITY;
+  h.t = t0;
+  h.cfl = c->cfg.cfl;
+  h.fixed_dt = c->cfg.fixed_dt;
+  h.bad_cell = ULLONG_MAX;
+  HIPCHK(hipMemcpyAsync(c->B.S[0], fields, c->nf * c->N * sizeof(double),
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->B.sc, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
+  k_scan_begin<<<1, 64, 0, c->stream>>>(c->B.sc);
+  const unsigned nb = (unsigned)((c->N + 255) / 256);
+  if (c->cfg.dim == 2) k_scan<4><<<nb, 256, 0, c->stream>>>(c->G, c->B);
+  else k_scan<3><<<nb, 256, 0, c->stream>>>(c->G, c->B);
+  k_scan_end<<<1, 64, 0, c->stream>>>(c->B.sc);
+  HIPCHK(hipGetLastError());
+  int rc = pull_scalars(c);
+  if (rc) return rc;
+  c->has_state = 1;
+  if (h.status != 0) {
+    c->has_state = 0;
+    return CGKS_ENONPHYS;
+  }
+  return CGKS_OK;
+}
+
+static void launch_step(cgks_ctx* c) {
+  const Geom& G = c->G;
+  hipStream_t s = c->stream;
+  k_begin<<<1, 64, 0, s>>>(c->B.sc);
+  if (G.dim == 2) {
+    const dim3 gx((G.nx + 1 + TF - 1) / TF, (G.ny + TT - 1) / TT);
+    const dim3 gy((G.nx + TT - 1) / TT, (G.ny + 1 + TF - 1) / TF);
+    const dim3 gu((G.nx + 63) / 64, (G.ny + 3) / 4);
+    const Bufs B = c->B;
+    timed(c, 0, [&] { k_faces2<0, 1><<<gx, 256, 0, s>>>(G, B); });
+    timed(c, 1, [&] { k_faces2<1, 1><<<gy, 256, 0, s>>>(G, B); });
+    timed(c, 2, [&] { k_update2<1><<<gu, 256, 0, s>>>(G, B); });
+    timed(c, 3, [&] { k_faces2<0, 2><<<gx, 256, 0, s>>>(G, B); });
+    timed(c, 4, [&] { k_faces2<1, 2><<<gy, 256, 0, s>>>(G, B); });
+    timed(c, 5, [&] { k_update2<2><<<gu, 256, 0, s>>>(G, B); });
+  } else {
+    const unsigned nf = (unsigned)((G.nx + 1 + 255) / 256), nc = (unsigned)((G.nx + 255) / 256);
+    const Bufs B = c->B;
+    timed(c, 0, [&] { k_faces1<1><<<nf, 256, 0, s>>>(G, B); });
+    timed(c, 1, [&] { k_update1<1><<<nc, 256, 0, s>>>(G, B); });
+    timed(c, 2, [&] { k_faces1<2><<<nf, 256, 0, s>>>(G, B); });
+    timed(c, 3, [&] { k_update1<2><<<nc, 256, 0, s>>>(G, B); });
+  }
+  k_end<<<1, 64, 0, s>>>(c->B.sc);
+}
+
+extern "C" int cgks_step_dt(cgks_ctx* c, double dt, double* dt_used) {
+  if (!c) return CGKS_EINVAL;
+  if (!c->has_state) return CGKS_ESTATE;
+  int rc = push_params(c, INFINITY, dt > 0.0 ? dt : 0.0);
+  if (rc) return rc;
+  const long long before = c->host_sc->step;
+  launch_step(c);
+  HIPCHK(hipGetLastError());
+  rc = pull_scalars(c);
+  if (rc) return rc;
+  if (c->host_sc->status) return c->host_sc->status;
+  if (c->host_sc->step != before + 1) return CGKS_EDEVICE;
+  if (dt_used) *dt_used = c->host_sc->last_dt;
+  return CGKS_OK;
+}
+
+extern "C" int cgks_step(cgks_ctx* c, double* dt_used) { return cgks_step_dt(c, 0.0, dt_used); }
+
+extern "C" int cgks_run_steps(cgks_ctx* c, long n) {
+  if (!c || n < 0) return CGKS_EINVAL;
+  if (!c->has_state) return CGKS_ESTATE;
+  int rc = push_params(c, INFINITY, 0.0);
+  if (rc) return rc;
+  for (long k = 0; k < n; ++k) launch_step(c);
+  HIPCHK(hipGetLastError());
+  rc = pull_scalars(c);
+  if (rc) return rc;
+  return c->host_sc->status;
+}
+
+extern "C" int cgks_advance_to(cgks_ctx* c, double t_end, long max_steps, long* steps_taken) {
+  if (!c) return CGKS_EINVAL;
+  if (!c->has_state) return CGKS_ESTATE;
+  int rc = push_params(c, t_end, 0.0);
+  if (rc) return rc;
+  const long long start = c->host_sc->step;
+  long launched = 0;
+  int chunk = 8;
+  while (c->host_sc->t < t_end && c->host_sc->status == 0) {
+    long n = chunk;
+    if (max_steps > 0) n = n < max_steps - launched ? n : max_steps - launched;
+    if (n <= 0) break;
+    for (long k = 0; k < n; ++k) launch_step(c);
+    launched += n;
+    HIPCHK(hipGetLastError());
+    rc = pull_scalars(c);
+    if (rc) return rc;
+    if (chunk < 64) chunk *= 2;
+  }
+  if (steps_taken) *steps_taken = (long)(c->host_sc->step - start);
+  return c->host_sc->status;
+}
+
+extern "C" int cgks_get_state(cgks_ctx* c, double* out, int on_device, double* t, long* step) {
+  if (!c) return CGKS_EINVAL;
+  if (!c->has_state) return CGKS_ESTATE;
+  int rc = pull_scalars(c);
+  if (rc) return rc;
+  if (out) {
+    HIPCHK(hipMemcpyAsync(out, c->B.S[c->host_sc->cur], c->nf * c->N * sizeof(double),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  if (t) *t = c->host_sc->t;
+  if (step) *step = (long)c->host_sc->step;
+  return CGKS_OK;
+}
+
+extern "C" int cgks_last_bad_cell(const cgks_ctx* c, long* cell) {
+  if (!c || !cell) return CGKS_EINVAL;
+  *cell = c->host_sc->bad_cell == ULLONG_MAX ? -1 : (long)c->host_sc->bad_cell;
+  return CGKS_OK;
+}
+
+extern "C" int cgks_counters(cgks_ctx* c, cgks_counters_t* out) {
+  if (!c || !out) return CGKS_EINVAL;
+  int rc = pull_scalars(c);
+  if (rc) return rc;
+  out->steps = (long)c->host_sc->step;
+  out->guard_w0 = (long)c->host_sc->guard_w0;
+  out->guard_weno = (long)c->host_sc->guard_weno;
+  out->last_dt = c->host_sc->last_dt;
+  out->t = c->host_sc->t;
+  return CGKS_OK;
+}
+
+extern "C" const char* cgks_strerror(int code) {
+  switch (code) {
+    case CGKS_OK: return "ok";
+    case CGKS_EINVAL: return "invalid argument or configuration";
+    case CGKS_ENOMEM: return "out of memory";
+    case CGKS_EDEVICE: return "HIP runtime error";
+    case CGKS_ENONPHYS: return "non-physical state (rho <= 0, p <= 0 or NaN); step not committed";
+    case CGKS_EBUSY: return "no free slot or memory budget exhausted";
+    case CGKS_ESTATE: return "no state loaded";
+    default: return "unknown error";
+  }
+}

@@ -1,0 +1,523 @@
+// Device arithmetic of the compact 8th-order gas-kinetic scheme for gfx950.
+//
+// Sec. 3.2-3.3 (compact linear and WENO-Z reconstruction), Sec. 2.1-2.2
+// (gas-kinetic interface evolution, flux extraction, interface state) of
+// Zhao, Ji, Shyy, Xu, arXiv 2001.01570.  All FP64.
+//
+// Data along one reconstruction line are shifted by the average of the cell
+// left of the interface (Q_i): the reconstructions commute with adding a
+// constant, and the shift keeps every derivative-type quantity and every
+// smoothness indicator free of cancellation against the O(1) background.
+#pragma once
+#include <hip/hip_runtime.h>
+
+// device functions are also host-callable so that their arithmetic can be
+// exercised on the CPU
+#define CGKS_HD __host__ __device__
+
+namespace cgks {
+
+// ----------------------------------------------------------------------------
+// compact reconstruction on one line, one component (scaled cell width h = 1)
+// inputs (shifted by Q_i): a = Q_{i-1}-Q_i, c = Q_{i+1}-Q_i, d = Q_{i+2}-Q_i,
+// A..D = h Q'_{i-1..i+2}
+// ----------------------------------------------------------------------------
+
+struct Line5 {       // outputs of the normal reconstruction of one component
+  double v;          // P7 value at x_{i+1/2} (shifted)
+  double vn;         // h * dP7/dx
+  double vnn;        // h^2 * d2P7/dx2
+  double wl, wr;     // WENO-Z left / right values (shifted)
+};
+
+// Eq. (recons-8th-val) with the constant part removed (coefficients of Q_i
+// vanish in the derivatives; in the value 185 Q_i combines with the others to 420 Q_i).
+CGKS_HD __forceinline__ void p7_shifted(double a, double c, double d, double A, double B,
+                                           double C, double D, double& v, double& vn, double& vnn) {
+  v = (25.0 * a + 185.0 * c + 25.0 * d + 6.0 * A + 102.0 * B - 102.0 * C - 6.0 * D) * (1.0 / 420.0);
+  vn = (-14.0 * a + 270.0 * c + 14.0 * d - 3.0 * A - 99.0 * B - 99.0 * C - 3.0 * D) * (1.0 / 108.0);
+  vnn = (-4.0 * a + 4.0 * c - 4.0 * d - A - 9.0 * B + 9.0 * C + D) * 0.25;
+}
+
+// Left WENO-Z value at x_{i+1/2}, eqs. (right-left), (sub-stencil), (WENO-Z-w),
+// (smooth-indicator), (tau).  The indicators are written as sums of squares of
+// the candidate polynomials' derivative coefficients on I_i = [-1/2, 1/2]:
+//   quadratic   beta = k1^2 + 13/3 k2^2
+//   cubic       beta = (k1 + k3/4)^2 + 13/3 k2^2 + 781/20 k3^2
+//   quartic     beta = (k1 + k3/4)^2 + 13/3 (k2 + 63/130 k4)^2 + 781/20 k3^2 + 1421461/2275 k4^2
+// (exact integrals of sum_r (q^(r))^2; beta_1 from the cubic on Q_{i-1}, Q_i,
+// Q_{i+1}, Q'_{i-1}).
+CGKS_HD __forceinline__ double weno_left(double a, double c, double d, double A, double B,
+                                            double C, double D, double eps) {
+  constexpr double S2 = 13.0 / 3.0, S3 = 781.0 / 20.0, S4 = 1421461.0 / 2275.0, L42 = 63.0 / 130.0;
+  // candidate values q_k(x_{i+1/2}) with Q_i removed
+  const double q0 = (-7.0 * a - 4.0 * A) * (1.0 / 6.0);
+  const double q1 = (-a + 2.0 * c) * (1.0 / 6.0);       // q1 == q3
+  const double q2 = (32.0 * c - 13.0 * d + 6.0 * D) * (1.0 / 24.0);
+  const double q4 = (5.0 * c - d) * (1.0 / 6.0);
+  const double q5 = (10.0 * a + c + 3.0 * A + 21.0 * B) * (1.0 / 30.0);
+  const double q6 = (19.0 * c + 10.0 * d - 21.0 * C - 3.0 * D) * (1.0 / 30.0);
+  double k1, k2, k3, k4, t;
+  // beta_0: S0 = {Q_{i-1}, Q_i, Q'_{i-1}}
+  k1 = -A - 2.0 * a; k2 = -A - a;
+  const double b0 = k1 * k1 + S2 * k2 * k2;
+  // beta_1: cubic on {Q_{i-1}, Q_i, Q_{i+1}, Q'_{i-1}}
+  k1 = -0.625 * A - 1.4375 * a + 0.1875 * c; k2 = 0.5 * (a + c); k3 = 0.5 * A + 0.75 * a + 0.25 * c;
+  t = k1 + 0.25 * k3;
+  const double b1 = t * t + S2 * k2 * k2 + S3 * k3 * k3;
+  // beta_2: cubic on {Q_i, Q_{i+1}, Q_{i+2}, Q'_{i+2}}
+  k1 = 0.875 * D + 3.75 * c - 1.8125 * d; k2 = -1.5 * D - 4.0 * c + 2.75 * d; k3 = 0.5 * D + c - 0.75 * d;
+  t = k1 + 0.25 * k3;
+  const double b2 = t * t + S2 * k2 * k2 + S3 * k3 * k3;
+  // beta_3: quadratic on {Q_{i-1}, Q_i, Q_{i+1}}
+  k1 = 0.5 * (c - a); k2 = 0.5 * (a + c);
+  const double b3 = k1 * k1 + S2 * k2 * k2;
+  // beta_4: quadratic on {Q_i, Q_{i+1}, Q_{i+2}}
+  k1 = 2.0 * c - 0.5 * d; k2 = -c + 0.5 * d;
+  const double b4 = k1 * k1 + S2 * k2 * k2;
+  // beta_5: quartic on {Q_{i-1}, Q_i, Q_{i+1}, Q'_{i-1}, Q'_i}
+  k1 = 1.25 * B + 0.125 * (a - c); k2 = 0.75 * A + 1.5 * B + 2.375 * a + 0.125 * c;
+  k3 = -B + 0.5 * (c - a); k4 = -0.5 * A - B - 1.25 * a + 0.25 * c;
+  t = k1 + 0.25 * k3;
+  double u = k2 + L42 * k4;
+  const double b5 = t * t + S2 * u * u + S3 * k3 * k3 + S4 * k4 * k4;
+  // beta_6: quartic on {Q_i, Q_{i+1}, Q_{i+2}, Q'_{i+1}, Q'_{i+2}}
+  k1 = -2.75 * C - 0.5 * D + c + 1.625 * d; k2 = 7.5 * C + 2.25 * D + 3.5 * c - 6.625 * d;
+  k3 = -5.0 * C - 2.0 * D - 4.0 * c + 5.5 * d; k4 = C + 0.5 * D + c - 1.25 * d;
+  t = k1 + 0.25 * k3;
+  u = k2 + L42 * k4;
+  const double b6 = t * t + S2 * u * u + S3 * k3 * k3 + S4 * k4 * k4;
+  // WENO-Z weights with the reference value of eq. (tau)
+  const double z = fabs(3.0 * (b0 - b4) + (b4 - b3));
+  const double a0 = (3.0 / 98.0) * (1.0 + z / (b0 + eps));
+  const double a1 = (5.0 / 98.0) * (1.0 + z / (b1 + eps));
+  const double a2 = (4.0 / 49.0) * (1.0 + z / (b2 + eps));
+  const double a3 = (7.0 / 98.0) * (1.0 + z / (b3 + eps));
+  const double a4 = (7.0 / 98.0) * (1.0 + z / (b4 + eps));
+  const double a5 = (17.0 / 49.0) * (1.0 + z / (b5 + eps));
+  const double a6 = (17.0 / 49.0) * (1.0 + z / (b6 + eps));
+  const double num = a0 * q0 + (a1 + a3) * q1 + a2 * q2 + a4 * q4 + a5 * q5 + a6 * q6;
+  const double den = a0 + a1 + a2 + a3 + a4 + a5 + a6;
+  return num / den;
+}
+
+// Full normal reconstruction of one component on one line.  Q[0..3] are the
+// averages of cells i-1..i+2 minus Q_i, D[0..3] = h Q'.  The right value is the
+// left procedure on the stencil mirrored about the interface (cell i+1 becomes
+// the reference there, hence the "+ c").
+CGKS_HD __forceinline__ Line5 normal_line(double a, double c, double d, double A, double B,
+                                             double C, double D, double eps) {
+  Line5 r;
+  p7_shifted(a, c, d, A, B, C, D, r.v, r.vn, r.vnn);
+  r.wl = weno_left(a, c, d, A, B, C, D, eps);
+  r.wr = weno_left(d - c, -c, a - c, -D, -C, -B, -A, eps) + c;
+  return r;
+}
+
+// ----------------------------------------------------------------------------
+// Tangential quartic through 5 segment averages (offsets -2..2) evaluated at
+// the 2-point Gauss-Legendre nodes eta = -+1/(2 sqrt 3) of the segment
+// (value, d/deta, d2/deta2).  Weights derived symbolically.
+// ----------------------------------------------------------------------------
+struct TangW { double v[5], d1[5], d2[5]; };
+
+__constant__ static const TangW kTang[2] = {
+  {{-0.028297119567088289478, 0.20139476939454598305, 0.99861111111111111111, -0.19954291754269413120, 0.027834156604125326515},
+   {0.11540834828831254247, -1.0836418610813963855, 0.76980035891950101935, 0.24969147225193694785, -0.051258318378354124194},
+   {0.061004233964073107794, 1.0446581987385204511, -2.5, 1.6220084679281462156, -0.22767090063073977446}},
+  {{0.027834156604125326515, -0.19954291754269413120, 0.99861111111111111111, 0.20139476939454598305, -0.028297119567088289478},
+   {0.051258318378354124194, -0.24969147225193694785, -0.76980035891950101935, 1.0836418610813963855, -0.11540834828831254247},
+   {-0.22767090063073977446, 1.6220084679281462156, -2.5, 1.0446581987385204511, 0.061004233964073107794}},
+};
+
+// ----------------------------------------------------------------------------
+// gas-kinetic evolution at one interface point (normal = first velocity
+// component).  NC = 3 (1D: rho, rhoU, rhoE) or 4 (2D: rho, rhoU, rhoV, rhoE).
+// ----------------------------------------------------------------------------
+
+template <int NC> struct Vec { double c[NC]; };
+
+struct Gas {
+  double gamma, K;     // K: internal degrees of freedom (K + dim = 2/(gamma-1))
+  double tau_eps, tau_C;
+};
+
+// Moments of a (half-)Maxwellian normalised by rho: mu[n] = <u^n> n<=6,
+// mv[m] = <v^m> m<=5 (2D), x1 = <xi^2>, x2 = <xi^4>.
+template <int NC>
+struct Mom {
+  double rho, U, V, lam;
+  double mu[7];
+  double mv[6];
+  double x1, x2;
+};
+
+template <int NC>
+CGKS_HD __forceinline__ double pressure(const double* W, double gamma) {
+  const double ir = 1.0 / W[0];
+  double ke = W[1] * W[1];
+  if constexpr (NC == 4) ke += W[2] * W[2];
+  return (gamma - 1.0) * (W[NC - 1] - 0.5 * ke * ir);
+}
+
+template <int NC>
+CGKS_HD __forceinline__ bool admissible(const double* W, double gamma) {
+  if (!(W[0] > 0.0)) return false;
+  const double p = pressure<NC>(W, gamma);
+  return p > 0.0 && p < INFINITY && W[0] < INFINITY;
+}
+
+// half: 0 full space, +1 u > 0, -1 u < 0
+template <int NC>
+CGKS_HD __forceinline__ void moments(const double* W, const Gas& g, int half, Mom<NC>& m) {
+  m.rho = W[0];
+  const double ir = 1.0 / W[0];
+  m.U = W[1] * ir;
+  m.V = (NC == 4) ? W[2] * ir : 0.0;
+  const double p = pressure<NC>(W, g.gamma);
+  m.lam = 0.5 * m.rho / p;
+  const double h = 0.5 / m.lam;   // 1/(2 lambda) = p/rho
+  if (half == 0) {
+    m.mu[0] = 1.0;
+    m.mu[1] = m.U;
+  } else {
+    const double s = (double)half;
+    const double sl = sqrt(m.lam);
+    m.mu[0] = 0.5 * erfc(-s * sl * m.U);
+    m.mu[1] = m.U * m.mu[0] + s * exp(-m.lam * m.U * m.U) * (0.5 * 0.56418958354775628695 / sl);
+  }
+#pragma unroll
+  for (int n = 1; n < 6; ++n) m.mu[n + 1] = m.U * m.mu[n] + (double)n * h * m.mu[n - 1];
+  if constexpr (NC == 4) {
+    m.mv[0] = 1.0;
+    m.mv[1] = m.V;
+#pragma unroll
+    for (int n = 1; n < 5; ++n) m.mv[n + 1] = m.V * m.mv[n] + (double)n * h * m.mv[n - 1];
+  }
+  m.x1 = g.K * h;
+  m.x2 = (g.K * g.K + 2.0 * g.K) * h * h;
+}
+
+// Solve <psi a> = b for the expansion a = a0 + a1 u [+ a2 v] + a_e (u^2 [+ v^2] + xi^2)/2
+// of a Maxwellian (closed-form inverse of the moment matrix).
+template <int NC>
+CGKS_HD __forceinline__ void slope(const Mom<NC>& m, const Gas& g, const double* b, double* a) {
+  const double KD = g.K + (NC == 4 ? 2.0 : 1.0);   // = 2/(gamma-1)
+  const double U = m.U, V = m.V, lam = m.lam;
+  double q = U * U + KD / (2.0 * lam);
+  if constexpr (NC == 4) q += V * V;
+  const double Re = 2.0 * b[NC - 1] - q * b[0];
+  const double Ru = b[1] - U * b[0];
+  if constexpr (NC == 4) {
+    const double Rv = b[2] - V * b[0];
+    a[3] = 4.0 * lam * lam * (Re - 2.0 * U * Ru - 2.0 * V * Rv) / KD;
+    a[2] = 2.0 * lam * Rv - V * a[3];
+    a[1] = 2.0 * lam * Ru - U * a[3];
+    a[0] = b[0] - U * a[1] - V * a[2] - 0.5 * a[3] * q;
+  } else {
+    a[2] = 4.0 * lam * lam * (Re - 2.0 * U * Ru) / KD;
+    a[1] = 2.0 * lam * Ru - U * a[2];
+    a[0] = b[0] - U * a[1] - 0.5 * a[2] * q;
+  }
+}
+
+// <u^n v^m psi a> for a Maxwellian (rho factor not included).
+template <int NC>
+CGKS_HD __forceinline__ void mom_psi_a(const Mom<NC>& M, int n, int m, const double* a, double* out) {
+  auto E = [&](int p, int q) -> double {
+    if constexpr (NC == 4) return M.mu[p] * M.mv[q]; else return q == 0 ? M.mu[p] : 0.0;
+  };
+  // <u^p v^q psi_e>, psi_e = (u^2 [+ v^2] + xi^2)/2
+  auto H = [&](int p, int q) -> double {
+    double s = E(p + 2, q) + E(p, q) * M.x1;
+    if constexpr (NC == 4) s += E(p, q + 2);
+    return 0.5 * s;
+  };
+  // <u^p v^q psi_e^2>
+  auto Q = [&](int p, int q) -> double {
+    double s = E(p + 4, q) + E(p, q) * M.x2 + 2.0 * E(p + 2, q) * M.x1;
+    if constexpr (NC == 4) s += E(p, q + 4) + 2.0 * E(p + 2, q + 2) + 2.0 * E(p, q + 2) * M.x1;
+    return 0.25 * s;
+  };
+  if constexpr (NC == 4) {
+    out[0] = a[0] * E(n, m) + a[1] * E(n + 1, m) + a[2] * E(n, m + 1) + a[3] * H(n, m);
+    out[1] = a[0] * E(n + 1, m) + a[1] * E(n + 2, m) + a[2] * E(n + 1, m + 1) + a[3] * H(n + 1, m);
+    out[2] = a[0] * E(n, m + 1) + a[1] * E(n + 1, m + 1) + a[2] * E(n, m + 2) + a[3] * H(n, m + 1);
+    out[3] = a[0] * H(n, m) + a[1] * H(n + 1, m) + a[2] * H(n, m + 1) + a[3] * Q(n, m);
+  } else {
+    out[0] = a[0] * E(n, 0) + a[1] * E(n + 1, 0) + a[2] * H(n, 0);
+    out[1] = a[0] * E(n + 1, 0) + a[1] * E(n + 2, 0) + a[2] * H(n + 1, 0);
+    out[2] = a[0] * H(n, 0) + a[1] * H(n + 1, 0) + a[2] * Q(n, 0);
+  }
+}
+
+// <u^n v^m psi>
+template <int NC>
+CGKS_HD __forceinline__ void mom_psi(const Mom<NC>& M, int n, int m, double* out) {
+  double one[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) one[k] = (k == 0) ? 1.0 : 0.0;
+  mom_psi_a<NC>(M, n, m, one, out);
+}
+
+// Exact Euler first and second time derivatives at a point (Cauchy-Kowalewski
+// in primitive variables) and the flux time derivative dF/dt along the
+// solution.  2D form; the 1D case has no y dependence and V = 0.
+struct CK {
+  double Wt[4], Wtt[4], Ft[4];
+};
+
+CGKS_HD __forceinline__ void euler_ck(double gamma, const double* W, const double* Wx, const double* Wy,
+                                         const double* Wxx, const double* Wxy, const double* Wyy, CK& o) {
+  const double g1 = gamma - 1.0;
+  const double r = W[0], ir = 1.0 / r;
+  const double U = W[1] * ir, V = W[2] * ir;
+  const double q2 = U * U + V * V;
+  const double p = g1 * (W[3] - 0.5 * r * q2);
+  // first derivatives of primitives (a = x, y)
+  const double rx = Wx[0], ry = Wy[0];
+  const double Ux = (Wx[1] - U * rx) * ir, Uy = (Wy[1] - U * ry) * ir;
+  const double Vx = (Wx[2] - V * rx) * ir, Vy = (Wy[2] - V * ry) * ir;
+  const double px = g1 * (Wx[3] - 0.5 * rx * q2 - r * (U * Ux + V * Vx));
+  const double py = g1 * (Wy[3] - 0.5 * ry * q2 - r * (U * Uy + V * Vy));
+  // second derivatives
+  const double rxx = Wxx[0], rxy = Wxy[0], ryy = Wyy[0];
+  const double Uxx = (Wxx[1] - rxx * U - 2.0 * rx * Ux) * ir;
+  const double Uxy = (Wxy[1] - rxy * U - rx * Uy - ry * Ux) * ir;
+  const double Uyy = (Wyy[1] - ryy * U - 2.0 * ry * Uy) * ir;
+  const double Vxx = (Wxx[2] - rxx * V - 2.0 * rx * Vx) * ir;
+  const double Vxy = (Wxy[2] - rxy * V - rx * Vy - ry * Vx) * ir;
+  const double Vyy = (Wyy[2] - ryy * V - 2.0 * ry * Vy) * ir;
+  const double pxx = g1 * (Wxx[3] - 0.5 * rxx * q2 - 2.0 * rx * (U * Ux + V * Vx) - r * (Ux * Ux + Vx * Vx) - r * (U * Uxx + V * Vxx));
+  const double pxy = g1 * (Wxy[3] - 0.5 * rxy * q2 - rx * (U * Uy + V * Vy) - ry * (U * Ux + V * Vx) - r * (Ux * Uy + Vx * Vy) - r * (U * Uxy + V * Vxy));
+  const double pyy = g1 * (Wyy[3] - 0.5 * ryy * q2 - 2.0 * ry * (U * Uy + V * Vy) - r * (Uy * Uy + Vy * Vy) - r * (U * Uyy + V * Vyy));
+  // first time derivatives
+  const double dv = Ux + Vy;
+  const double rt = -(U * rx + V * ry + r * dv);
+  const double Ut = -(U * Ux + V * Uy + px * ir);
+  const double Vt = -(U * Vx + V * Vy + py * ir);
+  const double pt = -(U * px + V * py + gamma * p * dv);
+  // mixed derivatives q_tx, q_ty
+  const double dvx = Uxx + Vxy, dvy = Uxy + Vyy;
+  const double ir2 = ir * ir;
+  const double rtx = -(Ux * rx + U * rxx + Vx * ry + V * rxy + rx * dv + r * dvx);
+  const double rty = -(Uy * rx + U * rxy + Vy * ry + V * ryy + ry * dv + r * dvy);
+  const double Utx = -(Ux * Ux + U * Uxx + Vx * Uy + V * Uxy + pxx * ir - px * rx * ir2);
+  const double Uty = -(Uy * Ux + U * Uxy + Vy * Uy + V * Uyy + pxy * ir - px * ry * ir2);
+  const double Vtx = -(Ux * Vx + U * Vxx + Vx * Vy + V * Vxy + pxy * ir - py * rx * ir2);
+  const double Vty = -(Uy * Vx + U * Vxy + Vy * Vy + V * Vyy + pyy * ir - py * ry * ir2);
+  const double ptx = -(Ux * px + U * pxx + Vx * py + V * pxy + gamma * px * dv + gamma * p * dvx);
+  const double pty = -(Uy * px + U * pxy + Vy * py + V * pyy + gamma * py * dv + gamma * p * dvy);
+  // second time derivatives
+  const double dvt = Utx + Vty;
+  const double rtt = -(Ut * rx + U * rtx + Vt * ry + V * rty + rt * dv + r * dvt);
+  const double Utt = -(Ut * Ux + U * Utx + Vt * Uy + V * Uty + ptx * ir - px * rt * ir2);
+  const double Vtt = -(Ut * Vx + U * Vtx + Vt * Vy + V * Vty + pty * ir - py * rt * ir2);
+  const double ptt = -(Ut * px + U * ptx + Vt * py + V * pty + gamma * pt * dv + gamma * p * dvt);
+  const double E = W[3];
+  const double Et = pt / g1 + 0.5 * rt * q2 + r * (U * Ut + V * Vt);
+  o.Wt[0] = rt;
+  o.Wt[1] = rt * U + r * Ut;
+  o.Wt[2] = rt * V + r * Vt;
+  o.Wt[3] = Et;
+  o.Wtt[0] = rtt;
+  o.Wtt[1] = rtt * U + 2.0 * rt * Ut + r * Utt;
+  o.Wtt[2] = rtt * V + 2.0 * rt * Vt + r * Vtt;
+  o.Wtt[3] = ptt / g1 + 0.5 * rtt * q2 + 2.0 * rt * (U * Ut + V * Vt) + r * (Ut * Ut + Vt * Vt) + r * (U * Utt + V * Vtt);
+  // d/dt of the x flux (rhoU, rhoU^2 + p, rhoUV, U(E + p)) along the solution
+  o.Ft[0] = o.Wt[1];
+  o.Ft[1] = rt * U * U + 2.0 * r * U * Ut + pt;
+  o.Ft[2] = rt * U * V + r * Ut * V + r * U * Vt;
+  o.Ft[3] = Ut * (E + p) + U * (Et + pt);
+}
+
+// Inputs / outputs of one interface point.
+template <int NC>
+struct PointIn {
+  double W0[NC], Wn[NC], Wt[NC], Wnn[NC], Wnt[NC], Wtt[NC], Wl[NC], Wr[NC];
+};
+
+template <int NC>
+struct PointOut {
+  double F[NC], Ft[NC], Wt[NC], Wtt[NC], Nh[NC], Nf[NC], W0[NC];
+  int guard;
+};
+
+// The interface evolution (eq. 3rd-simplify-flux, second-order part for the
+// flux): numerical collision time in exp(-t/tau) only, physical collision
+// time zero for the Euler equations.  Flux extraction in coefficient form:
+//   F  = M1 + e4 (M4 - M1) + e3 (M3 - M5)
+//   Ft = M2 + e1' (M1 - M4) + e3' (M3 - M5)
+// M1 = F(W0), M2 = dF/dt (Euler), M3 = rho0 <u psi (a_n u + a_t v)>_0,
+// M4 = rho_l <u psi>_{l,u>0} + rho_r <u psi>_{r,u<0}, M5 the slope part of
+// M4.  FULL = false computes only what the second stage needs (Ft, Wtt).
+template <int NC, bool FULL>
+CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, double dt,
+                                          PointOut<NC>& out) {
+  const double pl = pressure<NC>(in.Wl, g.gamma), pr = pressure<NC>(in.Wr, g.gamma);
+  const double tau = g.tau_eps * dt + g.tau_C * fabs((pl - pr) / (pl + pr)) * dt;
+
+  double M4[NC], D35[NC], Slr[NC], Salr[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) { M4[k] = 0.0; D35[k] = 0.0; Slr[k] = 0.0; Salr[k] = 0.0; }
+
+  // the two nonlinear (non-equilibrium) sides
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const double* Ws = side == 0 ? in.Wl : in.Wr;
+    Mom<NC> m;
+    moments<NC>(Ws, g, side == 0 ? +1 : -1, m);
+    Mom<NC> mf = m;   // full-space u moments for the slope system
+    mf.mu[0] = 1.0; mf.mu[1] = m.U;
+    {
+      const double h = 0.5 / m.lam;
+#pragma unroll
+      for (int n = 1; n < 6; ++n) mf.mu[n + 1] = m.U * mf.mu[n] + (double)n * h * mf.mu[n - 1];
+    }
+    double bn[NC], an[NC], at[NC], t1[NC], t2[NC];
+    const double ir = 1.0 / m.rho;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) bn[k] = in.Wn[k] * ir;
+    slope<NC>(mf, g, bn, an);
+    if constexpr (NC == 4) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) bn[k] = in.Wt[k] * ir;
+      slope<NC>(mf, g, bn, at);
+    }
+    mom_psi<NC>(m, 1, 0, t1);                   // <u psi>
+#pragma unroll
+    for (int k = 0; k < NC; ++k) M4[k] += m.rho * t1[k];
+    mom_psi_a<NC>(m, 2, 0, an, t1);             // <u^2 psi a_n>
+    if constexpr (NC == 4) {
+      mom_psi_a<NC>(m, 1, 1, at, t2);           // <u v psi a_t>
+#pragma unroll
+      for (int k = 0; k < NC; ++k) t1[k] += t2[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) D35[k] -= m.rho * t1[k];
+    if constexpr (FULL) {
+      mom_psi<NC>(m, 0, 0, t1);                 // <psi>
+#pragma unroll
+      for (int k = 0; k < NC; ++k) Slr[k] += m.rho * t1[k];
+      mom_psi_a<NC>(m, 1, 0, an, t1);           // <u psi a_n>
+      if constexpr (NC == 4) {
+        mom_psi_a<NC>(m, 0, 1, at, t2);         // <v psi a_t>
+#pragma unroll
+        for (int k = 0; k < NC; ++k) t1[k] += t2[k];
+      }
+#pragma unroll
+      for (int k = 0; k < NC; ++k) Salr[k] += m.rho * t1[k];
+    }
+  }
+
+  // equilibrium state from the linear reconstruction; kinetic collision state
+  // of the two sides if it is not admissible
+  double W0[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) W0[k] = in.W0[k];
+  out.guard = 0;
+  if (!admissible<NC>(W0, g.gamma)) {
+    if constexpr (!FULL) {
+      Mom<NC> ml, mr;
+      double t1[NC];
+      moments<NC>(in.Wl, g, +1, ml);
+      moments<NC>(in.Wr, g, -1, mr);
+      mom_psi<NC>(ml, 0, 0, t1);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) Slr[k] = ml.rho * t1[k];
+      mom_psi<NC>(mr, 0, 0, t1);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) Slr[k] += mr.rho * t1[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) W0[k] = Slr[k];
+    out.guard = 1;
+  }
+
+  {  // M3: slope part of the equilibrium
+    Mom<NC> m;
+    moments<NC>(W0, g, 0, m);
+    double bn[NC], an[NC], at[NC], t1[NC], t2[NC];
+    const double ir = 1.0 / m.rho;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) bn[k] = in.Wn[k] * ir;
+    slope<NC>(m, g, bn, an);
+    mom_psi_a<NC>(m, 2, 0, an, t1);
+    if constexpr (NC == 4) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) bn[k] = in.Wt[k] * ir;
+      slope<NC>(m, g, bn, at);
+      mom_psi_a<NC>(m, 1, 1, at, t2);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) t1[k] += t2[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) D35[k] += m.rho * t1[k];   // D35 = M3 - M5
+  }
+
+  // Euler derivatives at the point (2D form)
+  CK ck;
+  {
+    double W4[4], x4[4], y4[4], xx4[4], xy4[4], yy4[4];
+    if constexpr (NC == 4) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        W4[k] = W0[k]; x4[k] = in.Wn[k]; y4[k] = in.Wt[k];
+        xx4[k] = in.Wnn[k]; xy4[k] = in.Wnt[k]; yy4[k] = in.Wtt[k];
+      }
+    } else {
+      W4[0] = W0[0]; W4[1] = W0[1]; W4[2] = 0.0; W4[3] = W0[2];
+      x4[0] = in.Wn[0]; x4[1] = in.Wn[1]; x4[2] = 0.0; x4[3] = in.Wn[2];
+      xx4[0] = in.Wnn[0]; xx4[1] = in.Wnn[1]; xx4[2] = 0.0; xx4[3] = in.Wnn[2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) { y4[k] = 0.0; xy4[k] = 0.0; yy4[k] = 0.0; }
+    }
+    euler_ck(g.gamma, W4, x4, y4, xx4, xy4, yy4, ck);
+  }
+  auto from4 = [&](const double* v4, double* v) {
+    if constexpr (NC == 4) { v[0] = v4[0]; v[1] = v4[1]; v[2] = v4[2]; v[3] = v4[3]; }
+    else { v[0] = v4[0]; v[1] = v4[1]; v[2] = v4[3]; }
+  };
+  double M2[NC];
+  from4(ck.Ft, M2);
+  from4(ck.Wtt, out.Wtt);
+
+  // M1 = Euler flux of W0
+  double M1[NC];
+  {
+    const double ir = 1.0 / W0[0];
+    const double U = W0[1] * ir;
+    const double p = pressure<NC>(W0, g.gamma);
+    M1[0] = W0[1];
+    M1[1] = W0[1] * U + p;
+    if constexpr (NC == 4) M1[2] = W0[2] * U;
+    M1[NC - 1] = (W0[NC - 1] + p) * U;
+  }
+
+  // time coefficients of the extraction (Eh = e^{-dt/(2 tau)}, E = Eh^2)
+  const double Eh = exp(-0.5 * dt / tau);
+  const double omh = 1.0 - Eh;
+  const double idt = 1.0 / dt;
+  const double e1p = 4.0 * tau * omh * omh * idt * idt;
+  const double e3p = 4.0 * tau * omh * (dt * Eh - tau * omh) * idt * idt;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) out.Ft[k] = M2[k] + e1p * (M1[k] - M4[k]) + e3p * D35[k];
+  if constexpr (FULL) {
+    const double e4 = tau * omh * (3.0 - Eh) * idt;
+    const double e3 = (tau * tau * omh * (3.0 - Eh) - tau * dt * Eh * (2.0 - Eh)) * idt;
+    const double E = Eh * Eh;
+    from4(ck.Wt, out.Wt);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      out.F[k] = M1[k] + e4 * (M4[k] - M1[k]) + e3 * D35[k];
+      // non-equilibrium remainder e^{-t/tau} [ -W0 - t W_t + S_lr - t S_alr ]
+      const double base = Slr[k] - W0[k];
+      const double slp = out.Wt[k] + Salr[k];
+      out.Nh[k] = Eh * (base - 0.5 * dt * slp);
+      out.Nf[k] = E * (base - dt * slp);
+      out.W0[k] = W0[k];
+    }
+  }
+}
+
+}  // namespace cgks

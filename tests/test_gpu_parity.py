@@ -1,0 +1,237 @@
+"""Parity of the HIP path (through the C ABI) against the oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2001_01570_amd import inputs as I
+from tests.conftest import golden
+from tests.parity import field_errors, field_scales, scaled_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def solver(prob):
+    from paper_2001_01570_amd.cgks import Solver
+    return Solver(prob)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def single_step(prob, steps_before=0):
+    """advance both to the same state, then compare one step from identical input"""
+    s, o = solver(prob), O.Oracle(prob, threads=8)
+    for _ in range(steps_before):
+        dt = o.step()
+        s.step(dt)
+    st, t, _ = o.get_state()
+    s.set_state(st, t)
+    dt = o.cfl_dt()
+    dt_gpu = s.step()
+    o.step(dt_gpu)
+    return field_errors(s.state, o.state), dt, dt_gpu
+
+
+# ---------------------------------------------------------------- 1D
+
+def test_1d_config1_single_step_and_full_run():
+    p = I.sine_wave_1d(100, eps=0.2, t_end=2.0, cfl=0.3)
+    say('1d config1 n=100')
+    e, dt, dtg = single_step(p)
+    assert dtg == pytest.approx(dt, rel=1e-14)
+    assert e.max() < TOL, e
+    s, o = solver(p), O.Oracle(p)
+    ns = s.advance_to(2.0)
+    no = o.advance_to(2.0)
+    assert ns == no
+    g, tg, _ = s.get_state()
+    r, to, _ = o.get_state()
+    assert tg == to == 2.0
+    err = scaled_errors(g, r, p.dx)
+    say('config1 full-run scaled errors', err, 'field errors', field_errors(g, r))
+    assert err.max() < TOL
+    assert s.counters()['guard_w0'] == 0
+
+
+def test_1d_config2_shock_entropy_full_run():
+    p = I.shock_entropy_1d(400, t_end=1.8)
+    say('1d config2 n=400')
+    e, _, _ = single_step(p, steps_before=3)
+    assert e.max() < TOL, e
+    s, o = solver(p), O.Oracle(p)
+    ns = s.advance_to(1.8)
+    no = o.advance_to(1.8)
+    assert ns == no
+    g, r = s.state, o.state
+    err = scaled_errors(g, r, p.dx)
+    say('config2 scaled errors', err)
+    assert err.max() < TOL
+    c = s.counters()
+    assert c['guard_w0'] == o.counters()['guard_w0']
+
+
+@pytest.mark.parametrize('n', [5, 17, 64])
+def test_1d_ragged_sizes(n):
+    p = I.sine_wave_1d(n, eps=0.3, cfl=0.6)
+    e, _, _ = single_step(p)
+    assert e.max() < TOL, (n, e)
+
+
+def test_1d_shock_tube_free_boundaries():
+    p = I.shock_tube_1d(100)
+    s, o = solver(p), O.Oracle(p)
+    for _ in range(30):
+        dt = o.step()
+        s.step(dt)
+    err = scaled_errors(s.state, o.state, p.dx)
+    assert err.max() < TOL, err
+
+
+# ---------------------------------------------------------------- 2D small
+
+CASES_2D = [
+    ('pulse_ragged', lambda: I.acoustic_pulse_2d(37, seed=4, amp=0.05, half_width=0.3, ny=21)),
+    ('pulse_tiles', lambda: I.acoustic_pulse_2d(48, seed=5, amp=1e-3, half_width=0.2, ny=33)),
+    ('shock_vortex', lambda: I.shock_vortex_2d(64, 32, Rc=0.12)),
+    ('vortex_translation', lambda: I.vortex_translation_2d(24)),
+    ('diagonal', lambda: I.diagonal_wave_2d(20, eps=0.2)),
+]
+
+
+@pytest.mark.parametrize('name,mk', CASES_2D, ids=[c[0] for c in CASES_2D])
+def test_2d_single_step(name, mk):
+    p = mk()
+    say('2d single step', name, p.nx, p.ny)
+    e, dt, dtg = single_step(p, steps_before=2)
+    say(name, 'field errors', e)
+    assert dtg == pytest.approx(dt, rel=1e-13)
+    assert e.max() < TOL, e
+
+
+@pytest.mark.parametrize('name,mk', CASES_2D[:3], ids=[c[0] for c in CASES_2D[:3]])
+def test_2d_multi_step(name, mk):
+    p = mk()
+    s, o = solver(p), O.Oracle(p, threads=8)
+    for _ in range(20):
+        dt = o.step()
+        s.step(dt)
+    err = scaled_errors(s.state, o.state, p.dx, p.dy)
+    say(name, '20-step scaled errors', err)
+    assert err.max() < TOL, err
+
+
+def test_2d_wall_and_inflow_free_stream():
+    for bc in ((I.WALL,) * 4, (I.INFLOW, I.FREE, I.WALL, I.INFLOW)):
+        p = I.uniform_2d(19, 13, prim=(0.9, 0.0, 0.0, 1.3) if bc[0] == I.WALL else (0.9, 0.4, 0.0, 1.3), bc=bc)
+        s = solver(p)
+        for _ in range(3):
+            s.step()
+        st = s.state
+        for k in range(4):
+            np.testing.assert_allclose(st[k], p.fields[k], rtol=1e-14, atol=1e-15)
+
+
+def test_2d_transposed_input_gives_transposed_output():
+    from tests.test_oracle_scheme import transpose_fields
+    p = I.acoustic_pulse_2d(24, seed=3, amp=0.05, half_width=0.3, ny=18)
+    p.fields[1] += 0.2 * p.fields[0]
+    p.fields[3] += 0.02 * p.fields[0]
+    pt = I.Problem('T', 2, 18, 24, -1.0, 1.0, -1.0, 1.0, transpose_fields(p.fields))
+    a, b = solver(p), solver(pt)
+    for _ in range(3):
+        dt = a.step()
+        b.step(dt)
+    d = np.abs(transpose_fields(a.state) - b.state)
+    assert d.max() < 1e-13
+
+
+def test_checkpoint_resume_bitwise():
+    p = I.acoustic_pulse_2d(32, seed=2, amp=0.05, half_width=0.3)
+    a = solver(p)
+    a.run_steps(4)
+    b = solver(p)
+    b.run_steps(2)
+    st, t, _ = b.get_state()
+    c = solver(p)
+    c.set_state(st, t)
+    c.run_steps(2)
+    assert np.array_equal(a.state, c.state)
+    assert a.t == c.t
+
+
+def test_nonphysical_input_rejected_and_failed_step_not_committed():
+    from paper_2001_01570_amd.cgks import CgksError, CGKS_ENONPHYS
+    p = I.acoustic_pulse_2d(16, seed=1, amp=0.05, half_width=0.3)
+    s = solver(p)
+    bad = p.fields.copy()
+    bad[0, 3, 5] = -1.0
+    with pytest.raises(CgksError) as ei:
+        s.set_state(bad)
+    assert ei.value.code == CGKS_ENONPHYS
+    assert s.last_bad_cell() == 3 * 16 + 5
+    s.set_state(p.fields)
+    before = s.state
+    with pytest.raises(CgksError) as ei:
+        s.step(50.0)          # far beyond any stable step: the new state is not physical
+    assert ei.value.code == CGKS_ENONPHYS
+    assert np.array_equal(s.get_state()[0], before)
+
+
+# ---------------------------------------------------------------- full size, sampled
+
+def _sampled(prob, windows, size=8):
+    from tests.window import window_step
+    s = solver(prob)
+    dt = s.step()
+    g = s.state
+    scales = field_scales(g)        # norms of the full fields
+    worst = 0.0
+    for (i0, j0) in windows:
+        core, (iy, ix) = window_step(prob, prob.fields, i0, j0, size, dt)
+        gc = g[:, iy][:, :, ix]
+        e = field_errors(gc, core, scales)
+        worst = max(worst, e.max())
+        assert e.max() < TOL, (i0, j0, e)
+    return worst, s
+
+
+def test_config3_full_size_single_step_sampled():
+    p = I.acoustic_pulse_2d(1024, seed=0)
+    cx, cy = p.meta['centre']
+    ic = int((cx + 1.0) / p.dx)
+    jc = int((cy + 1.0) / p.dy)
+    wins = [(ic - 4, jc - 4), (ic + 10, jc - 20), (0, 0), (1016, 1016), (ic, 1020), (500, 3)]
+    say('config3 sampled windows', wins)
+    worst, s = _sampled(p, [(i % 1024, j % 1024) for i, j in wins])
+    say('config3 worst field error', worst)
+    # conservation at full size over a few more steps
+    tot0 = np.array([math.fsum(p.fields[k].ravel()) for k in range(4)])
+    s.run_steps(9)
+    st = s.state
+    tot = np.array([math.fsum(st[k].ravel()) for k in range(4)])
+    scale = np.array([math.fsum(np.abs(p.fields[k]).ravel()) for k in range(4)])
+    assert (np.abs(tot - tot0) / np.maximum(scale, 1.0)).max() < 1e-14
+
+
+def test_config4_full_size_single_step_sampled():
+    p = I.shock_vortex_2d(2048, 1024)
+    wins = [(0, 0), (508, 500), (254, 508), (2040, 1016), (1024, 0), (0, 1016), (250, 470)]
+    say('config4 sampled windows', wins)
+    worst, s = _sampled(p, wins)
+    say('config4 worst field error', worst)
+
+
+def test_tam_webb_step_counts():
+    p = I.tam_webb_2d(200)
+    s = solver(p)
+    total = 0
+    for t_end, steps in golden('tamwebb_steps.txt'):
+        total += s.advance_to(t_end)
+        assert total == int(steps), (t_end, total)
+        assert s.t == t_end
