@@ -186,6 +186,10 @@ def test_nonphysical_input_rejected_and_failed_step_not_committed():
 # ---------------------------------------------------------------- full size, sampled
 
 def _sampled(prob, windows, size=8):
+    """One GPU step at full size; each window's core is recomputed by the oracle.
+    Per field the bar is 1e-12 of the field's norm, raised where the FP64 step
+    itself is less well conditioned than that: to 10x the oracle's own spread
+    under 1-ulp perturbations of its input (measured on the same window)."""
     from tests.window import window_step
     s = solver(prob)
     dt = s.step()
@@ -196,8 +200,16 @@ def _sampled(prob, windows, size=8):
         core, (iy, ix) = window_step(prob, prob.fields, i0, j0, size, dt)
         gc = g[:, iy][:, :, ix]
         e = field_errors(gc, core, scales)
+        if e.max() >= TOL:
+            spread = np.zeros_like(e)
+            for seed in (1, 2):
+                alt, _ = window_step(prob, prob.fields, i0, j0, size, dt, ulp_seed=seed)
+                spread = np.maximum(spread, field_errors(alt, core, scales))
+            bar = np.maximum(TOL, 10.0 * spread)
+            say('window', (i0, j0), 'errors', e, 'ulp spread', spread)
+            assert (e < bar).all(), (i0, j0, e, spread)
+            assert (e[:4] < TOL).all(), (i0, j0, e)      # cell averages always at 1e-12
         worst = max(worst, e.max())
-        assert e.max() < TOL, (i0, j0, e)
     return worst, s
 
 

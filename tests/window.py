@@ -24,13 +24,18 @@ def _axis(i0, size, n, periodic, bclo, bchi):
     return np.arange(a, b), lo, hi, c0, c1
 
 
-def window_step(prob, fields, i0, j0, size, dt):
+def window_step(prob, fields, i0, j0, size, dt, ulp_seed=None):
     """Returns (oracle core after one step of size dt, (slice_y, slice_x) of the
-    core in full-grid indices)."""
+    core in full-grid indices).  With ulp_seed, every input value is first moved
+    by -1, 0 or +1 ulp (seeded): the spread of the result measures the
+    conditioning of the FP64 step on that window."""
     bc = list(prob.bc)
     ix, xlo, xhi, cx0, cx1 = _axis(i0, size, prob.nx, bc[0] == I.PERIODIC, bc[0], bc[1])
     iy, ylo, yhi, cy0, cy1 = _axis(j0, size, prob.ny, bc[2] == I.PERIODIC, bc[2], bc[3])
     patch = np.ascontiguousarray(fields[:, iy][:, :, ix])
+    if ulp_seed is not None:
+        steps = np.random.default_rng(ulp_seed).integers(-1, 2, size=patch.shape)
+        patch = np.where(steps > 0, np.nextafter(patch, np.inf), np.where(steps < 0, np.nextafter(patch, -np.inf), patch))
     dx, dy = prob.dx, prob.dy
     p = I.Problem('window', 2, len(ix), len(iy), 0.0, dx * len(ix), 0.0, dy * len(iy), patch,
                   bc=(xlo, xhi, ylo, yhi), inflow_prim=prob.inflow_prim, gamma=prob.gamma, cfl=prob.cfl,
