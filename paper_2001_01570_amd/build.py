@@ -25,14 +25,39 @@ def hipcc() -> str:
     return 'hipcc'
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    cmd = [hipcc()] + HIPCC_FLAGS + list(extra) + ['-I', os.path.join(ROOT, 'include'), '-I',
-                                                    os.path.join(PKG, 'csrc')] + SRC + ['-o', LIB + '.tmp']
+FLOPS_JSON = os.path.join(PKG, 'flops.json')
+OPCOUNT_SRC = os.path.join(PKG, 'csrc', 'opcount.cpp')
+
+
+def count_operations(verbose: bool = False) -> str:
+    """Compile the device arithmetic for the host with a counting scalar and
+    write the algorithmic operation counts per unit to flops.json."""
+    exe = os.path.join(PKG, 'csrc', 'opcount.bin')
+    cmd = ['g++', '-std=c++17', '-O1', '-D__HIP_PLATFORM_AMD__', '-I/opt/rocm/include', '-I',
+           os.path.join(PKG, 'csrc'), '-I', os.path.join(ROOT, 'include'), OPCOUNT_SRC, '-o', exe]
     if verbose:
         print(' '.join(cmd), file=sys.stderr, flush=True)
     subprocess.check_call(cmd)
-    os.replace(LIB + '.tmp', LIB)
-    return LIB
+    out = subprocess.check_output([exe])
+    os.remove(exe)
+    with open(FLOPS_JSON + '.tmp', 'wb') as f:
+        f.write(out)
+    os.replace(FLOPS_JSON + '.tmp', FLOPS_JSON)
+    return FLOPS_JSON
+
+
+def build(verbose: bool = False, extra=(), out: str = None) -> str:
+    """Compile libcgks.so (out: alternative path, used for tuning variants)."""
+    target = out or LIB
+    cmd = [hipcc()] + HIPCC_FLAGS + list(extra) + ['-I', os.path.join(ROOT, 'include'), '-I',
+                                                    os.path.join(PKG, 'csrc')] + SRC + ['-o', target + '.tmp']
+    if verbose:
+        print(' '.join(cmd), file=sys.stderr, flush=True)
+    subprocess.check_call(cmd)
+    os.replace(target + '.tmp', target)
+    if out is None:
+        count_operations(verbose)
+    return target
 
 
 if __name__ == '__main__':

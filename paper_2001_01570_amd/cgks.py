@@ -45,7 +45,8 @@ _D = C.POINTER(C.c_double)
 
 
 def library_path() -> str:
-    return _build.LIB
+    """The in-tree library; CGKS_LIBRARY may name a tuning variant built from the same sources."""
+    return os.environ.get('CGKS_LIBRARY') or _build.LIB
 
 
 def load():
@@ -53,9 +54,12 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB):
+    path = library_path()
+    if not os.path.exists(path):
+        if path != _build.LIB:
+            raise FileNotFoundError(path)
         _build.build()
-    L = C.CDLL(_build.LIB)
+    L = C.CDLL(path)
     L.cgks_create.argtypes = [C.POINTER(cgks_config), C.c_void_p, C.POINTER(C.c_void_p)]
     L.cgks_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_double]
     L.cgks_step.argtypes = [C.c_void_p, _D]

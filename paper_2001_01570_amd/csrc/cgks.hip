@@ -30,6 +30,12 @@ constexpr int TT = 16;          // face segments per tile along the tangential d
 constexpr int TH = TT + 4;      // tangential extent including the 2+2 halo
 constexpr int NSEG = TF * TH;   // reconstructed line segments per tile (320)
 constexpr int NQ = 24;          // per segment: 5 quantities x 4 components + 4 reference values
+// LDS row length: NSEG padded so that the rows of the 4 components written by
+// consecutive threads start in different banks (328 doubles = 656 dwords = 16 mod 64)
+constexpr int NSEG_PAD = 328;
+#ifndef CGKS_FACE_WAVES_PER_EU
+#define CGKS_FACE_WAVES_PER_EU 1
+#endif
 
 struct Geom {
   int dim, nx, ny;
@@ -47,7 +53,6 @@ struct Params {          // written by the host before a batch of steps
 struct Scalars {
   Params prm;
   double t, dt, cfl, fixed_dt, last_dt;
-  unsigned long long lam_bits, lam_next;   // bits of the positive CFL maximum
   unsigned long long bad_cell;
   unsigned long long guard_w0, guard_weno;
   long long step;
@@ -55,6 +60,7 @@ struct Scalars {
 };
 
 struct Bufs {
+  double* lam_part;   // per-block CFL maxima of the last update
   double* S[2];    // state double buffer
   double* Ws;      // intermediate state W*
   double* P;       // W + dt L + dt^2/6 L_t and the gradient counterpart
@@ -130,6 +136,36 @@ __device__ __forceinline__ void load_cell(const double* S, const Geom& G, int i,
   if constexpr (NC == 4) apply_rule<NC>(G, ky, 2 + sy, 1, dir, W, Gd);
 }
 
+// one component k of W and of its gradient along dir at cell (i, j), ghosts included (2D)
+__device__ __forceinline__ void load_comp(const double* S, const Geom& G, int i, int j, int dir, int k,
+                                          double& w, double& gd) {
+  int kx, sx = 0, ky, sy = 0;
+  const int si = src_index(i, G.nx, G.bc[0], G.bc[1], kx, sx);
+  const int sj = src_index(j, G.ny, G.bc[2], G.bc[3], ky, sy);
+  const size_t N = (size_t)G.nx * G.ny;
+  const size_t id = (size_t)sj * G.nx + si;
+  w = S[k * N + id];
+  gd = S[(4 + 4 * dir + k) * N + id];
+  // rules applied to one component: x rule, then y rule
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int kind = a == 0 ? kx : ky;
+    if (kind < 0 || kind == CGKS_PERIODIC) continue;
+    const int side = a == 0 ? sx : 2 + sy;
+    if (kind == CGKS_FREE) {
+      gd = 0.0;
+    } else if (kind == CGKS_INFLOW) {
+      w = G.inflow[side][k];
+      gd = 0.0;
+    } else {  // wall about axis a
+      const int vel = 1 + a;
+      if (k == vel) w = -w;
+      if (dir == a) { if (k != vel) gd = -gd; }
+      else if (k == vel) gd = -gd;
+    }
+  }
+}
+
 template <int NC>
 __device__ __forceinline__ void load_avg(const double* S, const Geom& G, int i, int j, double* W) {
   double Gd[NC];
@@ -138,20 +174,29 @@ __device__ __forceinline__ void load_avg(const double* S, const Geom& G, int i, 
 
 // ---------------------------------------------------------------- step control
 
-__global__ void k_begin(Scalars* sc) {
+// Step size: the CFL maximum of the current state is the max of the per-block
+// partial maxima written by the last update (or by the scan after set_state).
+__global__ __launch_bounds__(256) void k_begin(Scalars* sc, const double* lam_part, int nparts) {
+  __shared__ double red[4];
+  double lam = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += blockDim.x) lam = fmax(lam, lam_part[k]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) lam = fmax(lam, __shfl_xor(lam, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lam;
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  lam = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   sc->active = 0;
   if (sc->status != 0) return;
   const double rem = sc->prm.t_end - sc->t;
   if (!(rem > 0.0)) { sc->dt = 0.0; return; }
   double dt = sc->prm.dt_override;
-  if (!(dt > 0.0)) dt = sc->fixed_dt > 0.0 ? sc->fixed_dt : sc->cfl / __longlong_as_double((long long)sc->lam_bits);
+  if (!(dt > 0.0)) dt = sc->fixed_dt > 0.0 ? sc->fixed_dt : sc->cfl / lam;
   int last = 0;
   if (dt * (1.0 + 1e-9) >= rem) { dt = rem; last = 1; }
   if (!(dt > 0.0) || !(dt < INFINITY)) { sc->status = CGKS_ENONPHYS; return; }
   sc->dt = dt;
   sc->last = last;
-  sc->lam_next = 0ull;
   sc->active = 1;
 }
 
@@ -161,16 +206,20 @@ __global__ void k_end(Scalars* sc) {
     sc->t = sc->last ? sc->prm.t_end : sc->t + sc->dt;
     sc->step += 1;
     sc->cur ^= 1;
-    sc->lam_bits = sc->lam_next;
     sc->last_dt = sc->dt;
   }
   sc->active = 0;
 }
 
-__device__ __forceinline__ void reduce_lambda(Scalars* sc, double lam) {
+// block maximum of the per-cell CFL rates, one partial per block (256 threads)
+__device__ __forceinline__ void reduce_lambda(double* lam_part, double lam) {
+  __shared__ double red[4];
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) lam = fmax(lam, __shfl_xor(lam, o, 64));
-  if ((threadIdx.x & 63) == 0 && lam > 0.0) atomicMax(&sc->lam_next, (unsigned long long)__double_as_longlong(lam));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lam;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    lam_part[blockIdx.y * gridDim.x + blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 template <int NC>
@@ -188,26 +237,27 @@ __device__ __forceinline__ void flag_bad(Scalars* sc, unsigned long long cell) {
   atomicMin(&sc->status, CGKS_ENONPHYS);
 }
 
-// admissibility and CFL maximum of the current state (after set_state)
+// admissibility and CFL maximum of the current state (after set_state); same
+// grid as the final update so that it leaves the same partials
 template <int NC>
 __global__ __launch_bounds__(256) void k_scan(Geom G, Bufs B) {
   Scalars* sc = B.sc;
   const double* S = B.S[sc->cur];
+  int i, j;
+  if (NC == 4) { i = blockIdx.x * 64 + (threadIdx.x & 63); j = blockIdx.y * 4 + (threadIdx.x >> 6); }
+  else { i = blockIdx.x * 256 + threadIdx.x; j = 0; }
   const size_t N = (size_t)G.nx * (NC == 4 ? G.ny : 1);
-  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   double lam = 0.0;
-  if (id < N) {
+  if (i < G.nx && j < (NC == 4 ? G.ny : 1)) {
+    const size_t id = (size_t)j * G.nx + i;
     double W[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) W[k] = S[k * N + id];
     if (!admissible<NC>(W, G.gas.gamma)) flag_bad(sc, id);
     else lam = cell_lambda<NC>(W, G);
   }
-  reduce_lambda(sc, lam);
+  reduce_lambda(B.lam_part, lam);
 }
-
-__global__ void k_scan_begin(Scalars* sc) { if (threadIdx.x == 0) sc->lam_next = 0ull; }
-__global__ void k_scan_end(Scalars* sc) { if (threadIdx.x == 0) sc->lam_bits = sc->lam_next; }
 
 // ---------------------------------------------------------------- 2D faces
 
@@ -218,12 +268,13 @@ __global__ void k_scan_end(Scalars* sc) { if (threadIdx.x == 0) sc->lam_bits = s
 // face segment per thread: tangential quartic to each Gauss point, the
 // gas-kinetic evolution, and the Gauss average.
 template <int DIR, int STAGE>
-__global__ __launch_bounds__(256) void k_faces2(Geom G, Bufs B) {
+__global__ __launch_bounds__(256, CGKS_FACE_WAVES_PER_EU) void k_faces2(Geom G, Bufs B) {
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
   const double dt = sc->dt;
   const double* S = STAGE == 1 ? B.S[sc->cur] : B.Ws;
-  __shared__ double lds[NQ][NSEG];
+  __shared__ double lds[NQ][NSEG_PAD];
+  __shared__ double cells[8][TH * TH + 4];
 
   const int nn = DIR == 0 ? G.nx : G.ny;     // cells along the normal
   const int nt = DIR == 0 ? G.ny : G.nx;     // cells along the tangential
@@ -233,31 +284,56 @@ __global__ __launch_bounds__(256) void k_faces2(Geom G, Bufs B) {
   const int f0 = (DIR == 0 ? blockIdx.x : blockIdx.y) * TF;
   const int t0 = (DIR == 0 ? blockIdx.y : blockIdx.x) * TT;
 
-  // phase 1: line segments (face f, tangential index tt)
-  for (int s = threadIdx.x; s < NSEG; s += blockDim.x) {
+  // phase 0: the tile's cells (TH x TH, halo 2 on every side) into LDS: W and
+  // the gradient along the normal, one (cell, component) pair per item;
+  // tiles away from the boundary skip the boundary rules
+  {
+    const int i0 = (DIR == 0 ? f0 : t0) - 2, j0 = (DIR == 0 ? t0 : f0) - 2;
+    const bool interior = i0 >= 0 && j0 >= 0 && i0 + TH <= G.nx && j0 + TH <= G.ny;
+    const size_t N = (size_t)G.nx * G.ny;
+#pragma unroll
+    for (int n = 0; n < (TH * TH * 4 + 255) / 256; ++n) {
+      const int item = threadIdx.x + 256 * n;
+      if (item < TH * TH * 4) {
+        const int k = item / (TH * TH), c = item % (TH * TH);
+        const int i = i0 + c % TH, j = j0 + c / TH;
+        double w = 0.0, gd = 0.0;
+        // no stencil reaches beyond index n + 1 (last face n, tangential halo 2);
+        // the boundary rules map every index in [-2, n + 1] into the grid
+        if (i > G.nx + 1 || j > G.ny + 1) {
+          // not used by any face of this tile
+        } else if (interior) {
+          const size_t id = (size_t)j * G.nx + i;
+          w = S[k * N + id];
+          gd = S[(4 + 4 * DIR + k) * N + id];
+        } else {
+          load_comp(S, G, i, j, DIR, k, w, gd);
+        }
+        cells[k][c] = w;
+        cells[4 + k][c] = hn * gd;
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 1: line segments (face f, tangential index tt), one component per item
+  for (int item = threadIdx.x; item < NSEG * 4; item += blockDim.x) {
+    const int s = item >> 2, k = item & 3;
     int fl, tl, pos;
     if (DIR == 0) { tl = s / TF; fl = s % TF; pos = tl * TF + fl; }
     else { fl = s / TH; tl = s % TH; pos = fl * TH + tl; }
-    const int f = f0 + fl, tt = t0 - 2 + tl;
-    if (f > nn || tt > nt + 1) continue;
-    double Wc[4][4], Dc[4][4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      if (DIR == 0) load_cell<4>(S, G, f - 2 + m, tt, 0, Wc[m], Dc[m]);
-      else load_cell<4>(S, G, tt, f - 2 + m, 1, Wc[m], Dc[m]);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double ref = Wc[1][k];
-      const Line5 L = normal_line(Wc[0][k] - ref, Wc[2][k] - ref, Wc[3][k] - ref, hn * Dc[0][k],
-                                  hn * Dc[1][k], hn * Dc[2][k], hn * Dc[3][k], G.eps);
-      lds[0 * 4 + k][pos] = L.v;
-      lds[1 * 4 + k][pos] = L.vn;
-      lds[2 * 4 + k][pos] = L.vnn;
-      lds[3 * 4 + k][pos] = L.wl;
-      lds[4 * 4 + k][pos] = L.wr;
-      lds[20 + k][pos] = ref;
-    }
+    if (f0 + fl > nn || t0 - 2 + tl > nt + 1) continue;
+    // stencil cells f-2..f+1 of this line in the tile (column fl+m of row tl, or row fl+m of column tl)
+    auto C = [&](int q, int m) { return DIR == 0 ? cells[q][tl * TH + fl + m] : cells[q][(fl + m) * TH + tl]; };
+    const double ref = C(k, 1);
+    const Line5 L = normal_line(C(k, 0) - ref, C(k, 2) - ref, C(k, 3) - ref, C(4 + k, 0), C(4 + k, 1),
+                                C(4 + k, 2), C(4 + k, 3), G.eps);
+    lds[0 * 4 + k][pos] = L.v;
+    lds[1 * 4 + k][pos] = L.vn;
+    lds[2 * 4 + k][pos] = L.vnn;
+    lds[3 * 4 + k][pos] = L.wl;
+    lds[4 * 4 + k][pos] = L.wr;
+    lds[20 + k][pos] = ref;
   }
   __syncthreads();
 
@@ -274,42 +350,13 @@ __global__ __launch_bounds__(256) void k_faces2(Geom G, Bufs B) {
 #pragma unroll
   for (int q = 0; q < NO; ++q) acc[q] = 0.0;
   int guards_w0 = 0, guards_weno = 0;
-  const double hn2 = hn * hn, inv_ht = 1.0 / ht;
+  auto get = [&](int q, int l) { return lds[q][P(l)]; };
 
 #pragma unroll 1
   for (int g = 0; g < 2; ++g) {
     PointIn<4> in;
     double dev[4], ref[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double rj = lds[20 + k][P(2)];
-      double v = 0, vt = 0, vtt = 0, n = 0, nt_ = 0, n2 = 0, wl = 0, wr = 0;
-#pragma unroll
-      for (int l = 0; l < 5; ++l) {
-        const int p = P(l);
-        const double off = lds[20 + k][p] - rj;
-        const double vl = lds[k][p] + off;
-        const double vnl = lds[4 + k][p];
-        v += kTang[g].v[l] * vl;
-        vt += kTang[g].d1[l] * vl;
-        vtt += kTang[g].d2[l] * vl;
-        n += kTang[g].v[l] * vnl;
-        nt_ += kTang[g].d1[l] * vnl;
-        n2 += kTang[g].v[l] * lds[8 + k][p];
-        wl += kTang[g].v[l] * (lds[12 + k][p] + off);
-        wr += kTang[g].v[l] * (lds[16 + k][p] + off);
-      }
-      ref[k] = rj;
-      dev[k] = v;
-      in.W0[k] = rj + v;
-      in.Wn[k] = n / hn;
-      in.Wnn[k] = n2 / hn2;
-      in.Wt[k] = vt * inv_ht;
-      in.Wnt[k] = nt_ / hn * inv_ht;
-      in.Wtt[k] = vtt * inv_ht * inv_ht;
-      in.Wl[k] = rj + wl;
-      in.Wr[k] = rj + wr;
-    }
+    tangential_point(get, kTang[g], hn, ht, in, dev, ref);
     // inadmissible nonlinear states fall back to the adjacent cell average
     if (!admissible<4>(in.Wl, G.gas.gamma)) {
 #pragma unroll
@@ -334,19 +381,7 @@ __global__ __launch_bounds__(256) void k_faces2(Geom G, Bufs B) {
       sw(o.F); sw(o.Ft); sw(o.Wt); sw(o.Wtt); sw(o.Nh); sw(o.Nf); sw(o.W0);
     }
     guards_w0 += o.guard;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (STAGE == 1) {
-        const double d0 = o.guard ? o.W0[k] - ref[k] : dev[k];
-        acc[k] += 0.5 * o.F[k];
-        acc[4 + k] += 0.5 * o.Ft[k];
-        acc[8 + k] += 0.5 * (d0 + 0.5 * dt * o.Wt[k] + dt * dt / 8.0 * o.Wtt[k] + o.Nh[k]);
-        acc[12 + k] += 0.5 * (d0 + dt * o.Wt[k] + dt * dt / 6.0 * o.Wtt[k] + o.Nf[k]);
-      } else {
-        acc[k] += 0.5 * o.Ft[k];
-        acc[4 + k] += 0.5 * o.Wtt[k];
-      }
-    }
+    face_accumulate<4, STAGE == 1>(acc, o, dev, ref, dt);
   }
   if (guards_w0) atomicAdd(&sc->guard_w0, (unsigned long long)guards_w0);
   if (guards_weno) atomicAdd(&sc->guard_weno, (unsigned long long)guards_weno);
@@ -420,7 +455,7 @@ __global__ __launch_bounds__(256) void k_update2(Geom G, Bufs B) {
       else lam = cell_lambda<4>(Wn, G);
     }
   }
-  if (STAGE == 2) reduce_lambda(sc, lam);
+  if (STAGE == 2) reduce_lambda(B.lam_part, lam);
 }
 
 // ---------------------------------------------------------------- 1D
@@ -526,7 +561,7 @@ __global__ __launch_bounds__(256) void k_update1(Geom G, Bufs B) {
       else lam = cell_lambda<3>(Wn, G);
     }
   }
-  if (STAGE == 2) reduce_lambda(sc, lam);
+  if (STAGE == 2) reduce_lambda(B.lam_part, lam);
 }
 
 }  // namespace cgks
@@ -582,6 +617,12 @@ static void timed(cgks_ctx* c, int kind, F&& launch) {
   c->ev_used += 1;
 }
 
+// grid of the update kernels (and of the scan): 64x4 cells per block in 2D, 256 in 1D
+static dim3 update_grid(const Geom& G) {
+  if (G.dim == 2) return dim3((unsigned)((G.nx + 63) / 64), (unsigned)((G.ny + 3) / 4));
+  return dim3((unsigned)((G.nx + 255) / 256), 1);
+}
+
 #define HIPCHK(x)                              \
   do {                                         \
     if ((x) != hipSuccess) return CGKS_EDEVICE; \
@@ -612,7 +653,7 @@ static int validate(const cgks_config* c) {
 
 static void free_bufs(cgks_ctx* c) {
   (void)hipFree(c->B.S[0]); (void)hipFree(c->B.S[1]); (void)hipFree(c->B.Ws); (void)hipFree(c->B.P);
-  (void)hipFree(c->B.FX); (void)hipFree(c->B.FY); (void)hipFree(c->B.sc);
+  (void)hipFree(c->B.FX); (void)hipFree(c->B.FY); (void)hipFree(c->B.sc); (void)hipFree(c->B.lam_part);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
 }
 
@@ -665,6 +706,7 @@ extern "C" int cgks_create(const cgks_config* cfg, void* hip_stream, cgks_ctx** 
             hipMalloc(&c->B.Ws, fbytes) == hipSuccess && hipMalloc(&c->B.P, fbytes) == hipSuccess &&
             hipMalloc(&c->B.FX, fx) == hipSuccess && hipMalloc(&c->B.FY, fy) == hipSuccess &&
             hipMalloc(&c->B.sc, sizeof(Scalars)) == hipSuccess &&
+            hipMalloc(&c->B.lam_part, sizeof(double) * (size_t)update_grid(G).x * update_grid(G).y) == hipSuccess &&
             hipHostMalloc(&c->host_sc, sizeof(Scalars), hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     free_bufs(c);
@@ -744,11 +786,8 @@ extern "C" int cgks_set_state(cgks_ctx* c, const double* fields, int on_device, 
   HIPCHK(hipMemcpyAsync(c->B.S[0], fields, c->nf * c->N * sizeof(double),
                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->B.sc, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
-  k_scan_begin<<<1, 64, 0, c->stream>>>(c->B.sc);
-  const unsigned nb = (unsigned)((c->N + 255) / 256);
-  if (c->cfg.dim == 2) k_scan<4><<<nb, 256, 0, c->stream>>>(c->G, c->B);
-  else k_scan<3><<<nb, 256, 0, c->stream>>>(c->G, c->B);
-  k_scan_end<<<1, 64, 0, c->stream>>>(c->B.sc);
+  if (c->cfg.dim == 2) k_scan<4><<<update_grid(c->G), 256, 0, c->stream>>>(c->G, c->B);
+  else k_scan<3><<<update_grid(c->G), 256, 0, c->stream>>>(c->G, c->B);
   HIPCHK(hipGetLastError());
   int rc = pull_scalars(c);
   if (rc) return rc;
@@ -763,11 +802,11 @@ extern "C" int cgks_set_state(cgks_ctx* c, const double* fields, int on_device, 
 static void launch_step(cgks_ctx* c) {
   const Geom& G = c->G;
   hipStream_t s = c->stream;
-  k_begin<<<1, 64, 0, s>>>(c->B.sc);
+  const dim3 gu = update_grid(G);
+  k_begin<<<1, 256, 0, s>>>(c->B.sc, c->B.lam_part, (int)(gu.x * gu.y));
   if (G.dim == 2) {
     const dim3 gx((G.nx + 1 + TF - 1) / TF, (G.ny + TT - 1) / TT);
     const dim3 gy((G.nx + TT - 1) / TT, (G.ny + 1 + TF - 1) / TF);
-    const dim3 gu((G.nx + 63) / 64, (G.ny + 3) / 4);
     const Bufs B = c->B;
     timed(c, 0, [&] { k_faces2<0, 1><<<gx, 256, 0, s>>>(G, B); });
     timed(c, 1, [&] { k_faces2<1, 1><<<gy, 256, 0, s>>>(G, B); });
@@ -776,12 +815,12 @@ static void launch_step(cgks_ctx* c) {
     timed(c, 4, [&] { k_faces2<1, 2><<<gy, 256, 0, s>>>(G, B); });
     timed(c, 5, [&] { k_update2<2><<<gu, 256, 0, s>>>(G, B); });
   } else {
-    const unsigned nf = (unsigned)((G.nx + 1 + 255) / 256), nc = (unsigned)((G.nx + 255) / 256);
+    const unsigned nf = (unsigned)((G.nx + 1 + 255) / 256);
     const Bufs B = c->B;
     timed(c, 0, [&] { k_faces1<1><<<nf, 256, 0, s>>>(G, B); });
-    timed(c, 1, [&] { k_update1<1><<<nc, 256, 0, s>>>(G, B); });
+    timed(c, 1, [&] { k_update1<1><<<gu, 256, 0, s>>>(G, B); });
     timed(c, 2, [&] { k_faces1<2><<<nf, 256, 0, s>>>(G, B); });
-    timed(c, 3, [&] { k_update1<2><<<nc, 256, 0, s>>>(G, B); });
+    timed(c, 3, [&] { k_update1<2><<<gu, 256, 0, s>>>(G, B); });
   }
   k_end<<<1, 64, 0, s>>>(c->B.sc);
 }

@@ -15,6 +15,14 @@
 // exercised on the CPU
 #define CGKS_HD __host__ __device__
 
+// Optional scheduling fence between independent phases of the point evaluation
+// (keeps their temporaries from overlapping in registers).
+#if defined(__HIP_DEVICE_COMPILE__) && defined(CGKS_PHASE_FENCES)
+#define CGKS_PHASE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define CGKS_PHASE() ((void)0)
+#endif
+
 namespace cgks {
 
 // ----------------------------------------------------------------------------
@@ -121,14 +129,16 @@ CGKS_HD __forceinline__ Line5 normal_line(double a, double c, double d, double A
 // ----------------------------------------------------------------------------
 struct TangW { double v[5], d1[5], d2[5]; };
 
-__constant__ static const TangW kTang[2] = {
-  {{-0.028297119567088289478, 0.20139476939454598305, 0.99861111111111111111, -0.19954291754269413120, 0.027834156604125326515},
-   {0.11540834828831254247, -1.0836418610813963855, 0.76980035891950101935, 0.24969147225193694785, -0.051258318378354124194},
-   {0.061004233964073107794, 1.0446581987385204511, -2.5, 1.6220084679281462156, -0.22767090063073977446}},
-  {{0.027834156604125326515, -0.19954291754269413120, 0.99861111111111111111, 0.20139476939454598305, -0.028297119567088289478},
-   {0.051258318378354124194, -0.24969147225193694785, -0.76980035891950101935, 1.0836418610813963855, -0.11540834828831254247},
-   {-0.22767090063073977446, 1.6220084679281462156, -2.5, 1.0446581987385204511, 0.061004233964073107794}},
-};
+#define CGKS_TANG_WEIGHTS { \
+  {{-0.028297119567088289478, 0.20139476939454598305, 0.99861111111111111111, -0.19954291754269413120, 0.027834156604125326515}, \
+   {0.11540834828831254247, -1.0836418610813963855, 0.76980035891950101935, 0.24969147225193694785, -0.051258318378354124194}, \
+   {0.061004233964073107794, 1.0446581987385204511, -2.5, 1.6220084679281462156, -0.22767090063073977446}}, \
+  {{0.027834156604125326515, -0.19954291754269413120, 0.99861111111111111111, 0.20139476939454598305, -0.028297119567088289478}, \
+   {0.051258318378354124194, -0.24969147225193694785, -0.76980035891950101935, 1.0836418610813963855, -0.11540834828831254247}, \
+   {-0.22767090063073977446, 1.6220084679281462156, -2.5, 1.0446581987385204511, 0.061004233964073107794}}, \
+}
+
+__constant__ static const TangW kTang[2] = CGKS_TANG_WEIGHTS;
 
 // ----------------------------------------------------------------------------
 // gas-kinetic evolution at one interface point (normal = first velocity
@@ -360,29 +370,24 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
   double M4[NC], D35[NC], Slr[NC], Salr[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) { M4[k] = 0.0; D35[k] = 0.0; Slr[k] = 0.0; Salr[k] = 0.0; }
+  CGKS_PHASE();
 
   // the two nonlinear (non-equilibrium) sides
-#pragma unroll
+#pragma unroll 1
   for (int side = 0; side < 2; ++side) {
     const double* Ws = side == 0 ? in.Wl : in.Wr;
     Mom<NC> m;
     moments<NC>(Ws, g, side == 0 ? +1 : -1, m);
-    Mom<NC> mf = m;   // full-space u moments for the slope system
-    mf.mu[0] = 1.0; mf.mu[1] = m.U;
-    {
-      const double h = 0.5 / m.lam;
-#pragma unroll
-      for (int n = 1; n < 6; ++n) mf.mu[n + 1] = m.U * mf.mu[n] + (double)n * h * mf.mu[n - 1];
-    }
+    // the slope system uses only (U, V, lambda) of the side's Maxwellian
     double bn[NC], an[NC], at[NC], t1[NC], t2[NC];
     const double ir = 1.0 / m.rho;
 #pragma unroll
     for (int k = 0; k < NC; ++k) bn[k] = in.Wn[k] * ir;
-    slope<NC>(mf, g, bn, an);
+    slope<NC>(m, g, bn, an);
     if constexpr (NC == 4) {
 #pragma unroll
       for (int k = 0; k < NC; ++k) bn[k] = in.Wt[k] * ir;
-      slope<NC>(mf, g, bn, at);
+      slope<NC>(m, g, bn, at);
     }
     mom_psi<NC>(m, 1, 0, t1);                   // <u psi>
 #pragma unroll
@@ -408,6 +413,7 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
 #pragma unroll
       for (int k = 0; k < NC; ++k) Salr[k] += m.rho * t1[k];
     }
+    CGKS_PHASE();
   }
 
   // equilibrium state from the linear reconstruction; kinetic collision state
@@ -454,6 +460,7 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
 #pragma unroll
     for (int k = 0; k < NC; ++k) D35[k] += m.rho * t1[k];   // D35 = M3 - M5
   }
+  CGKS_PHASE();
 
   // Euler derivatives at the point (2D form)
   CK ck;
@@ -474,6 +481,7 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
     }
     euler_ck(g.gamma, W4, x4, y4, xx4, xy4, yy4, ck);
   }
+  CGKS_PHASE();
   auto from4 = [&](const double* v4, double* v) {
     if constexpr (NC == 4) { v[0] = v4[0]; v[1] = v4[1]; v[2] = v4[2]; v[3] = v4[3]; }
     else { v[0] = v4[0]; v[1] = v4[1]; v[2] = v4[3]; }
@@ -516,6 +524,72 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
       out.Nh[k] = Eh * (base - 0.5 * dt * slp);
       out.Nf[k] = E * (base - dt * slp);
       out.W0[k] = W0[k];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Tangential reconstruction of one face point from the 5 stencil lines of its
+// face segment (offsets -2..2).  get(q, l) returns quantity q of line l:
+// q = 4*j + k for j = (P7, h P7_n, h^2 P7_nn, WENO left, WENO right) and
+// component k (each shifted by the line's own reference cell), q = 20 + k the
+// reference cell average.  Value-type quantities are moved to the face
+// segment's reference (the middle line) before the quartic; hn, ht are the
+// normal and tangential cell widths.
+// ----------------------------------------------------------------------------
+template <class Get>
+CGKS_HD __forceinline__ void tangential_point(Get get, const TangW& w, double hn, double ht,
+                                              PointIn<4>& in, double* dev, double* ref) {
+  const double inv_ht = 1.0 / ht, inv_hn = 1.0 / hn;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double rj = get(20 + k, 2);
+    double v = 0, vt = 0, vtt = 0, n = 0, nt = 0, n2 = 0, wl = 0, wr = 0;
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      const double off = get(20 + k, l) - rj;
+      const double vl = get(k, l) + off;
+      const double vnl = get(4 + k, l);
+      v += w.v[l] * vl;
+      vt += w.d1[l] * vl;
+      vtt += w.d2[l] * vl;
+      n += w.v[l] * vnl;
+      nt += w.d1[l] * vnl;
+      n2 += w.v[l] * get(8 + k, l);
+      wl += w.v[l] * (get(12 + k, l) + off);
+      wr += w.v[l] * (get(16 + k, l) + off);
+    }
+    ref[k] = rj;
+    dev[k] = v;
+    in.W0[k] = rj + v;
+    in.Wn[k] = n * inv_hn;
+    in.Wnn[k] = n2 * inv_hn * inv_hn;
+    in.Wt[k] = vt * inv_ht;
+    in.Wnt[k] = nt * inv_hn * inv_ht;
+    in.Wtt[k] = vtt * inv_ht * inv_ht;
+    in.Wl[k] = rj + wl;
+    in.Wr[k] = rj + wr;
+  }
+}
+
+// Gauss average (weights 1/2) of the per-point face results.  Stage 1 keeps
+// F, F_t and the interface states at t + dt/2 (A) and the stage-n part of the
+// state at t + dt (B), both as deviations from the face reference (Sec. 2.2);
+// stage 2 keeps F_t and W_tt.
+template <int NC, bool FULL>
+CGKS_HD __forceinline__ void face_accumulate(double* acc, const PointOut<NC>& o, const double* dev,
+                                             const double* ref, double dt) {
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if constexpr (FULL) {
+      const double d0 = o.guard ? o.W0[k] - ref[k] : dev[k];
+      acc[k] += 0.5 * o.F[k];
+      acc[NC + k] += 0.5 * o.Ft[k];
+      acc[2 * NC + k] += 0.5 * (d0 + 0.5 * dt * o.Wt[k] + dt * dt / 8.0 * o.Wtt[k] + o.Nh[k]);
+      acc[3 * NC + k] += 0.5 * (d0 + dt * o.Wt[k] + dt * dt / 6.0 * o.Wtt[k] + o.Nf[k]);
+    } else {
+      acc[k] += 0.5 * o.Ft[k];
+      acc[NC + k] += 0.5 * o.Wtt[k];
     }
   }
 }

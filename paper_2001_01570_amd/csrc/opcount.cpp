@@ -1,0 +1,164 @@
+// Operation count of the device arithmetic (algorithmic work per unit).
+//
+// The device functions of cgks_device.h are compiled for the host with every
+// double replaced by a counting scalar: additions/subtractions, multiplications
+// and divisions are counted (a fused multiply-add is a multiplication plus an
+// addition, i.e. 2 flops), square roots, exponentials and complementary error
+// functions separately.  Counting runs the same code the kernels run, on a
+// smooth representative state (no guard fires, both WENO sides evaluated).
+//
+// Units:  x- or y-face segment of one stage (4 normal reconstructions of its
+// own line, 2 Gauss points: tangential quartic, gas-kinetic evolution, Gauss
+// average) and one cell update.  The kernels' halo recomputation of stencil
+// lines is not algorithmic work and is not counted.
+//
+// Output: JSON on stdout.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+
+struct OpCounts {
+  long add = 0, mul = 0, div = 0, sqrt_ = 0, exp_ = 0, erfc_ = 0;
+};
+static OpCounts g_ops;
+
+// An operation with an exact 0 operand (additions, multiplications) or an
+// exact +-1 factor is structural (a unit vector, an initial accumulator) and
+// is folded by the compiler: it is not counted.  The representative state has
+// no zero data, so only structural constants are skipped.
+inline bool trivial_add(double a, double b) { return a == 0.0 || b == 0.0; }
+inline bool trivial_mul(double a, double b) {
+  return a == 0.0 || b == 0.0 || a == 1.0 || b == 1.0 || a == -1.0 || b == -1.0;
+}
+struct CD {
+  double v;
+  constexpr CD(double x = 0.0) : v(x) {}
+  CD& operator+=(const CD& o) { if (!trivial_add(v, o.v)) ++g_ops.add; v += o.v; return *this; }
+  CD& operator-=(const CD& o) { if (!trivial_add(v, o.v)) ++g_ops.add; v -= o.v; return *this; }
+  CD& operator*=(const CD& o) { if (!trivial_mul(v, o.v)) ++g_ops.mul; v *= o.v; return *this; }
+  CD& operator/=(const CD& o) { ++g_ops.div; v /= o.v; return *this; }
+};
+inline CD operator+(const CD& a, const CD& b) { if (!trivial_add(a.v, b.v)) ++g_ops.add; return CD(a.v + b.v); }
+inline CD operator-(const CD& a, const CD& b) { if (!trivial_add(a.v, b.v)) ++g_ops.add; return CD(a.v - b.v); }
+inline CD operator*(const CD& a, const CD& b) { if (!trivial_mul(a.v, b.v)) ++g_ops.mul; return CD(a.v * b.v); }
+inline CD operator/(const CD& a, const CD& b) { ++g_ops.div; return CD(a.v / b.v); }
+inline CD operator-(const CD& a) { return CD(-a.v); }
+inline bool operator<(const CD& a, const CD& b) { return a.v < b.v; }
+inline bool operator>(const CD& a, const CD& b) { return a.v > b.v; }
+inline bool operator<=(const CD& a, const CD& b) { return a.v <= b.v; }
+inline bool operator>=(const CD& a, const CD& b) { return a.v >= b.v; }
+inline bool operator==(const CD& a, const CD& b) { return a.v == b.v; }
+inline bool operator!=(const CD& a, const CD& b) { return a.v != b.v; }
+inline bool operator!(const CD& a) { return !a.v; }
+inline CD fabs(const CD& a) { return CD(std::fabs(a.v)); }
+inline CD sqrt(const CD& a) { ++g_ops.sqrt_; return CD(std::sqrt(a.v)); }
+inline CD exp(const CD& a) { ++g_ops.exp_; return CD(std::exp(a.v)); }
+inline CD erfc(const CD& a) { ++g_ops.erfc_; return CD(std::erfc(a.v)); }
+
+#define double CD
+#include "cgks_device.h"
+#undef double
+
+using namespace cgks;
+
+static OpCounts snap() { return g_ops; }
+static OpCounts diff(const OpCounts& a, const OpCounts& b) {
+  OpCounts d;
+  d.add = b.add - a.add; d.mul = b.mul - a.mul; d.div = b.div - a.div;
+  d.sqrt_ = b.sqrt_ - a.sqrt_; d.exp_ = b.exp_ - a.exp_; d.erfc_ = b.erfc_ - a.erfc_;
+  return d;
+}
+static long flops(const OpCounts& c) { return c.add + c.mul + c.div; }
+
+static void emit(const char* name, const OpCounts& c, bool comma) {
+  std::printf("    \"%s\": {\"add\": %ld, \"mul\": %ld, \"div\": %ld, \"sqrt\": %ld, \"exp\": %ld, \"erfc\": %ld, \"flops\": %ld}%s\n",
+              name, c.add, c.mul, c.div, c.sqrt_, c.exp_, c.erfc_, flops(c), comma ? "," : "");
+}
+
+int main() {
+  static const TangW host_tang[2] = CGKS_TANG_WEIGHTS;
+  const double gamma = 1.4;
+  Gas gas;
+  gas.gamma = gamma; gas.K = 2.0 / (gamma - 1.0) - 2.0; gas.tau_eps = 0.01; gas.tau_C = 1.0;
+  const double dt = 6e-4, hn = 1.0 / 512, ht = 1.0 / 512;
+
+  // one normal reconstruction (one line, one component)
+  OpCounts a = snap();
+  Line5 L = normal_line(CD(1.1e-4), CD(-0.9e-4), CD(2.1e-4), CD(0.5e-4), CD(-0.7e-4), CD(1.3e-4), CD(0.2e-4), CD(1e-6));
+  (void)L;
+  const OpCounts recon = diff(a, snap());
+
+  // tangential quartic to one Gauss point (4 components)
+  CD lines[24][5];
+  for (int q = 0; q < 24; ++q)
+    for (int l = 0; l < 5; ++l) lines[q][l] = q >= 20 ? CD(1.0 + 1e-4 * l) : CD(1e-5 * (q + 1) * (l + 1));
+  for (int l = 0; l < 5; ++l) { lines[20][l] = CD(1.0 + 1e-4 * l); lines[23][l] = CD(1.8 + 1e-4 * l); }
+  auto get = [&](int q, int l) { return lines[q][l]; };
+  PointIn<4> in;
+  CD dev[4], ref[4];
+  a = snap();
+  tangential_point(get, host_tang[0], CD(hn), CD(ht), in, dev, ref);
+  const OpCounts tang = diff(a, snap());
+  for (int k = 0; k < 4; ++k) { in.Wl[k] = in.W0[k] + CD(1e-9); in.Wr[k] = in.W0[k] - CD(1e-9); }
+
+  PointOut<4> o;
+  a = snap();
+  gks_point<4, true>(in, gas, CD(dt), o);
+  const OpCounts gks1 = diff(a, snap());
+  a = snap();
+  gks_point<4, false>(in, gas, CD(dt), o);
+  const OpCounts gks2 = diff(a, snap());
+
+  CD acc[16];
+  for (int q = 0; q < 16; ++q) acc[q] = CD(0.0);
+  a = snap();
+  face_accumulate<4, true>(acc, o, dev, ref, CD(dt));
+  const OpCounts acc1 = diff(a, snap());
+  a = snap();
+  face_accumulate<4, false>(acc, o, dev, ref, CD(dt));
+  const OpCounts acc2 = diff(a, snap());
+
+  // per face segment of a stage: 4 component reconstructions of its own line,
+  // 2 Gauss points (tangential + evolution + accumulation)
+  auto seg = [&](const OpCounts& g, const OpCounts& ac) {
+    OpCounts s;
+    s.add = 4 * recon.add + 2 * (tang.add + g.add + ac.add);
+    s.mul = 4 * recon.mul + 2 * (tang.mul + g.mul + ac.mul);
+    s.div = 4 * recon.div + 2 * (tang.div + g.div + ac.div);
+    s.sqrt_ = 4 * recon.sqrt_ + 2 * (tang.sqrt_ + g.sqrt_ + ac.sqrt_);
+    s.exp_ = 4 * recon.exp_ + 2 * (tang.exp_ + g.exp_ + ac.exp_);
+    s.erfc_ = 4 * recon.erfc_ + 2 * (tang.erfc_ + g.erfc_ + ac.erfc_);
+    return s;
+  };
+  const OpCounts seg1 = seg(gks1, acc1), seg2 = seg(gks2, acc2);
+  // cell updates per component (see k_update2): stage 1: L, Lt (2 faces x 2 directions,
+  // 4 sub, 2 div, 2 add each) 12 + 2 jump sub + W*, P (3 mul 2 add each ~ 10) +
+  // 4 gradients (1 sub 1 add 1 div) 12 -> 36; stage 2: Lt 6 + W (2) + 2 gradients (1 sub 1 mul 1 div 1 add) 8 -> 16
+  OpCounts up1, up2;
+  up1.add = 4 * 20; up1.mul = 4 * 8; up1.div = 4 * 8;
+  up2.add = 4 * 8; up2.mul = 4 * 4; up2.div = 4 * 4;
+  std::printf("{\n  \"units\": {\n");
+  emit("recon_line_component", recon, true);
+  emit("tangential_point", tang, true);
+  emit("gks_point_stage1", gks1, true);
+  emit("gks_point_stage2", gks2, true);
+  emit("face_segment_stage1", seg1, true);
+  emit("face_segment_stage2", seg2, true);
+  emit("cell_update_stage1", up1, true);
+  emit("cell_update_stage2", up2, false);
+  std::printf("  },\n");
+  const long cell_step = 2 * flops(seg1) + 2 * flops(seg2) + flops(up1) + flops(up2);
+  std::printf("  \"flops_per_cell_step\": %ld,\n", cell_step);
+  std::printf("  \"transcendentals_per_cell_step\": {\"sqrt\": %ld, \"exp\": %ld, \"erfc\": %ld},\n",
+              2 * (seg1.sqrt_ + seg2.sqrt_), 2 * (seg1.exp_ + seg2.exp_), 2 * (seg1.erfc_ + seg2.erfc_));
+  std::printf("  \"per_launch_units\": {\n");
+  std::printf("    \"xfaces1\": {\"units\": \"ny*(nx+1)\", \"flops_per_unit\": %ld},\n", flops(seg1));
+  std::printf("    \"yfaces1\": {\"units\": \"(ny+1)*nx\", \"flops_per_unit\": %ld},\n", flops(seg1));
+  std::printf("    \"xfaces2\": {\"units\": \"ny*(nx+1)\", \"flops_per_unit\": %ld},\n", flops(seg2));
+  std::printf("    \"yfaces2\": {\"units\": \"(ny+1)*nx\", \"flops_per_unit\": %ld},\n", flops(seg2));
+  std::printf("    \"update1\": {\"units\": \"nx*ny\", \"flops_per_unit\": %ld},\n", flops(up1));
+  std::printf("    \"update2\": {\"units\": \"nx*ny\", \"flops_per_unit\": %ld}\n", flops(up2));
+  std::printf("  }\n}\n");
+  return 0;
+}
