@@ -33,9 +33,10 @@ constexpr int NQ = 24;          // per segment: 5 quantities x 4 components + 4 
 // LDS row length: NSEG padded so that the rows of the 4 components written by
 // consecutive threads start in different banks (328 doubles = 656 dwords = 16 mod 64)
 constexpr int NSEG_PAD = 328;
-#ifndef CGKS_FACE_WAVES_PER_EU
-#define CGKS_FACE_WAVES_PER_EU 1
-#endif
+constexpr int FACE_THREADS = 2 * TF * TT;   // one thread per Gauss point of the tile's face segments
+
+// Compiler-level memory barrier between the phases of the point evaluation:
+// LDS values are re-read in each phase instead of being held in registers.
 
 struct Geom {
   int dim, nx, ny;
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(256) void k_scan(Geom G, Bufs B) {
 // face segment per thread: tangential quartic to each Gauss point, the
 // gas-kinetic evolution, and the Gauss average.
 template <int DIR, int STAGE>
-__global__ __launch_bounds__(256, CGKS_FACE_WAVES_PER_EU) void k_faces2(Geom G, Bufs B) {
+__global__ __launch_bounds__(FACE_THREADS) void k_faces2(Geom G, Bufs B) {
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
   const double dt = sc->dt;
@@ -292,8 +293,8 @@ __global__ __launch_bounds__(256, CGKS_FACE_WAVES_PER_EU) void k_faces2(Geom G, 
     const bool interior = i0 >= 0 && j0 >= 0 && i0 + TH <= G.nx && j0 + TH <= G.ny;
     const size_t N = (size_t)G.nx * G.ny;
 #pragma unroll
-    for (int n = 0; n < (TH * TH * 4 + 255) / 256; ++n) {
-      const int item = threadIdx.x + 256 * n;
+    for (int n = 0; n < (TH * TH * 4 + FACE_THREADS - 1) / FACE_THREADS; ++n) {
+      const int item = threadIdx.x + FACE_THREADS * n;
       if (item < TH * TH * 4) {
         const int k = item / (TH * TH), c = item % (TH * TH);
         const int i = i0 + c % TH, j = j0 + c / TH;
@@ -337,54 +338,44 @@ __global__ __launch_bounds__(256, CGKS_FACE_WAVES_PER_EU) void k_faces2(Geom G, 
   }
   __syncthreads();
 
-  // phase 2: one face segment per thread, lanes along the contiguous index
-  const int lane16 = threadIdx.x % 16, row16 = threadIdx.x / 16;
-  int fl, tl;
-  if (DIR == 0) { fl = lane16; tl = row16; } else { tl = lane16; fl = row16; }
+  // phase 2: one Gauss point per thread (face_point).  The second Gauss point
+  // reads the 5 stencil lines in reverse order.  y faces: the two points of a
+  // segment in adjacent lanes (their reads of a line row coincide or fall in
+  // different banks).  x faces: the two points in the two half-waves (within a
+  // half-wave, reads of lines 2 or 4 rows apart would share LDS banks); a
+  // half-wave covers 2 rows of 16 faces.
+  int gp, fl, tl;
+  if (DIR == 0) {
+    const int lane = threadIdx.x & 63;
+    gp = lane >> 5;
+    fl = lane & 15;
+    tl = 2 * (threadIdx.x >> 6) + ((lane >> 4) & 1);
+  } else {
+    gp = threadIdx.x & 1;
+    tl = (threadIdx.x >> 1) % 16;
+    fl = (threadIdx.x >> 1) / 16;
+  }
+  constexpr int PAIR = DIR == 0 ? 32 : 1;   // lane distance of the two points of a segment
   const int f = f0 + fl, tt = t0 + tl;
   if (f > nn || tt >= nt) return;
-  auto P = [&](int l) { return DIR == 0 ? (tl + l) * TF + fl : fl * TH + tl + l; };
-
+  const int lstride = DIR == 0 ? TF : 1;                          // next stencil line in LDS
+  const int lfirst = (DIR == 0 ? tl * TF + fl : fl * TH + tl) + (gp ? 4 * lstride : 0);
+  const int lstep = gp ? -lstride : lstride;
+  auto get = [&](int q, int l) { return lds[q][lfirst + lstep * l]; };
+  // the cell right of the face (phase 0 loaded it with its boundary rule)
+  const int rc = DIR == 0 ? (tl + 2) * TH + fl + 2 : (fl + 2) * TH + tl + 2;
+  auto right_cell = [&](int k) { return cells[k][rc]; };
   constexpr int NO = STAGE == 1 ? 16 : 8;
   double acc[NO];
-#pragma unroll
-  for (int q = 0; q < NO; ++q) acc[q] = 0.0;
-  int guards_w0 = 0, guards_weno = 0;
-  auto get = [&](int q, int l) { return lds[q][P(l)]; };
+  int guard, nbad;
+  face_point<DIR, STAGE == 1>(get, right_cell, kTang[0], gp ? -1.0 : 1.0, hn, ht, G.gas, dt, acc, guard, nbad);
 
-#pragma unroll 1
-  for (int g = 0; g < 2; ++g) {
-    PointIn<4> in;
-    double dev[4], ref[4];
-    tangential_point(get, kTang[g], hn, ht, in, dev, ref);
-    // inadmissible nonlinear states fall back to the adjacent cell average
-    if (!admissible<4>(in.Wl, G.gas.gamma)) {
+  // Gauss average over the two lanes of the segment; the first point's lane writes
+  if (guard) atomicAdd(&sc->guard_w0, 1ull);
+  if (nbad) atomicAdd(&sc->guard_weno, (unsigned long long)nbad);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) in.Wl[k] = ref[k];
-      ++guards_weno;
-    }
-    if (!admissible<4>(in.Wr, G.gas.gamma)) {
-      double Wn_[4];
-      if (DIR == 0) load_avg<4>(S, G, f, tt, Wn_); else load_avg<4>(S, G, tt, f, Wn_);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) in.Wr[k] = Wn_[k];
-      ++guards_weno;
-    }
-    if (DIR == 1) {   // rotate: the normal momentum becomes the first velocity component
-      auto sw = [](double* v) { const double t = v[1]; v[1] = v[2]; v[2] = t; };
-      sw(in.W0); sw(in.Wn); sw(in.Wt); sw(in.Wnn); sw(in.Wnt); sw(in.Wtt); sw(in.Wl); sw(in.Wr);
-    }
-    PointOut<4> o;
-    gks_point<4, STAGE == 1>(in, G.gas, dt, o);
-    if (DIR == 1) {
-      auto sw = [](double* v) { const double t = v[1]; v[1] = v[2]; v[2] = t; };
-      sw(o.F); sw(o.Ft); sw(o.Wt); sw(o.Wtt); sw(o.Nh); sw(o.Nf); sw(o.W0);
-    }
-    guards_w0 += o.guard;
-    face_accumulate<4, STAGE == 1>(acc, o, dev, ref, dt);
-  }
-  if (guards_w0) atomicAdd(&sc->guard_w0, (unsigned long long)guards_w0);
-  if (guards_weno) atomicAdd(&sc->guard_weno, (unsigned long long)guards_weno);
+  for (int q = 0; q < NO; ++q) acc[q] += __shfl_xor(acc[q], PAIR, 64);
+  if (gp) return;
   double* F = DIR == 0 ? B.FX : B.FY;
   // x faces: [q][row][face] (nx+1 per row); y faces: [q][face][column] (nx per row)
   const size_t plane = DIR == 0 ? (size_t)G.ny * (G.nx + 1) : (size_t)(G.ny + 1) * G.nx;
@@ -808,11 +799,11 @@ static void launch_step(cgks_ctx* c) {
     const dim3 gx((G.nx + 1 + TF - 1) / TF, (G.ny + TT - 1) / TT);
     const dim3 gy((G.nx + TT - 1) / TT, (G.ny + 1 + TF - 1) / TF);
     const Bufs B = c->B;
-    timed(c, 0, [&] { k_faces2<0, 1><<<gx, 256, 0, s>>>(G, B); });
-    timed(c, 1, [&] { k_faces2<1, 1><<<gy, 256, 0, s>>>(G, B); });
+    timed(c, 0, [&] { k_faces2<0, 1><<<gx, FACE_THREADS, 0, s>>>(G, B); });
+    timed(c, 1, [&] { k_faces2<1, 1><<<gy, FACE_THREADS, 0, s>>>(G, B); });
     timed(c, 2, [&] { k_update2<1><<<gu, 256, 0, s>>>(G, B); });
-    timed(c, 3, [&] { k_faces2<0, 2><<<gx, 256, 0, s>>>(G, B); });
-    timed(c, 4, [&] { k_faces2<1, 2><<<gy, 256, 0, s>>>(G, B); });
+    timed(c, 3, [&] { k_faces2<0, 2><<<gx, FACE_THREADS, 0, s>>>(G, B); });
+    timed(c, 4, [&] { k_faces2<1, 2><<<gy, FACE_THREADS, 0, s>>>(G, B); });
     timed(c, 5, [&] { k_update2<2><<<gu, 256, 0, s>>>(G, B); });
   } else {
     const unsigned nf = (unsigned)((G.nx + 1 + 255) / 256);

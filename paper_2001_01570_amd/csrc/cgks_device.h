@@ -15,12 +15,22 @@
 // exercised on the CPU
 #define CGKS_HD __host__ __device__
 
-// Optional scheduling fence between independent phases of the point evaluation
-// (keeps their temporaries from overlapping in registers).
-#if defined(__HIP_DEVICE_COMPILE__) && defined(CGKS_PHASE_FENCES)
-#define CGKS_PHASE() __builtin_amdgcn_sched_barrier(0)
+// Register-pressure controls of the face-point evaluation (no effect on the
+// arithmetic; no-ops on the host):
+//   CGKS_PIN(x)   materialise x here (the compiler may not sink the arithmetic
+//                 that produces it towards its later uses)
+//   CGKS_BREAK()  compiler memory barrier + scheduling barrier: LDS values are
+//                 re-read after it instead of being held in registers
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CGKS_PIN(x) asm volatile("" : "+v"(x))
+#define CGKS_BREAK()                    \
+  do {                                  \
+    asm volatile("" ::: "memory");      \
+    __builtin_amdgcn_sched_barrier(0);  \
+  } while (0)
 #else
-#define CGKS_PHASE() ((void)0)
+#define CGKS_PIN(x) ((void)0)
+#define CGKS_BREAK() ((void)0)
 #endif
 
 namespace cgks {
@@ -353,144 +363,144 @@ struct PointOut {
   int guard;
 };
 
-// The interface evolution (eq. 3rd-simplify-flux, second-order part for the
-// flux): numerical collision time in exp(-t/tau) only, physical collision
-// time zero for the Euler equations.  Flux extraction in coefficient form:
+// Kinetic sums of the two non-equilibrium sides: M4 = sum rho <u psi>_side,
+// D35 accumulates -rho <u psi (a_n u + a_t v)>_side (and later + the
+// equilibrium's slope term), Slr = sum rho <psi>_side,
+// Salr = sum rho <psi (a_n u + a_t v)>_side.
+template <int NC>
+struct SideSums {
+  double M4[NC], D35[NC], Slr[NC], Salr[NC];
+  CGKS_HD __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) { M4[k] = 0.0; D35[k] = 0.0; Slr[k] = 0.0; Salr[k] = 0.0; }
+  }
+};
+
+// Numerical collision time of Sec. 4 (inviscid): tau = eps dt + C |p_l - p_r|/(p_l + p_r) dt,
+// p_l, p_r of the nonlinear (WENO) states.
+template <int NC>
+CGKS_HD __forceinline__ double collision_time(const double* Wl, const double* Wr, const Gas& g, double dt) {
+  const double pl = pressure<NC>(Wl, g.gamma), pr = pressure<NC>(Wr, g.gamma);
+  return g.tau_eps * dt + g.tau_C * fabs((pl - pr) / (pl + pr)) * dt;
+}
+
+// One non-equilibrium side (half space u > 0 for side = +1, u < 0 for -1):
+// the slopes of the linear reconstruction (Wn, Wt) expressed in this side's
+// Maxwellian (they use only its U, V, lambda), and its kinetic sums.
+template <int NC, bool FULL>
+CGKS_HD __forceinline__ void side_terms(const double* Ws, int side, const double* Wn, const double* Wt,
+                                        const Gas& g, SideSums<NC>& acc) {
+  Mom<NC> m;
+  moments<NC>(Ws, g, side, m);
+  double bn[NC], an[NC], at[NC], t1[NC], t2[NC];
+  const double ir = 1.0 / m.rho;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) bn[k] = Wn[k] * ir;
+  slope<NC>(m, g, bn, an);
+  if constexpr (NC == 4) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) bn[k] = Wt[k] * ir;
+    slope<NC>(m, g, bn, at);
+  }
+  mom_psi<NC>(m, 1, 0, t1);                   // <u psi>
+#pragma unroll
+  for (int k = 0; k < NC; ++k) acc.M4[k] += m.rho * t1[k];
+  mom_psi_a<NC>(m, 2, 0, an, t1);             // <u^2 psi a_n>
+  if constexpr (NC == 4) {
+    mom_psi_a<NC>(m, 1, 1, at, t2);           // <u v psi a_t>
+#pragma unroll
+    for (int k = 0; k < NC; ++k) t1[k] += t2[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) acc.D35[k] -= m.rho * t1[k];
+  if constexpr (FULL) {
+    mom_psi<NC>(m, 0, 0, t1);                 // <psi>
+#pragma unroll
+    for (int k = 0; k < NC; ++k) acc.Slr[k] += m.rho * t1[k];
+    mom_psi_a<NC>(m, 1, 0, an, t1);           // <u psi a_n>
+    if constexpr (NC == 4) {
+      mom_psi_a<NC>(m, 0, 1, at, t2);         // <v psi a_t>
+#pragma unroll
+      for (int k = 0; k < NC; ++k) t1[k] += t2[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) acc.Salr[k] += m.rho * t1[k];
+  }
+}
+
+// Kinetic collision state of the two sides, rho_l <psi>_{l,u>0} + rho_r <psi>_{r,u<0}
+// (used in place of an inadmissible linear equilibrium state).
+template <int NC>
+CGKS_HD __forceinline__ void collision_state(const double* Wl, const double* Wr, const Gas& g, double* S) {
+  Mom<NC> m;
+  double t1[NC];
+  moments<NC>(Wl, g, +1, m);
+  mom_psi<NC>(m, 0, 0, t1);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) S[k] = m.rho * t1[k];
+  moments<NC>(Wr, g, -1, m);
+  mom_psi<NC>(m, 0, 0, t1);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) S[k] += m.rho * t1[k];
+}
+
+// Slope part of the equilibrium: D35 += rho0 <u psi (a_n u + a_t v)>_0.
+template <int NC>
+CGKS_HD __forceinline__ void equilibrium_terms(const double* W0, const double* Wn, const double* Wt, const Gas& g,
+                                               double* D35) {
+  Mom<NC> m;
+  moments<NC>(W0, g, 0, m);
+  double bn[NC], an[NC], t1[NC];
+  const double ir = 1.0 / m.rho;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) bn[k] = Wn[k] * ir;
+  slope<NC>(m, g, bn, an);
+  mom_psi_a<NC>(m, 2, 0, an, t1);
+  if constexpr (NC == 4) {
+    double at[NC], t2[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) bn[k] = Wt[k] * ir;
+    slope<NC>(m, g, bn, at);
+    mom_psi_a<NC>(m, 1, 1, at, t2);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) t1[k] += t2[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) D35[k] += m.rho * t1[k];
+}
+
+// Exact Euler derivatives of the equilibrium at the point, in the NC layout:
+// W_t, W_tt and the flux time derivative M2 = dF/dt.
+template <int NC>
+CGKS_HD __forceinline__ void ck_terms(double gamma, const double* W0, const double* Wn, const double* Wt,
+                                      const double* Wnn, const double* Wnt, const double* Wtt,
+                                      double* Wt_o, double* Wtt_o, double* M2) {
+  CK ck;
+  if constexpr (NC == 4) {
+    euler_ck(gamma, W0, Wn, Wt, Wnn, Wnt, Wtt, ck);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { Wt_o[k] = ck.Wt[k]; Wtt_o[k] = ck.Wtt[k]; M2[k] = ck.Ft[k]; }
+  } else {   // 1D embedded as V = 0 without y dependence
+    const double W4[4] = {W0[0], W0[1], 0.0, W0[2]};
+    const double x4[4] = {Wn[0], Wn[1], 0.0, Wn[2]};
+    const double xx4[4] = {Wnn[0], Wnn[1], 0.0, Wnn[2]};
+    const double z4[4] = {0.0, 0.0, 0.0, 0.0};
+    euler_ck(gamma, W4, x4, z4, xx4, z4, z4, ck);
+    Wt_o[0] = ck.Wt[0]; Wt_o[1] = ck.Wt[1]; Wt_o[2] = ck.Wt[3];
+    Wtt_o[0] = ck.Wtt[0]; Wtt_o[1] = ck.Wtt[1]; Wtt_o[2] = ck.Wtt[3];
+    M2[0] = ck.Ft[0]; M2[1] = ck.Ft[1]; M2[2] = ck.Ft[3];
+  }
+}
+
+// Combination of the moment vectors with the time coefficients of the flux
+// extraction (Eh = e^{-dt/(2 tau)}, E = Eh^2):
 //   F  = M1 + e4 (M4 - M1) + e3 (M3 - M5)
 //   Ft = M2 + e1' (M1 - M4) + e3' (M3 - M5)
-// M1 = F(W0), M2 = dF/dt (Euler), M3 = rho0 <u psi (a_n u + a_t v)>_0,
-// M4 = rho_l <u psi>_{l,u>0} + rho_r <u psi>_{r,u<0}, M5 the slope part of
-// M4.  FULL = false computes only what the second stage needs (Ft, Wtt).
+// and (FULL) the non-equilibrium remainders e^{-t/tau}[-W0 - t W_t + S_lr - t S_alr]
+// at t = dt/2 (Nh) and t = dt (Nf).  M1 = F(W0), the Euler flux.
 template <int NC, bool FULL>
-CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, double dt,
-                                          PointOut<NC>& out) {
-  const double pl = pressure<NC>(in.Wl, g.gamma), pr = pressure<NC>(in.Wr, g.gamma);
-  const double tau = g.tau_eps * dt + g.tau_C * fabs((pl - pr) / (pl + pr)) * dt;
-
-  double M4[NC], D35[NC], Slr[NC], Salr[NC];
-#pragma unroll
-  for (int k = 0; k < NC; ++k) { M4[k] = 0.0; D35[k] = 0.0; Slr[k] = 0.0; Salr[k] = 0.0; }
-  CGKS_PHASE();
-
-  // the two nonlinear (non-equilibrium) sides
-#pragma unroll 1
-  for (int side = 0; side < 2; ++side) {
-    const double* Ws = side == 0 ? in.Wl : in.Wr;
-    Mom<NC> m;
-    moments<NC>(Ws, g, side == 0 ? +1 : -1, m);
-    // the slope system uses only (U, V, lambda) of the side's Maxwellian
-    double bn[NC], an[NC], at[NC], t1[NC], t2[NC];
-    const double ir = 1.0 / m.rho;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) bn[k] = in.Wn[k] * ir;
-    slope<NC>(m, g, bn, an);
-    if constexpr (NC == 4) {
-#pragma unroll
-      for (int k = 0; k < NC; ++k) bn[k] = in.Wt[k] * ir;
-      slope<NC>(m, g, bn, at);
-    }
-    mom_psi<NC>(m, 1, 0, t1);                   // <u psi>
-#pragma unroll
-    for (int k = 0; k < NC; ++k) M4[k] += m.rho * t1[k];
-    mom_psi_a<NC>(m, 2, 0, an, t1);             // <u^2 psi a_n>
-    if constexpr (NC == 4) {
-      mom_psi_a<NC>(m, 1, 1, at, t2);           // <u v psi a_t>
-#pragma unroll
-      for (int k = 0; k < NC; ++k) t1[k] += t2[k];
-    }
-#pragma unroll
-    for (int k = 0; k < NC; ++k) D35[k] -= m.rho * t1[k];
-    if constexpr (FULL) {
-      mom_psi<NC>(m, 0, 0, t1);                 // <psi>
-#pragma unroll
-      for (int k = 0; k < NC; ++k) Slr[k] += m.rho * t1[k];
-      mom_psi_a<NC>(m, 1, 0, an, t1);           // <u psi a_n>
-      if constexpr (NC == 4) {
-        mom_psi_a<NC>(m, 0, 1, at, t2);         // <v psi a_t>
-#pragma unroll
-        for (int k = 0; k < NC; ++k) t1[k] += t2[k];
-      }
-#pragma unroll
-      for (int k = 0; k < NC; ++k) Salr[k] += m.rho * t1[k];
-    }
-    CGKS_PHASE();
-  }
-
-  // equilibrium state from the linear reconstruction; kinetic collision state
-  // of the two sides if it is not admissible
-  double W0[NC];
-#pragma unroll
-  for (int k = 0; k < NC; ++k) W0[k] = in.W0[k];
-  out.guard = 0;
-  if (!admissible<NC>(W0, g.gamma)) {
-    if constexpr (!FULL) {
-      Mom<NC> ml, mr;
-      double t1[NC];
-      moments<NC>(in.Wl, g, +1, ml);
-      moments<NC>(in.Wr, g, -1, mr);
-      mom_psi<NC>(ml, 0, 0, t1);
-#pragma unroll
-      for (int k = 0; k < NC; ++k) Slr[k] = ml.rho * t1[k];
-      mom_psi<NC>(mr, 0, 0, t1);
-#pragma unroll
-      for (int k = 0; k < NC; ++k) Slr[k] += mr.rho * t1[k];
-    }
-#pragma unroll
-    for (int k = 0; k < NC; ++k) W0[k] = Slr[k];
-    out.guard = 1;
-  }
-
-  {  // M3: slope part of the equilibrium
-    Mom<NC> m;
-    moments<NC>(W0, g, 0, m);
-    double bn[NC], an[NC], at[NC], t1[NC], t2[NC];
-    const double ir = 1.0 / m.rho;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) bn[k] = in.Wn[k] * ir;
-    slope<NC>(m, g, bn, an);
-    mom_psi_a<NC>(m, 2, 0, an, t1);
-    if constexpr (NC == 4) {
-#pragma unroll
-      for (int k = 0; k < NC; ++k) bn[k] = in.Wt[k] * ir;
-      slope<NC>(m, g, bn, at);
-      mom_psi_a<NC>(m, 1, 1, at, t2);
-#pragma unroll
-      for (int k = 0; k < NC; ++k) t1[k] += t2[k];
-    }
-#pragma unroll
-    for (int k = 0; k < NC; ++k) D35[k] += m.rho * t1[k];   // D35 = M3 - M5
-  }
-  CGKS_PHASE();
-
-  // Euler derivatives at the point (2D form)
-  CK ck;
-  {
-    double W4[4], x4[4], y4[4], xx4[4], xy4[4], yy4[4];
-    if constexpr (NC == 4) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        W4[k] = W0[k]; x4[k] = in.Wn[k]; y4[k] = in.Wt[k];
-        xx4[k] = in.Wnn[k]; xy4[k] = in.Wnt[k]; yy4[k] = in.Wtt[k];
-      }
-    } else {
-      W4[0] = W0[0]; W4[1] = W0[1]; W4[2] = 0.0; W4[3] = W0[2];
-      x4[0] = in.Wn[0]; x4[1] = in.Wn[1]; x4[2] = 0.0; x4[3] = in.Wn[2];
-      xx4[0] = in.Wnn[0]; xx4[1] = in.Wnn[1]; xx4[2] = 0.0; xx4[3] = in.Wnn[2];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) { y4[k] = 0.0; xy4[k] = 0.0; yy4[k] = 0.0; }
-    }
-    euler_ck(g.gamma, W4, x4, y4, xx4, xy4, yy4, ck);
-  }
-  CGKS_PHASE();
-  auto from4 = [&](const double* v4, double* v) {
-    if constexpr (NC == 4) { v[0] = v4[0]; v[1] = v4[1]; v[2] = v4[2]; v[3] = v4[3]; }
-    else { v[0] = v4[0]; v[1] = v4[1]; v[2] = v4[3]; }
-  };
-  double M2[NC];
-  from4(ck.Ft, M2);
-  from4(ck.Wtt, out.Wtt);
-
-  // M1 = Euler flux of W0
+CGKS_HD __forceinline__ void combine(const double* W0, const double* M2, const SideSums<NC>& sd, double tau,
+                                     double dt, const Gas& g, PointOut<NC>& out) {
   double M1[NC];
   {
     const double ir = 1.0 / W0[0];
@@ -501,31 +511,54 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
     if constexpr (NC == 4) M1[2] = W0[2] * U;
     M1[NC - 1] = (W0[NC - 1] + p) * U;
   }
-
-  // time coefficients of the extraction (Eh = e^{-dt/(2 tau)}, E = Eh^2)
   const double Eh = exp(-0.5 * dt / tau);
   const double omh = 1.0 - Eh;
   const double idt = 1.0 / dt;
   const double e1p = 4.0 * tau * omh * omh * idt * idt;
   const double e3p = 4.0 * tau * omh * (dt * Eh - tau * omh) * idt * idt;
 #pragma unroll
-  for (int k = 0; k < NC; ++k) out.Ft[k] = M2[k] + e1p * (M1[k] - M4[k]) + e3p * D35[k];
+  for (int k = 0; k < NC; ++k) out.Ft[k] = M2[k] + e1p * (M1[k] - sd.M4[k]) + e3p * sd.D35[k];
   if constexpr (FULL) {
     const double e4 = tau * omh * (3.0 - Eh) * idt;
     const double e3 = (tau * tau * omh * (3.0 - Eh) - tau * dt * Eh * (2.0 - Eh)) * idt;
     const double E = Eh * Eh;
-    from4(ck.Wt, out.Wt);
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      out.F[k] = M1[k] + e4 * (M4[k] - M1[k]) + e3 * D35[k];
-      // non-equilibrium remainder e^{-t/tau} [ -W0 - t W_t + S_lr - t S_alr ]
-      const double base = Slr[k] - W0[k];
-      const double slp = out.Wt[k] + Salr[k];
+      out.F[k] = M1[k] + e4 * (sd.M4[k] - M1[k]) + e3 * sd.D35[k];
+      const double base = sd.Slr[k] - W0[k];
+      const double slp = out.Wt[k] + sd.Salr[k];
       out.Nh[k] = Eh * (base - 0.5 * dt * slp);
       out.Nf[k] = E * (base - dt * slp);
       out.W0[k] = W0[k];
     }
   }
+}
+
+// The interface evolution at one point (eq. 3rd-simplify-flux, second-order
+// part for the flux): numerical collision time in exp(-t/tau) only, physical
+// collision time zero for the Euler equations.  The phases above in order;
+// FULL = false computes only what the second stage needs (Ft, Wtt).
+template <int NC, bool FULL>
+CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, double dt, PointOut<NC>& out) {
+  // equilibrium from the linear reconstruction; the kinetic collision state
+  // of the two sides if it is not admissible
+  double W0[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) W0[k] = in.W0[k];
+  out.guard = 0;
+  if (!admissible<NC>(W0, g.gamma)) {
+    collision_state<NC>(in.Wl, in.Wr, g, W0);
+    out.guard = 1;
+  }
+  double M2[NC];
+  ck_terms<NC>(g.gamma, W0, in.Wn, in.Wt, in.Wnn, in.Wnt, in.Wtt, out.Wt, out.Wtt, M2);
+  const double tau = collision_time<NC>(in.Wl, in.Wr, g, dt);
+  SideSums<NC> sd;
+  sd.zero();
+  side_terms<NC, FULL>(in.Wl, +1, in.Wn, in.Wt, g, sd);
+  side_terms<NC, FULL>(in.Wr, -1, in.Wn, in.Wt, g, sd);
+  equilibrium_terms<NC>(W0, in.Wn, in.Wt, g, sd.D35);   // D35 = M3 - M5
+  combine<NC, FULL>(W0, M2, sd, tau, dt, g, out);
 }
 
 // ----------------------------------------------------------------------------
@@ -537,38 +570,53 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
 // segment's reference (the middle line) before the quartic; hn, ht are the
 // normal and tangential cell widths.
 // ----------------------------------------------------------------------------
+// Offsets that move the value-type quantities of line l to the middle line's
+// reference: off[l] = ref(l) - ref(2); returns ref(2).
+template <class Get>
+CGKS_HD __forceinline__ double tang_offsets(Get get, int k, double* off) {
+  const double rj = get(20 + k, 2);
+#pragma unroll
+  for (int l = 0; l < 5; ++l) off[l] = get(20 + k, l) - rj;
+  return rj;
+}
+
+// sum_l c[l] (get(q, l) + off[l]) (value-type quantity, off from tang_offsets)
+template <class Get>
+CGKS_HD __forceinline__ double tang_value(Get get, const double* c, int q, const double* off) {
+  double s = 0;
+#pragma unroll
+  for (int l = 0; l < 5; ++l) s += c[l] * (get(q, l) + off[l]);
+  return s;
+}
+
+// sum_l c[l] get(q, l) (derivative-type quantity, no reference shift)
+template <class Get>
+CGKS_HD __forceinline__ double tang_deriv(Get get, const double* c, int q) {
+  double s = 0;
+#pragma unroll
+  for (int l = 0; l < 5; ++l) s += c[l] * get(q, l);
+  return s;
+}
+
 template <class Get>
 CGKS_HD __forceinline__ void tangential_point(Get get, const TangW& w, double hn, double ht,
                                               PointIn<4>& in, double* dev, double* ref) {
   const double inv_ht = 1.0 / ht, inv_hn = 1.0 / hn;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const double rj = get(20 + k, 2);
-    double v = 0, vt = 0, vtt = 0, n = 0, nt = 0, n2 = 0, wl = 0, wr = 0;
-#pragma unroll
-    for (int l = 0; l < 5; ++l) {
-      const double off = get(20 + k, l) - rj;
-      const double vl = get(k, l) + off;
-      const double vnl = get(4 + k, l);
-      v += w.v[l] * vl;
-      vt += w.d1[l] * vl;
-      vtt += w.d2[l] * vl;
-      n += w.v[l] * vnl;
-      nt += w.d1[l] * vnl;
-      n2 += w.v[l] * get(8 + k, l);
-      wl += w.v[l] * (get(12 + k, l) + off);
-      wr += w.v[l] * (get(16 + k, l) + off);
-    }
+    double off[5];
+    const double rj = tang_offsets(get, k, off);
+    const double v = tang_value(get, w.v, k, off);
     ref[k] = rj;
     dev[k] = v;
     in.W0[k] = rj + v;
-    in.Wn[k] = n * inv_hn;
-    in.Wnn[k] = n2 * inv_hn * inv_hn;
-    in.Wt[k] = vt * inv_ht;
-    in.Wnt[k] = nt * inv_hn * inv_ht;
-    in.Wtt[k] = vtt * inv_ht * inv_ht;
-    in.Wl[k] = rj + wl;
-    in.Wr[k] = rj + wr;
+    in.Wn[k] = tang_deriv(get, w.v, 4 + k) * inv_hn;
+    in.Wnn[k] = tang_deriv(get, w.v, 8 + k) * inv_hn * inv_hn;
+    in.Wt[k] = tang_value(get, w.d1, k, off) * inv_ht;
+    in.Wnt[k] = tang_deriv(get, w.d1, 4 + k) * inv_hn * inv_ht;
+    in.Wtt[k] = tang_value(get, w.d2, k, off) * inv_ht * inv_ht;
+    in.Wl[k] = rj + tang_value(get, w.v, 12 + k, off);
+    in.Wr[k] = rj + tang_value(get, w.v, 16 + k, off);
   }
 }
 
@@ -592,6 +640,136 @@ CGKS_HD __forceinline__ void face_accumulate(double* acc, const PointOut<NC>& o,
       acc[NC + k] += 0.5 * o.Wtt[k];
     }
   }
+}
+
+// One Gauss point of a 2D face segment, evaluated phase by phase so that few
+// values are live at a time: every tangential quantity is evaluated from the
+// line data right before the phase that first needs it (the reference/deviation
+// pair of the final state is re-read at the end).  get(q, l) as for
+// tangential_point, with the weights w; sgn = -1 when get presents the lines
+// in reverse order (the other Gauss point: same value and second-derivative
+// weights mirrored, first-derivative weights mirrored with opposite sign).
+// right(k): average of the cell right of the face (fallback of an inadmissible
+// right WENO state; the left one falls back to the reference cell).
+// DIR 1 (y faces) rotates the momenta so that the normal one comes first.
+// acc receives this point's half of the Gauss average (face_accumulate from
+// zero); guard / nbad count the equilibrium and WENO fallbacks.
+template <int DIR, bool FULL, class Get, class Right>
+CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, double sgn, double hn, double ht,
+                                        const Gas& gas, double dt, double* acc, int& guard, int& nbad) {
+  const double inv_hn = 1.0 / hn, inv_ht = sgn / ht;
+  auto rot = [](double* v) {
+    if (DIR == 1) { const double t = v[1]; v[1] = v[2]; v[2] = t; }
+  };
+
+  // nonlinear states (inadmissible ones fall back to the adjacent cell
+  // averages) and the linear equilibrium state (the kinetic collision state
+  // of the two sides if it is inadmissible)
+  double Wl[4], Wr[4], W0[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double off[5];
+    const double rj = tang_offsets(get, k, off);
+    Wl[k] = rj + tang_value(get, w.v, 12 + k, off);
+    Wr[k] = rj + tang_value(get, w.v, 16 + k, off);
+    W0[k] = rj + tang_value(get, w.v, k, off);
+    CGKS_PIN(Wl[k]);
+    CGKS_PIN(Wr[k]);
+    CGKS_PIN(W0[k]);
+    CGKS_BREAK();
+  }
+  nbad = 0;
+  if (!admissible<4>(Wl, gas.gamma)) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Wl[k] = get(20 + k, 2);
+    ++nbad;
+  }
+  if (!admissible<4>(Wr, gas.gamma)) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Wr[k] = right(k);
+    ++nbad;
+  }
+  rot(Wl);
+  rot(Wr);
+  rot(W0);
+  guard = 0;
+  if (!admissible<4>(W0, gas.gamma)) {
+    collision_state<4>(Wl, Wr, gas, W0);
+    guard = 1;
+  }
+  const double tau = collision_time<4>(Wl, Wr, gas, dt);
+
+  // normal and tangential first derivatives
+  double Wn[4], Wt[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double off[5];
+    tang_offsets(get, k, off);
+    Wn[k] = tang_deriv(get, w.v, 4 + k) * inv_hn;
+    Wt[k] = tang_value(get, w.d1, k, off) * inv_ht;
+    CGKS_PIN(Wn[k]);
+    CGKS_PIN(Wt[k]);
+    CGKS_BREAK();
+  }
+  rot(Wn);
+  rot(Wt);
+
+  // the two non-equilibrium sides
+  SideSums<4> sd;
+  sd.zero();
+  side_terms<4, FULL>(Wl, +1, Wn, Wt, gas, sd);
+  CGKS_BREAK();
+  side_terms<4, FULL>(Wr, -1, Wn, Wt, gas, sd);
+  CGKS_BREAK();
+
+  // Euler derivatives of the equilibrium
+  double Wt_o[4], Wtt_o[4], M2[4];
+  {
+    double Wnn[4], Wnt[4], Wtt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double off[5];
+      tang_offsets(get, k, off);
+      Wnn[k] = tang_deriv(get, w.v, 8 + k) * inv_hn * inv_hn;
+      Wnt[k] = tang_deriv(get, w.d1, 4 + k) * inv_hn * inv_ht;
+      Wtt[k] = tang_value(get, w.d2, k, off) * inv_ht * inv_ht;
+      CGKS_PIN(Wnn[k]);
+      CGKS_PIN(Wnt[k]);
+      CGKS_PIN(Wtt[k]);
+      CGKS_BREAK();
+    }
+    rot(Wnn);
+    rot(Wnt);
+    rot(Wtt);
+    ck_terms<4>(gas.gamma, W0, Wn, Wt, Wnn, Wnt, Wtt, Wt_o, Wtt_o, M2);
+  }
+  CGKS_BREAK();
+
+  // slope part of the equilibrium and the combination
+  equilibrium_terms<4>(W0, Wn, Wt, gas, sd.D35);
+  PointOut<4> o;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) { o.Wt[k] = Wt_o[k]; o.Wtt[k] = Wtt_o[k]; }
+  combine<4, FULL>(W0, M2, sd, tau, dt, gas, o);
+  o.guard = guard;
+  rot(o.F); rot(o.Ft); rot(o.Wt); rot(o.Wtt); rot(o.Nh); rot(o.Nf); rot(o.W0);
+  CGKS_BREAK();
+
+  // dev, ref in the grid frame, like the outputs rotated back above
+  double dev[4], ref[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double off[5];
+    ref[k] = tang_offsets(get, k, off);
+    dev[k] = tang_value(get, w.v, k, off);
+    CGKS_PIN(ref[k]);
+    CGKS_PIN(dev[k]);
+    CGKS_BREAK();
+  }
+  constexpr int NO = FULL ? 16 : 8;
+#pragma unroll
+  for (int q = 0; q < NO; ++q) acc[q] = 0.0;
+  face_accumulate<4, FULL>(acc, o, dev, ref, dt);
 }
 
 }  // namespace cgks

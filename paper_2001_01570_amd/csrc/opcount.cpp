@@ -4,13 +4,16 @@
 // double replaced by a counting scalar: additions/subtractions, multiplications
 // and divisions are counted (a fused multiply-add is a multiplication plus an
 // addition, i.e. 2 flops), square roots, exponentials and complementary error
-// functions separately.  Counting runs the same code the kernels run, on a
-// smooth representative state (no guard fires, both WENO sides evaluated).
+// functions separately.  Counting runs the device building blocks the kernels
+// run (reconstruction, tangential quartic, point evolution, Gauss average),
+// each tangential quantity once per point, on a smooth representative state
+// (no guard fires, both WENO sides evaluated).
 //
 // Units:  x- or y-face segment of one stage (4 normal reconstructions of its
 // own line, 2 Gauss points: tangential quartic, gas-kinetic evolution, Gauss
 // average) and one cell update.  The kernels' halo recomputation of stencil
-// lines is not algorithmic work and is not counted.
+// lines and the face kernels' second read of each point's reference state are
+// not algorithmic work and are not counted.
 //
 // Output: JSON on stdout.
 #include <hip/hip_runtime.h>
