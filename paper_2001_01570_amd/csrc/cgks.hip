@@ -25,14 +25,11 @@
 
 namespace cgks {
 
-constexpr int TF = 16;          // faces per tile along the normal direction
+constexpr int TF = 8;           // faces per tile along the normal direction
 constexpr int TT = 16;          // face segments per tile along the tangential direction
 constexpr int TH = TT + 4;      // tangential extent including the 2+2 halo
-constexpr int NSEG = TF * TH;   // reconstructed line segments per tile (320)
+constexpr int NSEG = TF * TH;   // reconstructed line segments per tile (160)
 constexpr int NQ = 24;          // per segment: 5 quantities x 4 components + 4 reference values
-// LDS row length: NSEG padded so that the rows of the 4 components written by
-// consecutive threads start in different banks (328 doubles = 656 dwords = 16 mod 64)
-constexpr int NSEG_PAD = 328;
 constexpr int FACE_THREADS = 2 * TF * TT;   // one thread per Gauss point of the tile's face segments
 
 // Compiler-level memory barrier between the phases of the point evaluation:
@@ -264,18 +261,19 @@ __global__ __launch_bounds__(256) void k_scan(Geom G, Bufs B) {
 
 // Face kernel of one direction.  DIR 0: x faces (normal x, tangential y);
 // DIR 1: y faces (normal y, tangential x, momenta swapped for the evolution).
-// Tile: TF faces x TT segments.  Phase 1 reconstructs TF x (TT+4) line
-// segments (each shifted by its own reference cell) into LDS; phase 2 runs one
-// face segment per thread: tangential quartic to each Gauss point, the
-// gas-kinetic evolution, and the Gauss average.
+// Tile: TF faces x TT segments, 256 threads, small enough in LDS and registers
+// for two blocks per CU (one block's reconstruction overlaps the other's point
+// evaluation).  Phase 1 reconstructs TF x (TT+4) line segments (each shifted
+// by its own reference cell) into LDS; phase 2 runs one Gauss point per
+// thread: tangential quartic, gas-kinetic evolution, Gauss average over the
+// lane pair.
 template <int DIR, int STAGE>
-__global__ __launch_bounds__(FACE_THREADS) void k_faces2(Geom G, Bufs B) {
+__global__ __launch_bounds__(FACE_THREADS, 2) void k_faces2(Geom G, Bufs B) {
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
   const double dt = sc->dt;
   const double* S = STAGE == 1 ? B.S[sc->cur] : B.Ws;
-  __shared__ double lds[NQ][NSEG_PAD];
-  __shared__ double cells[8][TH * TH + 4];
+  __shared__ double lds[NQ][NSEG];
 
   const int nn = DIR == 0 ? G.nx : G.ny;     // cells along the normal
   const int nt = DIR == 0 ? G.ny : G.nx;     // cells along the tangential
@@ -285,94 +283,86 @@ __global__ __launch_bounds__(FACE_THREADS) void k_faces2(Geom G, Bufs B) {
   const int f0 = (DIR == 0 ? blockIdx.x : blockIdx.y) * TF;
   const int t0 = (DIR == 0 ? blockIdx.y : blockIdx.x) * TT;
 
-  // phase 0: the tile's cells (TH x TH, halo 2 on every side) into LDS: W and
-  // the gradient along the normal, one (cell, component) pair per item;
-  // tiles away from the boundary skip the boundary rules
+  // phase 1: line segments (face f, tangential index tt), one (component,
+  // segment) pair per item, component-major so that consecutive threads read
+  // consecutive cells along x.  The 4 stencil cells f-2..f+1 of a line come
+  // straight from memory (each cell serves 4 lines: cache hits); tiles away
+  // from the boundary skip the boundary rules, which map every index in
+  // [-2, n + 1] into the grid.
   {
     const int i0 = (DIR == 0 ? f0 : t0) - 2, j0 = (DIR == 0 ? t0 : f0) - 2;
     const bool interior = i0 >= 0 && j0 >= 0 && i0 + TH <= G.nx && j0 + TH <= G.ny;
     const size_t N = (size_t)G.nx * G.ny;
+#pragma unroll 1
+    for (int item = threadIdx.x; item < NSEG * 4; item += FACE_THREADS) {
+      const int k = item / NSEG, s = item % NSEG;
+      int fl, tl, pos;
+      if (DIR == 0) { tl = s / TF; fl = s % TF; pos = tl * TF + fl; }
+      else { fl = s / TH; tl = s % TH; pos = fl * TH + tl; }
+      const int f = f0 + fl, ta = t0 - 2 + tl;
+      if (f > nn || ta > nt + 1) continue;
+      double w[4], gd[4];
 #pragma unroll
-    for (int n = 0; n < (TH * TH * 4 + FACE_THREADS - 1) / FACE_THREADS; ++n) {
-      const int item = threadIdx.x + FACE_THREADS * n;
-      if (item < TH * TH * 4) {
-        const int k = item / (TH * TH), c = item % (TH * TH);
-        const int i = i0 + c % TH, j = j0 + c / TH;
-        double w = 0.0, gd = 0.0;
-        // no stencil reaches beyond index n + 1 (last face n, tangential halo 2);
-        // the boundary rules map every index in [-2, n + 1] into the grid
-        if (i > G.nx + 1 || j > G.ny + 1) {
-          // not used by any face of this tile
-        } else if (interior) {
+      for (int m = 0; m < 4; ++m) {
+        const int i = DIR == 0 ? f - 2 + m : ta, j = DIR == 0 ? ta : f - 2 + m;
+        if (interior) {
           const size_t id = (size_t)j * G.nx + i;
-          w = S[k * N + id];
-          gd = S[(4 + 4 * DIR + k) * N + id];
+          w[m] = S[k * N + id];
+          gd[m] = S[(4 + 4 * DIR + k) * N + id];
         } else {
-          load_comp(S, G, i, j, DIR, k, w, gd);
+          load_comp(S, G, i, j, DIR, k, w[m], gd[m]);
         }
-        cells[k][c] = w;
-        cells[4 + k][c] = hn * gd;
       }
+      const double ref = w[1];
+      const Line5 L = normal_line(w[0] - ref, w[2] - ref, w[3] - ref, hn * gd[0], hn * gd[1], hn * gd[2],
+                                  hn * gd[3], G.eps);
+      lds[0 * 4 + k][pos] = L.v;
+      lds[1 * 4 + k][pos] = L.vn;
+      lds[2 * 4 + k][pos] = L.vnn;
+      lds[3 * 4 + k][pos] = L.wl;
+      lds[4 * 4 + k][pos] = L.wr;
+      lds[20 + k][pos] = ref;
     }
   }
   __syncthreads();
 
-  // phase 1: line segments (face f, tangential index tt), one component per item
-  for (int item = threadIdx.x; item < NSEG * 4; item += blockDim.x) {
-    const int s = item >> 2, k = item & 3;
-    int fl, tl, pos;
-    if (DIR == 0) { tl = s / TF; fl = s % TF; pos = tl * TF + fl; }
-    else { fl = s / TH; tl = s % TH; pos = fl * TH + tl; }
-    if (f0 + fl > nn || t0 - 2 + tl > nt + 1) continue;
-    // stencil cells f-2..f+1 of this line in the tile (column fl+m of row tl, or row fl+m of column tl)
-    auto C = [&](int q, int m) { return DIR == 0 ? cells[q][tl * TH + fl + m] : cells[q][(fl + m) * TH + tl]; };
-    const double ref = C(k, 1);
-    const Line5 L = normal_line(C(k, 0) - ref, C(k, 2) - ref, C(k, 3) - ref, C(4 + k, 0), C(4 + k, 1),
-                                C(4 + k, 2), C(4 + k, 3), G.eps);
-    lds[0 * 4 + k][pos] = L.v;
-    lds[1 * 4 + k][pos] = L.vn;
-    lds[2 * 4 + k][pos] = L.vnn;
-    lds[3 * 4 + k][pos] = L.wl;
-    lds[4 * 4 + k][pos] = L.wr;
-    lds[20 + k][pos] = ref;
-  }
-  __syncthreads();
-
-  // phase 2: one Gauss point per thread (face_point).  The second Gauss point
-  // reads the 5 stencil lines in reverse order.  y faces: the two points of a
-  // segment in adjacent lanes (their reads of a line row coincide or fall in
-  // different banks).  x faces: the two points in the two half-waves (within a
-  // half-wave, reads of lines 2 or 4 rows apart would share LDS banks); a
-  // half-wave covers 2 rows of 16 faces.
+  // phase 2: one Gauss point per thread (face_point); the second point reads
+  // the 5 stencil lines in reverse order.  y faces: the two points of a segment
+  // in adjacent lanes (their reads of a line row coincide or fall in different
+  // banks), a half-wave covers 16 segments along x.  x faces: the two points in
+  // the two half-waves (within a half-wave, reads of lines 2 or 4 rows apart
+  // would share LDS banks), a half-wave covers 4 rows of TF faces.
   int gp, fl, tl;
   if (DIR == 0) {
     const int lane = threadIdx.x & 63;
     gp = lane >> 5;
-    fl = lane & 15;
-    tl = 2 * (threadIdx.x >> 6) + ((lane >> 4) & 1);
+    fl = lane % TF;
+    tl = (32 / TF) * (threadIdx.x >> 6) + (lane & 31) / TF;
   } else {
     gp = threadIdx.x & 1;
-    tl = (threadIdx.x >> 1) % 16;
-    fl = (threadIdx.x >> 1) / 16;
+    tl = (threadIdx.x >> 1) % TT;
+    fl = (threadIdx.x >> 1) / TT;
   }
   constexpr int PAIR = DIR == 0 ? 32 : 1;   // lane distance of the two points of a segment
   const int f = f0 + fl, tt = t0 + tl;
   if (f > nn || tt >= nt) return;
-  const int lstride = DIR == 0 ? TF : 1;                          // next stencil line in LDS
+  const int lstride = DIR == 0 ? TF : 1;    // next stencil line in LDS
   const int lfirst = (DIR == 0 ? tl * TF + fl : fl * TH + tl) + (gp ? 4 * lstride : 0);
   const int lstep = gp ? -lstride : lstride;
   auto get = [&](int q, int l) { return lds[q][lfirst + lstep * l]; };
-  // the cell right of the face (phase 0 loaded it with its boundary rule)
-  const int rc = DIR == 0 ? (tl + 2) * TH + fl + 2 : (fl + 2) * TH + tl + 2;
-  auto right_cell = [&](int k) { return cells[k][rc]; };
+  auto right_cell = [&](int k) {            // the cell right of the face, boundary rule applied
+    double W[4];
+    if (DIR == 0) load_avg<4>(S, G, f, tt, W); else load_avg<4>(S, G, tt, f, W);
+    return W[k];
+  };
   constexpr int NO = STAGE == 1 ? 16 : 8;
   double acc[NO];
   int guard, nbad;
   face_point<DIR, STAGE == 1>(get, right_cell, kTang[0], gp ? -1.0 : 1.0, hn, ht, G.gas, dt, acc, guard, nbad);
-
-  // Gauss average over the two lanes of the segment; the first point's lane writes
   if (guard) atomicAdd(&sc->guard_w0, 1ull);
   if (nbad) atomicAdd(&sc->guard_weno, (unsigned long long)nbad);
+
+  // Gauss average over the two lanes of the segment; the first point's lane writes
 #pragma unroll
   for (int q = 0; q < NO; ++q) acc[q] += __shfl_xor(acc[q], PAIR, 64);
   if (gp) return;
