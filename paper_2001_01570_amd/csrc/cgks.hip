@@ -31,6 +31,12 @@ constexpr int TH = TT + 4;      // tangential extent including the 2+2 halo
 constexpr int NSEG = TF * TH;   // reconstructed line segments per tile (160)
 constexpr int NQ = 24;          // per segment: 5 quantities x 4 components + 4 reference values
 constexpr int FACE_THREADS = 2 * TF * TT;   // one thread per Gauss point of the tile's face segments
+// waves per SIMD the face kernels are compiled for (register budget 512 / waves:
+// 168 at 3; the latency of the point evaluation needs the occupancy more than
+// stage 1 needs its last few registers)
+#ifndef FACE_WAVES
+#define FACE_WAVES(stage) 3
+#endif
 
 // Compiler-level memory barrier between the phases of the point evaluation:
 // LDS values are re-read in each phase instead of being held in registers.
@@ -38,6 +44,7 @@ constexpr int FACE_THREADS = 2 * TF * TT;   // one thread per Gauss point of the
 struct Geom {
   int dim, nx, ny;
   double dx, dy, eps;
+  double inv_dx, inv_dy;
   int bc[4];
   double inflow[4][4];   // conservative inflow state per side
   Gas gas;
@@ -268,7 +275,7 @@ __global__ __launch_bounds__(256) void k_scan(Geom G, Bufs B) {
 // thread: tangential quartic, gas-kinetic evolution, Gauss average over the
 // lane pair.
 template <int DIR, int STAGE>
-__global__ __launch_bounds__(FACE_THREADS, 2) void k_faces2(Geom G, Bufs B) {
+__global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom G, Bufs B) {
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
   const double dt = sc->dt;
@@ -358,7 +365,8 @@ __global__ __launch_bounds__(FACE_THREADS, 2) void k_faces2(Geom G, Bufs B) {
   constexpr int NO = STAGE == 1 ? 16 : 8;
   double acc[NO];
   int guard, nbad;
-  face_point<DIR, STAGE == 1>(get, right_cell, kTang[0], gp ? -1.0 : 1.0, hn, ht, G.gas, dt, acc, guard, nbad);
+  const double inv_hn = DIR == 0 ? G.inv_dx : G.inv_dy, inv_ht = DIR == 0 ? G.inv_dy : G.inv_dx;
+  face_point<DIR, STAGE == 1>(get, right_cell, kTang[0], inv_hn, gp ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad);
   if (guard) atomicAdd(&sc->guard_w0, 1ull);
   if (nbad) atomicAdd(&sc->guard_weno, (unsigned long long)nbad);
 
@@ -655,11 +663,10 @@ extern "C" int cgks_create(const cgks_config* cfg, void* hip_stream, cgks_ctx** 
   G.ny = c->cfg.ny;
   G.dx = (cfg->x1 - cfg->x0) / cfg->nx;
   G.dy = cfg->dim == 2 ? (cfg->y1 - cfg->y0) / cfg->ny : 1.0;
+  G.inv_dx = 1.0 / G.dx;
+  G.inv_dy = 1.0 / G.dy;
   G.eps = cfg->weno_eps;
-  G.gas.gamma = cfg->gamma;
-  G.gas.K = 2.0 / (cfg->gamma - 1.0) - cfg->dim;
-  G.gas.tau_eps = cfg->tau_eps;
-  G.gas.tau_C = cfg->tau_C;
+  G.gas = make_gas(cfg->gamma, cfg->dim, cfg->tau_eps, cfg->tau_C);
   for (int s = 0; s < 4; ++s) {
     G.bc[s] = s < 2 * cfg->dim ? cfg->bc[s] : CGKS_PERIODIC;
     const double* q = cfg->inflow_prim[s];

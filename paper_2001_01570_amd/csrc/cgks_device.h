@@ -35,6 +35,21 @@
 
 namespace cgks {
 
+// Reciprocal: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r) (each step squares the relative error), within about an
+// ulp of 1/x for finite nonzero x.  The host build divides.
+CGKS_HD __forceinline__ double recip(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
 // ----------------------------------------------------------------------------
 // compact reconstruction on one line, one component (scaled cell width h = 1)
 // inputs (shifted by Q_i): a = Q_{i-1}-Q_i, c = Q_{i+1}-Q_i, d = Q_{i+2}-Q_i,
@@ -107,16 +122,16 @@ CGKS_HD __forceinline__ double weno_left(double a, double c, double d, double A,
   const double b6 = t * t + S2 * u * u + S3 * k3 * k3 + S4 * k4 * k4;
   // WENO-Z weights with the reference value of eq. (tau)
   const double z = fabs(3.0 * (b0 - b4) + (b4 - b3));
-  const double a0 = (3.0 / 98.0) * (1.0 + z / (b0 + eps));
-  const double a1 = (5.0 / 98.0) * (1.0 + z / (b1 + eps));
-  const double a2 = (4.0 / 49.0) * (1.0 + z / (b2 + eps));
-  const double a3 = (7.0 / 98.0) * (1.0 + z / (b3 + eps));
-  const double a4 = (7.0 / 98.0) * (1.0 + z / (b4 + eps));
-  const double a5 = (17.0 / 49.0) * (1.0 + z / (b5 + eps));
-  const double a6 = (17.0 / 49.0) * (1.0 + z / (b6 + eps));
+  const double a0 = (3.0 / 98.0) * (1.0 + z * recip(b0 + eps));
+  const double a1 = (5.0 / 98.0) * (1.0 + z * recip(b1 + eps));
+  const double a2 = (4.0 / 49.0) * (1.0 + z * recip(b2 + eps));
+  const double a3 = (7.0 / 98.0) * (1.0 + z * recip(b3 + eps));
+  const double a4 = (7.0 / 98.0) * (1.0 + z * recip(b4 + eps));
+  const double a5 = (17.0 / 49.0) * (1.0 + z * recip(b5 + eps));
+  const double a6 = (17.0 / 49.0) * (1.0 + z * recip(b6 + eps));
   const double num = a0 * q0 + (a1 + a3) * q1 + a2 * q2 + a4 * q4 + a5 * q5 + a6 * q6;
   const double den = a0 + a1 + a2 + a3 + a4 + a5 + a6;
-  return num / den;
+  return num * recip(den);
 }
 
 // Full normal reconstruction of one component on one line.  Q[0..3] are the
@@ -160,13 +175,28 @@ template <int NC> struct Vec { double c[NC]; };
 struct Gas {
   double gamma, K;     // K: internal degrees of freedom (K + dim = 2/(gamma-1))
   double tau_eps, tau_C;
+  double inv_g1;       // 1/(gamma - 1)
+  double inv_KD;       // 1/(K + dim)
 };
+
+// Gas constants of a problem of dimension dim.
+CGKS_HD inline Gas make_gas(double gamma, int dim, double tau_eps, double tau_C) {
+  Gas g;
+  g.gamma = gamma;
+  g.K = 2.0 / (gamma - 1.0) - dim;
+  g.tau_eps = tau_eps;
+  g.tau_C = tau_C;
+  g.inv_g1 = 1.0 / (gamma - 1.0);
+  g.inv_KD = 1.0 / (g.K + dim);
+  return g;
+}
 
 // Moments of a (half-)Maxwellian normalised by rho: mu[n] = <u^n> n<=6,
 // mv[m] = <v^m> m<=5 (2D), x1 = <xi^2>, x2 = <xi^4>.
 template <int NC>
 struct Mom {
   double rho, U, V, lam;
+  double ir, h;         // 1/rho, 1/(2 lambda) = p/rho
   double mu[7];
   double mv[6];
   double x1, x2;
@@ -174,7 +204,7 @@ struct Mom {
 
 template <int NC>
 CGKS_HD __forceinline__ double pressure(const double* W, double gamma) {
-  const double ir = 1.0 / W[0];
+  const double ir = recip(W[0]);
   double ke = W[1] * W[1];
   if constexpr (NC == 4) ke += W[2] * W[2];
   return (gamma - 1.0) * (W[NC - 1] - 0.5 * ke * ir);
@@ -191,12 +221,14 @@ CGKS_HD __forceinline__ bool admissible(const double* W, double gamma) {
 template <int NC>
 CGKS_HD __forceinline__ void moments(const double* W, const Gas& g, int half, Mom<NC>& m) {
   m.rho = W[0];
-  const double ir = 1.0 / W[0];
+  const double ir = recip(W[0]);
+  m.ir = ir;
   m.U = W[1] * ir;
   m.V = (NC == 4) ? W[2] * ir : 0.0;
   const double p = pressure<NC>(W, g.gamma);
-  m.lam = 0.5 * m.rho / p;
-  const double h = 0.5 / m.lam;   // 1/(2 lambda) = p/rho
+  m.lam = 0.5 * m.rho * recip(p);
+  const double h = p * ir;        // 1/(2 lambda)
+  m.h = h;
   if (half == 0) {
     m.mu[0] = 1.0;
     m.mu[1] = m.U;
@@ -204,7 +236,8 @@ CGKS_HD __forceinline__ void moments(const double* W, const Gas& g, int half, Mo
     const double s = (double)half;
     const double sl = sqrt(m.lam);
     m.mu[0] = 0.5 * erfc(-s * sl * m.U);
-    m.mu[1] = m.U * m.mu[0] + s * exp(-m.lam * m.U * m.U) * (0.5 * 0.56418958354775628695 / sl);
+    // 1/sqrt(lambda) = 2 h sqrt(lambda)
+    m.mu[1] = m.U * m.mu[0] + s * exp(-m.lam * m.U * m.U) * (0.56418958354775628695 * h * sl);
   }
 #pragma unroll
   for (int n = 1; n < 6; ++n) m.mu[n + 1] = m.U * m.mu[n] + (double)n * h * m.mu[n - 1];
@@ -224,18 +257,18 @@ template <int NC>
 CGKS_HD __forceinline__ void slope(const Mom<NC>& m, const Gas& g, const double* b, double* a) {
   const double KD = g.K + (NC == 4 ? 2.0 : 1.0);   // = 2/(gamma-1)
   const double U = m.U, V = m.V, lam = m.lam;
-  double q = U * U + KD / (2.0 * lam);
+  double q = U * U + KD * m.h;
   if constexpr (NC == 4) q += V * V;
   const double Re = 2.0 * b[NC - 1] - q * b[0];
   const double Ru = b[1] - U * b[0];
   if constexpr (NC == 4) {
     const double Rv = b[2] - V * b[0];
-    a[3] = 4.0 * lam * lam * (Re - 2.0 * U * Ru - 2.0 * V * Rv) / KD;
+    a[3] = 4.0 * lam * lam * (Re - 2.0 * U * Ru - 2.0 * V * Rv) * g.inv_KD;
     a[2] = 2.0 * lam * Rv - V * a[3];
     a[1] = 2.0 * lam * Ru - U * a[3];
     a[0] = b[0] - U * a[1] - V * a[2] - 0.5 * a[3] * q;
   } else {
-    a[2] = 4.0 * lam * lam * (Re - 2.0 * U * Ru) / KD;
+    a[2] = 4.0 * lam * lam * (Re - 2.0 * U * Ru) * g.inv_KD;
     a[1] = 2.0 * lam * Ru - U * a[2];
     a[0] = b[0] - U * a[1] - 0.5 * a[2] * q;
   }
@@ -287,10 +320,11 @@ struct CK {
   double Wt[4], Wtt[4], Ft[4];
 };
 
-CGKS_HD __forceinline__ void euler_ck(double gamma, const double* W, const double* Wx, const double* Wy,
+CGKS_HD __forceinline__ void euler_ck(const Gas& gas, const double* W, const double* Wx, const double* Wy,
                                          const double* Wxx, const double* Wxy, const double* Wyy, CK& o) {
+  const double gamma = gas.gamma;
   const double g1 = gamma - 1.0;
-  const double r = W[0], ir = 1.0 / r;
+  const double r = W[0], ir = recip(r);
   const double U = W[1] * ir, V = W[2] * ir;
   const double q2 = U * U + V * V;
   const double p = g1 * (W[3] - 0.5 * r * q2);
@@ -335,7 +369,7 @@ CGKS_HD __forceinline__ void euler_ck(double gamma, const double* W, const doubl
   const double Vtt = -(Ut * Vx + U * Vtx + Vt * Vy + V * Vty + pty * ir - py * rt * ir2);
   const double ptt = -(Ut * px + U * ptx + Vt * py + V * pty + gamma * pt * dv + gamma * p * dvt);
   const double E = W[3];
-  const double Et = pt / g1 + 0.5 * rt * q2 + r * (U * Ut + V * Vt);
+  const double Et = pt * gas.inv_g1 + 0.5 * rt * q2 + r * (U * Ut + V * Vt);
   o.Wt[0] = rt;
   o.Wt[1] = rt * U + r * Ut;
   o.Wt[2] = rt * V + r * Vt;
@@ -343,7 +377,7 @@ CGKS_HD __forceinline__ void euler_ck(double gamma, const double* W, const doubl
   o.Wtt[0] = rtt;
   o.Wtt[1] = rtt * U + 2.0 * rt * Ut + r * Utt;
   o.Wtt[2] = rtt * V + 2.0 * rt * Vt + r * Vtt;
-  o.Wtt[3] = ptt / g1 + 0.5 * rtt * q2 + 2.0 * rt * (U * Ut + V * Vt) + r * (Ut * Ut + Vt * Vt) + r * (U * Utt + V * Vtt);
+  o.Wtt[3] = ptt * gas.inv_g1 + 0.5 * rtt * q2 + 2.0 * rt * (U * Ut + V * Vt) + r * (Ut * Ut + Vt * Vt) + r * (U * Utt + V * Vtt);
   // d/dt of the x flux (rhoU, rhoU^2 + p, rhoUV, U(E + p)) along the solution
   o.Ft[0] = o.Wt[1];
   o.Ft[1] = rt * U * U + 2.0 * r * U * Ut + pt;
@@ -374,6 +408,15 @@ struct SideSums {
 #pragma unroll
     for (int k = 0; k < NC; ++k) { M4[k] = 0.0; D35[k] = 0.0; Slr[k] = 0.0; Salr[k] = 0.0; }
   }
+  template <bool FULL>
+  CGKS_HD __forceinline__ void pin() {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      CGKS_PIN(M4[k]);
+      CGKS_PIN(D35[k]);
+      if constexpr (FULL) { CGKS_PIN(Slr[k]); CGKS_PIN(Salr[k]); }
+    }
+  }
 };
 
 // Numerical collision time of Sec. 4 (inviscid): tau = eps dt + C |p_l - p_r|/(p_l + p_r) dt,
@@ -381,7 +424,7 @@ struct SideSums {
 template <int NC>
 CGKS_HD __forceinline__ double collision_time(const double* Wl, const double* Wr, const Gas& g, double dt) {
   const double pl = pressure<NC>(Wl, g.gamma), pr = pressure<NC>(Wr, g.gamma);
-  return g.tau_eps * dt + g.tau_C * fabs((pl - pr) / (pl + pr)) * dt;
+  return g.tau_eps * dt + g.tau_C * fabs((pl - pr) * recip(pl + pr)) * dt;
 }
 
 // One non-equilibrium side (half space u > 0 for side = +1, u < 0 for -1):
@@ -393,7 +436,7 @@ CGKS_HD __forceinline__ void side_terms(const double* Ws, int side, const double
   Mom<NC> m;
   moments<NC>(Ws, g, side, m);
   double bn[NC], an[NC], at[NC], t1[NC], t2[NC];
-  const double ir = 1.0 / m.rho;
+  const double ir = m.ir;
 #pragma unroll
   for (int k = 0; k < NC; ++k) bn[k] = Wn[k] * ir;
   slope<NC>(m, g, bn, an);
@@ -451,7 +494,7 @@ CGKS_HD __forceinline__ void equilibrium_terms(const double* W0, const double* W
   Mom<NC> m;
   moments<NC>(W0, g, 0, m);
   double bn[NC], an[NC], t1[NC];
-  const double ir = 1.0 / m.rho;
+  const double ir = m.ir;
 #pragma unroll
   for (int k = 0; k < NC; ++k) bn[k] = Wn[k] * ir;
   slope<NC>(m, g, bn, an);
@@ -472,12 +515,12 @@ CGKS_HD __forceinline__ void equilibrium_terms(const double* W0, const double* W
 // Exact Euler derivatives of the equilibrium at the point, in the NC layout:
 // W_t, W_tt and the flux time derivative M2 = dF/dt.
 template <int NC>
-CGKS_HD __forceinline__ void ck_terms(double gamma, const double* W0, const double* Wn, const double* Wt,
+CGKS_HD __forceinline__ void ck_terms(const Gas& gas, const double* W0, const double* Wn, const double* Wt,
                                       const double* Wnn, const double* Wnt, const double* Wtt,
                                       double* Wt_o, double* Wtt_o, double* M2) {
   CK ck;
   if constexpr (NC == 4) {
-    euler_ck(gamma, W0, Wn, Wt, Wnn, Wnt, Wtt, ck);
+    euler_ck(gas, W0, Wn, Wt, Wnn, Wnt, Wtt, ck);
 #pragma unroll
     for (int k = 0; k < 4; ++k) { Wt_o[k] = ck.Wt[k]; Wtt_o[k] = ck.Wtt[k]; M2[k] = ck.Ft[k]; }
   } else {   // 1D embedded as V = 0 without y dependence
@@ -485,7 +528,7 @@ CGKS_HD __forceinline__ void ck_terms(double gamma, const double* W0, const doub
     const double x4[4] = {Wn[0], Wn[1], 0.0, Wn[2]};
     const double xx4[4] = {Wnn[0], Wnn[1], 0.0, Wnn[2]};
     const double z4[4] = {0.0, 0.0, 0.0, 0.0};
-    euler_ck(gamma, W4, x4, z4, xx4, z4, z4, ck);
+    euler_ck(gas, W4, x4, z4, xx4, z4, z4, ck);
     Wt_o[0] = ck.Wt[0]; Wt_o[1] = ck.Wt[1]; Wt_o[2] = ck.Wt[3];
     Wtt_o[0] = ck.Wtt[0]; Wtt_o[1] = ck.Wtt[1]; Wtt_o[2] = ck.Wtt[3];
     M2[0] = ck.Ft[0]; M2[1] = ck.Ft[1]; M2[2] = ck.Ft[3];
@@ -503,7 +546,7 @@ CGKS_HD __forceinline__ void combine(const double* W0, const double* M2, const S
                                      double dt, const Gas& g, PointOut<NC>& out) {
   double M1[NC];
   {
-    const double ir = 1.0 / W0[0];
+    const double ir = recip(W0[0]);
     const double U = W0[1] * ir;
     const double p = pressure<NC>(W0, g.gamma);
     M1[0] = W0[1];
@@ -511,9 +554,9 @@ CGKS_HD __forceinline__ void combine(const double* W0, const double* M2, const S
     if constexpr (NC == 4) M1[2] = W0[2] * U;
     M1[NC - 1] = (W0[NC - 1] + p) * U;
   }
-  const double Eh = exp(-0.5 * dt / tau);
+  const double Eh = exp(-0.5 * dt * recip(tau));
   const double omh = 1.0 - Eh;
-  const double idt = 1.0 / dt;
+  const double idt = recip(dt);
   const double e1p = 4.0 * tau * omh * omh * idt * idt;
   const double e3p = 4.0 * tau * omh * (dt * Eh - tau * omh) * idt * idt;
 #pragma unroll
@@ -551,7 +594,7 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
     out.guard = 1;
   }
   double M2[NC];
-  ck_terms<NC>(g.gamma, W0, in.Wn, in.Wt, in.Wnn, in.Wnt, in.Wtt, out.Wt, out.Wtt, M2);
+  ck_terms<NC>(g, W0, in.Wn, in.Wt, in.Wnn, in.Wnt, in.Wtt, out.Wt, out.Wtt, M2);
   const double tau = collision_time<NC>(in.Wl, in.Wr, g, dt);
   SideSums<NC> sd;
   sd.zero();
@@ -646,8 +689,9 @@ CGKS_HD __forceinline__ void face_accumulate(double* acc, const PointOut<NC>& o,
 // values are live at a time: every tangential quantity is evaluated from the
 // line data right before the phase that first needs it (the reference/deviation
 // pair of the final state is re-read at the end).  get(q, l) as for
-// tangential_point, with the weights w; sgn = -1 when get presents the lines
-// in reverse order (the other Gauss point: same value and second-derivative
+// tangential_point, with the weights w; inv_hn, inv_ht: inverse normal and
+// tangential cell widths, inv_ht negated when get presents the lines in
+// reverse order (the other Gauss point: same value and second-derivative
 // weights mirrored, first-derivative weights mirrored with opposite sign).
 // right(k): average of the cell right of the face (fallback of an inadmissible
 // right WENO state; the left one falls back to the reference cell).
@@ -655,9 +699,8 @@ CGKS_HD __forceinline__ void face_accumulate(double* acc, const PointOut<NC>& o,
 // acc receives this point's half of the Gauss average (face_accumulate from
 // zero); guard / nbad count the equilibrium and WENO fallbacks.
 template <int DIR, bool FULL, class Get, class Right>
-CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, double sgn, double hn, double ht,
+CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, double inv_hn, double inv_ht,
                                         const Gas& gas, double dt, double* acc, int& guard, int& nbad) {
-  const double inv_hn = 1.0 / hn, inv_ht = sgn / ht;
   auto rot = [](double* v) {
     if (DIR == 1) { const double t = v[1]; v[1] = v[2]; v[2] = t; }
   };
@@ -697,7 +740,11 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
     collision_state<4>(Wl, Wr, gas, W0);
     guard = 1;
   }
-  const double tau = collision_time<4>(Wl, Wr, gas, dt);
+  double tau = collision_time<4>(Wl, Wr, gas, dt);
+  CGKS_PIN(tau);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) CGKS_PIN(W0[k]);
+  CGKS_BREAK();
 
   // normal and tangential first derivatives
   double Wn[4], Wt[4];
@@ -714,12 +761,15 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
   rot(Wn);
   rot(Wt);
 
-  // the two non-equilibrium sides
+  // the two non-equilibrium sides (each phase's results are pinned before its
+  // barrier so that its arithmetic stays in the phase)
   SideSums<4> sd;
   sd.zero();
   side_terms<4, FULL>(Wl, +1, Wn, Wt, gas, sd);
+  sd.pin<FULL>();
   CGKS_BREAK();
   side_terms<4, FULL>(Wr, -1, Wn, Wt, gas, sd);
+  sd.pin<FULL>();
   CGKS_BREAK();
 
   // Euler derivatives of the equilibrium
@@ -741,12 +791,21 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
     rot(Wnn);
     rot(Wnt);
     rot(Wtt);
-    ck_terms<4>(gas.gamma, W0, Wn, Wt, Wnn, Wnt, Wtt, Wt_o, Wtt_o, M2);
+    ck_terms<4>(gas, W0, Wn, Wt, Wnn, Wnt, Wtt, Wt_o, Wtt_o, M2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      CGKS_PIN(Wt_o[k]);
+      CGKS_PIN(Wtt_o[k]);
+      CGKS_PIN(M2[k]);
+    }
   }
   CGKS_BREAK();
 
   // slope part of the equilibrium and the combination
   equilibrium_terms<4>(W0, Wn, Wt, gas, sd.D35);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) CGKS_PIN(sd.D35[k]);
+  CGKS_BREAK();
   PointOut<4> o;
 #pragma unroll
   for (int k = 0; k < 4; ++k) { o.Wt[k] = Wt_o[k]; o.Wtt[k] = Wtt_o[k]; }

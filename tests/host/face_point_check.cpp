@@ -41,7 +41,7 @@ static double run(const double (&lines)[24][5], const double* right, int gp, con
   auto getm = [&](int q, int l) { return lines[q][gp ? 4 - l : l]; };
   auto rightf = [&](int k) { return right[k]; };
   double a_new[16];
-  face_point<DIR, FULL>(getm, rightf, kW[0], gp ? -1.0 : 1.0, hn, ht, gas, dt, a_new, guard_new, bad_new);
+  face_point<DIR, FULL>(getm, rightf, kW[0], 1.0 / hn, gp ? -1.0 / ht : 1.0 / ht, gas, dt, a_new, guard_new, bad_new);
   double err = 0.0;
   for (int q = 0; q < NO; ++q) {
     const double s = std::fmax(std::fabs(a_ref[q]), 1e-300);
@@ -53,8 +53,7 @@ static double run(const double (&lines)[24][5], const double* right, int gp, con
 int main() {
   std::mt19937_64 rng(12345);
   std::uniform_real_distribution<double> U(-1.0, 1.0);
-  Gas gas;
-  gas.gamma = 1.4; gas.K = 2.0 / (gas.gamma - 1.0) - 2.0; gas.tau_eps = 0.01; gas.tau_C = 1.0;
+  const Gas gas = make_gas(1.4, 2, 0.01, 1.0);
   const double hn = 1.0 / 300, ht = 1.0 / 200, dt = 1.5e-3;
   const double base[4] = {1.0, 0.35, -0.27, 2.6};
   int fails = 0;
