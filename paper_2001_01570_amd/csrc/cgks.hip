@@ -274,6 +274,20 @@ __global__ __launch_bounds__(256) void k_scan(Geom G, Bufs B) {
 // by its own reference cell) into LDS; phase 2 runs one Gauss point per
 // thread: tangential quartic, gas-kinetic evolution, Gauss average over the
 // lane pair.
+// Tile of this block when consecutive blocks go round-robin to the XCDs: each
+// XCD (its own L2) gets a contiguous run of tiles in row-major order, so the
+// stencil halos shared by neighbouring tiles are fetched into one L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+  const int n = gridDim.x * gridDim.y;
+  const int b = blockIdx.y * gridDim.x + blockIdx.x;
+  const int q = n / NXCD, r = n % NXCD;
+  const int x = b % NXCD, local = b / NXCD;
+  const int logical = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + local;
+  bx = logical % gridDim.x;
+  by = logical / gridDim.x;
+}
+
 template <int DIR, int STAGE>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom G, Bufs B) {
   Scalars* sc = B.sc;
@@ -286,9 +300,11 @@ __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom
   const int nt = DIR == 0 ? G.ny : G.nx;     // cells along the tangential
   const double hn = DIR == 0 ? G.dx : G.dy;
   const double ht = DIR == 0 ? G.dy : G.dx;
-  // DIR 0: blockIdx.x over faces, blockIdx.y over rows; DIR 1: blockIdx.x over columns, blockIdx.y over faces
-  const int f0 = (DIR == 0 ? blockIdx.x : blockIdx.y) * TF;
-  const int t0 = (DIR == 0 ? blockIdx.y : blockIdx.x) * TT;
+  // DIR 0: tiles (faces, rows); DIR 1: tiles (columns, faces), on a 2D grid of blocks
+  int bx, by;
+  xcd_tile(bx, by);
+  const int f0 = (DIR == 0 ? bx : by) * TF;
+  const int t0 = (DIR == 0 ? by : bx) * TT;
 
   // phase 1: line segments (face f, tangential index tt), one (component,
   // segment) pair per item, component-major so that consecutive threads read
