@@ -107,6 +107,50 @@ int cgks_counters(cgks_ctx *ctx, cgks_counters_t *out);
 void cgks_destroy(cgks_ctx *ctx);
 const char *cgks_strerror(int code);
 
+/* ---- Batch: many independent 2D problems advanced together (serving) ------
+ *
+ * Same scheme and kernels as a context; the requests of a serving workload
+ * are independent solves of the problem statement above.  A batch owns one
+ * device arena of hbm_budget_bytes (first-fit with coalescing) from which each
+ * admitted problem, a "slot", takes its buffers (about 130 bytes per cell:
+ * 4 x 12 fields plus the face results).  cgks_batch_run advances every running
+ * slot together: each of the 8 kernels of a step is one launch covering the
+ * blocks of all running slots, and the requested number of steps is one HIP
+ * graph, captured again only when the set of running slots or the step count
+ * changes.  A slot stops by itself at its end time or step bound; its state
+ * stays readable until it is released.  All calls are synchronous with
+ * respect to the host and not thread-safe. */
+typedef struct cgks_batch cgks_batch;
+
+enum { CGKS_SLOT_FREE = 0, CGKS_SLOT_RUNNING = 1, CGKS_SLOT_DONE = 2, CGKS_SLOT_FAILED = 3 };
+
+/* max_slots in [1, 1024].  hip_stream NULL: the batch creates its own stream;
+ * otherwise the given stream is used and must be capturable (not the legacy
+ * null stream).  CGKS_ENOMEM if the arena cannot be allocated. */
+int cgks_batch_create(size_t hbm_budget_bytes, int max_slots, void *hip_stream, cgks_batch **out);
+
+/* Admit a 2D problem (configuration and initial state as for a context; the
+ * state is copied, host or device pointer) that runs until t_end (> 0) or for
+ * max_steps (> 0) steps, whichever comes first (one of them must be given).
+ * Returns its slot.  CGKS_EBUSY: no free slot or no room in the arena;
+ * CGKS_ENONPHYS: non-physical initial state; CGKS_EINVAL: bad configuration or
+ * dim != 2.  A device pointer must be ready (its producer synchronized). */
+int cgks_batch_admit(cgks_batch *b, const cgks_config *cfg, const double *fields, int on_device,
+                     double t_end, long max_steps, int *slot);
+
+/* Advance every running slot by up to `steps` (>= 1) steps. */
+int cgks_batch_run(cgks_batch *b, int steps);
+
+/* Slot state after the last run or admit: CGKS_SLOT_*; t and step may be NULL. */
+int cgks_batch_poll(cgks_batch *b, int slot, int *state, double *t, long *step);
+
+/* Copy a slot's current state out (layout as for a context). */
+int cgks_batch_read(cgks_batch *b, int slot, double *fields_out, int on_device);
+
+/* Free a slot and return its memory to the arena. */
+int cgks_batch_release(cgks_batch *b, int slot);
+void cgks_batch_destroy(cgks_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,15 @@ def load():
     L.cgks_set_profiling.argtypes = [C.c_void_p, C.c_int]
     L.cgks_kernel_times.argtypes = [C.c_void_p, _D, C.POINTER(C.c_long), C.c_int]
     L.cgks_kernel_times.restype = C.c_int
+    L.cgks_batch_create.argtypes = [C.c_size_t, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]
+    L.cgks_batch_admit.argtypes = [C.c_void_p, C.POINTER(cgks_config), C.c_void_p, C.c_int, C.c_double, C.c_long,
+                                   C.POINTER(C.c_int)]
+    L.cgks_batch_run.argtypes = [C.c_void_p, C.c_int]
+    L.cgks_batch_poll.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), _D, C.POINTER(C.c_long)]
+    L.cgks_batch_read.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
+    L.cgks_batch_release.argtypes = [C.c_void_p, C.c_int]
+    L.cgks_batch_destroy.argtypes = [C.c_void_p]
+    L.cgks_batch_destroy.restype = None
     _lib = L
     return L
 
@@ -211,3 +220,87 @@ class Solver:
             raise CgksError(k, 'cgks_kernel_times')
         names = KERNEL_NAMES_2D if self.dim == 2 else KERNEL_NAMES_1D
         return {names[i]: (ms[i], calls[i]) for i in range(min(k, len(names)))}
+
+
+SLOT_FREE, SLOT_RUNNING, SLOT_DONE, SLOT_FAILED = 0, 1, 2, 3
+
+
+class Batch:
+    """Many independent 2D problems advanced together (see cgks_batch_* in
+    include/cgks.h).  Slots are admitted with a configuration (a Problem) and
+    an initial state and run until their end time or step bound."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, stream=None):
+        _torch()
+        L = load()
+        h = C.c_void_p()
+        ptr = None if stream is None else C.c_void_p(stream.cuda_stream)
+        rc = L.cgks_batch_create(int(hbm_budget_bytes), int(max_slots), ptr, C.byref(h))
+        if rc:
+            raise CgksError(rc, 'cgks_batch_create')
+        self.h = h
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, 'h', None):
+            load().cgks_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, prob, fields=None, t_end: float = 0.0, max_steps: int = 0) -> int:
+        """Returns the slot; raises CgksError (code CGKS_EBUSY when full)."""
+        torch = _torch()
+        fields = prob.fields if fields is None else fields
+        shape = (12, prob.ny, prob.nx) if prob.dim == 2 else (6, prob.nx)   # the library rejects dim 1
+        slot = C.c_int()
+        cfg = make_config(prob)
+        if isinstance(fields, torch.Tensor) and fields.is_cuda:
+            assert tuple(fields.shape) == shape and fields.dtype == torch.float64
+            f = fields.contiguous()
+            rc = load().cgks_batch_admit(self.h, C.byref(cfg), C.c_void_p(f.data_ptr()), 1, float(t_end),
+                                         int(max_steps), C.byref(slot))
+        else:
+            a = np.ascontiguousarray(np.asarray(fields, dtype=np.float64))
+            assert a.shape == shape, (a.shape, shape)
+            rc = load().cgks_batch_admit(self.h, C.byref(cfg), C.c_void_p(a.ctypes.data), 0, float(t_end),
+                                         int(max_steps), C.byref(slot))
+        if rc:
+            raise CgksError(rc, 'cgks_batch_admit')
+        self.shapes[slot.value] = shape
+        return slot.value
+
+    def run(self, steps: int):
+        rc = load().cgks_batch_run(self.h, int(steps))
+        if rc:
+            raise CgksError(rc, 'cgks_batch_run')
+
+    def poll(self, slot: int):
+        st, t, n = C.c_int(), C.c_double(), C.c_long()
+        rc = load().cgks_batch_poll(self.h, int(slot), C.byref(st), C.byref(t), C.byref(n))
+        if rc:
+            raise CgksError(rc, 'cgks_batch_poll')
+        return st.value, t.value, n.value
+
+    def read(self, slot: int, device: bool = False):
+        shape = self.shapes[slot]
+        if device:
+            torch = _torch()
+            out = torch.empty(shape, dtype=torch.float64, device='cuda')
+            rc = load().cgks_batch_read(self.h, int(slot), C.c_void_p(out.data_ptr()), 1)
+        else:
+            out = np.empty(shape)
+            rc = load().cgks_batch_read(self.h, int(slot), C.c_void_p(out.ctypes.data), 0)
+        if rc:
+            raise CgksError(rc, 'cgks_batch_read')
+        return out
+
+    def release(self, slot: int):
+        rc = load().cgks_batch_release(self.h, int(slot))
+        if rc:
+            raise CgksError(rc, 'cgks_batch_release')
+        self.shapes.pop(slot, None)

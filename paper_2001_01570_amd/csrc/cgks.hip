@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -53,6 +54,7 @@ struct Geom {
 struct Params {          // written by the host before a batch of steps
   double t_end;          // +inf: no end time
   double dt_override;    // > 0: use this step size
+  long long max_step;    // no step begins once the step count reaches this
 };
 
 struct Scalars {
@@ -181,7 +183,7 @@ __device__ __forceinline__ void load_avg(const double* S, const Geom& G, int i, 
 
 // Step size: the CFL maximum of the current state is the max of the per-block
 // partial maxima written by the last update (or by the scan after set_state).
-__global__ __launch_bounds__(256) void k_begin(Scalars* sc, const double* lam_part, int nparts) {
+__device__ __forceinline__ void begin_body(Scalars* sc, const double* lam_part, int nparts) {
   __shared__ double red[4];
   double lam = 0.0;
   for (int k = threadIdx.x; k < nparts; k += blockDim.x) lam = fmax(lam, lam_part[k]);
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(256) void k_begin(Scalars* sc, const double* lam_pa
   if (threadIdx.x != 0) return;
   lam = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   sc->active = 0;
-  if (sc->status != 0) return;
+  if (sc->status != 0 || sc->step >= sc->prm.max_step) return;
   const double rem = sc->prm.t_end - sc->t;
   if (!(rem > 0.0)) { sc->dt = 0.0; return; }
   double dt = sc->prm.dt_override;
@@ -205,7 +207,11 @@ __global__ __launch_bounds__(256) void k_begin(Scalars* sc, const double* lam_pa
   sc->active = 1;
 }
 
-__global__ void k_end(Scalars* sc) {
+__global__ __launch_bounds__(256) void k_begin(Scalars* sc, const double* lam_part, int nparts) {
+  begin_body(sc, lam_part, nparts);
+}
+
+__device__ __forceinline__ void end_body(Scalars* sc) {
   if (threadIdx.x != 0 || !sc->active) return;
   if (sc->status == 0) {
     sc->t = sc->last ? sc->prm.t_end : sc->t + sc->dt;
@@ -216,15 +222,16 @@ __global__ void k_end(Scalars* sc) {
   sc->active = 0;
 }
 
+__global__ void k_end(Scalars* sc) { end_body(sc); }
+
 // block maximum of the per-cell CFL rates, one partial per block (256 threads)
-__device__ __forceinline__ void reduce_lambda(double* lam_part, double lam) {
+__device__ __forceinline__ void reduce_lambda(double* lam_part, int part, double lam) {
   __shared__ double red[4];
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) lam = fmax(lam, __shfl_xor(lam, o, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lam;
   __syncthreads();
-  if (threadIdx.x == 0)
-    lam_part[blockIdx.y * gridDim.x + blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  if (threadIdx.x == 0) lam_part[part] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 template <int NC>
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(256) void k_scan(Geom G, Bufs B) {
     if (!admissible<NC>(W, G.gas.gamma)) flag_bad(sc, id);
     else lam = cell_lambda<NC>(W, G);
   }
-  reduce_lambda(B.lam_part, lam);
+  reduce_lambda(B.lam_part, blockIdx.y * gridDim.x + blockIdx.x, lam);
 }
 
 // ---------------------------------------------------------------- 2D faces
@@ -288,8 +295,10 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
   by = logical / gridDim.x;
 }
 
+// Tile (bx, by) of the face grid of one direction: DIR 0 tiles (faces, rows),
+// DIR 1 tiles (columns, faces).
 template <int DIR, int STAGE>
-__global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom G, Bufs B) {
+__device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx, int by) {
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
   const double dt = sc->dt;
@@ -300,9 +309,6 @@ __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom
   const int nt = DIR == 0 ? G.ny : G.nx;     // cells along the tangential
   const double hn = DIR == 0 ? G.dx : G.dy;
   const double ht = DIR == 0 ? G.dy : G.dx;
-  // DIR 0: tiles (faces, rows); DIR 1: tiles (columns, faces), on a 2D grid of blocks
-  int bx, by;
-  xcd_tile(bx, by);
   const int f0 = (DIR == 0 ? bx : by) * TF;
   const int t0 = (DIR == 0 ? by : bx) * TT;
 
@@ -398,15 +404,23 @@ __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom
   for (int q = 0; q < NO; ++q) F[q * plane + idx] = acc[q];
 }
 
+template <int DIR, int STAGE>
+__global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom G, Bufs B) {
+  int bx, by;
+  xcd_tile(bx, by);
+  faces2_body<DIR, STAGE>(G, B, bx, by);
+}
+
 // ---------------------------------------------------------------- 2D update
 
+// Cell block (bx, by) of 64 x 4 cells; part: its index among the CFL partials.
 template <int STAGE>
-__global__ __launch_bounds__(256) void k_update2(Geom G, Bufs B) {
+__device__ __forceinline__ void update2_body(const Geom& G, const Bufs& B, int bx, int by, int part) {
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
   const double dt = sc->dt;
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int i = bx * 64 + (threadIdx.x & 63);
+  const int j = by * 4 + (threadIdx.x >> 6);
   const bool in = i < G.nx && j < G.ny;
   const size_t N = (size_t)G.nx * G.ny;
   const size_t id = (size_t)j * G.nx + i;
@@ -460,7 +474,12 @@ __global__ __launch_bounds__(256) void k_update2(Geom G, Bufs B) {
       else lam = cell_lambda<4>(Wn, G);
     }
   }
-  if (STAGE == 2) reduce_lambda(B.lam_part, lam);
+  if (STAGE == 2) reduce_lambda(B.lam_part, part, lam);
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_update2(Geom G, Bufs B) {
+  update2_body<STAGE>(G, B, blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // ---------------------------------------------------------------- 1D
@@ -566,7 +585,66 @@ __global__ __launch_bounds__(256) void k_update1(Geom G, Bufs B) {
       else lam = cell_lambda<3>(Wn, G);
     }
   }
-  if (STAGE == 2) reduce_lambda(B.lam_part, lam);
+  if (STAGE == 2) reduce_lambda(B.lam_part, blockIdx.x, lam);
+}
+
+// ---------------------------------------------------------------- batch
+
+// Many independent 2D problems advanced by the same launches: every batched
+// kernel covers the blocks of all running slots, and a block finds its slot
+// from the prefix sums of the per-slot block counts.
+constexpr int kMaxSlots = 1024;
+
+struct SlotDev {
+  Geom G;
+  Bufs B;
+  int gxw, gyw, guw;   // blocks along the first grid axis: x-face, y-face and update grids
+  int nparts;          // CFL partial maxima (update blocks)
+};
+
+// Running slots of a batched launch: block b belongs to the k-th of them when
+// pre[k] <= b < pre[k + 1] (one prefix array per grid kind).
+struct BatchTable {
+  int n;
+  int slot[kMaxSlots];
+  int pre_x[kMaxSlots + 1], pre_y[kMaxSlots + 1], pre_u[kMaxSlots + 1];
+};
+
+__device__ __forceinline__ int find_slot(const int* pre, int n, int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void kb_begin(const SlotDev* slots, const BatchTable* tab) {
+  const SlotDev& sd = slots[tab->slot[blockIdx.x]];
+  begin_body(sd.B.sc, sd.B.lam_part, sd.nparts);
+}
+
+__global__ void kb_end(const SlotDev* slots, const BatchTable* tab) {
+  end_body(slots[tab->slot[blockIdx.x]].B.sc);
+}
+
+template <int DIR, int STAGE>
+__global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces2(const SlotDev* slots,
+                                                                             const BatchTable* tab) {
+  const int* pre = DIR == 0 ? tab->pre_x : tab->pre_y;
+  const int k = find_slot(pre, tab->n, blockIdx.x);
+  const SlotDev& sd = slots[tab->slot[k]];
+  const int local = blockIdx.x - pre[k];
+  const int w = DIR == 0 ? sd.gxw : sd.gyw;
+  faces2_body<DIR, STAGE>(sd.G, sd.B, local % w, local / w);
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void kb_update2(const SlotDev* slots, const BatchTable* tab) {
+  const int k = find_slot(tab->pre_u, tab->n, blockIdx.x);
+  const SlotDev& sd = slots[tab->slot[k]];
+  const int local = blockIdx.x - tab->pre_u[k];
+  update2_body<STAGE>(sd.G, sd.B, local % sd.guw, local / sd.guw, local);
 }
 
 }  // namespace cgks
@@ -656,6 +734,32 @@ static int validate(const cgks_config* c) {
   return CGKS_OK;
 }
 
+// Geometry, gas constants and conservative inflow states of a configuration.
+static void make_geom(const cgks_config& cfg, Geom& G) {
+  std::memset(&G, 0, sizeof G);
+  G.dim = cfg.dim;
+  G.nx = cfg.nx;
+  G.ny = cfg.dim == 2 ? cfg.ny : 1;
+  G.dx = (cfg.x1 - cfg.x0) / cfg.nx;
+  G.dy = cfg.dim == 2 ? (cfg.y1 - cfg.y0) / cfg.ny : 1.0;
+  G.inv_dx = 1.0 / G.dx;
+  G.inv_dy = 1.0 / G.dy;
+  G.eps = cfg.weno_eps;
+  G.gas = make_gas(cfg.gamma, cfg.dim, cfg.tau_eps, cfg.tau_C);
+  for (int s = 0; s < 4; ++s) {
+    G.bc[s] = s < 2 * cfg.dim ? cfg.bc[s] : CGKS_PERIODIC;
+    const double* q = cfg.inflow_prim[s];
+    const double g1 = cfg.gamma - 1.0;
+    if (cfg.dim == 2) {
+      G.inflow[s][0] = q[0]; G.inflow[s][1] = q[0] * q[1]; G.inflow[s][2] = q[0] * q[2];
+      G.inflow[s][3] = q[3] / g1 + 0.5 * q[0] * (q[1] * q[1] + q[2] * q[2]);
+    } else {
+      G.inflow[s][0] = q[0]; G.inflow[s][1] = q[0] * q[1];
+      G.inflow[s][2] = q[3] / g1 + 0.5 * q[0] * q[1] * q[1]; G.inflow[s][3] = 0.0;
+    }
+  }
+}
+
 static void free_bufs(cgks_ctx* c) {
   (void)hipFree(c->B.S[0]); (void)hipFree(c->B.S[1]); (void)hipFree(c->B.Ws); (void)hipFree(c->B.P);
   (void)hipFree(c->B.FX); (void)hipFree(c->B.FY); (void)hipFree(c->B.sc); (void)hipFree(c->B.lam_part);
@@ -674,27 +778,7 @@ extern "C" int cgks_create(const cgks_config* cfg, void* hip_stream, cgks_ctx** 
   if (cfg->dim == 1) c->cfg.ny = 1;
   c->stream = (hipStream_t)hip_stream;
   Geom& G = c->G;
-  G.dim = cfg->dim;
-  G.nx = cfg->nx;
-  G.ny = c->cfg.ny;
-  G.dx = (cfg->x1 - cfg->x0) / cfg->nx;
-  G.dy = cfg->dim == 2 ? (cfg->y1 - cfg->y0) / cfg->ny : 1.0;
-  G.inv_dx = 1.0 / G.dx;
-  G.inv_dy = 1.0 / G.dy;
-  G.eps = cfg->weno_eps;
-  G.gas = make_gas(cfg->gamma, cfg->dim, cfg->tau_eps, cfg->tau_C);
-  for (int s = 0; s < 4; ++s) {
-    G.bc[s] = s < 2 * cfg->dim ? cfg->bc[s] : CGKS_PERIODIC;
-    const double* q = cfg->inflow_prim[s];
-    const double g1 = cfg->gamma - 1.0;
-    if (cfg->dim == 2) {
-      G.inflow[s][0] = q[0]; G.inflow[s][1] = q[0] * q[1]; G.inflow[s][2] = q[0] * q[2];
-      G.inflow[s][3] = q[3] / g1 + 0.5 * q[0] * (q[1] * q[1] + q[2] * q[2]);
-    } else {
-      G.inflow[s][0] = q[0]; G.inflow[s][1] = q[0] * q[1];
-      G.inflow[s][2] = q[3] / g1 + 0.5 * q[0] * q[1] * q[1]; G.inflow[s][3] = 0.0;
-    }
-  }
+  make_geom(c->cfg, G);
   c->N = (size_t)G.nx * G.ny;
   c->nf = cfg->dim == 2 ? 12 : 6;
   const size_t fbytes = c->nf * c->N * sizeof(double);
@@ -773,6 +857,7 @@ static int push_params(cgks_ctx* c, double t_end, double dt_override) {
   // the pinned mirror holds the last pulled scalars; only the parameter block is sent
   c->host_sc->prm.t_end = t_end;
   c->host_sc->prm.dt_override = dt_override;
+  c->host_sc->prm.max_step = LLONG_MAX;
   HIPCHK(hipMemcpyAsync(c->B.sc, c->host_sc, sizeof(Params), hipMemcpyHostToDevice, c->stream));
   return CGKS_OK;
 }
@@ -926,4 +1011,309 @@ extern "C" const char* cgks_strerror(int code) {
     case CGKS_ESTATE: return "no state loaded";
     default: return "unknown error";
   }
+}
+
+// ============================================================== batch (serving)
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator with coalescing over one device allocation.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_;   // offset -> length, no two adjacent
+
+  bool alloc(size_t n, size_t& off) {
+    n = round_up(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      off = it->first;
+      const size_t rest = it->second - n;
+      free_.erase(it);
+      if (rest) free_[off + n] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = round_up(n);
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct SlotInfo {
+  int used = 0;
+  size_t off = 0, bytes = 0;
+  size_t N = 0;
+  int nbx = 0, nby = 0, nbu = 0;   // blocks of the x-face, y-face and update grids
+};
+
+}  // namespace
+
+struct cgks_batch {
+  hipStream_t stream = nullptr;
+  int own_stream = 0;
+  int max_slots = 0;
+  Arena arena;
+  SlotDev* d_slots = nullptr;
+  std::vector<SlotDev> h_slots;
+  Scalars* d_sc = nullptr;
+  Scalars* h_sc = nullptr;          // pinned mirror, refreshed after admit and run
+  BatchTable* d_tab = nullptr;
+  BatchTable* h_tab = nullptr;      // pinned
+  std::vector<SlotInfo> info;
+  std::vector<int> table;           // running slots in the current table
+  int tx = 0, ty = 0, tu = 0;       // total blocks per grid kind of the table
+  hipGraphExec_t exec = nullptr;
+  int graph_steps = 0;
+};
+
+static int slot_state(const cgks_batch* b, int k) {
+  if (!b->info[k].used) return CGKS_SLOT_FREE;
+  const Scalars& h = b->h_sc[k];
+  if (h.status != 0) return CGKS_SLOT_FAILED;
+  if (h.step >= h.prm.max_step || !(h.prm.t_end - h.t > 0.0)) return CGKS_SLOT_DONE;
+  return CGKS_SLOT_RUNNING;
+}
+
+static void drop_graph(cgks_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->graph_steps = 0;
+}
+
+extern "C" void cgks_batch_destroy(cgks_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  (void)hipFree(b->arena.base);
+  (void)hipFree(b->d_slots);
+  (void)hipFree(b->d_sc);
+  (void)hipFree(b->d_tab);
+  if (b->h_sc) (void)hipHostFree(b->h_sc);
+  if (b->h_tab) (void)hipHostFree(b->h_tab);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+extern "C" int cgks_batch_create(size_t hbm_budget_bytes, int max_slots, void* hip_stream, cgks_batch** out) {
+  if (!out) return CGKS_EINVAL;
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > kMaxSlots || hbm_budget_bytes < kAlign) return CGKS_EINVAL;
+  cgks_batch* b = new (std::nothrow) cgks_batch();
+  if (!b) return CGKS_ENOMEM;
+  b->max_slots = max_slots;
+  if (hip_stream) {
+    b->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return CGKS_EDEVICE;
+    }
+    b->own_stream = 1;
+  }
+  b->arena.size = hbm_budget_bytes / kAlign * kAlign;
+  bool ok = hipMalloc(&b->arena.base, b->arena.size) == hipSuccess &&
+            hipMalloc(&b->d_slots, sizeof(SlotDev) * max_slots) == hipSuccess &&
+            hipMalloc(&b->d_sc, sizeof(Scalars) * max_slots) == hipSuccess &&
+            hipMalloc(&b->d_tab, sizeof(BatchTable)) == hipSuccess &&
+            hipHostMalloc(&b->h_sc, sizeof(Scalars) * max_slots, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(&b->h_tab, sizeof(BatchTable), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    cgks_batch_destroy(b);
+    return CGKS_ENOMEM;
+  }
+  b->arena.free_[0] = b->arena.size;
+  b->h_slots.assign(max_slots, SlotDev());
+  b->info.assign(max_slots, SlotInfo());
+  std::memset(b->h_sc, 0, sizeof(Scalars) * max_slots);
+  std::memset(b->h_tab, 0, sizeof(BatchTable));
+  *out = b;
+  return CGKS_OK;
+}
+
+extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const double* fields, int on_device,
+                                double t_end, long max_steps, int* slot) {
+  if (!b || !fields || !slot) return CGKS_EINVAL;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (cfg->dim != 2) return CGKS_EINVAL;
+  if (!(t_end > 0.0) && max_steps <= 0) return CGKS_EINVAL;   // a request needs an end
+  int k = 0;
+  while (k < b->max_slots && b->info[k].used) ++k;
+  if (k == b->max_slots) return CGKS_EBUSY;
+
+  SlotDev& sd = b->h_slots[k];
+  SlotInfo& in = b->info[k];
+  make_geom(*cfg, sd.G);
+  const Geom& G = sd.G;
+  const size_t N = (size_t)G.nx * G.ny;
+  const dim3 gu = update_grid(G);
+  const size_t fbytes = round_up(12 * N * sizeof(double));
+  const size_t fx = round_up((size_t)16 * G.ny * (G.nx + 1) * sizeof(double));
+  const size_t fy = round_up((size_t)16 * (G.ny + 1) * G.nx * sizeof(double));
+  const size_t lp = round_up(sizeof(double) * (size_t)gu.x * gu.y);
+  const size_t bytes = 4 * fbytes + fx + fy + lp;
+  size_t off = 0;
+  if (!b->arena.alloc(bytes, off)) return CGKS_EBUSY;
+  char* p = b->arena.base + off;
+  sd.B.S[0] = (double*)p; p += fbytes;
+  sd.B.S[1] = (double*)p; p += fbytes;
+  sd.B.Ws = (double*)p; p += fbytes;
+  sd.B.P = (double*)p; p += fbytes;
+  sd.B.FX = (double*)p; p += fx;
+  sd.B.FY = (double*)p; p += fy;
+  sd.B.lam_part = (double*)p;
+  sd.B.sc = b->d_sc + k;
+  sd.gxw = (G.nx + 1 + TF - 1) / TF;
+  sd.gyw = (G.nx + TT - 1) / TT;
+  sd.guw = (int)gu.x;
+  sd.nparts = (int)(gu.x * gu.y);
+  in.used = 1;
+  in.off = off;
+  in.bytes = bytes;
+  in.N = N;
+  in.nbx = sd.gxw * ((G.ny + TT - 1) / TT);
+  in.nby = sd.gyw * ((G.ny + 1 + TF - 1) / TF);
+  in.nbu = sd.nparts;
+
+  Scalars& h = b->h_sc[k];
+  std::memset(&h, 0, sizeof h);
+  h.prm.t_end = t_end > 0.0 ? t_end : INFINITY;
+  h.prm.dt_override = 0.0;
+  h.prm.max_step = max_steps > 0 ? (long long)max_steps : LLONG_MAX;
+  h.cfl = cfg->cfl;
+  h.fixed_dt = cfg->fixed_dt;
+  h.bad_cell = ULLONG_MAX;
+  bool ok = hipMemcpyAsync(sd.B.S[0], fields, 12 * N * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            hipMemcpyAsync(b->d_sc + k, &h, sizeof h, hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            hipMemcpyAsync(b->d_slots + k, &sd, sizeof sd, hipMemcpyHostToDevice, b->stream) == hipSuccess;
+  if (ok) {
+    k_scan<4><<<gu, 256, 0, b->stream>>>(sd.G, sd.B);
+    ok = hipGetLastError() == hipSuccess &&
+         hipMemcpyAsync(&h, b->d_sc + k, sizeof h, hipMemcpyDeviceToHost, b->stream) == hipSuccess &&
+         hipStreamSynchronize(b->stream) == hipSuccess;
+  }
+  if (!ok || h.status != 0) {
+    b->arena.release(off, bytes);
+    in = SlotInfo();
+    return ok ? CGKS_ENONPHYS : CGKS_EDEVICE;
+  }
+  *slot = k;
+  return CGKS_OK;
+}
+
+// Table of the running slots; the graph is dropped when the set changes.
+static int refresh_table(cgks_batch* b) {
+  std::vector<int> run;
+  for (int k = 0; k < b->max_slots; ++k)
+    if (slot_state(b, k) == CGKS_SLOT_RUNNING) run.push_back(k);
+  if (run == b->table) return CGKS_OK;
+  drop_graph(b);
+  b->table = run;
+  BatchTable& t = *b->h_tab;
+  t.n = (int)run.size();
+  t.pre_x[0] = t.pre_y[0] = t.pre_u[0] = 0;
+  for (int i = 0; i < t.n; ++i) {
+    const SlotInfo& in = b->info[run[i]];
+    t.slot[i] = run[i];
+    t.pre_x[i + 1] = t.pre_x[i] + in.nbx;
+    t.pre_y[i + 1] = t.pre_y[i] + in.nby;
+    t.pre_u[i + 1] = t.pre_u[i] + in.nbu;
+  }
+  b->tx = t.pre_x[t.n];
+  b->ty = t.pre_y[t.n];
+  b->tu = t.pre_u[t.n];
+  HIPCHK(hipMemcpyAsync(b->d_tab, &t, sizeof t, hipMemcpyHostToDevice, b->stream));
+  return CGKS_OK;
+}
+
+static void launch_batch_step(cgks_batch* b) {
+  hipStream_t s = b->stream;
+  const int n = (int)b->table.size();
+  const SlotDev* sl = b->d_slots;
+  const BatchTable* t = b->d_tab;
+  kb_begin<<<n, 256, 0, s>>>(sl, t);
+  kb_faces2<0, 1><<<b->tx, FACE_THREADS, 0, s>>>(sl, t);
+  kb_faces2<1, 1><<<b->ty, FACE_THREADS, 0, s>>>(sl, t);
+  kb_update2<1><<<b->tu, 256, 0, s>>>(sl, t);
+  kb_faces2<0, 2><<<b->tx, FACE_THREADS, 0, s>>>(sl, t);
+  kb_faces2<1, 2><<<b->ty, FACE_THREADS, 0, s>>>(sl, t);
+  kb_update2<2><<<b->tu, 256, 0, s>>>(sl, t);
+  kb_end<<<n, 64, 0, s>>>(sl, t);
+}
+
+extern "C" int cgks_batch_run(cgks_batch* b, int steps) {
+  if (!b || steps < 1) return CGKS_EINVAL;
+  int rc = refresh_table(b);
+  if (rc) return rc;
+  if (b->table.empty()) return CGKS_OK;
+  if (!b->exec || b->graph_steps != steps) {
+    drop_graph(b);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < steps; ++k) launch_batch_step(b);
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return CGKS_EDEVICE;
+    }
+    const hipError_t e3 = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) {
+      b->exec = nullptr;
+      return CGKS_EDEVICE;
+    }
+    b->graph_steps = steps;
+  }
+  HIPCHK(hipGraphLaunch(b->exec, b->stream));
+  HIPCHK(hipMemcpyAsync(b->h_sc, b->d_sc, sizeof(Scalars) * b->max_slots, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return CGKS_OK;
+}
+
+extern "C" int cgks_batch_poll(cgks_batch* b, int slot, int* state, double* t, long* step) {
+  if (!b || slot < 0 || slot >= b->max_slots) return CGKS_EINVAL;
+  if (state) *state = slot_state(b, slot);
+  if (t) *t = b->h_sc[slot].t;
+  if (step) *step = (long)b->h_sc[slot].step;
+  return CGKS_OK;
+}
+
+extern "C" int cgks_batch_read(cgks_batch* b, int slot, double* fields_out, int on_device) {
+  if (!b || !fields_out || slot < 0 || slot >= b->max_slots) return CGKS_EINVAL;
+  if (!b->info[slot].used) return CGKS_ESTATE;
+  const SlotDev& sd = b->h_slots[slot];
+  HIPCHK(hipMemcpyAsync(fields_out, sd.B.S[b->h_sc[slot].cur], 12 * b->info[slot].N * sizeof(double),
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return CGKS_OK;
+}
+
+extern "C" int cgks_batch_release(cgks_batch* b, int slot) {
+  if (!b || slot < 0 || slot >= b->max_slots) return CGKS_EINVAL;
+  SlotInfo& in = b->info[slot];
+  if (!in.used) return CGKS_ESTATE;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  b->arena.release(in.off, in.bytes);
+  in = SlotInfo();
+  std::memset(&b->h_sc[slot], 0, sizeof(Scalars));
+  return CGKS_OK;
 }

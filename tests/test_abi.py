@@ -22,7 +22,9 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for n in ('cgks_create', 'cgks_set_state', 'cgks_step', 'cgks_advance_to', 'cgks_get_state', 'cgks_destroy'):
+    for n in ('cgks_create', 'cgks_set_state', 'cgks_step', 'cgks_advance_to', 'cgks_get_state', 'cgks_destroy',
+              'cgks_batch_create', 'cgks_batch_admit', 'cgks_batch_run', 'cgks_batch_poll', 'cgks_batch_read',
+              'cgks_batch_release', 'cgks_batch_destroy'):
         assert n in names
 
 
