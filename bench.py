@@ -105,6 +105,134 @@ def measured_traffic(kernel, nx, ny):
     return None if k is None else k['bytes_per_launch']
 
 
+def _make_request(k):
+    from paper_2001_01570_amd import inputs as I
+    p = I.serving_request(k)
+    return k, p
+
+
+def serving(nreq, steps_per_run=10):
+    """Serving workload: nreq independent requests (inputs.serving_request:
+    side 64..512, pulse + vortex, 200 steps each).  (1) the plain path closed
+    loop (one context per request: create, load from host, 200 steps, read to
+    host) gives the rate r; (2) Poisson arrivals at 2r (default_rng(7)) are
+    replayed in real time through the plain path (FIFO, one request at a time)
+    and through the batch API (admit on arrival, advance all running requests
+    steps_per_run steps per graph replay, read and release on completion).
+    Latency = completion - arrival."""
+    import numpy as np
+    from multiprocessing import get_context
+
+    # inputs first, in worker processes started before anything touches the GPU
+    log('[serving] generating %d requests' % nreq)
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, 'sched_getaffinity') else 4))
+    with get_context('spawn').Pool(workers) as pool:
+        reqs = dict(pool.map(_make_request, range(nreq)))
+    reqs = [reqs[k] for k in range(nreq)]
+    steps = reqs[0].steps
+
+    import torch
+    from paper_2001_01570_amd.cgks import Batch, Solver, SLOT_DONE, SLOT_FAILED, CgksError, CGKS_EBUSY
+    torch.cuda.init()
+
+    def plain_solve(p):
+        s = Solver(p)
+        s.run_steps(steps)
+        out = s.get_state()[0]
+        s.close()
+        return out
+
+    plain_solve(reqs[0])                      # warm up
+    log('[serving] closed loop, plain path')
+    t0 = time.perf_counter()
+    for p in reqs:
+        plain_solve(p)
+    closed = nreq / (time.perf_counter() - t0)
+    rate = 2.0 * closed
+    arrivals = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, size=nreq))
+    log('[serving] closed loop %.2f solves/s; arrivals at %.2f /s over %.2f s' % (closed, rate, arrivals[-1]))
+
+    def wait_until(t_abs):
+        while True:
+            d = t_abs - time.perf_counter()
+            if d <= 0:
+                return
+            time.sleep(min(d, 1e-3))
+
+    # plain path, open loop
+    log('[serving] replay: plain path')
+    lat_plain = np.zeros(nreq)
+    t0 = time.perf_counter()
+    for k, p in enumerate(reqs):
+        wait_until(t0 + arrivals[k])
+        plain_solve(p)
+        lat_plain[k] = time.perf_counter() - t0 - arrivals[k]
+    span_plain = time.perf_counter() - t0
+
+    # batch path, open loop
+    log('[serving] replay: batch path')
+    b = Batch(48 << 30, max_slots=min(nreq, 1024))
+    lat_batch = np.full(nreq, np.nan)
+    slot_of = {}
+    nxt = 0
+    done = 0
+    pending = []
+    t0 = time.perf_counter()
+    while done < nreq:
+        now = time.perf_counter() - t0
+        while nxt < nreq and arrivals[nxt] <= now:
+            pending.append(nxt)
+            nxt += 1
+        still = []
+        for k in pending:
+            try:
+                slot_of[b.admit(reqs[k], max_steps=steps)] = k
+            except CgksError as e:
+                if e.code != CGKS_EBUSY:
+                    raise
+                still.append(k)
+        pending = still
+        if not slot_of:
+            if nxt < nreq:
+                wait_until(t0 + arrivals[nxt])
+            continue
+        b.run(steps_per_run)
+        for s in list(slot_of):
+            st = b.poll(s)[0]
+            if st in (SLOT_DONE, SLOT_FAILED):
+                if st == SLOT_FAILED:
+                    raise RuntimeError('request %d failed' % slot_of[s])
+                b.read(s)
+                b.release(s)
+                k = slot_of.pop(s)
+                lat_batch[k] = time.perf_counter() - t0 - arrivals[k]
+                done += 1
+    span_batch = time.perf_counter() - t0
+    b.close()
+
+    def pct(a, q):
+        return float(np.percentile(a, q))
+    cells = sum(p.nx * p.ny for p in reqs)
+    out = {
+        'metric': 'solves/s (serving, Poisson arrivals at 2x the plain closed-loop rate)',
+        'value': nreq / span_batch,
+        'unit': 'solves/s',
+        'n_gpus': 1,
+        'higher_is_better': True,
+        'dtype': 'f64',
+        'data': 'synthetic',
+        'config': {'workload': '%d serving requests (sides 64-512, pulse + vortex, %d steps each, default_rng(1000+k)),'
+                               ' arrivals default_rng(7)' % (nreq, steps), 'cells_total': cells,
+                   'steps_per_run': steps_per_run},
+        'batched': {'solves_per_s': nreq / span_batch, 'p50_s': pct(lat_batch, 50), 'p99_s': pct(lat_batch, 99),
+                    'span_s': span_batch},
+        'plain': {'closed_loop_solves_per_s': closed, 'solves_per_s': nreq / span_plain,
+                  'p50_s': pct(lat_plain, 50), 'p99_s': pct(lat_plain, 99), 'span_s': span_plain},
+        'arrival_rate_per_s': rate,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split('\n')[0])
     ap.add_argument('--gpus', type=int, default=1)
@@ -114,10 +242,15 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--copy-calibration', type=int, default=0, metavar='MIB',
                     help='also run one plain device copy of this many MiB (reference for HBM byte counters)')
+    ap.add_argument('--serving', type=int, default=0, metavar='R',
+                    help='instead: the serving workload with R requests (Poisson arrivals), batched vs per-request')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py measures one GPU: the solver runs on a single MI355X (use --gpus 1).', file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        serving(args.serving)
+        return
 
     import torch
     from paper_2001_01570_amd import inputs as I

@@ -1078,6 +1078,7 @@ struct cgks_batch {
   BatchTable* h_tab = nullptr;      // pinned
   std::vector<SlotInfo> info;
   std::vector<int> table;           // running slots in the current table
+  int dirty = 1;                    // a slot was admitted or released since the table was built
   int tx = 0, ty = 0, tu = 0;       // total blocks per grid kind of the table
   hipGraphExec_t exec = nullptr;
   int graph_steps = 0;
@@ -1215,6 +1216,7 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
     in = SlotInfo();
     return ok ? CGKS_ENONPHYS : CGKS_EDEVICE;
   }
+  b->dirty = 1;
   *slot = k;
   return CGKS_OK;
 }
@@ -1224,8 +1226,10 @@ static int refresh_table(cgks_batch* b) {
   std::vector<int> run;
   for (int k = 0; k < b->max_slots; ++k)
     if (slot_state(b, k) == CGKS_SLOT_RUNNING) run.push_back(k);
-  if (run == b->table) return CGKS_OK;
+  // an admit or release may reuse a slot index with another grid: rebuild then too
+  if (!b->dirty && run == b->table) return CGKS_OK;
   drop_graph(b);
+  b->dirty = 0;
   b->table = run;
   BatchTable& t = *b->h_tab;
   t.n = (int)run.size();
@@ -1315,5 +1319,6 @@ extern "C" int cgks_batch_release(cgks_batch* b, int slot) {
   b->arena.release(in.off, in.bytes);
   in = SlotInfo();
   std::memset(&b->h_sc[slot], 0, sizeof(Scalars));
+  b->dirty = 1;
   return CGKS_OK;
 }

@@ -121,3 +121,28 @@ def test_batch_admission_and_release():
     for s in (s2, s3):
         assert b.poll(s)[2] == 2
     b.close()
+
+
+def test_batch_slot_reused_by_another_grid():
+    """A released slot index taken by a problem of another size between two
+    runs: the launches must follow the new grid (regression: the block table
+    was kept when the set of running slot indices looked unchanged)."""
+    from paper_2001_01570_amd.cgks import Batch, Solver
+    a = I.acoustic_pulse_2d(96, seed=3, amp=1e-3, half_width=0.2)
+    c = I.vortex_translation_2d(24)
+    d = I.acoustic_pulse_2d(40, seed=6, amp=1e-3, half_width=0.2, ny=28)
+    b = Batch(GiB // 4, max_slots=4)
+    sa = b.admit(a, max_steps=4)
+    sc = b.admit(c, max_steps=4)
+    b.run(2)
+    b.release(sa)
+    sd = b.admit(d, max_steps=4)
+    assert sd == sa
+    b.run(2)
+    rc, rd = Solver(c), Solver(d)
+    rc.run_steps(4)
+    rd.run_steps(2)
+    assert b.poll(sc)[2] == 4 and b.poll(sd)[2] == 2
+    assert np.array_equal(b.read(sc), rc.get_state()[0])
+    assert np.array_equal(b.read(sd), rd.get_state()[0])
+    b.close()
