@@ -87,7 +87,9 @@ int cgks_step_dt(cgks_ctx *ctx, double dt, double *dt_used);
  * max_steps > 0 bounds the number of steps of this call. */
 int cgks_advance_to(cgks_ctx *ctx, double t_end, long max_steps, long *steps_taken);
 
-/* Exactly n steps of the rule (no end time); used to time fixed step counts. */
+/* Exactly n steps of the rule (no end time); used to time fixed step counts.
+ * On a capturable stream (not the legacy null stream) and with profiling
+ * off, runs of 25 steps replay one captured HIP graph. */
 int cgks_run_steps(cgks_ctx *ctx, long n);
 
 /* Copy the current state out (host or device pointer); t and step may be NULL. */
@@ -95,13 +97,15 @@ int cgks_get_state(cgks_ctx *ctx, double *fields_out, int on_device, double *t, 
 
 int cgks_last_bad_cell(const cgks_ctx *ctx, long *cell);
 
-/* Measurement: while profiling is on, every hot kernel launch of a step is
- * bracketed by HIP events on the context's stream.  cgks_kernel_times fills
- * ms[k] (accumulated device milliseconds) and calls[k] for kernel kind k
- * (2D: xfaces1, yfaces1, update1, xfaces2, yfaces2, update2; 1D: faces1,
- * update1, faces2, update2) and returns the number of kinds, or an error.
- * Turning profiling on clears the accumulators. */
-int cgks_set_profiling(cgks_ctx *ctx, int on);
+/* Measurement: kernel kind k (2D: xfaces1, yfaces1, update1, xfaces2,
+ * yfaces2, update2; 1D: faces1, update1, faces2, update2) is bracketed by HIP
+ * events on the context's stream at every launch while bit k of the
+ * profiling mask is set (mask -1: all kinds; 0: off; fewer kinds, fewer
+ * events in the stream).  cgks_kernel_times fills ms[k] (accumulated device
+ * milliseconds) and calls[k] and returns the number of kinds, or an error.
+ * Setting a nonzero mask clears the accumulators.  While profiling is on,
+ * cgks_run_steps launches step by step instead of replaying its graph. */
+int cgks_set_profiling(cgks_ctx *ctx, int mask);
 int cgks_kernel_times(cgks_ctx *ctx, double *ms, long *calls, int n);
 int cgks_counters(cgks_ctx *ctx, cgks_counters_t *out);
 void cgks_destroy(cgks_ctx *ctx);

@@ -206,8 +206,16 @@ class Solver:
         load().cgks_last_bad_cell(self.h, C.byref(c))
         return c.value
 
-    def set_profiling(self, on: bool):
-        self._check(load().cgks_set_profiling(self.h, 1 if on else 0), 'cgks_set_profiling')
+    def set_profiling(self, on=True, kinds=None):
+        """Profile every kernel kind (on=True), none (False), or only the named kinds."""
+        if not on:
+            mask = 0
+        elif kinds is None:
+            mask = -1
+        else:
+            names = KERNEL_NAMES_2D if self.dim == 2 else KERNEL_NAMES_1D
+            mask = sum(1 << names.index(k) for k in kinds)
+        self._check(load().cgks_set_profiling(self.h, mask), 'cgks_set_profiling')
 
     def kernel_times(self) -> dict:
         """Per-kernel accumulated device time (ms) and launch counts recorded with

@@ -671,7 +671,11 @@ struct cgks_ctx {
   size_t ev_used;
   double ms[kKinds];
   long calls[kKinds];
+  // run_steps replays GRAPH_STEPS steps as one HIP graph (captured on first use)
+  hipGraphExec_t exec;
 };
+
+constexpr long GRAPH_STEPS = 25;
 
 // resolve recorded event pairs into the per-kernel accumulators (synchronises)
 static int resolve_events(cgks_ctx* c) {
@@ -691,7 +695,7 @@ static int resolve_events(cgks_ctx* c) {
 // launch helper: records an event pair around the launch while profiling
 template <class F>
 static void timed(cgks_ctx* c, int kind, F&& launch) {
-  if (!c->profiling) { launch(); return; }
+  if (!(c->profiling & (1 << kind))) { launch(); return; }
   if (c->ev_used == kEventPairs) resolve_events(c);
   (void)hipEventRecord((*c->events)[2 * c->ev_used], c->stream);
   launch();
@@ -809,6 +813,7 @@ extern "C" int cgks_create(const cgks_config* cfg, void* hip_stream, cgks_ctx** 
 extern "C" void cgks_destroy(cgks_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
   if (c->events) {
     for (hipEvent_t e : *c->events) (void)hipEventDestroy(e);
     delete c->events;
@@ -834,7 +839,7 @@ extern "C" int cgks_set_profiling(cgks_ctx* c, int on) {
     int rc = resolve_events(c);
     if (rc) return rc;
   }
-  c->profiling = on ? 1 : 0;
+  c->profiling = on;
   return CGKS_OK;
 }
 
@@ -932,12 +937,39 @@ extern "C" int cgks_step_dt(cgks_ctx* c, double dt, double* dt_used) {
 
 extern "C" int cgks_step(cgks_ctx* c, double* dt_used) { return cgks_step_dt(c, 0.0, dt_used); }
 
+// Capture GRAPH_STEPS steps of the context into a graph.  Only on a stream
+// that may be captured (not the legacy null stream) and with profiling off;
+// returns false (and leaves eager launching) otherwise.
+static bool ensure_graph(cgks_ctx* c) {
+  if (c->exec) return true;
+  if (!c->stream || c->profiling) return false;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  for (long k = 0; k < GRAPH_STEPS; ++k) launch_step(c);
+  const hipError_t e1 = hipGetLastError();
+  const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+  bool ok = e1 == hipSuccess && e2 == hipSuccess && g &&
+            hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (!ok) {
+    c->exec = nullptr;
+    (void)hipGetLastError();
+  }
+  return ok;
+}
+
 extern "C" int cgks_run_steps(cgks_ctx* c, long n) {
   if (!c || n < 0) return CGKS_EINVAL;
   if (!c->has_state) return CGKS_ESTATE;
   int rc = push_params(c, INFINITY, 0.0);
   if (rc) return rc;
-  for (long k = 0; k < n; ++k) launch_step(c);
+  long k = 0;
+  if (n >= GRAPH_STEPS && !c->profiling && ensure_graph(c))
+    for (; k + GRAPH_STEPS <= n; k += GRAPH_STEPS) HIPCHK(hipGraphLaunch(c->exec, c->stream));
+  for (; k < n; ++k) launch_step(c);
   HIPCHK(hipGetLastError());
   rc = pull_scalars(c);
   if (rc) return rc;
