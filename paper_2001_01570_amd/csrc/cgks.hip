@@ -297,13 +297,13 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 
 // Tile (bx, by) of the face grid of one direction: DIR 0 tiles (faces, rows),
 // DIR 1 tiles (columns, faces).
+// lds: the kernel's LDS tile, NQ rows of NSEG line segments.
 template <int DIR, int STAGE>
-__device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx, int by) {
+__device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx, int by, double (*lds)[NSEG]) {
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
   const double dt = sc->dt;
   const double* S = STAGE == 1 ? B.S[sc->cur] : B.Ws;
-  __shared__ double lds[NQ][NSEG];
 
   const int nn = DIR == 0 ? G.nx : G.ny;     // cells along the normal
   const int nt = DIR == 0 ? G.ny : G.nx;     // cells along the tangential
@@ -406,9 +406,10 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
 
 template <int DIR, int STAGE>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom G, Bufs B) {
+  __shared__ double lds[NQ][NSEG];
   int bx, by;
   xcd_tile(bx, by);
-  faces2_body<DIR, STAGE>(G, B, bx, by);
+  faces2_body<DIR, STAGE>(G, B, bx, by, lds);
 }
 
 // ---------------------------------------------------------------- 2D update
@@ -590,9 +591,12 @@ __global__ __launch_bounds__(256) void k_update1(Geom G, Bufs B) {
 
 // ---------------------------------------------------------------- batch
 
-// Many independent 2D problems advanced by the same launches: every batched
-// kernel covers the blocks of all running slots, and a block finds its slot
-// from the prefix sums of the per-slot block counts.
+// Many independent 2D problems advanced by the same launches.  A batched
+// launch covers a device-resident work list: the tiles (or cell blocks) of
+// all running slots, one block each.  Its grid is a power-of-two bucket of
+// the list's length (blocks past the end return at once), so the list may
+// change between runs without a new graph until it outgrows its bucket.
+// Within a run each slot keeps its own step size, time and status.
 constexpr int kMaxSlots = 1024;
 
 struct SlotDev {
@@ -602,8 +606,8 @@ struct SlotDev {
   int nparts;          // CFL partial maxima (update blocks)
 };
 
-// Running slots of a batched launch: block b belongs to the k-th of them when
-// pre[k] <= b < pre[k + 1] (one prefix array per grid kind).
+// Running slots: work item i of a kind belongs to the k-th of them when
+// pre[k] <= i < pre[k + 1] (x-face tiles, y-face tiles, update blocks).
 struct BatchTable {
   int n;
   int slot[kMaxSlots];
@@ -619,31 +623,51 @@ __device__ __forceinline__ int find_slot(const int* pre, int n, int b) {
   return lo;
 }
 
+// Work item of this block in a list of `total` items, or -1: consecutive
+// blocks go round-robin to the XCDs, so each XCD takes a contiguous share of
+// the list (neighbouring tiles of a slot share an L2).  The grid (a multiple
+// of the XCD count) must hold at least NXCD * ceil(total / NXCD) blocks.
+__device__ __forceinline__ int xcd_item(int total) {
+  const int per = (total + NXCD - 1) / NXCD;
+  const int x = blockIdx.x % NXCD, local = blockIdx.x / NXCD;
+  const int item = x * per + local;
+  return local < per && item < total ? item : -1;
+}
+
 __global__ __launch_bounds__(256) void kb_begin(const SlotDev* slots, const BatchTable* tab) {
+  if ((int)blockIdx.x >= tab->n) return;
   const SlotDev& sd = slots[tab->slot[blockIdx.x]];
   begin_body(sd.B.sc, sd.B.lam_part, sd.nparts);
 }
 
 __global__ void kb_end(const SlotDev* slots, const BatchTable* tab) {
+  if ((int)blockIdx.x >= tab->n) return;
   end_body(slots[tab->slot[blockIdx.x]].B.sc);
 }
 
 template <int DIR, int STAGE>
-__global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces2(const SlotDev* slots,
-                                                                             const BatchTable* tab) {
+__global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces(const SlotDev* slots,
+                                                                            const BatchTable* tab) {
+  __shared__ double lds[NQ][NSEG];
+  const int n = tab->n;
   const int* pre = DIR == 0 ? tab->pre_x : tab->pre_y;
-  const int k = find_slot(pre, tab->n, blockIdx.x);
+  const int item = xcd_item(pre[n]);
+  if (item < 0) return;
+  const int k = find_slot(pre, n, item);
   const SlotDev& sd = slots[tab->slot[k]];
-  const int local = blockIdx.x - pre[k];
+  const int local = item - pre[k];
   const int w = DIR == 0 ? sd.gxw : sd.gyw;
-  faces2_body<DIR, STAGE>(sd.G, sd.B, local % w, local / w);
+  faces2_body<DIR, STAGE>(sd.G, sd.B, local % w, local / w, lds);
 }
 
 template <int STAGE>
-__global__ __launch_bounds__(256) void kb_update2(const SlotDev* slots, const BatchTable* tab) {
-  const int k = find_slot(tab->pre_u, tab->n, blockIdx.x);
+__global__ __launch_bounds__(256) void kb_update(const SlotDev* slots, const BatchTable* tab) {
+  const int n = tab->n;
+  const int item = blockIdx.x;
+  if (item >= tab->pre_u[n]) return;
+  const int k = find_slot(tab->pre_u, n, item);
   const SlotDev& sd = slots[tab->slot[k]];
-  const int local = blockIdx.x - tab->pre_u[k];
+  const int local = item - tab->pre_u[k];
   update2_body<STAGE>(sd.G, sd.B, local % sd.guw, local / sd.guw, local);
 }
 
@@ -1111,7 +1135,7 @@ struct cgks_batch {
   std::vector<SlotInfo> info;
   std::vector<int> table;           // running slots in the current table
   int dirty = 1;                    // a slot was admitted or released since the table was built
-  int tx = 0, ty = 0, tu = 0;       // total blocks per grid kind of the table
+  int cap_n = 0, cap_x = 0, cap_y = 0, cap_u = 0;   // grid buckets of the captured graph
   hipGraphExec_t exec = nullptr;
   int graph_steps = 0;
 };
@@ -1253,14 +1277,14 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   return CGKS_OK;
 }
 
-// Table of the running slots; the graph is dropped when the set changes.
+// Work list of the running slots (the graph reads it from device memory and
+// needs no new capture while each list stays in its grid bucket).
 static int refresh_table(cgks_batch* b) {
   std::vector<int> run;
   for (int k = 0; k < b->max_slots; ++k)
     if (slot_state(b, k) == CGKS_SLOT_RUNNING) run.push_back(k);
   // an admit or release may reuse a slot index with another grid: rebuild then too
   if (!b->dirty && run == b->table) return CGKS_OK;
-  drop_graph(b);
   b->dirty = 0;
   b->table = run;
   BatchTable& t = *b->h_tab;
@@ -1273,26 +1297,39 @@ static int refresh_table(cgks_batch* b) {
     t.pre_y[i + 1] = t.pre_y[i] + in.nby;
     t.pre_u[i + 1] = t.pre_u[i] + in.nbu;
   }
-  b->tx = t.pre_x[t.n];
-  b->ty = t.pre_y[t.n];
-  b->tu = t.pre_u[t.n];
+  // grids: power-of-two buckets; a new graph only when a list leaves its bucket
+  // (buckets are multiples of NXCD and >= NXCD * ceil(len / NXCD), as the
+  // face kernels' XCD mapping needs)
+  auto bucket = [](int len, int cap) {
+    const int need = (len + NXCD - 1) / NXCD * NXCD;
+    if (cap > 0 && need <= cap && 4 * need > cap) return cap;
+    int c = 64;
+    while (c < need) c *= 2;
+    return c;
+  };
+  const int cn = bucket(t.n, b->cap_n), cx = bucket(t.pre_x[t.n], b->cap_x);
+  const int cy = bucket(t.pre_y[t.n], b->cap_y), cu = bucket(t.pre_u[t.n], b->cap_u);
+  if (cn != b->cap_n || cx != b->cap_x || cy != b->cap_y || cu != b->cap_u) {
+    drop_graph(b);
+    b->cap_n = cn; b->cap_x = cx; b->cap_y = cy; b->cap_u = cu;
+  }
   HIPCHK(hipMemcpyAsync(b->d_tab, &t, sizeof t, hipMemcpyHostToDevice, b->stream));
   return CGKS_OK;
 }
 
+// One step of every running slot: eight launches of fixed size.
 static void launch_batch_step(cgks_batch* b) {
   hipStream_t s = b->stream;
-  const int n = (int)b->table.size();
   const SlotDev* sl = b->d_slots;
   const BatchTable* t = b->d_tab;
-  kb_begin<<<n, 256, 0, s>>>(sl, t);
-  kb_faces2<0, 1><<<b->tx, FACE_THREADS, 0, s>>>(sl, t);
-  kb_faces2<1, 1><<<b->ty, FACE_THREADS, 0, s>>>(sl, t);
-  kb_update2<1><<<b->tu, 256, 0, s>>>(sl, t);
-  kb_faces2<0, 2><<<b->tx, FACE_THREADS, 0, s>>>(sl, t);
-  kb_faces2<1, 2><<<b->ty, FACE_THREADS, 0, s>>>(sl, t);
-  kb_update2<2><<<b->tu, 256, 0, s>>>(sl, t);
-  kb_end<<<n, 64, 0, s>>>(sl, t);
+  kb_begin<<<b->cap_n, 256, 0, s>>>(sl, t);
+  kb_faces<0, 1><<<b->cap_x, FACE_THREADS, 0, s>>>(sl, t);
+  kb_faces<1, 1><<<b->cap_y, FACE_THREADS, 0, s>>>(sl, t);
+  kb_update<1><<<b->cap_u, 256, 0, s>>>(sl, t);
+  kb_faces<0, 2><<<b->cap_x, FACE_THREADS, 0, s>>>(sl, t);
+  kb_faces<1, 2><<<b->cap_y, FACE_THREADS, 0, s>>>(sl, t);
+  kb_update<2><<<b->cap_u, 256, 0, s>>>(sl, t);
+  kb_end<<<b->cap_n, 64, 0, s>>>(sl, t);
 }
 
 extern "C" int cgks_batch_run(cgks_batch* b, int steps) {
