@@ -39,7 +39,12 @@ extern "C" {
 #define CGKS_ESTATE (-6)     /* call not valid in the current state (e.g. no state) */
 
 enum { CGKS_PERIODIC = 0, CGKS_FREE = 1, CGKS_WALL = 2, CGKS_INFLOW = 3 };
-enum { CGKS_FP64 = 0 };
+/* Storage of the state fields.  CGKS_FP32_STORAGE (2D only): the 8 cell-
+ * averaged gradient fields of the state and of the stage buffers are kept in
+ * FP32; cell averages, all arithmetic, the conservative accumulation and the
+ * tau/exp evaluation stay FP64.  Fields cross the boundary in FP64 either way
+ * (the gradients are rounded to FP32 on set_state). */
+enum { CGKS_FP64 = 0, CGKS_FP32_STORAGE = 1 };
 
 typedef struct cgks_ctx cgks_ctx;
 
@@ -55,7 +60,7 @@ typedef struct {
   double weno_eps;           /* epsilon of the WENO-Z weights (eq. WENO-Z-w), e.g. 1e-6  */
   double tau_eps, tau_C;     /* collision time eps*dt + C|dp/sum p|*dt (Sec. 4): 0.01, 1 */
   double fixed_dt;           /* 0: CFL rule; > 0: fixed step (accuracy tests, Sec. 4.1) */
-  int storage;               /* CGKS_FP64                                                */
+  int storage;               /* CGKS_FP64 or CGKS_FP32_STORAGE (2D)                      */
 } cgks_config;
 
 typedef struct {

@@ -17,6 +17,7 @@ from . import build as _build
 
 CGKS_OK, CGKS_EINVAL, CGKS_ENOMEM, CGKS_EDEVICE, CGKS_ENONPHYS, CGKS_EBUSY, CGKS_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PERIODIC, FREE, WALL, INFLOW = 0, 1, 2, 3
+CGKS_FP64, CGKS_FP32_STORAGE = 0, 1
 
 
 class cgks_config(C.Structure):
@@ -96,7 +97,7 @@ def _torch():
     return torch
 
 
-def make_config(prob) -> cgks_config:
+def make_config(prob, storage: int = CGKS_FP64) -> cgks_config:
     d = prob.config_dict()
     cfg = cgks_config()
     for k in ('dim', 'nx', 'ny'):
@@ -107,7 +108,7 @@ def make_config(prob) -> cgks_config:
         cfg.bc[s] = int(d['bc'][s])
         for q in range(4):
             cfg.inflow_prim[s][q] = float(d['inflow_prim'][s][q])
-    cfg.storage = 0
+    cfg.storage = int(storage)
     return cfg
 
 
@@ -118,7 +119,7 @@ KERNEL_NAMES_1D = ['faces1', 'update1', 'faces2', 'update2']
 class Solver:
     """One simulation on the GPU (see paper_2001_01570_amd.inputs.Problem)."""
 
-    def __init__(self, prob, stream=None, load_state: bool = True):
+    def __init__(self, prob, stream=None, load_state: bool = True, storage: int = CGKS_FP64):
         torch = _torch()
         L = load()
         self.prob = prob
@@ -128,7 +129,7 @@ class Solver:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = C.c_void_p()
-        rc = L.cgks_create(C.byref(make_config(prob)), C.c_void_p(stream.cuda_stream), C.byref(h))
+        rc = L.cgks_create(C.byref(make_config(prob, storage)), C.c_void_p(stream.cuda_stream), C.byref(h))
         if rc:
             raise CgksError(rc, 'cgks_create')
         self.h = h

@@ -124,8 +124,20 @@ __device__ __forceinline__ void apply_rule(const Geom& G, int kind, int side, in
   }
 }
 
+// Gradient planes of a state buffer (NC averages, then 2 x NC gradient planes
+// in 2D, NC in 1D, each N values).  GT = double: FP64 storage; GT = float:
+// the gradient planes are stored as FP32 in the same buffer (averages FP64).
+template <class GT>
+__device__ __forceinline__ const GT* grad_planes(const double* S, size_t N, int nc) {
+  return reinterpret_cast<const GT*>(S + nc * N);
+}
+template <class GT>
+__device__ __forceinline__ GT* grad_planes(double* S, size_t N, int nc) {
+  return reinterpret_cast<GT*>(S + nc * N);
+}
+
 // W and its gradient along dir (0: x, 1: y) of cell (i, j), ghosts included
-template <int NC>
+template <int NC, class GT = double>
 __device__ __forceinline__ void load_cell(const double* S, const Geom& G, int i, int j, int dir,
                                           double* W, double* Gd) {
   int kx, sx = 0, ky = -1, sy = 0;
@@ -137,13 +149,14 @@ __device__ __forceinline__ void load_cell(const double* S, const Geom& G, int i,
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     W[k] = S[k * N + id];
-    Gd[k] = S[(NC + NC * dir + k) * N + id];
+    Gd[k] = grad_planes<GT>(S, N, NC)[(NC * dir + k) * N + id];
   }
   apply_rule<NC>(G, kx, sx, 0, dir, W, Gd);
   if constexpr (NC == 4) apply_rule<NC>(G, ky, 2 + sy, 1, dir, W, Gd);
 }
 
 // one component k of W and of its gradient along dir at cell (i, j), ghosts included (2D)
+template <class GT>
 __device__ __forceinline__ void load_comp(const double* S, const Geom& G, int i, int j, int dir, int k,
                                           double& w, double& gd) {
   int kx, sx = 0, ky, sy = 0;
@@ -152,7 +165,7 @@ __device__ __forceinline__ void load_comp(const double* S, const Geom& G, int i,
   const size_t N = (size_t)G.nx * G.ny;
   const size_t id = (size_t)sj * G.nx + si;
   w = S[k * N + id];
-  gd = S[(4 + 4 * dir + k) * N + id];
+  gd = grad_planes<GT>(S, N, 4)[(4 * dir + k) * N + id];
   // rules applied to one component: x rule, then y rule
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -173,10 +186,20 @@ __device__ __forceinline__ void load_comp(const double* S, const Geom& G, int i,
   }
 }
 
+// the averages only (any storage of the gradients)
 template <int NC>
 __device__ __forceinline__ void load_avg(const double* S, const Geom& G, int i, int j, double* W) {
+  int kx, sx = 0, ky = -1, sy = 0;
+  const int si = src_index(i, G.nx, G.bc[0], G.bc[1], kx, sx);
+  int sj = 0;
+  if constexpr (NC == 4) sj = src_index(j, G.ny, G.bc[2], G.bc[3], ky, sy);
+  const size_t N = (size_t)G.nx * (NC == 4 ? G.ny : 1);
+  const size_t id = (size_t)sj * G.nx + si;
   double Gd[NC];
-  load_cell<NC>(S, G, i, j, 0, W, Gd);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) { W[k] = S[k * N + id]; Gd[k] = 0.0; }
+  apply_rule<NC>(G, kx, sx, 0, 0, W, Gd);
+  if constexpr (NC == 4) apply_rule<NC>(G, ky, 2 + sy, 1, 0, W, Gd);
 }
 
 // ---------------------------------------------------------------- step control
@@ -298,7 +321,7 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 // Tile (bx, by) of the face grid of one direction: DIR 0 tiles (faces, rows),
 // DIR 1 tiles (columns, faces).
 // lds: the kernel's LDS tile, NQ rows of NSEG line segments.
-template <int DIR, int STAGE>
+template <int DIR, int STAGE, class GT = double>
 __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx, int by, double (*lds)[NSEG]) {
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
@@ -337,9 +360,9 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
         if (interior) {
           const size_t id = (size_t)j * G.nx + i;
           w[m] = S[k * N + id];
-          gd[m] = S[(4 + 4 * DIR + k) * N + id];
+          gd[m] = grad_planes<GT>(S, N, 4)[(4 * DIR + k) * N + id];
         } else {
-          load_comp(S, G, i, j, DIR, k, w[m], gd[m]);
+          load_comp<GT>(S, G, i, j, DIR, k, w[m], gd[m]);
         }
       }
       const double ref = w[1];
@@ -404,18 +427,18 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   for (int q = 0; q < NO; ++q) F[q * plane + idx] = acc[q];
 }
 
-template <int DIR, int STAGE>
+template <int DIR, int STAGE, class GT>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom G, Bufs B) {
   __shared__ double lds[NQ][NSEG];
   int bx, by;
   xcd_tile(bx, by);
-  faces2_body<DIR, STAGE>(G, B, bx, by, lds);
+  faces2_body<DIR, STAGE, GT>(G, B, bx, by, lds);
 }
 
 // ---------------------------------------------------------------- 2D update
 
 // Cell block (bx, by) of 64 x 4 cells; part: its index among the CFL partials.
-template <int STAGE>
+template <int STAGE, class GT = double>
 __device__ __forceinline__ void update2_body(const Geom& G, const Bufs& B, int bx, int by, int part) {
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
@@ -450,10 +473,12 @@ __device__ __forceinline__ void update2_body(const Geom& G, const Bufs& B, int b
         Wst[k] = W[k] + 0.5 * dt * L + dt * dt / 8.0 * Lt;
         B.Ws[k * N + id] = Wst[k];
         B.P[k * N + id] = W[k] + dt * L + dt * dt / 6.0 * Lt;
-        B.Ws[(4 + k) * N + id] = ((FX[(8 + k) * px + xr] - FX[(8 + k) * px + xl]) + jx) / G.dx;
-        B.P[(4 + k) * N + id] = ((FX[(12 + k) * px + xr] - FX[(12 + k) * px + xl]) + jx) / G.dx;
-        B.Ws[(8 + k) * N + id] = ((FY[(8 + k) * py + yr] - FY[(8 + k) * py + yl]) + jy) / G.dy;
-        B.P[(8 + k) * N + id] = ((FY[(12 + k) * py + yr] - FY[(12 + k) * py + yl]) + jy) / G.dy;
+        GT* gws = grad_planes<GT>(B.Ws, N, 4);
+        GT* gp = grad_planes<GT>(B.P, N, 4);
+        gws[k * N + id] = (GT)(((FX[(8 + k) * px + xr] - FX[(8 + k) * px + xl]) + jx) / G.dx);
+        gp[k * N + id] = (GT)(((FX[(12 + k) * px + xr] - FX[(12 + k) * px + xl]) + jx) / G.dx);
+        gws[(4 + k) * N + id] = (GT)(((FY[(8 + k) * py + yr] - FY[(8 + k) * py + yl]) + jy) / G.dy);
+        gp[(4 + k) * N + id] = (GT)(((FY[(12 + k) * py + yr] - FY[(12 + k) * py + yl]) + jy) / G.dy);
       }
       if (!admissible<4>(Wst, G.gas.gamma)) flag_bad(sc, id);
     } else {
@@ -468,8 +493,11 @@ __device__ __forceinline__ void update2_body(const Geom& G, const Bufs& B, int b
         Lt += -(FY[k * py + yr] - FY[k * py + yl]) / G.dy;
         Wn[k] = B.P[k * N + id] + c3 * Lt;
         So[k * N + id] = Wn[k];
-        So[(4 + k) * N + id] = B.P[(4 + k) * N + id] + c3 * (FX[(4 + k) * px + xr] - FX[(4 + k) * px + xl]) / G.dx;
-        So[(8 + k) * N + id] = B.P[(8 + k) * N + id] + c3 * (FY[(4 + k) * py + yr] - FY[(4 + k) * py + yl]) / G.dy;
+        GT* go = grad_planes<GT>(So, N, 4);
+        const GT* gp = grad_planes<GT>(B.P, N, 4);
+        go[k * N + id] = (GT)((double)gp[k * N + id] + c3 * (FX[(4 + k) * px + xr] - FX[(4 + k) * px + xl]) / G.dx);
+        go[(4 + k) * N + id] =
+            (GT)((double)gp[(4 + k) * N + id] + c3 * (FY[(4 + k) * py + yr] - FY[(4 + k) * py + yl]) / G.dy);
       }
       if (!admissible<4>(Wn, G.gas.gamma)) flag_bad(sc, id);
       else lam = cell_lambda<4>(Wn, G);
@@ -478,9 +506,31 @@ __device__ __forceinline__ void update2_body(const Geom& G, const Bufs& B, int b
   if (STAGE == 2) reduce_lambda(B.lam_part, part, lam);
 }
 
-template <int STAGE>
+template <int STAGE, class GT>
 __global__ __launch_bounds__(256) void k_update2(Geom G, Bufs B) {
-  update2_body<STAGE>(G, B, blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x);
+  update2_body<STAGE, GT>(G, B, blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// State layout conversion for FP32 storage (2D): the averages are copied, the
+// 8 gradient planes converted (to storage: rounded to nearest FP32).
+__global__ __launch_bounds__(256) void k_to_storage32(const double* src, double* dst, size_t N) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= N) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) dst[k * N + id] = src[k * N + id];
+  float* g = grad_planes<float>(dst, N, 4);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) g[q * N + id] = (float)src[(4 + q) * N + id];
+}
+
+__global__ __launch_bounds__(256) void k_from_storage32(const double* src, double* dst, size_t N) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= N) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) dst[k * N + id] = src[k * N + id];
+  const float* g = grad_planes<float>(src, N, 4);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) dst[(4 + q) * N + id] = (double)g[q * N + id];
 }
 
 // ---------------------------------------------------------------- 1D
@@ -747,7 +797,7 @@ static int validate(const cgks_config* c) {
   if (!(c->gamma > 1.0) || !(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) return CGKS_EINVAL;
   if (!(c->cfl > 0.0) && !(c->fixed_dt > 0.0)) return CGKS_EINVAL;
   if (!(c->weno_eps > 0.0) || !(c->tau_eps > 0.0) || c->tau_C < 0.0) return CGKS_EINVAL;
-  if (c->storage != CGKS_FP64) return CGKS_EINVAL;
+  if (c->storage != CGKS_FP64 && !(c->storage == CGKS_FP32_STORAGE && c->dim == 2)) return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
     if (c->bc[s] < 0 || c->bc[s] > 3) return CGKS_EINVAL;
     const int n = s < 2 ? c->nx : c->ny;
@@ -901,8 +951,19 @@ extern "C" int cgks_set_state(cgks_ctx* c, const double* fields, int on_device, 
   h.cfl = c->cfg.cfl;
   h.fixed_dt = c->cfg.fixed_dt;
   h.bad_cell = ULLONG_MAX;
-  HIPCHK(hipMemcpyAsync(c->B.S[0], fields, c->nf * c->N * sizeof(double),
-                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  if (c->cfg.storage == CGKS_FP32_STORAGE) {
+    // host fields are staged in W* (free between steps), then converted
+    const double* src = fields;
+    if (!on_device) {
+      HIPCHK(hipMemcpyAsync(c->B.Ws, fields, c->nf * c->N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      src = c->B.Ws;
+    }
+    k_to_storage32<<<(unsigned)((c->N + 255) / 256), 256, 0, c->stream>>>(src, c->B.S[0], c->N);
+    HIPCHK(hipGetLastError());
+  } else {
+    HIPCHK(hipMemcpyAsync(c->B.S[0], fields, c->nf * c->N * sizeof(double),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  }
   HIPCHK(hipMemcpyAsync(c->B.sc, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
   if (c->cfg.dim == 2) k_scan<4><<<update_grid(c->G), 256, 0, c->stream>>>(c->G, c->B);
   else k_scan<3><<<update_grid(c->G), 256, 0, c->stream>>>(c->G, c->B);
@@ -926,12 +987,17 @@ static void launch_step(cgks_ctx* c) {
     const dim3 gx((G.nx + 1 + TF - 1) / TF, (G.ny + TT - 1) / TT);
     const dim3 gy((G.nx + TT - 1) / TT, (G.ny + 1 + TF - 1) / TF);
     const Bufs B = c->B;
-    timed(c, 0, [&] { k_faces2<0, 1><<<gx, FACE_THREADS, 0, s>>>(G, B); });
-    timed(c, 1, [&] { k_faces2<1, 1><<<gy, FACE_THREADS, 0, s>>>(G, B); });
-    timed(c, 2, [&] { k_update2<1><<<gu, 256, 0, s>>>(G, B); });
-    timed(c, 3, [&] { k_faces2<0, 2><<<gx, FACE_THREADS, 0, s>>>(G, B); });
-    timed(c, 4, [&] { k_faces2<1, 2><<<gy, FACE_THREADS, 0, s>>>(G, B); });
-    timed(c, 5, [&] { k_update2<2><<<gu, 256, 0, s>>>(G, B); });
+    auto stage_kernels = [&](auto gt) {
+      using GT = decltype(gt);
+      timed(c, 0, [&] { k_faces2<0, 1, GT><<<gx, FACE_THREADS, 0, s>>>(G, B); });
+      timed(c, 1, [&] { k_faces2<1, 1, GT><<<gy, FACE_THREADS, 0, s>>>(G, B); });
+      timed(c, 2, [&] { k_update2<1, GT><<<gu, 256, 0, s>>>(G, B); });
+      timed(c, 3, [&] { k_faces2<0, 2, GT><<<gx, FACE_THREADS, 0, s>>>(G, B); });
+      timed(c, 4, [&] { k_faces2<1, 2, GT><<<gy, FACE_THREADS, 0, s>>>(G, B); });
+      timed(c, 5, [&] { k_update2<2, GT><<<gu, 256, 0, s>>>(G, B); });
+    };
+    if (c->cfg.storage == CGKS_FP32_STORAGE) stage_kernels(0.0f);
+    else stage_kernels(0.0);
   } else {
     const unsigned nf = (unsigned)((G.nx + 1 + 255) / 256);
     const Bufs B = c->B;
@@ -1029,8 +1095,18 @@ extern "C" int cgks_get_state(cgks_ctx* c, double* out, int on_device, double* t
   int rc = pull_scalars(c);
   if (rc) return rc;
   if (out) {
-    HIPCHK(hipMemcpyAsync(out, c->B.S[c->host_sc->cur], c->nf * c->N * sizeof(double),
-                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    const double* S = c->B.S[c->host_sc->cur];
+    if (c->cfg.storage == CGKS_FP32_STORAGE) {
+      // converted to FP64 straight into a device output, else via W* (free between steps)
+      double* dst = on_device ? out : c->B.Ws;
+      k_from_storage32<<<(unsigned)((c->N + 255) / 256), 256, 0, c->stream>>>(S, dst, c->N);
+      HIPCHK(hipGetLastError());
+      if (!on_device)
+        HIPCHK(hipMemcpyAsync(out, c->B.Ws, c->nf * c->N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(out, S, c->nf * c->N * sizeof(double),
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
   }
   if (t) *t = c->host_sc->t;
@@ -1209,7 +1285,7 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   if (!b || !fields || !slot) return CGKS_EINVAL;
   int rc = validate(cfg);
   if (rc) return rc;
-  if (cfg->dim != 2) return CGKS_EINVAL;
+  if (cfg->dim != 2 || cfg->storage != CGKS_FP64) return CGKS_EINVAL;
   if (!(t_end > 0.0) && max_steps <= 0) return CGKS_EINVAL;   // a request needs an end
   int k = 0;
   while (k < b->max_slots && b->info[k].used) ++k;
