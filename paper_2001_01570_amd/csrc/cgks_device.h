@@ -120,15 +120,25 @@ CGKS_HD __forceinline__ double weno_left(double a, double c, double d, double A,
   t = k1 + 0.25 * k3;
   u = k2 + L42 * k4;
   const double b6 = t * t + S2 * u * u + S3 * k3 * k3 + S4 * k4 * k4;
-  // WENO-Z weights with the reference value of eq. (tau)
+  // WENO-Z weights with the reference value of eq. (tau):
+  //   alpha_k = d_k (1 + z / x_k),  x_k = beta_k + eps,  value = sum alpha_k q_k / sum alpha_k.
+  // Numerator and denominator are both multiplied by P = prod_j x_j, so that
+  // alpha_k becomes d_k (P + z P_k) with P_k = prod_{j != k} x_j (prefix times
+  // suffix products) and one reciprocal remains.  (x_k >= eps keeps P far from
+  // underflow; it overflows only for indicators beyond 1e40.)
   const double z = fabs(3.0 * (b0 - b4) + (b4 - b3));
-  const double a0 = (3.0 / 98.0) * (1.0 + z * recip(b0 + eps));
-  const double a1 = (5.0 / 98.0) * (1.0 + z * recip(b1 + eps));
-  const double a2 = (4.0 / 49.0) * (1.0 + z * recip(b2 + eps));
-  const double a3 = (7.0 / 98.0) * (1.0 + z * recip(b3 + eps));
-  const double a4 = (7.0 / 98.0) * (1.0 + z * recip(b4 + eps));
-  const double a5 = (17.0 / 49.0) * (1.0 + z * recip(b5 + eps));
-  const double a6 = (17.0 / 49.0) * (1.0 + z * recip(b6 + eps));
+  const double x0 = b0 + eps, x1 = b1 + eps, x2 = b2 + eps, x3 = b3 + eps, x4 = b4 + eps, x5 = b5 + eps,
+               x6 = b6 + eps;
+  const double l1 = x0, l2 = l1 * x1, l3 = l2 * x2, l4 = l3 * x3, l5 = l4 * x4, l6 = l5 * x5;
+  const double r5 = x6, r4 = r5 * x5, r3 = r4 * x4, r2 = r3 * x3, r1 = r2 * x2, r0 = r1 * x1;
+  const double P = l6 * x6;
+  const double a0 = (3.0 / 98.0) * (P + z * r0);
+  const double a1 = (5.0 / 98.0) * (P + z * (l1 * r1));
+  const double a2 = (4.0 / 49.0) * (P + z * (l2 * r2));
+  const double a3 = (7.0 / 98.0) * (P + z * (l3 * r3));
+  const double a4 = (7.0 / 98.0) * (P + z * (l4 * r4));
+  const double a5 = (17.0 / 49.0) * (P + z * (l5 * r5));
+  const double a6 = (17.0 / 49.0) * (P + z * l6);
   const double num = a0 * q0 + (a1 + a3) * q1 + a2 * q2 + a4 * q4 + a5 * q5 + a6 * q6;
   const double den = a0 + a1 + a2 + a3 + a4 + a5 + a6;
   return num * recip(den);
@@ -164,6 +174,55 @@ struct TangW { double v[5], d1[5], d2[5]; };
 }
 
 __constant__ static const TangW kTang[2] = CGKS_TANG_WEIGHTS;
+
+// ----------------------------------------------------------------------------
+// erfc and exp near zero.  The half-space moments take erfc(-s sqrt(lambda) U)
+// and exp(-lambda U^2); at low Mach numbers both arguments are small, where the
+// Maclaurin series converge fast:
+//   erf(x) = 2/sqrt(pi) sum_n (-1)^n x^(2n+1) / (n! (2n+1)),   |x| <= 1/2, n <= 11
+//            (first omitted term < 3e-18, relative to erfc >= 0.47: < 6e-18)
+//   exp(y) = sum_n y^n / n!,                                     |y| <= 1/4, n <= 13
+//            (first omitted term < 5e-20)
+// Larger arguments use the library functions.  The operation counter keeps the
+// library calls (one transcendental each).
+// ----------------------------------------------------------------------------
+#ifndef CGKS_OPCOUNT
+CGKS_HD __forceinline__ double erfc_moment(double x) {
+  if (!(fabs(x) <= 0.5)) return erfc(x);
+  // coefficients (-1)^n / (n! (2n+1)), Horner in x^2, times 2/sqrt(pi)
+  constexpr double c[12] = {1.0,
+                            -1.0 / 3.0,
+                            1.0 / 10.0,
+                            -1.0 / 42.0,
+                            1.0 / 216.0,
+                            -1.0 / 1320.0,
+                            1.0 / 9360.0,
+                            -1.0 / 75600.0,
+                            1.0 / 685440.0,
+                            -1.0 / 6894720.0,
+                            1.0 / 76204800.0,
+                            -1.0 / 918086400.0};
+  const double x2 = x * x;
+  double sum = c[11];
+#pragma unroll
+  for (int n = 10; n >= 0; --n) sum = sum * x2 + c[n];
+  return 1.0 - 1.1283791670955125739 * x * sum;
+}
+
+CGKS_HD __forceinline__ double exp_moment(double y) {
+  if (!(fabs(y) <= 0.25)) return exp(y);
+  constexpr double c[14] = {1.0,           1.0,           1.0 / 2.0,         1.0 / 6.0,          1.0 / 24.0,
+                            1.0 / 120.0,   1.0 / 720.0,   1.0 / 5040.0,      1.0 / 40320.0,      1.0 / 362880.0,
+                            1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0};
+  double sum = c[13];
+#pragma unroll
+  for (int n = 12; n >= 0; --n) sum = sum * y + c[n];
+  return sum;
+}
+#else
+CGKS_HD __forceinline__ double erfc_moment(double x) { return erfc(x); }
+CGKS_HD __forceinline__ double exp_moment(double y) { return exp(y); }
+#endif
 
 // ----------------------------------------------------------------------------
 // gas-kinetic evolution at one interface point (normal = first velocity
@@ -235,9 +294,9 @@ CGKS_HD __forceinline__ void moments(const double* W, const Gas& g, int half, Mo
   } else {
     const double s = (double)half;
     const double sl = sqrt(m.lam);
-    m.mu[0] = 0.5 * erfc(-s * sl * m.U);
+    m.mu[0] = 0.5 * erfc_moment(-s * sl * m.U);
     // 1/sqrt(lambda) = 2 h sqrt(lambda)
-    m.mu[1] = m.U * m.mu[0] + s * exp(-m.lam * m.U * m.U) * (0.56418958354775628695 * h * sl);
+    m.mu[1] = m.U * m.mu[0] + s * exp_moment(-m.lam * m.U * m.U) * (0.56418958354775628695 * h * sl);
   }
 #pragma unroll
   for (int n = 1; n < 6; ++n) m.mu[n + 1] = m.U * m.mu[n] + (double)n * h * m.mu[n - 1];

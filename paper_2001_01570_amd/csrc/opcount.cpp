@@ -59,6 +59,7 @@ inline CD sqrt(const CD& a) { ++g_ops.sqrt_; return CD(std::sqrt(a.v)); }
 inline CD exp(const CD& a) { ++g_ops.exp_; return CD(std::exp(a.v)); }
 inline CD erfc(const CD& a) { ++g_ops.erfc_; return CD(std::erfc(a.v)); }
 
+#define CGKS_OPCOUNT
 #define double CD
 #include "cgks_device.h"
 #undef double
