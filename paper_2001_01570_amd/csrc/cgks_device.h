@@ -613,7 +613,12 @@ CGKS_HD __forceinline__ void combine(const double* W0, const double* M2, const S
     if constexpr (NC == 4) M1[2] = W0[2] * U;
     M1[NC - 1] = (W0[NC - 1] + p) * U;
   }
-  const double Eh = exp(-0.5 * dt * recip(tau));
+  // Eh = e^{a}, a = -dt/(2 tau).  Every term Eh contributes is at most
+  // (4/3)|a| e^{a} relative to the term it is added to, below 3.2e-17 for
+  // a < -42: there Eh is taken as 0 and the exponential skipped (the usual
+  // case in smooth flow, where a is about -50).
+  const double ah = -0.5 * dt * recip(tau);
+  const double Eh = ah < -42.0 ? 0.0 : exp(ah);
   const double omh = 1.0 - Eh;
   const double idt = recip(dt);
   const double e1p = 4.0 * tau * omh * omh * idt * idt;
