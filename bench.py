@@ -84,14 +84,8 @@ def launch_units(kernel, nx, ny):
 
 
 def source_digest():
-    """Digest of the HIP sources: counter-based figures are valid only for the
-    kernels they were taken on."""
-    import hashlib
-    h = hashlib.sha256()
-    for rel in ('paper_2001_01570_amd/csrc/cgks.hip', 'paper_2001_01570_amd/csrc/cgks_device.h'):
-        with open(os.path.join(ROOT, rel), 'rb') as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    from paper_2001_01570_amd.build import source_digest as d
+    return d()
 
 
 def measured_traffic(kernel, nx, ny):

@@ -113,6 +113,12 @@ int cgks_last_bad_cell(const cgks_ctx *ctx, long *cell);
 int cgks_set_profiling(cgks_ctx *ctx, int mask);
 int cgks_kernel_times(cgks_ctx *ctx, double *ms, long *calls, int n);
 int cgks_counters(cgks_ctx *ctx, cgks_counters_t *out);
+
+/* Tile shape of the face kernels per direction: 0 = 8 faces x 16 segments,
+ * 1 = 4 x 32, 2 = 2 x 64 (faces along the normal x segments along the face).
+ * Results do not depend on the shape (each face is computed alike); the
+ * choice only changes speed and is made by the autotuner's table. */
+int cgks_set_tiles(cgks_ctx *ctx, int x_shape, int y_shape);
 void cgks_destroy(cgks_ctx *ctx);
 const char *cgks_strerror(int code);
 

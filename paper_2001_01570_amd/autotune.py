@@ -1,0 +1,96 @@
+"""Autotuner of the face kernels' tile shape per direction and grid size.
+
+    python -m paper_2001_01570_amd.autotune [--sizes 64,128,256,512,1024,2048] [--steps 20]
+
+For each grid size it times every tile shape (HIP events around each face
+launch, two stages, over a few steps of the acoustic-pulse workload) and
+keeps the fastest shape per direction; the table (tuning.json, with the
+digest of the HIP sources it was measured on) is read by every 2D context at
+creation.  A table from other sources, or no table, leaves the default shape.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(PKG, 'tuning.json')
+SHAPES = {0: '8x16', 1: '4x32', 2: '2x64'}
+
+_table = None
+
+
+def _load():
+    global _table
+    if _table is None:
+        _table = {}
+        if os.path.exists(TABLE):
+            from .build import source_digest
+            with open(TABLE) as f:
+                t = json.load(f)
+            if t.get('source_digest') == source_digest():
+                _table = t
+    return _table
+
+
+def tiles_for(nx: int, ny: int):
+    """(x shape, y shape) for a grid: the entry nearest in cell count (log scale)."""
+    entries = _load().get('entries', [])
+    if not entries:
+        return 0, 0
+    e = min(entries, key=lambda e: abs(math.log(e['nx'] * e['ny']) - math.log(nx * ny)))
+    return e['x'], e['y']
+
+
+def tune(n: int, steps: int = 20, rounds: int = 3):
+    """Fastest shape per direction on an n x n grid: every shape is timed in
+    each of `rounds` interleaved rounds (clock and cache warm-up affect all
+    shapes alike) and keeps its best round."""
+    import torch
+    from . import inputs as I
+    from .cgks import Solver
+    p = I.acoustic_pulse_2d(n, seed=0, cfl=0.15)
+    s = Solver(p)
+    s.run_steps(10)
+    ms = {k: {'x': float('inf'), 'y': float('inf')} for k in SHAPES}
+    for _ in range(rounds):
+        for shape in SHAPES:
+            s.set_tiles(shape, shape)
+            s.run_steps(2)
+            s.set_profiling(True, kinds=['xfaces1', 'yfaces1', 'xfaces2', 'yfaces2'])
+            s.run_steps(steps)
+            torch.cuda.synchronize()
+            t = s.kernel_times()
+            s.set_profiling(False)
+            ms[shape]['x'] = min(ms[shape]['x'], (t['xfaces1'][0] + t['xfaces2'][0]) / steps)
+            ms[shape]['y'] = min(ms[shape]['y'], (t['yfaces1'][0] + t['yfaces2'][0]) / steps)
+    best_x = min(ms, key=lambda k: ms[k]['x'])
+    best_y = min(ms, key=lambda k: ms[k]['y'])
+    s.close()
+    return {'nx': n, 'ny': n, 'x': best_x, 'y': best_y,
+            'ms_per_step': {SHAPES[k]: v for k, v in ms.items()}}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split('\n')[0])
+    ap.add_argument('--sizes', default='64,128,256,512,1024,2048')
+    ap.add_argument('--steps', type=int, default=20)
+    ap.add_argument('--out', default=TABLE)
+    a = ap.parse_args(argv)
+    from .build import source_digest
+    entries = []
+    for n in [int(x) for x in a.sizes.split(',')]:
+        e = tune(n, a.steps)
+        print('[autotune] %d^2: x %s, y %s  %s' % (n, SHAPES[e['x']], SHAPES[e['y']], e['ms_per_step']),
+              file=sys.stderr, flush=True)
+        entries.append(e)
+    with open(a.out + '.tmp', 'w') as f:
+        json.dump({'source_digest': source_digest(), 'shapes': SHAPES, 'entries': entries}, f, indent=1)
+    os.replace(a.out + '.tmp', a.out)
+
+
+if __name__ == '__main__':
+    main()

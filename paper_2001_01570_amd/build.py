@@ -26,6 +26,17 @@ def hipcc() -> str:
 
 
 FLOPS_JSON = os.path.join(PKG, 'flops.json')
+
+
+def source_digest() -> str:
+    """Digest of the HIP sources: measured or tuned figures are valid only for
+    the kernels they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in (os.path.join(PKG, 'csrc', 'cgks.hip'), os.path.join(PKG, 'csrc', 'cgks_device.h')):
+        with open(path, 'rb') as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 OPCOUNT_SRC = os.path.join(PKG, 'csrc', 'opcount.cpp')
 
 

@@ -77,6 +77,7 @@ def load():
     L.cgks_set_profiling.argtypes = [C.c_void_p, C.c_int]
     L.cgks_kernel_times.argtypes = [C.c_void_p, _D, C.POINTER(C.c_long), C.c_int]
     L.cgks_kernel_times.restype = C.c_int
+    L.cgks_set_tiles.argtypes = [C.c_void_p, C.c_int, C.c_int]
     L.cgks_batch_create.argtypes = [C.c_size_t, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]
     L.cgks_batch_admit.argtypes = [C.c_void_p, C.POINTER(cgks_config), C.c_void_p, C.c_int, C.c_double, C.c_long,
                                    C.POINTER(C.c_int)]
@@ -133,6 +134,9 @@ class Solver:
         if rc:
             raise CgksError(rc, 'cgks_create')
         self.h = h
+        if prob.dim == 2:
+            from . import autotune
+            self.set_tiles(*autotune.tiles_for(prob.nx, prob.ny))
         if load_state:
             self.set_state(prob.fields, 0.0)
 
@@ -166,6 +170,10 @@ class Solver:
         used = C.c_double()
         self._check(load().cgks_step_dt(self.h, float(dt), C.byref(used)), 'cgks_step')
         return used.value
+
+    def set_tiles(self, x_shape: int, y_shape: int):
+        """Face tile shape per direction (see cgks_set_tiles); speed only."""
+        self._check(load().cgks_set_tiles(self.h, int(x_shape), int(y_shape)), 'cgks_set_tiles')
 
     def run_steps(self, n: int):
         self._check(load().cgks_run_steps(self.h, int(n)), 'cgks_run_steps')

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <new>
 #include <vector>
 
@@ -26,12 +27,25 @@
 
 namespace cgks {
 
-constexpr int TF = 8;           // faces per tile along the normal direction
-constexpr int TT = 16;          // face segments per tile along the tangential direction
-constexpr int TH = TT + 4;      // tangential extent including the 2+2 halo
-constexpr int NSEG = TF * TH;   // reconstructed line segments per tile (160)
+// Face tile: F faces along the normal x T face segments along the tangential,
+// 256 threads (one per Gauss point).  Shapes differ in halo overhead ((T+4)/T
+// reconstructed line segments per face segment) and in the width of the rows
+// they read and write; the shape is chosen per direction at run time (tuned).
+template <int F_, int T_>
+struct Tile {
+  static constexpr int F = F_, T = T_;
+  static constexpr int H = T_ + 4;          // tangential extent including the 2+2 halo
+  static constexpr int NSEG = F_ * H;       // reconstructed line segments per tile
+  static_assert(2 * F_ * T_ == 256 && 32 % F_ == 0, "one 256-thread block per tile");
+};
+using Tile8x16 = Tile<8, 16>;
+using Tile4x32 = Tile<4, 32>;
+using Tile2x64 = Tile<2, 64>;
+constexpr int kTileShapes = 3;
+constexpr int TF = Tile8x16::F, TT = Tile8x16::T;   // the batched kernels' shape
+constexpr int NSEG = Tile8x16::NSEG;
 constexpr int NQ = 24;          // per segment: 5 quantities x 4 components + 4 reference values
-constexpr int FACE_THREADS = 2 * TF * TT;   // one thread per Gauss point of the tile's face segments
+constexpr int FACE_THREADS = 256;   // one thread per Gauss point of the tile's face segments
 // waves per SIMD the face kernels are compiled for (register budget 512 / waves:
 // 168 at 3; the latency of the point evaluation needs the occupancy more than
 // stage 1 needs its last few registers)
@@ -321,8 +335,10 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 // Tile (bx, by) of the face grid of one direction: DIR 0 tiles (faces, rows),
 // DIR 1 tiles (columns, faces).
 // lds: the kernel's LDS tile, NQ rows of NSEG line segments.
-template <int DIR, int STAGE, class GT = double>
-__device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx, int by, double (*lds)[NSEG]) {
+template <int DIR, int STAGE, class GT = double, class TL = Tile8x16>
+__device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx, int by,
+                                            double (*lds)[TL::NSEG]) {
+  constexpr int TF = TL::F, TT = TL::T, TH = TL::H, NSEG = TL::NSEG;
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
   const double dt = sc->dt;
@@ -383,7 +399,7 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   // in adjacent lanes (their reads of a line row coincide or fall in different
   // banks), a half-wave covers 16 segments along x.  x faces: the two points in
   // the two half-waves (within a half-wave, reads of lines 2 or 4 rows apart
-  // would share LDS banks), a half-wave covers 4 rows of TF faces.
+  // would share LDS banks), a half-wave covers 32/TF rows of TF faces.
   int gp, fl, tl;
   if (DIR == 0) {
     const int lane = threadIdx.x & 63;
@@ -427,12 +443,12 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   for (int q = 0; q < NO; ++q) F[q * plane + idx] = acc[q];
 }
 
-template <int DIR, int STAGE, class GT>
+template <int DIR, int STAGE, class GT, class TL>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom G, Bufs B) {
-  __shared__ double lds[NQ][NSEG];
+  __shared__ double lds[NQ][TL::NSEG];
   int bx, by;
   xcd_tile(bx, by);
-  faces2_body<DIR, STAGE, GT>(G, B, bx, by, lds);
+  faces2_body<DIR, STAGE, GT, TL>(G, B, bx, by, lds);
 }
 
 // ---------------------------------------------------------------- 2D update
@@ -747,6 +763,7 @@ struct cgks_ctx {
   long calls[kKinds];
   // run_steps replays GRAPH_STEPS steps as one HIP graph (captured on first use)
   hipGraphExec_t exec;
+  int tile[2];          // face tile shape per direction (0: 8x16, 1: 4x32, 2: 2x64)
 };
 
 constexpr long GRAPH_STEPS = 25;
@@ -917,6 +934,18 @@ extern "C" int cgks_set_profiling(cgks_ctx* c, int on) {
   return CGKS_OK;
 }
 
+extern "C" int cgks_set_tiles(cgks_ctx* c, int x_shape, int y_shape) {
+  if (!c || x_shape < 0 || x_shape >= kTileShapes || y_shape < 0 || y_shape >= kTileShapes) return CGKS_EINVAL;
+  if (c->tile[0] != x_shape || c->tile[1] != y_shape) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);   // the graph holds the old launches
+    c->exec = nullptr;
+  }
+  c->tile[0] = x_shape;
+  c->tile[1] = y_shape;
+  return CGKS_OK;
+}
+
 extern "C" int cgks_kernel_times(cgks_ctx* c, double* ms, long* calls, int n) {
   if (!c || !ms || !calls) return CGKS_EINVAL;
   int rc = resolve_events(c);
@@ -984,16 +1013,34 @@ static void launch_step(cgks_ctx* c) {
   const dim3 gu = update_grid(G);
   k_begin<<<1, 256, 0, s>>>(c->B.sc, c->B.lam_part, (int)(gu.x * gu.y));
   if (G.dim == 2) {
-    const dim3 gx((G.nx + 1 + TF - 1) / TF, (G.ny + TT - 1) / TT);
-    const dim3 gy((G.nx + TT - 1) / TT, (G.ny + 1 + TF - 1) / TF);
     const Bufs B = c->B;
+    // one direction's face kernel of one stage with the context's tile shape
+    auto faces = [&](auto dir, auto stage, auto gt, int kind) {
+      constexpr int DIR = decltype(dir)::value, STAGE = decltype(stage)::value;
+      using GT = decltype(gt);
+      auto go = [&](auto tl) {
+        using TL = decltype(tl);
+        const dim3 g = DIR == 0 ? dim3((G.nx + 1 + TL::F - 1) / TL::F, (G.ny + TL::T - 1) / TL::T)
+                                : dim3((G.nx + TL::T - 1) / TL::T, (G.ny + 1 + TL::F - 1) / TL::F);
+        timed(c, kind, [&] { k_faces2<DIR, STAGE, GT, TL><<<g, FACE_THREADS, 0, s>>>(G, B); });
+      };
+      switch (c->tile[DIR]) {
+        case 1: go(Tile4x32()); break;
+        case 2: go(Tile2x64()); break;
+        default: go(Tile8x16()); break;
+      }
+    };
+    using D0 = std::integral_constant<int, 0>;
+    using D1 = std::integral_constant<int, 1>;
+    using S1 = std::integral_constant<int, 1>;
+    using S2 = std::integral_constant<int, 2>;
     auto stage_kernels = [&](auto gt) {
       using GT = decltype(gt);
-      timed(c, 0, [&] { k_faces2<0, 1, GT><<<gx, FACE_THREADS, 0, s>>>(G, B); });
-      timed(c, 1, [&] { k_faces2<1, 1, GT><<<gy, FACE_THREADS, 0, s>>>(G, B); });
+      faces(D0(), S1(), gt, 0);
+      faces(D1(), S1(), gt, 1);
       timed(c, 2, [&] { k_update2<1, GT><<<gu, 256, 0, s>>>(G, B); });
-      timed(c, 3, [&] { k_faces2<0, 2, GT><<<gx, FACE_THREADS, 0, s>>>(G, B); });
-      timed(c, 4, [&] { k_faces2<1, 2, GT><<<gy, FACE_THREADS, 0, s>>>(G, B); });
+      faces(D0(), S2(), gt, 3);
+      faces(D1(), S2(), gt, 4);
       timed(c, 5, [&] { k_update2<2, GT><<<gu, 256, 0, s>>>(G, B); });
     };
     if (c->cfg.storage == CGKS_FP32_STORAGE) stage_kernels(0.0f);
