@@ -83,8 +83,9 @@ void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double d
                    double *F, double *Ft, double *Wt, double *Wtt,
                    double *Nh, double *Nf, double *tau);
 /* The same evolution evaluated as the time integral of the interface flux over
- * [0, delta]: Fhat(delta) (exposed for the extraction tests). */
-void orc_flux_integral(int dim, double gamma, double tau, double delta,
+ * [0, delta]: Fhat(delta), with tau in the exponentials and tau_ce in the
+ * Chapman-Enskog term (exposed for the extraction tests). */
+void orc_flux_integral(int dim, double gamma, double tau, double tau_ce, double delta,
                        const double *W0, const double *W0n, const double *W0t,
                        const double *Wl, const double *Wr, double *Fhat);
 /* Tangential quartic through 5 segment averages s[0..4] (segments -2..2):

@@ -270,42 +270,50 @@ static void moment_vectors(const iface_t *s, double M[5][4]) {
   for (int c = 0; c < nc; ++c) M[4][c] += tmp[c];
 }
 
-/* Time coefficients of the five terms integrated over [0, delta].  For the
- * Euler equations the Chapman-Enskog terms carry the physical collision time,
- * zero here; the numerical collision time tau enters through exp(-t/tau):
- *   c1 = int (1 - e^{-t/tau}),  c2 = int t,  c3 = int e^{-t/tau} t,
- *   c4 = int e^{-t/tau},        c5 = -c3. */
-static void time_coefs(double tau, double delta, double c[5]) {
+/* Time coefficients of the five terms integrated over [0, delta].  The
+ * collision time tau enters through exp(-t/tau); the Chapman-Enskog part
+ * -tau (a.u + A) g0 of the distribution carries tau_ce, the part of tau that
+ * Sec. 4 adds at pressure jumps (for the Euler equations the physical
+ * collision time is zero and eps dt only keeps tau positive in the
+ * exponentials):
+ *   c1 = int (1 - e^{-t/tau}),        c2 = int (t - tau_ce),
+ *   c3 = int (t e^{-t/tau} - tau_ce), c4 = int e^{-t/tau},
+ *   c5 = -int t e^{-t/tau}. */
+static void time_coefs(double tau, double tau_ce, double delta, double c[5]) {
   const double Ed = exp(-delta / tau);
-  c[0] = delta - tau * (1.0 - Ed);
-  c[1] = 0.5 * delta * delta;
-  c[2] = tau * tau * (1.0 - Ed) - tau * delta * Ed;
-  c[3] = tau * (1.0 - Ed);
-  c[4] = -c[2];
+  const double i_e = tau * (1.0 - Ed);                            /* int e^{-t/tau} */
+  const double i_te = tau * tau * (1.0 - Ed) - tau * delta * Ed;  /* int t e^{-t/tau} */
+  c[0] = delta - i_e;
+  c[1] = 0.5 * delta * delta - tau_ce * delta;
+  c[2] = i_te - tau_ce * delta;
+  c[3] = i_e;
+  c[4] = -i_te;
 }
 
 /* Time integral over [0, delta] of the interface flux: sum_k c_k M_k. */
-static void fhat(const iface_t *s, double tau, double delta, double *out) {
+static void fhat(const iface_t *s, double tau, double tau_ce, double delta, double *out) {
   double M[5][4], c[5];
   moment_vectors(s, M);
-  time_coefs(tau, delta, c);
+  time_coefs(tau, tau_ce, delta, c);
   for (int k = 0; k < s->nc; ++k)
     out[k] = c[0] * M[0][k] + c[1] * M[1][k] + c[2] * M[2][k] + c[3] * M[3][k] + c[4] * M[4][k];
 }
 
+/* Collision times of Sec. 4 (inviscid flow): tau = eps dt + tau_ce with the
+ * pressure-jump part tau_ce = C |(p_l - p_r)/(p_l + p_r)| dt. */
 static double collision_time(int dim, double gamma, double tau_eps, double tau_C, double dt,
-                             const double *Wl, const double *Wr) {
-  /* tau = eps dt + C |(p_l - p_r)/(p_l + p_r)| dt  (Sec. 4, inviscid flow) */
+                             const double *Wl, const double *Wr, double *tau_ce) {
   const double pl = orc_pressure(dim, gamma, Wl), pr = orc_pressure(dim, gamma, Wr);
-  return tau_eps * dt + tau_C * fabs((pl - pr) / (pl + pr)) * dt;
+  *tau_ce = tau_C * fabs((pl - pr) / (pl + pr)) * dt;
+  return tau_eps * dt + *tau_ce;
 }
 
-void orc_flux_integral(int dim, double gamma, double tau, double delta,
+void orc_flux_integral(int dim, double gamma, double tau, double tau_ce, double delta,
                        const double *W0, const double *W0n, const double *W0t,
                        const double *Wl, const double *Wr, double *Fhat) {
   iface_t s;
   iface_setup(dim, gamma, W0, W0n, W0t, Wl, Wr, &s);
-  fhat(&s, tau, delta, Fhat);
+  fhat(&s, tau, tau_ce, delta, Fhat);
 }
 
 int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double dt,
@@ -318,7 +326,8 @@ int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double 
   double W0[4];
   int fired = 0;
   for (int c = 0; c < nc; ++c) W0[c] = W0in[c];
-  const double tau = collision_time(dim, gamma, tau_eps, tau_C, dt, Wl, Wr);
+  double tau_ce;
+  const double tau = collision_time(dim, gamma, tau_eps, tau_C, dt, Wl, Wr, &tau_ce);
 
   /* S_lr = rho_l <psi>_{l,u>0} + rho_r <psi>_{r,u<0}: the state the two
    * nonlinear distributions carry to the interface. */
@@ -341,21 +350,21 @@ int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double 
 
   /* flux extraction (Sec. 2.2): F(t) ~ F + Ft t fitted to the time integrals
    * over [0, dt/2] and [0, dt], Fhat(dt/2) = F dt/2 + Ft dt^2/8 and
-   * Fhat(dt) = F dt + Ft dt^2/2.  Fhat is linear in the moment vectors, so the
-   * fit is applied to each scalar time coefficient (fitting the vectors would
-   * subtract F dt from 2 F dt/2 and lose the small Ft).  With c1 = delta - c4
-   * and c5 = -c3 the integral reads delta M1 + c2 M2 + c4 (M4 - M1) + c3 (M3 - M5);
-   * delta fits to (1, 0) and c2 = delta^2/2 to (0, 1). */
+   * Fhat(dt) = F dt + Ft dt^2/2, i.e. F = (4 Fhat(dt/2) - Fhat(dt))/dt and
+   * Ft = 4 (Fhat(dt) - 2 Fhat(dt/2))/dt^2.  Fhat is linear in the moment
+   * vectors, so the fit is applied to each scalar time coefficient (fitting
+   * the vectors would subtract F dt from 2 F dt/2 and lose the small Ft). */
   double M[5][4], ch[5], cf[5];
   moment_vectors(&s, M);
-  time_coefs(tau, 0.5 * dt, ch);
-  time_coefs(tau, dt, cf);
-  const double e4 = (4.0 * ch[3] - cf[3]) / dt, e4t = 4.0 * (cf[3] - 2.0 * ch[3]) / (dt * dt);
-  const double e3 = (4.0 * ch[2] - cf[2]) / dt, e3t = 4.0 * (cf[2] - 2.0 * ch[2]) / (dt * dt);
-  for (int c = 0; c < nc; ++c) {
-    const double d41 = M[3][c] - M[0][c], d35 = M[2][c] - M[4][c];
-    F[c] = M[0][c] + e4 * d41 + e3 * d35;
-    Ft[c] = M[1][c] + e4t * d41 + e3t * d35;
+  time_coefs(tau, tau_ce, 0.5 * dt, ch);
+  time_coefs(tau, tau_ce, dt, cf);
+  for (int c = 0; c < nc; ++c) { F[c] = 0.0; Ft[c] = 0.0; }
+  for (int k = 0; k < 5; ++k) {
+    const double e = (4.0 * ch[k] - cf[k]) / dt, et = 4.0 * (cf[k] - 2.0 * ch[k]) / (dt * dt);
+    for (int c = 0; c < nc; ++c) {
+      F[c] += e * M[k][c];
+      Ft[c] += et * M[k][c];
+    }
   }
 
   /* time derivative of the equilibrium state: W_t = rho0 <psi A>_g0 */

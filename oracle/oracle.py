@@ -50,7 +50,8 @@ D = C.POINTER(C.c_double)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        srcs = [os.path.join(HERE, n) for n in SOURCES + ['cgks_oracle.h', 'oracle_internal.h']]
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(map(os.path.getmtime, srcs)):
             build()
         L = C.CDLL(LIB_PATH)
         L.orc_create.argtypes = [C.POINTER(_Cfg), C.POINTER(C.c_void_p)]
@@ -76,7 +77,7 @@ def lib():
         L.orc_slope.argtypes = [C.c_int, C.c_double, D, D, D]
         L.orc_euler_wtt.argtypes = [C.c_double] + [D] * 7
         L.orc_gks_point.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [D] * 8 + [D] * 7
-        L.orc_flux_integral.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double] + [D] * 6
+        L.orc_flux_integral.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [D] * 6
         L.orc_quartic.argtypes = [D, C.c_double, D]
         _lib = L
     return _lib
@@ -226,12 +227,12 @@ def gks_point(dim, gamma, dt, W0, W0n, W0nn, Wl, Wr, W0t=None, W0nt=None, W0tt=N
     return r
 
 
-def flux_integral(dim, gamma, tau, delta, W0, W0n, Wl, Wr, W0t=None):
+def flux_integral(dim, gamma, tau, delta, W0, W0n, Wl, Wr, W0t=None, tau_ce=0.0):
     nc = dim + 2
     z = np.zeros(nc)
     out = np.empty(nc)
     ins = [_vec(v, nc) for v in (W0, W0n, z if W0t is None else W0t, Wl, Wr)]
-    lib().orc_flux_integral(int(dim), float(gamma), float(tau), float(delta), *[_p(a) for a in ins], _p(out))
+    lib().orc_flux_integral(int(dim), float(gamma), float(tau), float(tau_ce), float(delta), *[_p(a) for a in ins], _p(out))
     return out
 
 

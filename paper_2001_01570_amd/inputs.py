@@ -243,6 +243,30 @@ def shock_tube_1d(n: int = 100, t_end: float = 0.16, cfl: float = 0.3) -> Proble
                    cfl=cfl, t_end=t_end, meta=dict(left=left, right=right, x_diaphragm=0.5))
 
 
+def stationary_shock_1d(n: int = 128, Ms: float = 1.1, t_end: float = 0.5, cfl: float = 0.3) -> Problem:
+    """Normal shock of Mach Ms at rest at x = 0.5 on [0, 1]: upstream rho = p = 1,
+    U = Ms sqrt(gamma), downstream from the Rankine-Hugoniot relations (the
+    1D cut through the shock of the shock-vortex case); fixed inflow at x = 0,
+    free flow at x = 1."""
+    g = GAMMA
+    U1 = Ms * math.sqrt(g)
+    r2 = (g + 1.0) * Ms * Ms / ((g - 1.0) * Ms * Ms + 2.0)
+    p2 = 1.0 + 2.0 * g / (g + 1.0) * (Ms * Ms - 1.0)
+    U2 = U1 / r2
+
+    def cons(x, side):
+        x = np.asarray(x, dtype=np.float64)
+        up = (x < 0.5) | ((x == 0.5) & (np.asarray(side) < 0))
+        return prim_to_cons(np.where(up, 1.0, r2), np.where(up, U1, U2), 0.0 * x, np.where(up, 1.0, p2), g, 1)
+
+    fields = _cell_fields_1d(cons, 0.0, 1.0, n)
+    inflow = np.zeros((4, 4))
+    inflow[0] = (1.0, U1, 0.0, 1.0)
+    return Problem('stationary_shock_1d', 1, n, 1, 0.0, 1.0, 0.0, 1.0, fields,
+                   bc=(INFLOW, FREE, PERIODIC, PERIODIC), inflow_prim=inflow, cfl=cfl, t_end=t_end,
+                   meta=dict(Ms=Ms, upstream=(1.0, U1, 1.0), downstream=(r2, U2, p2)))
+
+
 def square_wave_1d(n: int, x0: float, x1: float, t_end: float, cfl: float = 0.3) -> Problem:
     """rho = 1 + 0.5 (H(x+50) - H(x-50)), U = 1, p = 1 with free-flow boundaries
     (Sec. 4.4); the exact solution is the translated square."""

@@ -98,16 +98,16 @@ def _setup(dim, gamma, W0, W0n, W0t, Wl, Wr):
     return g0, gl, gr, an0, at0, anl, atl, anr, atr, A0
 
 
-def flux_time_integral(dim, gamma, tau, delta, W0, W0n, W0t, Wl, Wr):
+def flux_time_integral(dim, gamma, tau, delta, W0, W0n, W0t, Wl, Wr, tau_ce=0.0):
     """int_0^delta int u psi f dXi dt for the second-order interface distribution
-    (the third-order simplified distribution without a_tt, a_xt, a_yt), with the
-    Chapman-Enskog terms carrying a zero physical collision time and the
-    numerical tau only in exp(-t/tau)."""
+    (the third-order simplified distribution without a_tt, a_xt, a_yt), with
+    tau in exp(-t/tau) and tau_ce in the Chapman-Enskog term
+    -tau_ce (a_n u + a_t v + A) g0."""
     g0, gl, gr, an0, at0, anl, atl, anr, atr, A0 = _setup(dim, gamma, W0, W0n, W0t, Wl, Wr)
     T = lambda fn: integrate.quad(fn, 0.0, delta, epsabs=1e-300, epsrel=1e-13, limit=200)[0]
     t_g0 = T(lambda t: 1.0 - math.exp(-t / tau))
-    t_A = T(lambda t: t)
-    t_s0 = T(lambda t: math.exp(-t / tau) * t)
+    t_A = T(lambda t: t - tau_ce)
+    t_s0 = T(lambda t: math.exp(-t / tau) * t - tau_ce)
     t_lr = T(lambda t: math.exp(-t / tau))
     t_slr = T(lambda t: -math.exp(-t / tau) * t)
     up = lambda u, v, s: u * psi(u, v, s, dim)
@@ -120,13 +120,16 @@ def flux_time_integral(dim, gamma, tau, delta, W0, W0n, W0t, Wl, Wr):
     return F
 
 
-def state_at(dim, gamma, tau, t, W0, W0n, W0t, Wl, Wr):
-    """int psi f(t) dXi of the second-order interface distribution (no a_tt term)."""
+def state_at(dim, gamma, tau, t, W0, W0n, W0t, Wl, Wr, tau_ce=0.0):
+    """int psi f(t) dXi of the second-order interface distribution (no a_tt
+    term); the Chapman-Enskog term integrates to zero by compatibility but is
+    kept here as it stands."""
     g0, gl, gr, an0, at0, anl, atl, anr, atr, A0 = _setup(dim, gamma, W0, W0n, W0t, Wl, Wr)
     E = math.exp(-t / tau)
     P = lambda u, v, s: psi(u, v, s, dim)
     sl = lambda a_n, a_t: (lambda u, v, s: P(u, v, s) * (a_of(a_n, u, v, s, dim) * u + a_of(a_t, u, v, s, dim) * v))
     W = g0.rho * (g0.integrate(P) + t * g0.integrate(lambda u, v, s: P(u, v, s) * a_of(A0, u, v, s, dim)))
+    W = W - tau_ce * g0.rho * (g0.integrate(sl(an0, at0)) + g0.integrate(lambda u, v, s: P(u, v, s) * a_of(A0, u, v, s, dim)))
     W = W - E * g0.rho * (g0.integrate(P) - t * g0.integrate(sl(an0, at0)))
     W = W + E * gl.rho * (gl.integrate(P, +1) - t * gl.integrate(sl(anl, atl), +1))
     W = W + E * gr.rho * (gr.integrate(P, -1) - t * gr.integrate(sl(anr, atr), -1))

@@ -85,9 +85,9 @@ def test_flux_time_integral_against_bruteforce(dim):
     rng = np.random.default_rng(7)
     W0n = 0.3 * rng.normal(size=dim + 2)
     W0t = 0.2 * rng.normal(size=dim + 2) if dim == 2 else None
-    for tau, delta in ((0.02, 0.05), (0.04, 0.025)):
-        got = O.flux_integral(dim, G, tau, delta, W0, W0n, Wl, Wr, W0t=W0t)
-        ref = B.flux_time_integral(dim, G, tau, delta, W0, W0n, W0t, Wl, Wr)
+    for tau, tau_ce, delta in ((0.02, 0.0, 0.05), (0.04, 0.0, 0.025), (0.03, 0.02, 0.05)):
+        got = O.flux_integral(dim, G, tau, delta, W0, W0n, Wl, Wr, W0t=W0t, tau_ce=tau_ce)
+        ref = B.flux_time_integral(dim, G, tau, delta, W0, W0n, W0t, Wl, Wr, tau_ce=tau_ce)
         np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-12)
 
 
@@ -104,13 +104,15 @@ def test_interface_state_against_bruteforce(dim):
     r = O.gks_point(dim, G, dt, W0, W0n, z, Wl, Wr, W0t=W0t)
     # the collision time of Sec. 4 from the nonlinear states
     pl, pr = B.Maxw(Wl, G, dim).p, B.Maxw(Wr, G, dim).p
-    assert r['tau'] == pytest.approx(0.01 * dt + abs((pl - pr) / (pl + pr)) * dt, rel=1e-14)
+    tau_ce = abs((pl - pr) / (pl + pr)) * dt
+    assert r['tau'] == pytest.approx(0.01 * dt + tau_ce, rel=1e-14)
     for t, N in ((0.5 * dt, r['Nh']), (dt, r['Nf'])):
-        ref = B.state_at(dim, G, r['tau'], t, W0, W0n, W0t, Wl, Wr)
+        ref = B.state_at(dim, G, r['tau'], t, W0, W0n, W0t, Wl, Wr, tau_ce=tau_ce)
         np.testing.assert_allclose(W0 + t * r['Wt'] + N, ref, rtol=1e-9, atol=1e-12)
-    # the extracted F, Ft reproduce both time integrals of a linear-in-time flux fit
-    Fh = B.flux_time_integral(dim, G, r['tau'], 0.5 * dt, W0, W0n, W0t, Wl, Wr)
-    Ff = B.flux_time_integral(dim, G, r['tau'], dt, W0, W0n, W0t, Wl, Wr)
+    # the extracted F, Ft reproduce both time integrals of a linear-in-time flux
+    # fit; the pressure-jump part of tau is the Chapman-Enskog collision time
+    Fh = B.flux_time_integral(dim, G, r['tau'], 0.5 * dt, W0, W0n, W0t, Wl, Wr, tau_ce=tau_ce)
+    Ff = B.flux_time_integral(dim, G, r['tau'], dt, W0, W0n, W0t, Wl, Wr, tau_ce=tau_ce)
     np.testing.assert_allclose(r['F'] * 0.5 * dt + r['Ft'] * dt * dt / 8, Fh, rtol=1e-9, atol=1e-12)
     np.testing.assert_allclose(r['F'] * dt + r['Ft'] * dt * dt / 2, Ff, rtol=1e-9, atol=1e-12)
 
@@ -139,6 +141,46 @@ def test_smooth_limit_is_the_euler_flux_and_its_ck_derivative(dim):
     for delta in (dt, 0.5 * dt, 0.37 * dt):
         Fh = O.flux_integral(dim, G, r['tau'], delta, W0, W0n, W0, W0, W0t=W0t)
         np.testing.assert_allclose(Fh, r['F'] * delta + r['Ft'] * delta ** 2 / 2, rtol=1e-12, atol=1e-16)
+
+
+def _ce_flux(dim, W0, W0n, W0t=None, tau_ce=0.01, delta=0.05):
+    """Chapman-Enskog part of the flux time integral over [0, delta] per unit
+    time: the difference the tau_ce term makes, everything else equal."""
+    z = np.zeros(dim + 2)
+    f1 = O.flux_integral(dim, G, 0.02, delta, W0, W0n, W0, W0, W0t=W0t, tau_ce=tau_ce)
+    f0 = O.flux_integral(dim, G, 0.02, delta, W0, W0n, W0, W0, W0t=W0t)
+    return (f1 - f0) / delta
+
+
+def test_chapman_enskog_term_is_the_navier_stokes_flux():
+    """The BGK Chapman-Enskog flux with mu = tau p (Prandtl number 1): viscous
+    stress -tau p [2 U_x - 2/(K + dim) div U] on the normal momentum, shear
+    -tau p (U_y + V_x), viscous work U times the stress, heat flux
+    -tau p (K + dim + 2)/2 d(p/rho)/dx, nothing on the mass; K the internal
+    degrees of freedom (4 in 1D, 3 in 2D at gamma = 1.4)."""
+    t = 0.013
+    # 1D normal stress and its work: rho, p uniform, U = 0.4 with U_x = 0.7
+    rho, U, p, Ux = 1.1, 0.4, 0.9, 0.7
+    K1 = (3 - G) / (G - 1)
+    W0 = cons(1, rho, U, 0, p)
+    W0n = np.array([0.0, rho * Ux, rho * U * Ux])
+    s = -t * p * (2 * Ux - 2 / (K1 + 1) * Ux)
+    np.testing.assert_allclose(_ce_flux(1, W0, W0n, tau_ce=t), [0.0, s, U * s], rtol=1e-11, atol=1e-15)
+    # 1D heat flux: U = 0, p uniform, rho_x = -0.6
+    rx = -0.6
+    W0 = cons(1, rho, 0.0, 0, p)
+    W0n = np.array([rx, 0.0, 0.0])
+    q = -t * p * (K1 + 3) / 2 * (-p * rx / rho ** 2)
+    np.testing.assert_allclose(_ce_flux(1, W0, W0n, tau_ce=t), [0.0, 0.0, q], rtol=1e-11, atol=1e-15)
+    # 2D at rest, rho and p uniform: U_x, V_y (normal stress), V_x, U_y (shear)
+    K2 = (4 - 2 * G) / (G - 1)
+    Ux, Vy, Vx, Uy = 0.5, -0.3, 0.25, 0.45
+    W0 = cons(2, rho, 0.0, 0.0, p)
+    W0n = np.array([0.0, rho * Ux, rho * Vx, 0.0])
+    W0t = np.array([0.0, rho * Uy, rho * Vy, 0.0])
+    sxx = -t * p * (2 * Ux - 2 / (K2 + 2) * (Ux + Vy))
+    sxy = -t * p * (Uy + Vx)
+    np.testing.assert_allclose(_ce_flux(2, W0, W0n, W0t, tau_ce=t), [0.0, sxx, sxy, 0.0], rtol=1e-11, atol=1e-15)
 
 
 def _symbolic_wtt(W0, Wx, Wy, Wxx, Wxy, Wyy):
