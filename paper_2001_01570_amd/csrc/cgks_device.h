@@ -478,12 +478,16 @@ struct SideSums {
   }
 };
 
-// Numerical collision time of Sec. 4 (inviscid): tau = eps dt + C |p_l - p_r|/(p_l + p_r) dt,
-// p_l, p_r of the nonlinear (WENO) states.
+// Collision times of Sec. 4 (inviscid), p_l, p_r of the nonlinear (WENO)
+// states: the pressure-jump part tau_ce = C |p_l - p_r|/(p_l + p_r) dt, which
+// is also the collision time of the Chapman-Enskog term (the physical one is
+// zero for the Euler equations), and tau = eps dt + tau_ce in exp(-t/tau).
 template <int NC>
-CGKS_HD __forceinline__ double collision_time(const double* Wl, const double* Wr, const Gas& g, double dt) {
+CGKS_HD __forceinline__ double collision_time(const double* Wl, const double* Wr, const Gas& g, double dt,
+                                              double& tau_ce) {
   const double pl = pressure<NC>(Wl, g.gamma), pr = pressure<NC>(Wr, g.gamma);
-  return g.tau_eps * dt + g.tau_C * fabs((pl - pr) * recip(pl + pr)) * dt;
+  tau_ce = g.tau_C * fabs((pl - pr) * recip(pl + pr)) * dt;
+  return g.tau_eps * dt + tau_ce;
 }
 
 // One non-equilibrium side (half space u > 0 for side = +1, u < 0 for -1):
@@ -546,10 +550,12 @@ CGKS_HD __forceinline__ void collision_state(const double* Wl, const double* Wr,
   for (int k = 0; k < NC; ++k) S[k] += m.rho * t1[k];
 }
 
-// Slope part of the equilibrium: D35 += rho0 <u psi (a_n u + a_t v)>_0.
-template <int NC>
+// Slope part of the equilibrium M3 = rho0 <u psi (a_n u + a_t v)>_0: D35 += M3;
+// with FULL also the Chapman-Enskog flux Fce = -tau_ce (M2 + M3), M2 the
+// flux time derivative rho0 <u psi A>_0.
+template <int NC, bool FULL>
 CGKS_HD __forceinline__ void equilibrium_terms(const double* W0, const double* Wn, const double* Wt, const Gas& g,
-                                               double* D35) {
+                                               double tau_ce, const double* M2, double* D35, double* Fce) {
   Mom<NC> m;
   moments<NC>(W0, g, 0, m);
   double bn[NC], an[NC], t1[NC];
@@ -568,7 +574,11 @@ CGKS_HD __forceinline__ void equilibrium_terms(const double* W0, const double* W
     for (int k = 0; k < NC; ++k) t1[k] += t2[k];
   }
 #pragma unroll
-  for (int k = 0; k < NC; ++k) D35[k] += m.rho * t1[k];
+  for (int k = 0; k < NC; ++k) {
+    const double m3 = m.rho * t1[k];
+    D35[k] += m3;
+    if constexpr (FULL) Fce[k] = -tau_ce * (M2[k] + m3);
+  }
 }
 
 // Exact Euler derivatives of the equilibrium at the point, in the NC layout:
@@ -596,13 +606,14 @@ CGKS_HD __forceinline__ void ck_terms(const Gas& gas, const double* W0, const do
 
 // Combination of the moment vectors with the time coefficients of the flux
 // extraction (Eh = e^{-dt/(2 tau)}, E = Eh^2):
-//   F  = M1 + e4 (M4 - M1) + e3 (M3 - M5)
+//   F  = M1 + e4 (M4 - M1) + e3 (M3 - M5) + Fce
 //   Ft = M2 + e1' (M1 - M4) + e3' (M3 - M5)
 // and (FULL) the non-equilibrium remainders e^{-t/tau}[-W0 - t W_t + S_lr - t S_alr]
-// at t = dt/2 (Nh) and t = dt (Nf).  M1 = F(W0), the Euler flux.
+// at t = dt/2 (Nh) and t = dt (Nf).  M1 = F(W0), the Euler flux; Fce the
+// Chapman-Enskog flux (constant in time, so only in F; Fce may be out.F).
 template <int NC, bool FULL>
 CGKS_HD __forceinline__ void combine(const double* W0, const double* M2, const SideSums<NC>& sd, double tau,
-                                     double dt, const Gas& g, PointOut<NC>& out) {
+                                     double dt, const Gas& g, const double* Fce, PointOut<NC>& out) {
   double M1[NC];
   {
     const double ir = recip(W0[0]);
@@ -631,7 +642,7 @@ CGKS_HD __forceinline__ void combine(const double* W0, const double* M2, const S
     const double E = Eh * Eh;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      out.F[k] = M1[k] + e4 * (sd.M4[k] - M1[k]) + e3 * sd.D35[k];
+      out.F[k] = M1[k] + e4 * (sd.M4[k] - M1[k]) + e3 * sd.D35[k] + Fce[k];
       const double base = sd.Slr[k] - W0[k];
       const double slp = out.Wt[k] + sd.Salr[k];
       out.Nh[k] = Eh * (base - 0.5 * dt * slp);
@@ -642,9 +653,9 @@ CGKS_HD __forceinline__ void combine(const double* W0, const double* M2, const S
 }
 
 // The interface evolution at one point (eq. 3rd-simplify-flux, second-order
-// part for the flux): numerical collision time in exp(-t/tau) only, physical
-// collision time zero for the Euler equations.  The phases above in order;
-// FULL = false computes only what the second stage needs (Ft, Wtt).
+// part for the flux): the collision time tau in exp(-t/tau), its pressure-jump
+// part in the Chapman-Enskog term.  The phases above in order; FULL = false
+// computes only what the second stage needs (Ft, Wtt).
 template <int NC, bool FULL>
 CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, double dt, PointOut<NC>& out) {
   // equilibrium from the linear reconstruction; the kinetic collision state
@@ -659,13 +670,14 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
   }
   double M2[NC];
   ck_terms<NC>(g, W0, in.Wn, in.Wt, in.Wnn, in.Wnt, in.Wtt, out.Wt, out.Wtt, M2);
-  const double tau = collision_time<NC>(in.Wl, in.Wr, g, dt);
+  double tau_ce;
+  const double tau = collision_time<NC>(in.Wl, in.Wr, g, dt, tau_ce);
   SideSums<NC> sd;
   sd.zero();
   side_terms<NC, FULL>(in.Wl, +1, in.Wn, in.Wt, g, sd);
   side_terms<NC, FULL>(in.Wr, -1, in.Wn, in.Wt, g, sd);
-  equilibrium_terms<NC>(W0, in.Wn, in.Wt, g, sd.D35);   // D35 = M3 - M5
-  combine<NC, FULL>(W0, M2, sd, tau, dt, g, out);
+  equilibrium_terms<NC, FULL>(W0, in.Wn, in.Wt, g, tau_ce, M2, sd.D35, out.F);   // D35 = M3 - M5
+  combine<NC, FULL>(W0, M2, sd, tau, dt, g, out.F, out);
 }
 
 // ----------------------------------------------------------------------------
@@ -804,8 +816,11 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
     collision_state<4>(Wl, Wr, gas, W0);
     guard = 1;
   }
-  double tau = collision_time<4>(Wl, Wr, gas, dt);
-  CGKS_PIN(tau);
+  // only tau_ce is kept across the phases: tau = eps dt + tau_ce is formed
+  // again (the same operation) where the combination needs it
+  double tau_ce;
+  collision_time<4>(Wl, Wr, gas, dt, tau_ce);
+  CGKS_PIN(tau_ce);
 #pragma unroll
   for (int k = 0; k < 4; ++k) CGKS_PIN(W0[k]);
   CGKS_BREAK();
@@ -865,15 +880,18 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
   }
   CGKS_BREAK();
 
-  // slope part of the equilibrium and the combination
-  equilibrium_terms<4>(W0, Wn, Wt, gas, sd.D35);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) CGKS_PIN(sd.D35[k]);
-  CGKS_BREAK();
+  // slope part of the equilibrium, the Chapman-Enskog flux and the combination
   PointOut<4> o;
+  equilibrium_terms<4, FULL>(W0, Wn, Wt, gas, tau_ce, M2, sd.D35, o.F);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    CGKS_PIN(sd.D35[k]);
+    if constexpr (FULL) CGKS_PIN(o.F[k]);
+  }
+  CGKS_BREAK();
 #pragma unroll
   for (int k = 0; k < 4; ++k) { o.Wt[k] = Wt_o[k]; o.Wtt[k] = Wtt_o[k]; }
-  combine<4, FULL>(W0, M2, sd, tau, dt, gas, o);
+  combine<4, FULL>(W0, M2, sd, gas.tau_eps * dt + tau_ce, dt, gas, o.F, o);
   o.guard = guard;
   rot(o.F); rot(o.Ft); rot(o.Wt); rot(o.Wtt); rot(o.Nh); rot(o.Nf); rot(o.W0);
   CGKS_BREAK();
