@@ -61,6 +61,11 @@ typedef struct {
   double tau_eps, tau_C;     /* collision time eps*dt + C|dp/sum p|*dt (Sec. 4): 0.01, 1 */
   double fixed_dt;           /* 0: CFL rule; > 0: fixed step (accuracy tests, Sec. 4.1) */
   int storage;               /* CGKS_FP64 or CGKS_FP32_STORAGE (2D)                      */
+  double mu;                 /* dynamic viscosity (>= 0).  0: Euler equations.  > 0:
+                                Navier-Stokes with the BGK Prandtl number 1; the
+                                collision time is mu/p + C|dp/sum p|*dt in both of
+                                its roles (Sec. 4, viscous form) and tau_eps is
+                                unused; walls stay slip walls                        */
 } cgks_config;
 
 typedef struct {

@@ -33,6 +33,7 @@ typedef struct {
   double inflow_prim[4][4];  /* (rho, U, V, p) per side with ORC_INFLOW */
   double weno_eps, tau_eps, tau_C;
   double fixed_dt;           /* 0 -> CFL rule, >0 -> fixed step */
+  double mu;                 /* dynamic viscosity: 0 -> Euler, > 0 -> Navier-Stokes */
 } orc_config;
 
 typedef struct orc_ctx orc_ctx;
@@ -76,7 +77,7 @@ void orc_euler_wtt(double gamma, const double *W, const double *Wx, const double
 /* One interface point of the gas-kinetic evolution (Sec. 2.1-2.2).
  * in: W0, W0_n, W0_t, W0_nn, W0_nt, W0_tt, Wl, Wr (dim+2 each, normal = x);
  * out: F[nc], Ft[nc], Wt[nc], Wtt[nc], N_half[nc], N_full[nc], tau. */
-void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double dt,
+void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double mu, double dt,
                    const double *W0, const double *W0n, const double *W0t,
                    const double *W0nn, const double *W0nt, const double *W0tt,
                    const double *Wl, const double *Wr,

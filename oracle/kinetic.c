@@ -299,13 +299,20 @@ static void fhat(const iface_t *s, double tau, double tau_ce, double delta, doub
     out[k] = c[0] * M[0][k] + c[1] * M[1][k] + c[2] * M[2][k] + c[3] * M[3][k] + c[4] * M[4][k];
 }
 
-/* Collision times of Sec. 4 (inviscid flow): tau = eps dt + tau_ce with the
- * pressure-jump part tau_ce = C |(p_l - p_r)/(p_l + p_r)| dt. */
-static double collision_time(int dim, double gamma, double tau_eps, double tau_C, double dt,
-                             const double *Wl, const double *Wr, double *tau_ce) {
+/* Collision times of Sec. 4.  Inviscid flow (mu = 0): tau = eps dt + tau_ce
+ * with the pressure-jump part tau_ce = C |(p_l - p_r)/(p_l + p_r)| dt.
+ * Viscous flow: tau = tau_ce = mu/p + C |(p_l - p_r)/(p_l + p_r)| dt, p the
+ * pressure of the equilibrium state at the interface. */
+static double collision_time(int dim, double gamma, double tau_eps, double tau_C, double mu, double dt,
+                             const double *Wl, const double *Wr, const double *W0, double *tau_ce) {
   const double pl = orc_pressure(dim, gamma, Wl), pr = orc_pressure(dim, gamma, Wr);
-  *tau_ce = tau_C * fabs((pl - pr) / (pl + pr)) * dt;
-  return tau_eps * dt + *tau_ce;
+  const double jump = tau_C * fabs((pl - pr) / (pl + pr)) * dt;
+  if (mu > 0.0) {
+    *tau_ce = mu / orc_pressure(dim, gamma, W0) + jump;
+    return *tau_ce;
+  }
+  *tau_ce = jump;
+  return tau_eps * dt + jump;
 }
 
 void orc_flux_integral(int dim, double gamma, double tau, double tau_ce, double delta,
@@ -316,7 +323,7 @@ void orc_flux_integral(int dim, double gamma, double tau, double tau_ce, double 
   fhat(&s, tau, tau_ce, delta, Fhat);
 }
 
-int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double dt,
+int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double mu, double dt,
                     const double *W0in, const double *W0n, const double *W0t,
                     const double *W0nn, const double *W0nt, const double *W0tt,
                     const double *Wl, const double *Wr,
@@ -326,8 +333,6 @@ int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double 
   double W0[4];
   int fired = 0;
   for (int c = 0; c < nc; ++c) W0[c] = W0in[c];
-  double tau_ce;
-  const double tau = collision_time(dim, gamma, tau_eps, tau_C, dt, Wl, Wr, &tau_ce);
 
   /* S_lr = rho_l <psi>_{l,u>0} + rho_r <psi>_{r,u<0}: the state the two
    * nonlinear distributions carry to the interface. */
@@ -343,6 +348,8 @@ int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double 
     fired = 1;
   }
   if (W0used) for (int c = 0; c < nc; ++c) W0used[c] = W0[c];
+  double tau_ce;
+  const double tau = collision_time(dim, gamma, tau_eps, tau_C, mu, dt, Wl, Wr, W0, &tau_ce);
 
   iface_t s;
   double zero[4] = {0, 0, 0, 0};
@@ -409,12 +416,12 @@ int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double 
   return fired;
 }
 
-void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double dt,
+void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double mu, double dt,
                    const double *W0, const double *W0n, const double *W0t,
                    const double *W0nn, const double *W0nt, const double *W0tt,
                    const double *Wl, const double *Wr,
                    double *F, double *Ft, double *Wt, double *Wtt,
                    double *Nh, double *Nf, double *tau) {
-  orc_gks_point_g(dim, gamma, tau_eps, tau_C, dt, W0, W0n, W0t, W0nn, W0nt, W0tt, Wl, Wr,
+  orc_gks_point_g(dim, gamma, tau_eps, tau_C, mu, dt, W0, W0n, W0t, W0nn, W0nt, W0tt, Wl, Wr,
                   F, Ft, Wt, Wtt, Nh, Nf, tau, 0);
 }

@@ -35,7 +35,7 @@ class _Cfg(C.Structure):
                 ('gamma', C.c_double), ('cfl', C.c_double),
                 ('bc', C.c_int * 4), ('inflow_prim', (C.c_double * 4) * 4),
                 ('weno_eps', C.c_double), ('tau_eps', C.c_double), ('tau_C', C.c_double),
-                ('fixed_dt', C.c_double)]
+                ('fixed_dt', C.c_double), ('mu', C.c_double)]
 
 
 class _Counters(C.Structure):
@@ -76,7 +76,7 @@ def lib():
         L.orc_moment.restype = C.c_double
         L.orc_slope.argtypes = [C.c_int, C.c_double, D, D, D]
         L.orc_euler_wtt.argtypes = [C.c_double] + [D] * 7
-        L.orc_gks_point.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [D] * 8 + [D] * 7
+        L.orc_gks_point.argtypes = [C.c_int] + [C.c_double] * 5 + [D] * 8 + [D] * 7
         L.orc_flux_integral.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [D] * 6
         L.orc_quartic.argtypes = [D, C.c_double, D]
         _lib = L
@@ -108,7 +108,7 @@ class Oracle:
         d = prob.config_dict()
         for k in ('dim', 'nx', 'ny'):
             setattr(cfg, k, int(d[k]))
-        for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt'):
+        for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt', 'mu'):
             setattr(cfg, k, float(d[k]))
         for s in range(4):
             cfg.bc[s] = int(d['bc'][s])
@@ -212,14 +212,14 @@ def euler_wtt(gamma, W, Wx, Wy, Wxx, Wxy, Wyy):
 
 
 def gks_point(dim, gamma, dt, W0, W0n, W0nn, Wl, Wr, W0t=None, W0nt=None, W0tt=None,
-              tau_eps=0.01, tau_C=1.0):
+              tau_eps=0.01, tau_C=1.0, mu=0.0):
     nc = dim + 2
     z = np.zeros(nc)
     ins = [_vec(v, nc) for v in (W0, W0n, z if W0t is None else W0t, W0nn, z if W0nt is None else W0nt,
                                  z if W0tt is None else W0tt, Wl, Wr)]
     outs = [np.empty(nc) for _ in range(6)]
     tau = np.empty(1)
-    lib().orc_gks_point(int(dim), float(gamma), float(tau_eps), float(tau_C), float(dt),
+    lib().orc_gks_point(int(dim), float(gamma), float(tau_eps), float(tau_C), float(mu), float(dt),
                         *[_p(a) for a in ins], *[_p(a) for a in outs], _p(tau))
     names = ('F', 'Ft', 'Wt', 'Wtt', 'Nh', 'Nf')
     r = dict(zip(names, outs))

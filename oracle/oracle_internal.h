@@ -21,7 +21,7 @@ int orc_admissible(int dim, double gamma, const double *W);
 double orc_pressure(int dim, double gamma, const double *W);
 
 /* one interface point; returns 1 when the equilibrium-state guard fired */
-int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double dt,
+int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double mu, double dt,
                     const double *W0, const double *W0n, const double *W0t,
                     const double *W0nn, const double *W0nt, const double *W0tt,
                     const double *Wl, const double *Wr,

@@ -44,6 +44,7 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   for (int s = 0; s < 2 * cfg->dim; ++s) if (cfg->bc[s] < 0 || cfg->bc[s] > 3) return ORC_EINVAL;
   if ((cfg->bc[0] == ORC_PERIODIC) != (cfg->bc[1] == ORC_PERIODIC)) return ORC_EINVAL;
   if (cfg->dim == 2 && (cfg->bc[2] == ORC_PERIODIC) != (cfg->bc[3] == ORC_PERIODIC)) return ORC_EINVAL;
+  if (!(cfg->mu >= 0.0) || !isfinite(cfg->mu)) return ORC_EINVAL;
   orc_recon_init();
   orc_ctx *c = (orc_ctx *)calloc(1, sizeof *c);
   if (!c) return ORC_ENOMEM;
@@ -276,7 +277,7 @@ static void face_eval(orc_ctx *c, double lines[5][5][4], const double *ref, cons
       swap12(Wl); swap12(Wr);
     }
     double F[4], Ft[4], Wt[4], Wtt[4], Nh[4], Nf[4], tau, W0u[4];
-    const int fired = orc_gks_point_g(dim, gam, c->cfg.tau_eps, c->cfg.tau_C, dt, W0, Wn, Wt_, Wnn,
+    const int fired = orc_gks_point_g(dim, gam, c->cfg.tau_eps, c->cfg.tau_C, c->cfg.mu, dt, W0, Wn, Wt_, Wnn,
                                       Wnt, Wtt_, Wl, Wr, F, Ft, Wt, Wtt, Nh, Nf, &tau, W0u);
     if (rot) { swap12(F); swap12(Ft); swap12(Wt); swap12(Wtt); swap12(Nh); swap12(Nf); swap12(W0u); }
     if (fired) { gd->w0++; for (int k = 0; k < nc; ++k) W0d[k] = W0u[k] - ref[k]; }

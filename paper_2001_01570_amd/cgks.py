@@ -26,7 +26,7 @@ class cgks_config(C.Structure):
                 ('gamma', C.c_double), ('cfl', C.c_double),
                 ('bc', C.c_int * 4), ('inflow_prim', (C.c_double * 4) * 4),
                 ('weno_eps', C.c_double), ('tau_eps', C.c_double), ('tau_C', C.c_double),
-                ('fixed_dt', C.c_double), ('storage', C.c_int)]
+                ('fixed_dt', C.c_double), ('storage', C.c_int), ('mu', C.c_double)]
 
 
 class cgks_counters_t(C.Structure):
@@ -103,7 +103,7 @@ def make_config(prob, storage: int = CGKS_FP64) -> cgks_config:
     cfg = cgks_config()
     for k in ('dim', 'nx', 'ny'):
         setattr(cfg, k, int(d[k]))
-    for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt'):
+    for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt', 'mu'):
         setattr(cfg, k, float(d[k]))
     for s in range(4):
         cfg.bc[s] = int(d['bc'][s])

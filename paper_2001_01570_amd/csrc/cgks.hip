@@ -814,6 +814,7 @@ static int validate(const cgks_config* c) {
   if (!(c->gamma > 1.0) || !(c->x1 > c->x0) || (c->dim == 2 && !(c->y1 > c->y0))) return CGKS_EINVAL;
   if (!(c->cfl > 0.0) && !(c->fixed_dt > 0.0)) return CGKS_EINVAL;
   if (!(c->weno_eps > 0.0) || !(c->tau_eps > 0.0) || c->tau_C < 0.0) return CGKS_EINVAL;
+  if (!(c->mu >= 0.0) || !std::isfinite(c->mu)) return CGKS_EINVAL;
   if (c->storage != CGKS_FP64 && !(c->storage == CGKS_FP32_STORAGE && c->dim == 2)) return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
     if (c->bc[s] < 0 || c->bc[s] > 3) return CGKS_EINVAL;
@@ -840,7 +841,7 @@ static void make_geom(const cgks_config& cfg, Geom& G) {
   G.inv_dx = 1.0 / G.dx;
   G.inv_dy = 1.0 / G.dy;
   G.eps = cfg.weno_eps;
-  G.gas = make_gas(cfg.gamma, cfg.dim, cfg.tau_eps, cfg.tau_C);
+  G.gas = make_gas(cfg.gamma, cfg.dim, cfg.tau_eps, cfg.tau_C, cfg.mu);
   for (int s = 0; s < 4; ++s) {
     G.bc[s] = s < 2 * cfg.dim ? cfg.bc[s] : CGKS_PERIODIC;
     const double* q = cfg.inflow_prim[s];

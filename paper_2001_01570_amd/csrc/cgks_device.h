@@ -234,17 +234,19 @@ template <int NC> struct Vec { double c[NC]; };
 struct Gas {
   double gamma, K;     // K: internal degrees of freedom (K + dim = 2/(gamma-1))
   double tau_eps, tau_C;
+  double mu;           // dynamic viscosity; 0 for the Euler equations
   double inv_g1;       // 1/(gamma - 1)
   double inv_KD;       // 1/(K + dim)
 };
 
 // Gas constants of a problem of dimension dim.
-CGKS_HD inline Gas make_gas(double gamma, int dim, double tau_eps, double tau_C) {
+CGKS_HD inline Gas make_gas(double gamma, int dim, double tau_eps, double tau_C, double mu) {
   Gas g;
   g.gamma = gamma;
   g.K = 2.0 / (gamma - 1.0) - dim;
   g.tau_eps = tau_eps;
   g.tau_C = tau_C;
+  g.mu = mu;
   g.inv_g1 = 1.0 / (gamma - 1.0);
   g.inv_KD = 1.0 / (g.K + dim);
   return g;
@@ -478,16 +480,27 @@ struct SideSums {
   }
 };
 
-// Collision times of Sec. 4 (inviscid), p_l, p_r of the nonlinear (WENO)
-// states: the pressure-jump part tau_ce = C |p_l - p_r|/(p_l + p_r) dt, which
-// is also the collision time of the Chapman-Enskog term (the physical one is
-// zero for the Euler equations), and tau = eps dt + tau_ce in exp(-t/tau).
+// Collision times of Sec. 4, p_l, p_r of the nonlinear (WENO) states and p0
+// of the equilibrium state W0.  tau_ce is the collision time of the
+// Chapman-Enskog term, tau the one in exp(-t/tau):
+//   Euler (mu = 0):  tau_ce = C |p_l - p_r|/(p_l + p_r) dt,  tau = eps dt + tau_ce
+//   Navier-Stokes:   tau_ce = mu/p0 + C |p_l - p_r|/(p_l + p_r) dt = tau
 template <int NC>
-CGKS_HD __forceinline__ double collision_time(const double* Wl, const double* Wr, const Gas& g, double dt,
-                                              double& tau_ce) {
+CGKS_HD __forceinline__ double collision_time(const double* Wl, const double* Wr, const double* W0, const Gas& g,
+                                              double dt, double& tau_ce) {
   const double pl = pressure<NC>(Wl, g.gamma), pr = pressure<NC>(Wr, g.gamma);
-  tau_ce = g.tau_C * fabs((pl - pr) * recip(pl + pr)) * dt;
-  return g.tau_eps * dt + tau_ce;
+  const double jump = g.tau_C * fabs((pl - pr) * recip(pl + pr)) * dt;
+  if (g.mu > 0.0) {
+    tau_ce = g.mu * recip(pressure<NC>(W0, g.gamma)) + jump;
+    return tau_ce;
+  }
+  tau_ce = jump;
+  return g.tau_eps * dt + jump;
+}
+
+// tau from tau_ce (the same operations as collision_time).
+CGKS_HD __forceinline__ double tau_of(const Gas& g, double dt, double tau_ce) {
+  return g.mu > 0.0 ? tau_ce : g.tau_eps * dt + tau_ce;
 }
 
 // One non-equilibrium side (half space u > 0 for side = +1, u < 0 for -1):
@@ -671,7 +684,7 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
   double M2[NC];
   ck_terms<NC>(g, W0, in.Wn, in.Wt, in.Wnn, in.Wnt, in.Wtt, out.Wt, out.Wtt, M2);
   double tau_ce;
-  const double tau = collision_time<NC>(in.Wl, in.Wr, g, dt, tau_ce);
+  const double tau = collision_time<NC>(in.Wl, in.Wr, W0, g, dt, tau_ce);
   SideSums<NC> sd;
   sd.zero();
   side_terms<NC, FULL>(in.Wl, +1, in.Wn, in.Wt, g, sd);
@@ -816,10 +829,10 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
     collision_state<4>(Wl, Wr, gas, W0);
     guard = 1;
   }
-  // only tau_ce is kept across the phases: tau = eps dt + tau_ce is formed
-  // again (the same operation) where the combination needs it
+  // only tau_ce is kept across the phases: tau is formed again from it (the
+  // same operations) where the combination needs it
   double tau_ce;
-  collision_time<4>(Wl, Wr, gas, dt, tau_ce);
+  collision_time<4>(Wl, Wr, W0, gas, dt, tau_ce);
   CGKS_PIN(tau_ce);
 #pragma unroll
   for (int k = 0; k < 4; ++k) CGKS_PIN(W0[k]);
@@ -891,7 +904,7 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
   CGKS_BREAK();
 #pragma unroll
   for (int k = 0; k < 4; ++k) { o.Wt[k] = Wt_o[k]; o.Wtt[k] = Wtt_o[k]; }
-  combine<4, FULL>(W0, M2, sd, gas.tau_eps * dt + tau_ce, dt, gas, o.F, o);
+  combine<4, FULL>(W0, M2, sd, tau_of(gas, dt, tau_ce), dt, gas, o.F, o);
   o.guard = guard;
   rot(o.F); rot(o.Ft); rot(o.Wt); rot(o.Wtt); rot(o.Nh); rot(o.Nf); rot(o.W0);
   CGKS_BREAK();

@@ -83,7 +83,7 @@ static void emit(const char* name, const OpCounts& c, bool comma) {
 int main() {
   static const TangW host_tang[2] = CGKS_TANG_WEIGHTS;
   const double gamma = 1.4;
-  const Gas gas = make_gas(gamma, 2, 0.01, 1.0);
+  const Gas gas = make_gas(gamma, 2, 0.01, 1.0, 0.0);
   const double dt = 6e-4, hn = 1.0 / 512, ht = 1.0 / 512;
 
   // one normal reconstruction (one line, one component)

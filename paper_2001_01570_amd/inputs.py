@@ -51,6 +51,7 @@ class Problem:
     weno_eps: float = 1e-6
     tau_eps: float = 0.01
     tau_C: float = 1.0
+    mu: float = 0.0               # dynamic viscosity (0: Euler equations)
     exact: Optional[Callable[[float], np.ndarray]] = None   # t -> exact fields (cell averages)
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -72,7 +73,7 @@ class Problem:
                     y1=self.y1, gamma=self.gamma, cfl=self.cfl, bc=list(self.bc),
                     inflow_prim=np.asarray(inflow, dtype=np.float64).tolist(),
                     weno_eps=self.weno_eps, tau_eps=self.tau_eps, tau_C=self.tau_C,
-                    fixed_dt=self.fixed_dt)
+                    fixed_dt=self.fixed_dt, mu=self.mu)
 
 
 # ---------------------------------------------------------------- helpers
@@ -352,6 +353,34 @@ def shock_vortex_2d(nx: int = 2048, ny: int = 1024, Ms: float = 1.1, Mv: float =
                    meta=dict(Ms=Ms, Mv=Mv, Rc=Rc, downstream=(r2, U2, 0.0, p2)))
 
 
+def viscous_shock_vortex_2d(nx: int = 700, ny: int = 600, Ms: float = 1.2, Mv: float = 0.5, Re: float = 800.0,
+                            t_end: float = 6.0, cfl: float = 0.3) -> Problem:
+    """The viscous shock-vortex interaction of Sec. 4.9 on [-20,8]x[-12,12]:
+    a stationary normal shock of Mach Ms at x = 0, the supersonic stream
+    (rho = 1, p = 1/gamma, sound speed 1, U = -Ms) entering at x = 8 and
+    carrying a counter-clockwise isentropic vortex of strength Mv (core radius
+    1) from (2, 0); mu = rho a / Re of that stream; periodic in y, free flow
+    at x = -20 (standing in for the paper's non-reflecting boundary)."""
+    g = GAMMA
+    p1 = 1.0 / g
+    U1 = -Ms
+    r2 = (g + 1.0) * Ms * Ms / ((g - 1.0) * Ms * Ms + 2.0)
+    p2 = p1 * (1.0 + 2.0 * g / (g + 1.0) * (Ms * Ms - 1.0))
+    U2 = U1 / r2
+
+    def prim(x, y, sx, sy):
+        up = (x > 0.0) | ((x == 0.0) & (np.asarray(sx) > 0))
+        rv, Uv, Vv, pv = vortex_prim(x, y, 2.0, 0.0, Mv, 1.0, 1.0, U1, 0.0, p1)
+        return np.where(up, rv, r2), np.where(up, Uv, U2), np.where(up, Vv, 0.0), np.where(up, pv, p2)
+
+    fields = _cell_fields_2d(prim, -20.0, 8.0, -12.0, 12.0, nx, ny)
+    inflow = np.zeros((4, 4))
+    inflow[1] = (1.0, U1, 0.0, p1)
+    return Problem('viscous_shock_vortex_2d', 2, nx, ny, -20.0, 8.0, -12.0, 12.0, fields,
+                   bc=(FREE, INFLOW, PERIODIC, PERIODIC), inflow_prim=inflow, cfl=cfl, t_end=t_end, mu=1.0 / Re,
+                   meta=dict(Ms=Ms, Mv=Mv, Re=Re, downstream=(r2, U2, 0.0, p2), upstream=(1.0, U1, 0.0, p1)))
+
+
 def serving_request(k: int) -> Problem:
     """Request k of the serving workload: periodic [-1,1]^2, background
     (1,0,0,1/gamma), a Gaussian acoustic pulse (amplitude log-uniform in
@@ -449,6 +478,29 @@ def vortex_translation_2d(n: int, Mv: float = 0.3, Rc: float = 0.5, t_end: float
 
     return Problem('vortex_translation_2d', 2, n, n, -5.0, 5.0, -5.0, 5.0, fields, cfl=cfl, t_end=t_end,
                    exact=exact, meta=dict(Mv=Mv, Rc=Rc))
+
+
+def shear_wave_2d(n: int, mu: float, A: float = 1e-3, ny: int = 3, U: float = 0.0, rho: float = 1.0,
+                  p: float = 1.0, t_end: float = 1.0, cfl: float = 0.3, fixed_dt: float = 0.0) -> Problem:
+    """Viscous shear wave on periodic [0,1]^2: uniform rho, p, velocity
+    (U, A sin 2 pi (x - U t)) decaying as exp(-mu k^2 t / rho), k = 2 pi (the
+    Navier-Stokes solution up to the O(A^2) viscous heating); y-invariant."""
+    k = 2.0 * math.pi
+
+    def prim_at(t):
+        amp = A * math.exp(-mu * k * k * t / rho)
+
+        def prim(x, y, sx, sy):
+            x = np.asarray(x, dtype=np.float64)
+            one = np.ones_like(x + 0.0 * np.asarray(y))
+            return rho * one, U * one, amp * np.sin(k * (x - U * t)) * one, p * one
+        return prim
+
+    fields = _cell_fields_2d(prim_at(0.0), 0.0, 1.0, 0.0, 1.0, n, ny)
+    return Problem('shear_wave_2d', 2, n, ny, 0.0, 1.0, 0.0, 1.0, fields, cfl=cfl, t_end=t_end, mu=mu,
+                   fixed_dt=fixed_dt,
+                   exact=lambda t: _cell_fields_2d(prim_at(t), 0.0, 1.0, 0.0, 1.0, n, ny),
+                   meta=dict(A=A, k=k))
 
 
 def uniform_2d(nx: int, ny: int, prim=(1.0, 0.3, -0.2, 0.8), bc=(PERIODIC,) * 4) -> Problem:

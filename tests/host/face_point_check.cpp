@@ -1,7 +1,8 @@
 // Host check of the phase-by-phase face-point evaluation (face_point) against
 // the direct composition tangential_point -> gks_point -> face_accumulate, on
 // seeded random line data; both Gauss points, both face directions, both
-// stages, with and without the WENO / equilibrium fallbacks.
+// stages, Euler and Navier-Stokes collision times, with and without the WENO /
+// equilibrium fallbacks.
 //
 // Prints one line per case: "<dir> <stage> <gp> <case> <max relative difference>".
 #include <hip/hip_runtime.h>
@@ -53,11 +54,12 @@ static double run(const double (&lines)[24][5], const double* right, int gp, con
 int main() {
   std::mt19937_64 rng(12345);
   std::uniform_real_distribution<double> U(-1.0, 1.0);
-  const Gas gas = make_gas(1.4, 2, 0.01, 1.0);
   const double hn = 1.0 / 300, ht = 1.0 / 200, dt = 1.5e-3;
   const double base[4] = {1.0, 0.35, -0.27, 2.6};
   int fails = 0;
+  for (int vis = 0; vis < 2; ++vis)   // Euler, then Navier-Stokes (mu > 0)
   for (int c = 0; c < 40; ++c) {
+    const Gas gas = make_gas(1.4, 2, 0.01, 1.0, vis ? 2e-3 : 0.0);
     // case 0..29 smooth; 30..34 inadmissible right WENO state; 35..39 inadmissible linear state
     double lines[24][5], right[4];
     for (int l = 0; l < 5; ++l)

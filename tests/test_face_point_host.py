@@ -2,7 +2,8 @@
 kernels: the device header compiled for the CPU, face_point (one Gauss point,
 tangential quantities re-read per phase, mirrored line order for the second
 point) against the direct composition tangential_point -> gks_point ->
-face_accumulate, for both face directions, both stages and the fallbacks."""
+face_accumulate, for both face directions, both stages, Euler and
+Navier-Stokes collision times and the fallbacks."""
 import os
 import subprocess
 
@@ -20,6 +21,6 @@ def test_face_point_matches_direct_composition(tmp_path):
     assert lines[-1] == 'fails 0', '\n'.join(l for l in lines if 'FAIL' in l)[:2000]
     assert out.returncode == 0
     rows = [l.split() for l in lines[:-1]]
-    assert len(rows) == 40 * 8
+    assert len(rows) == 2 * 40 * 8
     # fallbacks were exercised: right WENO state and equilibrium state
     assert any(r[7] == '1' for r in rows) and any(r[5] == '1' for r in rows)

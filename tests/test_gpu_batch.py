@@ -3,6 +3,7 @@ different sizes and boundary conditions advanced by shared launches (one HIP
 graph per run) must give, slot by slot, exactly the states of separate
 contexts advanced eagerly — every replay checked, with eager work and
 synchronisation between replays — and the admission, end and release rules."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -25,7 +26,8 @@ def problems():
     return [I.acoustic_pulse_2d(48, seed=5, amp=1e-3, half_width=0.2, ny=33),
             I.shock_vortex_2d(64, 32, Rc=0.12),
             I.vortex_translation_2d(24),
-            I.acoustic_pulse_2d(37, seed=4, amp=0.05, half_width=0.3, ny=21)]
+            I.acoustic_pulse_2d(37, seed=4, amp=0.05, half_width=0.3, ny=21),
+            dataclasses.replace(I.shear_wave_2d(29, 0.01, A=0.05, ny=19, U=0.3, rho=1.2, p=0.7), mu=0.01)]
 
 
 def test_batch_replays_equal_separate_contexts():

@@ -118,6 +118,32 @@ def test_interface_state_against_bruteforce(dim):
 
 
 @pytest.mark.parametrize('dim', [1, 2])
+def test_viscous_collision_time_and_flux_against_bruteforce(dim):
+    """Navier-Stokes (Sec. 4, viscous form): tau = mu/p0 + C|dp/sum p| dt with
+    p0 the pressure of the interface equilibrium, used in both roles; the
+    whole distribution integrated by brute force with tau_ce = tau."""
+    W0 = cons(dim, 1.0, 0.3, 0.1, 1.0)
+    Wl = cons(dim, 1.3, 0.5, 0.15, 1.4)
+    Wr = cons(dim, 0.8, 0.1, -0.05, 0.7)
+    rng = np.random.default_rng(9)
+    W0n = 0.3 * rng.normal(size=dim + 2)
+    W0t = 0.2 * rng.normal(size=dim + 2) if dim == 2 else None
+    z = np.zeros(dim + 2)
+    dt, mu = 0.05, 0.004
+    r = O.gks_point(dim, G, dt, W0, W0n, z, Wl, Wr, W0t=W0t, mu=mu)
+    pl, pr, p0 = B.Maxw(Wl, G, dim).p, B.Maxw(Wr, G, dim).p, B.Maxw(W0, G, dim).p
+    tau = mu / p0 + abs((pl - pr) / (pl + pr)) * dt
+    assert r['tau'] == pytest.approx(tau, rel=1e-14)
+    Fh = B.flux_time_integral(dim, G, tau, 0.5 * dt, W0, W0n, W0t, Wl, Wr, tau_ce=tau)
+    Ff = B.flux_time_integral(dim, G, tau, dt, W0, W0n, W0t, Wl, Wr, tau_ce=tau)
+    np.testing.assert_allclose(r['F'] * 0.5 * dt + r['Ft'] * dt * dt / 8, Fh, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(r['F'] * dt + r['Ft'] * dt * dt / 2, Ff, rtol=1e-9, atol=1e-12)
+    for t, N in ((0.5 * dt, r['Nh']), (dt, r['Nf'])):
+        ref = B.state_at(dim, G, tau, t, W0, W0n, W0t, Wl, Wr, tau_ce=tau)
+        np.testing.assert_allclose(W0 + t * r['Wt'] + N, ref, rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize('dim', [1, 2])
 def test_smooth_limit_is_the_euler_flux_and_its_ck_derivative(dim):
     """W_l = W_r = W0 with shared slopes: the flux is F(W0) + t F_t exactly with
     F_t = dF/dW . W_t and W_t = -(dF/dW W_n + dG/dW W_t); no remainder."""

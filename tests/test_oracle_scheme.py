@@ -237,6 +237,29 @@ def test_stationary_shock_stays_in_place():
     assert o.counters()['guard_w0'] == 0
 
 
+def _shear_ratio(dt, U=0.0):
+    p = I.shear_wave_2d(16, 0.01, rho=1.2, p=0.7, U=U, t_end=0.5, fixed_dt=dt)
+    o = O.Oracle(p)
+    o.advance_to(0.5)
+    st, t, _ = o.get_state()
+    ex = p.exact(t)
+    s = np.sin(2 * math.pi * ((np.arange(16) + 0.5) / 16 - U * t))
+    return (st[2].mean(axis=0) @ s) / (ex[2].mean(axis=0) @ s) - 1.0
+
+
+def test_viscous_shear_wave_decays_at_the_navier_stokes_rate():
+    """Navier-Stokes (mu > 0): a shear wave with rho = 1.2, p = 0.7 decays as
+    exp(-mu k^2 t / rho) (kinematic viscosity mu/rho, so a collision time
+    mu/rho or a missing factor would show).  The second-order distribution
+    keeps the Chapman-Enskog flux constant over a step, so the decay converges
+    at first order in dt: the error halves with dt and its Richardson
+    extrapolation vanishes (to the O(A^2) heating)."""
+    e1, e2 = _shear_ratio(0.005), _shear_ratio(0.0025)
+    assert 0.0 < e2 < 3e-4
+    assert e2 / e1 == pytest.approx(0.5, abs=0.03)
+    assert abs(2 * e2 - e1) < 2e-5
+
+
 def test_shock_entropy_config2_positive_and_bounded():
     p = I.shock_entropy_1d(400, t_end=1.8)
     o = O.Oracle(p)

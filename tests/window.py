@@ -39,7 +39,7 @@ def window_step(prob, fields, i0, j0, size, dt, ulp_seed=None):
     dx, dy = prob.dx, prob.dy
     p = I.Problem('window', 2, len(ix), len(iy), 0.0, dx * len(ix), 0.0, dy * len(iy), patch,
                   bc=(xlo, xhi, ylo, yhi), inflow_prim=prob.inflow_prim, gamma=prob.gamma, cfl=prob.cfl,
-                  weno_eps=prob.weno_eps, tau_eps=prob.tau_eps, tau_C=prob.tau_C)
+                  weno_eps=prob.weno_eps, tau_eps=prob.tau_eps, tau_C=prob.tau_C, mu=prob.mu)
     o = O.Oracle(p, threads=4)
     o.step(dt)
     st = o.state
