@@ -16,22 +16,26 @@ import collections
 import csv
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-SHORT = {
-    'k_faces2<0, 1>': 'xfaces1', 'k_faces2<1, 1>': 'yfaces1', 'k_faces2<0, 2>': 'xfaces2',
-    'k_faces2<1, 2>': 'yfaces2', 'k_update2<1>': 'update1', 'k_update2<2>': 'update2',
-    'k_faces1<1>': 'faces1', 'k_faces1<2>': 'faces2', 'k_update1<1>': 'update1_1d', 'k_update1<2>': 'update2_1d',
-    'k_begin': 'begin', 'k_end': 'end', 'k_scan<4>': 'scan', 'k_scan<3>': 'scan_1d',
-}
+# kernel name patterns (template arguments after the leading ones, such as the
+# storage type and the tile shape, do not change the short name)
+SHORT = [
+    (r'k_faces2<0, 1\b', 'xfaces1'), (r'k_faces2<1, 1\b', 'yfaces1'), (r'k_faces2<0, 2\b', 'xfaces2'),
+    (r'k_faces2<1, 2\b', 'yfaces2'), (r'k_update2<1\b', 'update1'), (r'k_update2<2\b', 'update2'),
+    (r'k_faces1<1\b', 'faces1'), (r'k_faces1<2\b', 'faces2'), (r'k_update1<1\b', 'update1_1d'),
+    (r'k_update1<2\b', 'update2_1d'), (r'k_begin\b', 'begin'), (r'k_end\b', 'end'), (r'k_scan<4\b', 'scan'),
+    (r'k_scan<3\b', 'scan_1d'),
+]
 COPY_KERNEL = '__amd_rocclr_copyBuffer'
 
 
 def short_name(full: str) -> str:
-    for k, v in SHORT.items():
-        if k in full:
+    for pat, v in SHORT:
+        if re.search(pat, full):
             return v
     return full.split('(')[0][:60]
 
