@@ -1,8 +1,10 @@
 /*
  * cgks.h -- C ABI of the compact 8th-order gas-kinetic scheme on MI355X.
  *
- * The library advances the Euler equations on structured 1D and 2D grids by
- * the compact gas-kinetic scheme of Zhao, Ji, Shyy, Xu (arXiv 2001.01570):
+ * The library advances the Euler equations (with a viscosity mu > 0 in the
+ * configuration, the Navier-Stokes equations of the BGK model) on structured
+ * 1D and 2D grids by the compact gas-kinetic scheme of Zhao, Ji, Shyy, Xu
+ * (arXiv 2001.01570):
  * given cell averages W and cell-averaged gradients W' (Sec. 3.1, eqs.
  * compact-deriv-1 / compact-deriv), one step performs the compact linear and
  * WENO-Z reconstruction (Sec. 3.2-3.3), the gas-kinetic interface evolution
@@ -135,9 +137,11 @@ const char *cgks_strerror(int code);
  * admitted problem, a "slot", takes its buffers (about 130 bytes per cell:
  * 4 x 12 fields plus the face results).  cgks_batch_run advances every running
  * slot together: each of the 8 kernels of a step is one launch covering the
- * blocks of all running slots, and the requested number of steps is one HIP
- * graph, captured again only when the set of running slots or the step count
- * changes.  A slot stops by itself at its end time or step bound; its state
+ * blocks of all running slots (a work list in device memory, rewritten on
+ * admission and release), and the requested number of steps is one HIP graph,
+ * captured again only when a work list leaves the power-of-two bucket its
+ * launch grid was sized for, or the step count changes.  A slot stops by
+ * itself at its end time or step bound; its state
  * stays readable until it is released.  All calls are synchronous with
  * respect to the host and not thread-safe. */
 typedef struct cgks_batch cgks_batch;
