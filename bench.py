@@ -48,33 +48,42 @@ def cpu_baseline(prob, target_s=10.0):
     horizontal band of the same workload (full width, periodic in x) with a
     4-row margin, rows counted only in the band's exact core.  The band height
     is chosen from a 16-row probe so that the timed step takes about target_s
-    seconds (at most the whole grid).  Threads: the host cores this process may
-    use, at most 16 (one GPU's share of a host)."""
+    seconds; if the whole grid takes less, consecutive steps of it are timed
+    until about target_s.  Threads: the host cores this process may use, at
+    most 16 (one GPU's share of a host)."""
     import numpy as np
     from oracle import oracle as O
     from paper_2001_01570_amd import inputs as I
     threads = len(os.sched_getaffinity(0)) if hasattr(os, 'sched_getaffinity') else os.cpu_count()
     threads = max(1, min(threads, 16))
 
-    def band_step(rows):
-        j0 = prob.ny // 2 - rows // 2
-        iy = np.arange(j0 - 4, j0 + rows + 4) % prob.ny
-        band = np.ascontiguousarray(prob.fields[:, iy, :])
-        p = I.Problem('band', 2, prob.nx, len(iy), prob.x0, prob.x1, 0.0, prob.dy * len(iy), band,
-                      bc=(I.PERIODIC, I.PERIODIC, I.FREE, I.FREE), cfl=prob.cfl)
+    def band_step(rows, steps=1):
+        if rows == prob.ny:              # the whole periodic grid
+            p = prob
+        else:
+            j0 = prob.ny // 2 - rows // 2
+            iy = np.arange(j0 - 4, j0 + rows + 4) % prob.ny
+            band = np.ascontiguousarray(prob.fields[:, iy, :])
+            p = I.Problem('band', 2, prob.nx, len(iy), prob.x0, prob.x1, 0.0, prob.dy * len(iy), band,
+                          bc=(I.PERIODIC, I.PERIODIC, I.FREE, I.FREE), cfl=prob.cfl)
         o = O.Oracle(p, threads=threads)
-        dt = o.cfl_dt()
         t0 = time.perf_counter()
-        o.step(dt)
+        for _ in range(steps):
+            o.step(o.cfl_dt())
         return time.perf_counter() - t0
 
     probe = band_step(16)
     rows = int(min(prob.ny, max(16, 24 * target_s / max(probe, 1e-6) - 8)))   # the probe computes 24 rows
-    el = band_step(rows)
-    cells = prob.nx * rows
+    steps = 1
+    if rows == prob.ny:
+        steps = max(1, int(round(target_s / (probe * (prob.ny + 8) / 24))))
+    el = band_step(rows, steps)
+    cells = prob.nx * rows * steps
+    what = ('%d MSMD step%s of the whole %dx%d workload' % (steps, 's' if steps > 1 else '', prob.nx, prob.ny)
+            if rows == prob.ny else
+            '1 MSMD step of a %dx%d band (+4-row margins) of the %dx%d workload' % (prob.nx, rows, prob.nx, prob.ny))
     return dict(value=cells / el, unit='cell-updates/s', cores=threads, kind='oracle',
-                sample='1 MSMD step of a %dx%d band (+4-row margins) of the %dx%d workload, %.1f s on %d threads'
-                       % (prob.nx, rows, prob.nx, prob.ny, el, threads))
+                sample='%s, %.1f s on %d threads' % (what, el, threads))
 
 
 def launch_units(kernel, nx, ny):
