@@ -125,6 +125,28 @@ def test_batch_admission_and_release():
     b.close()
 
 
+def test_batch_failing_slot_leaves_the_others_unchanged():
+    """A slot whose step turns non-physical (a fixed step far beyond
+    stability) fails alone: its state stays at the last good step, the other
+    slots advance bitwise as separate contexts."""
+    from paper_2001_01570_amd.cgks import Batch, Solver, SLOT_FAILED, SLOT_DONE
+    good = [I.vortex_translation_2d(24), I.acoustic_pulse_2d(37, seed=4, amp=0.05, half_width=0.3, ny=21)]
+    bad = dataclasses.replace(I.acoustic_pulse_2d(32, seed=2, amp=0.05, half_width=0.3), fixed_dt=50.0)
+    b = Batch(GiB // 4, max_slots=4)
+    sg = [b.admit(p, max_steps=3) for p in good]
+    sb = b.admit(bad, max_steps=3)
+    b.run(3)
+    st, t, n = b.poll(sb)
+    assert st == SLOT_FAILED and n == 0 and t == 0.0
+    assert np.array_equal(b.read(sb), bad.fields)
+    for p, s in zip(good, sg):
+        r = Solver(p)
+        r.run_steps(3)
+        assert b.poll(s)[0] == SLOT_DONE
+        assert np.array_equal(b.read(s), r.get_state()[0])
+    b.close()
+
+
 def test_batch_slot_reused_by_another_grid():
     """A released slot index taken by a problem of another size between two
     runs: the launches must follow the new grid (regression: the block table
