@@ -264,6 +264,31 @@ def test_config3_full_size_single_step_sampled():
     assert (np.abs(tot - tot0) / np.maximum(scale, 1.0)).max() < 1e-14
 
 
+def test_config3_full_size_ten_steps_sampled():
+    """Ten GPU steps at full size with the bench's kernels and tile shapes
+    (stepped one by one to record each step size; the bench's graph replays
+    are bitwise the same launches, tested separately); each window is stepped
+    by the oracle with the GPU's ten step sizes and a 40-cell margin.  Compared with the multi-step metric (gradients x cell
+    width, relative to their component's averages)."""
+    from tests.window import window_step
+    p = I.acoustic_pulse_2d(1024, seed=0, cfl=0.15)
+    cx, cy = p.meta['centre']
+    ic, jc = int((cx + 1.0) / p.dx), int((cy + 1.0) / p.dy)
+    s = solver(p)
+    dts = []
+    for _ in range(10):
+        dts.append(s.step())
+    g = s.state
+    worst = 0.0
+    for (i0, j0) in [((ic - 4) % 1024, (jc - 4) % 1024), ((ic + 30) % 1024, (jc - 9) % 1024), (1020, 1020)]:
+        core, (iy, ix) = window_step(p, p.fields, i0, j0, 8, dts)
+        gc = g[:, iy][:, :, ix]
+        err = scaled_errors(gc, core, p.dx, p.dy)
+        say('10-step window', (i0, j0), err)
+        worst = max(worst, err.max())
+    assert worst < TOL, worst
+
+
 def test_config4_full_size_single_step_sampled():
     p = I.shock_vortex_2d(2048, 1024)
     wins = [(0, 0), (508, 500), (254, 508), (2040, 1016), (1024, 0), (0, 1016), (250, 470)]
