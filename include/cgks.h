@@ -40,7 +40,12 @@ extern "C" {
 #define CGKS_EBUSY (-5)      /* batch: no free slot or memory budget exhausted      */
 #define CGKS_ESTATE (-6)     /* call not valid in the current state (e.g. no state) */
 
-enum { CGKS_PERIODIC = 0, CGKS_FREE = 1, CGKS_WALL = 2, CGKS_INFLOW = 3 };
+/* Boundary conditions (two ghost layers, mirrored or copied cells): periodic;
+ * free (copy of the edge cell, zero gradients); slip wall (mirror, normal
+ * momentum odd); inflow (the side's fixed state, zero gradients); no-slip
+ * wall (mirror with every momentum odd: zero velocity and, the temperature
+ * being even, zero heat flux at the wall; for viscous flow). */
+enum { CGKS_PERIODIC = 0, CGKS_FREE = 1, CGKS_WALL = 2, CGKS_INFLOW = 3, CGKS_NOSLIP = 4 };
 /* Storage of the state fields.  CGKS_FP32_STORAGE (2D only): the 8 cell-
  * averaged gradient fields of the state and of the stage buffers are kept in
  * FP32; cell averages, all arithmetic, the conservative accumulation and the
@@ -56,7 +61,7 @@ typedef struct {
   double x0, x1, y0, y1;     /* domain                                                   */
   double gamma;              /* ratio of specific heats (> 1)                            */
   double cfl;                /* CFL number of the time step rule (Sec. 4)                */
-  int bc[4];                 /* xlo, xhi, ylo, yhi: CGKS_PERIODIC|FREE|WALL|INFLOW;
+  int bc[4];                 /* xlo, xhi, ylo, yhi: CGKS_PERIODIC|FREE|WALL|INFLOW|NOSLIP;
                                 periodic must be paired on both sides of an axis         */
   double inflow_prim[4][4];  /* (rho, U, V, p) of each CGKS_INFLOW side                  */
   double weno_eps;           /* epsilon of the WENO-Z weights (eq. WENO-Z-w), e.g. 1e-6  */
@@ -67,7 +72,7 @@ typedef struct {
                                 Navier-Stokes with the BGK Prandtl number 1; the
                                 collision time is mu/p + C|dp/sum p|*dt in both of
                                 its roles (Sec. 4, viscous form) and tau_eps is
-                                unused; walls stay slip walls                        */
+                                unused; CGKS_NOSLIP gives viscous walls              */
 } cgks_config;
 
 typedef struct {

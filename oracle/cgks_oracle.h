@@ -23,7 +23,7 @@
 extern "C" {
 #endif
 
-enum { ORC_PERIODIC = 0, ORC_FREE = 1, ORC_WALL = 2, ORC_INFLOW = 3 };
+enum { ORC_PERIODIC = 0, ORC_FREE = 1, ORC_WALL = 2, ORC_INFLOW = 3, ORC_NOSLIP = 4 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ENONPHYS = -4 };
 
 typedef struct {

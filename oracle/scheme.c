@@ -41,7 +41,7 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   if (cfg->nx < 1 || (cfg->dim == 2 && cfg->ny < 1)) return ORC_EINVAL;
   if (!(cfg->gamma > 1.0) || !(cfg->x1 > cfg->x0)) return ORC_EINVAL;
   if (cfg->dim == 2 && !(cfg->y1 > cfg->y0)) return ORC_EINVAL;
-  for (int s = 0; s < 2 * cfg->dim; ++s) if (cfg->bc[s] < 0 || cfg->bc[s] > 3) return ORC_EINVAL;
+  for (int s = 0; s < 2 * cfg->dim; ++s) if (cfg->bc[s] < 0 || cfg->bc[s] > 4) return ORC_EINVAL;
   if ((cfg->bc[0] == ORC_PERIODIC) != (cfg->bc[1] == ORC_PERIODIC)) return ORC_EINVAL;
   if (cfg->dim == 2 && (cfg->bc[2] == ORC_PERIODIC) != (cfg->bc[3] == ORC_PERIODIC)) return ORC_EINVAL;
   if (!(cfg->mu >= 0.0) || !isfinite(cfg->mu)) return ORC_EINVAL;
@@ -141,10 +141,12 @@ static void ghost_copy(orc_ctx *c, double *G, size_t dst, size_t src, int side, 
     inflow_state(c, side, W);
     for (int k = 0; k < nc; ++k) fld(c, G, k)[dst] = W[k];
     for (int f = nc; f < c->nf; ++f) fld(c, G, f)[dst] = 0.0;
-  } else {  /* wall */
+  } else {  /* wall: mirror; slip wall: the normal momentum is odd, no-slip
+             * (viscous, adiabatic) wall: both momenta are odd */
     const int vel = 1 + axis;     /* momentum component normal to the wall */
     for (int k = 0; k < nc; ++k) {
-      const double par = (k == vel) ? -1.0 : 1.0;
+      const int odd = k == vel || (bc == ORC_NOSLIP && k >= 1 && k <= c->cfg.dim);
+      const double par = odd ? -1.0 : 1.0;
       fld(c, G, k)[dst] = par * fld(c, G, k)[src];
       for (int a = 0; a < c->cfg.dim; ++a) {
         const double gpar = (a == axis) ? -par : par;
@@ -161,12 +163,12 @@ static void fill_ghosts(orc_ctx *c, double *G) {
       int src_lo, src_hi;
       switch (c->cfg.bc[0]) {
         case ORC_PERIODIC: src_lo = ((-k) % nx + nx) % nx; break;
-        case ORC_WALL: src_lo = k - 1 < nx ? k - 1 : nx - 1; break;
+        case ORC_WALL: case ORC_NOSLIP: src_lo = k - 1 < nx ? k - 1 : nx - 1; break;
         default: src_lo = 0;
       }
       switch (c->cfg.bc[1]) {
         case ORC_PERIODIC: src_hi = (nx - 1 + k) % nx; break;
-        case ORC_WALL: src_hi = nx - k >= 0 ? nx - k : 0; break;
+        case ORC_WALL: case ORC_NOSLIP: src_hi = nx - k >= 0 ? nx - k : 0; break;
         default: src_hi = nx - 1;
       }
       ghost_copy(c, G, gidx(c, -k, j), gidx(c, src_lo, j), 0, 0);
@@ -178,12 +180,12 @@ static void fill_ghosts(orc_ctx *c, double *G) {
       int src_lo, src_hi;
       switch (c->cfg.bc[2]) {
         case ORC_PERIODIC: src_lo = ((-k) % ny + ny) % ny; break;
-        case ORC_WALL: src_lo = k - 1 < ny ? k - 1 : ny - 1; break;
+        case ORC_WALL: case ORC_NOSLIP: src_lo = k - 1 < ny ? k - 1 : ny - 1; break;
         default: src_lo = 0;
       }
       switch (c->cfg.bc[3]) {
         case ORC_PERIODIC: src_hi = (ny - 1 + k) % ny; break;
-        case ORC_WALL: src_hi = ny - k >= 0 ? ny - k : 0; break;
+        case ORC_WALL: case ORC_NOSLIP: src_hi = ny - k >= 0 ? ny - k : 0; break;
         default: src_hi = ny - 1;
       }
       ghost_copy(c, G, gidx(c, i, -k), gidx(c, i, src_lo), 2, 1);

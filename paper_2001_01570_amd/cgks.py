@@ -16,7 +16,7 @@ import numpy as np
 from . import build as _build
 
 CGKS_OK, CGKS_EINVAL, CGKS_ENOMEM, CGKS_EDEVICE, CGKS_ENONPHYS, CGKS_EBUSY, CGKS_ESTATE = 0, -1, -2, -3, -4, -5, -6
-PERIODIC, FREE, WALL, INFLOW = 0, 1, 2, 3
+PERIODIC, FREE, WALL, INFLOW, NOSLIP = 0, 1, 2, 3, 4
 CGKS_FP64, CGKS_FP32_STORAGE = 0, 1
 
 

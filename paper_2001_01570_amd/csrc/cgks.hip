@@ -105,17 +105,24 @@ __device__ __forceinline__ int src_index(int i, int n, int bclo, int bchi, int& 
   if (i < 0) {
     kind = bclo; side = 0;
     if (bclo == CGKS_PERIODIC) return wrap(i, n);
-    if (bclo == CGKS_WALL) return -i - 1;
+    if (bclo == CGKS_WALL || bclo == CGKS_NOSLIP) return -i - 1;
     return 0;
   }
   kind = bchi; side = 1;
   if (bchi == CGKS_PERIODIC) return wrap(i, n);
-  if (bchi == CGKS_WALL) return 2 * n - 1 - i;
+  if (bchi == CGKS_WALL || bchi == CGKS_NOSLIP) return 2 * n - 1 - i;
   return n - 1;
 }
 
 // rule of one side on (W, gradient along dir): free -> zero gradients,
-// inflow -> fixed state and zero gradients, wall -> mirror
+// inflow -> fixed state and zero gradients, walls -> mirror
+// Parity of component k under the mirror about a wall normal to axis: the
+// normal momentum is odd (slip wall), every momentum for a no-slip wall.
+template <int NC>
+__device__ __forceinline__ double wall_parity(int kind, int axis, int k) {
+  return (k == 1 + axis || (kind == CGKS_NOSLIP && k >= 1 && k <= NC - 2)) ? -1.0 : 1.0;
+}
+
 template <int NC>
 __device__ __forceinline__ void apply_rule(const Geom& G, int kind, int side, int axis, int dir,
                                            double* W, double* Gd) {
@@ -126,14 +133,12 @@ __device__ __forceinline__ void apply_rule(const Geom& G, int kind, int side, in
   } else if (kind == CGKS_INFLOW) {
 #pragma unroll
     for (int k = 0; k < NC; ++k) { W[k] = G.inflow[side][k]; Gd[k] = 0.0; }
-  } else {  // wall: normal momentum odd; normal gradient opposite parity, tangential same
-    const int vel = 1 + axis;
-    W[vel] = -W[vel];
-    if (dir == axis) {
+  } else {  // walls: W with its parity, normal gradient opposite parity, tangential same
 #pragma unroll
-      for (int k = 0; k < NC; ++k) if (k != vel) Gd[k] = -Gd[k];
-    } else {
-      Gd[vel] = -Gd[vel];
+    for (int k = 0; k < NC; ++k) {
+      const double par = wall_parity<NC>(kind, axis, k);
+      W[k] *= par;
+      Gd[k] *= dir == axis ? -par : par;
     }
   }
 }
@@ -191,11 +196,10 @@ __device__ __forceinline__ void load_comp(const double* S, const Geom& G, int i,
     } else if (kind == CGKS_INFLOW) {
       w = G.inflow[side][k];
       gd = 0.0;
-    } else {  // wall about axis a
-      const int vel = 1 + a;
-      if (k == vel) w = -w;
-      if (dir == a) { if (k != vel) gd = -gd; }
-      else if (k == vel) gd = -gd;
+    } else {  // walls about axis a
+      const double par = wall_parity<4>(kind, a, k);
+      w *= par;
+      gd *= dir == a ? -par : par;
     }
   }
 }
@@ -817,9 +821,9 @@ static int validate(const cgks_config* c) {
   if (!(c->mu >= 0.0) || !std::isfinite(c->mu)) return CGKS_EINVAL;
   if (c->storage != CGKS_FP64 && !(c->storage == CGKS_FP32_STORAGE && c->dim == 2)) return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
-    if (c->bc[s] < 0 || c->bc[s] > 3) return CGKS_EINVAL;
+    if (c->bc[s] < 0 || c->bc[s] > 4) return CGKS_EINVAL;
     const int n = s < 2 ? c->nx : c->ny;
-    if (c->bc[s] == CGKS_WALL && n < 2) return CGKS_EINVAL;
+    if ((c->bc[s] == CGKS_WALL || c->bc[s] == CGKS_NOSLIP) && n < 2) return CGKS_EINVAL;
     if (c->bc[s] == CGKS_INFLOW) {
       const double* q = c->inflow_prim[s];
       if (!(q[0] > 0.0) || !(q[3] > 0.0)) return CGKS_EINVAL;

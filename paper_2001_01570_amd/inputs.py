@@ -26,7 +26,7 @@ from typing import Callable, List, Optional, Sequence
 import numpy as np
 
 GAMMA = 1.4
-PERIODIC, FREE, WALL, INFLOW = 0, 1, 2, 3
+PERIODIC, FREE, WALL, INFLOW, NOSLIP = 0, 1, 2, 3, 4
 
 
 @dataclasses.dataclass
@@ -501,6 +501,28 @@ def shear_wave_2d(n: int, mu: float, A: float = 1e-3, ny: int = 3, U: float = 0.
                    fixed_dt=fixed_dt,
                    exact=lambda t: _cell_fields_2d(prim_at(t), 0.0, 1.0, 0.0, 1.0, n, ny),
                    meta=dict(A=A, k=k))
+
+
+def channel_shear_2d(n: int, mu: float, A: float = 1e-3, ny: int = 3, rho: float = 1.0, p: float = 1.0,
+                     t_end: float = 1.0, cfl: float = 0.3, fixed_dt: float = 0.0) -> Problem:
+    """Viscous shear flow between no-slip walls at x = 0 and 1 (periodic in y):
+    uniform rho, p, velocity (0, A sin pi x) decaying as exp(-mu pi^2 t / rho)
+    (the Navier-Stokes solution up to the O(A^2) heating); y-invariant."""
+    k = math.pi
+
+    def prim_at(t):
+        amp = A * math.exp(-mu * k * k * t / rho)
+
+        def prim(x, y, sx, sy):
+            x = np.asarray(x, dtype=np.float64)
+            one = np.ones_like(x + 0.0 * np.asarray(y))
+            return rho * one, 0.0 * one, amp * np.sin(k * x) * one, p * one
+        return prim
+
+    fields = _cell_fields_2d(prim_at(0.0), 0.0, 1.0, 0.0, 1.0, n, ny)
+    return Problem('channel_shear_2d', 2, n, ny, 0.0, 1.0, 0.0, 1.0, fields, bc=(NOSLIP, NOSLIP, PERIODIC, PERIODIC),
+                   cfl=cfl, t_end=t_end, mu=mu, fixed_dt=fixed_dt,
+                   exact=lambda t: _cell_fields_2d(prim_at(t), 0.0, 1.0, 0.0, 1.0, n, ny), meta=dict(A=A, k=k))
 
 
 def uniform_2d(nx: int, ny: int, prim=(1.0, 0.3, -0.2, 0.8), bc=(PERIODIC,) * 4) -> Problem:

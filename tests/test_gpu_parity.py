@@ -108,6 +108,20 @@ def test_1d_shock_tube_free_boundaries():
 
 # ---------------------------------------------------------------- 2D small
 
+def _noslip_box():
+    """a flowing viscous pulse in a box of no-slip walls (momentum nonzero at
+    the walls, so the walls' parity rules are exercised)"""
+    p = I.acoustic_pulse_2d(37, seed=4, amp=0.05, half_width=0.3, ny=21)
+    p.fields[1] += 0.2 * p.fields[0]
+    p.fields[2] -= 0.1 * p.fields[0]
+    p.fields[3] += 0.025 * p.fields[0]
+    p.fields[5] += 0.2 * p.fields[4]
+    p.fields[6] -= 0.1 * p.fields[4]
+    p.fields[9] += 0.2 * p.fields[8]
+    p.fields[10] -= 0.1 * p.fields[8]
+    return dataclasses.replace(p, mu=0.01, bc=(I.NOSLIP,) * 4)
+
+
 CASES_2D = [
     ('pulse_ragged', lambda: I.acoustic_pulse_2d(37, seed=4, amp=0.05, half_width=0.3, ny=21)),
     ('pulse_tiles', lambda: I.acoustic_pulse_2d(48, seed=5, amp=1e-3, half_width=0.2, ny=33)),
@@ -117,11 +131,13 @@ CASES_2D = [
     ('viscous_pulse_ragged', lambda: dataclasses.replace(
         I.acoustic_pulse_2d(37, seed=4, amp=0.05, half_width=0.3, ny=21), mu=0.01)),
     ('viscous_shock_vortex', lambda: dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), mu=2e-3)),
+    ('viscous_noslip_box', lambda: _noslip_box()),
 ]
 # the shear wave's density is uniform, so its density gradients are rounding
 # noise with no scale of their own: it is compared with the multi-step metric
 VISCOUS = [c for c in CASES_2D if c[0].startswith('viscous')] + [
-    ('viscous_shear_ragged', lambda: I.shear_wave_2d(37, 0.01, A=0.05, ny=21, U=0.3, rho=1.2, p=0.7))]
+    ('viscous_shear_ragged', lambda: I.shear_wave_2d(37, 0.01, A=0.05, ny=21, U=0.3, rho=1.2, p=0.7)),
+    ('viscous_channel', lambda: I.channel_shear_2d(40, 0.01, A=0.05, ny=9, rho=1.2, p=0.7))]
 
 
 @pytest.mark.parametrize('name,mk', CASES_2D, ids=[c[0] for c in CASES_2D])

@@ -261,6 +261,31 @@ def test_viscous_shear_wave_decays_at_the_navier_stokes_rate():
     assert abs(2 * e2 - e1) < 2e-5
 
 
+def _channel_ratio(dt, bc=None):
+    p = I.channel_shear_2d(16, 0.01, rho=1.2, p=0.7, t_end=0.5, fixed_dt=dt)
+    if bc is not None:
+        p = dataclasses.replace(p, bc=bc)
+    o = O.Oracle(p)
+    o.advance_to(0.5)
+    st, t, _ = o.get_state()
+    ex = p.exact(t)
+    s = np.sin(math.pi * (np.arange(16) + 0.5) / 16)
+    return (st[2].mean(axis=0) @ s) / (ex[2].mean(axis=0) @ s) - 1.0
+
+
+def test_noslip_channel_decays_at_the_navier_stokes_rate():
+    """Shear flow A sin(pi x) between no-slip walls at x = 0 and 1: the wall's
+    mirror makes the tangential momentum odd, and the decay converges to
+    exp(-mu pi^2 t / rho) at first order in dt.  A slip wall (tangential
+    momentum even) is a different problem and misses it by far."""
+    e1, e2 = _channel_ratio(0.005), _channel_ratio(0.0025)
+    assert 0.0 < e2 < 3e-5
+    assert e2 / e1 == pytest.approx(0.5, abs=0.03)
+    assert abs(2 * e2 - e1) < 1e-6
+    slip = _channel_ratio(0.0025, bc=(I.WALL, I.WALL, I.PERIODIC, I.PERIODIC))
+    assert abs(slip) > 100 * e2
+
+
 def test_shock_entropy_config2_positive_and_bounded():
     p = I.shock_entropy_1d(400, t_end=1.8)
     o = O.Oracle(p)
