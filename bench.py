@@ -290,6 +290,9 @@ def main():
     ap.add_argument('--steps', type=int, default=500)
     ap.add_argument('--warmup', type=int, default=10)
     ap.add_argument('--n', type=int, default=1024, help='grid side (the workload is defined at 1024)')
+    ap.add_argument('--workload', choices=('pulse', 'shock_vortex'), default='pulse',
+                    help='pulse: the headline 1024^2 acoustic pulse; shock_vortex: the 2048x1024 Mach 1.1 '
+                         'shock-vortex case (throughput of its first steps; the work per step does not depend on t)')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--copy-calibration', type=int, default=0, metavar='MIB',
                     help='also run one plain device copy of this many MiB (reference for HBM byte counters)')
@@ -312,8 +315,16 @@ def main():
     from paper_2001_01570_amd import inputs as I
     from paper_2001_01570_amd.cgks import Solver
 
-    log('[bench] building workload %dx%d' % (args.n, args.n))
-    prob = I.acoustic_pulse_2d(args.n, seed=0, cfl=C3_CFL)
+    if args.workload == 'pulse':
+        log('[bench] building workload %dx%d' % (args.n, args.n))
+        prob = I.acoustic_pulse_2d(args.n, seed=0, cfl=C3_CFL)
+        workload = ('acoustic_pulse_2d periodic %dx%d on [-1,1]^2, amp 1e-3, half-width 0.05, CFL %g'
+                    % (prob.nx, prob.ny, C3_CFL))
+    else:
+        log('[bench] building workload shock_vortex 2048x1024')
+        prob = I.shock_vortex_2d(2048, 1024)
+        workload = ('shock_vortex_2d 2048x1024 on [0,2]x[0,1], Mach 1.1 normal shock + vortex Mv 0.3, '
+                    'walls, inflow, free outflow, CFL %g' % prob.cfl)
     fields = torch.from_numpy(prob.fields).to('cuda')
     torch.cuda.synchronize()
     s = Solver(prob, load_state=False)
@@ -392,8 +403,7 @@ def main():
         'vs_baseline': None,
         'dtype': 'f64',
         'data': 'synthetic',
-        'config': {'workload': 'acoustic_pulse_2d periodic %dx%d on [-1,1]^2, amp 1e-3, half-width 0.05, CFL %g'
-                               % (prob.nx, prob.ny, C3_CFL), 'cells': cells, 'seed': 0},
+        'config': {'workload': workload, 'cells': cells, 'seed': 0},
         'roofline': roof,
         'kernel_ms_per_launch_probe': {k: v[0] / max(v[1], 1) for k, v in probe.items()},
         'cpu_baseline': cpu,
