@@ -36,7 +36,9 @@ def field_scales(o):
             den = max(den, ms)
         if den == 0.0:    # identically zero field: measure against its component's scale
             den = np.abs(o[f % nc]).max()
-        out.append(den)
+            if 1 <= f % nc < nc - 1:
+                den = max(den, ms)
+        out.append(den if den > 0.0 else 1.0)
     return np.array(out)
 
 

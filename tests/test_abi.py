@@ -57,3 +57,53 @@ def test_binding_refuses_without_gpu():
         assert 'GPU' in str(e)
     else:
         raise AssertionError('the HIP binding must not run without a GPU')
+
+
+def test_create_rejects_invalid_configurations_before_touching_the_device():
+    """cgks_create validates the configuration first and returns CGKS_EINVAL
+    (no device call is made for a rejected configuration)."""
+    import dataclasses
+    from paper_2001_01570_amd import inputs as I
+    from paper_2001_01570_amd.cgks import make_config, CGKS_FP32_STORAGE
+    if not os.path.exists(B.LIB):
+        B.build()
+    lib = ctypes.CDLL(B.LIB)
+    lib.cgks_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    EINVAL = -1
+    base = I.acoustic_pulse_2d(8, seed=1)
+
+    def rc(prob, storage=0, **fix):
+        cfg = make_config(prob, storage)
+        for k, v in fix.items():
+            if k == 'bc':
+                for s in range(4):
+                    cfg.bc[s] = v[s]
+            else:
+                setattr(cfg, k, v)
+        h = ctypes.c_void_p()
+        r = lib.cgks_create(ctypes.addressof(cfg), None, ctypes.byref(h))
+        assert not h.value
+        return r
+
+    assert rc(base, nx=0) == EINVAL
+    assert rc(base, ny=0) == EINVAL
+    assert rc(base, dim=3) == EINVAL
+    assert rc(base, nx=65536, ny=65536) == EINVAL                 # beyond the index range
+    assert rc(base, gamma=1.0) == EINVAL
+    assert rc(base, x1=-1.0) == EINVAL
+    assert rc(base, cfl=0.0, fixed_dt=0.0) == EINVAL
+    assert rc(base, weno_eps=0.0) == EINVAL
+    assert rc(base, tau_eps=0.0) == EINVAL
+    assert rc(base, tau_C=-1.0) == EINVAL
+    assert rc(base, mu=-1e-3) == EINVAL
+    assert rc(base, mu=float('nan')) == EINVAL
+    assert rc(base, bc=(5, 5, 0, 0)) == EINVAL                    # unknown boundary kind
+    assert rc(base, bc=(0, 1, 0, 0)) == EINVAL                    # periodic on one side only
+    assert rc(base, storage=7) == EINVAL
+    assert rc(I.sine_wave_1d(8), storage=CGKS_FP32_STORAGE) == EINVAL   # FP32 storage is 2D only
+    walled = dataclasses.replace(base, bc=(I.WALL, I.WALL, I.NOSLIP, I.NOSLIP))
+    assert rc(walled, nx=1) == EINVAL                             # a wall needs 2 cells to mirror
+    assert rc(walled, ny=1) == EINVAL
+    inflow = dataclasses.replace(base, bc=(I.INFLOW, I.FREE, I.PERIODIC, I.PERIODIC),
+                                 inflow_prim=((-1.0, 0.0, 0.0, 1.0),) + ((1.0, 0.0, 0.0, 1.0),) * 3)
+    assert rc(inflow) == EINVAL                                   # non-physical inflow state

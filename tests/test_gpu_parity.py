@@ -150,6 +150,27 @@ def test_2d_single_step(name, mk):
     assert e.max() < TOL, e
 
 
+TINY = [(1, 1, 'periodic'), (1, 5, 'periodic'), (3, 2, 'periodic'), (2, 9, 'walls'), (2, 2, 'noslip'), (5, 3, 'inflow')]
+
+
+@pytest.mark.parametrize('nx,ny,kind', TINY, ids=['%dx%d-%s' % t for t in TINY])
+def test_2d_degenerate_tiny_grids(nx, ny, kind):
+    """Grids smaller than a tile and than the stencil (ghosts wrap onto or
+    mirror the same few cells): one step against the oracle."""
+    p = I.acoustic_pulse_2d(max(nx, ny), seed=3, amp=0.05, half_width=0.3, ny=max(nx, ny))
+    f = np.ascontiguousarray(p.fields[:, :ny, :nx])
+    f[1] += 0.2 * f[0]
+    f[3] += 0.02 * f[0]
+    bc = {'periodic': (I.PERIODIC,) * 4, 'walls': (I.WALL, I.WALL, I.PERIODIC, I.PERIODIC),
+          'noslip': (I.NOSLIP,) * 4, 'inflow': (I.INFLOW, I.FREE, I.WALL, I.FREE)}[kind]
+    q = I.Problem('tiny', 2, nx, ny, 0.0, nx * p.dx, 0.0, ny * p.dy, f, bc=bc,
+                  inflow_prim=((1.0, 0.3, 0.0, 0.7),) * 4, mu=0.01 if kind == 'noslip' else 0.0)
+    say('tiny', nx, ny, kind)
+    e, dt, dtg = single_step(q)
+    assert dtg == pytest.approx(dt, rel=1e-13)
+    assert e.max() < TOL, e
+
+
 @pytest.mark.parametrize('name,mk', CASES_2D[:3] + VISCOUS, ids=[c[0] for c in CASES_2D[:3] + VISCOUS])
 def test_2d_multi_step(name, mk):
     p = mk()
