@@ -126,6 +126,9 @@ def serving(nreq, steps_per_run=10):
     replayed in real time through the plain path (FIFO, one request at a time)
     and through the batch API (admit on arrival, advance all running requests
     steps_per_run steps per graph replay, read and release on completion).
+    (3) The batch's own capacity c (every request admitted at once), and a
+    second batch replay with the same draws at 0.7c, where the queue stays
+    short and the latency is the steady-state one.
     Latency = completion - arrival."""
     import numpy as np
     from multiprocessing import get_context
@@ -177,45 +180,56 @@ def serving(nreq, steps_per_run=10):
     span_plain = time.perf_counter() - t0
 
     # batch path, open loop
+    def batch_replay(arr):
+        b = Batch(48 << 30, max_slots=min(nreq, 1024))
+        lat = np.full(nreq, np.nan)
+        slot_of = {}
+        nxt = 0
+        done = 0
+        pending = []
+        t0 = time.perf_counter()
+        while done < nreq:
+            now = time.perf_counter() - t0
+            while nxt < nreq and arr[nxt] <= now:
+                pending.append(nxt)
+                nxt += 1
+            still = []
+            for k in pending:
+                try:
+                    slot_of[b.admit(reqs[k], max_steps=steps)] = k
+                except CgksError as e:
+                    if e.code != CGKS_EBUSY:
+                        raise
+                    still.append(k)
+            pending = still
+            if not slot_of:
+                if nxt < nreq:
+                    wait_until(t0 + arr[nxt])
+                continue
+            b.run(steps_per_run)
+            for s in list(slot_of):
+                st = b.poll(s)[0]
+                if st in (SLOT_DONE, SLOT_FAILED):
+                    if st == SLOT_FAILED:
+                        raise RuntimeError('request %d failed' % slot_of[s])
+                    b.read(s)
+                    b.release(s)
+                    k = slot_of.pop(s)
+                    lat[k] = time.perf_counter() - t0 - arr[k]
+                    done += 1
+        span = time.perf_counter() - t0
+        b.close()
+        return lat, span
+
     log('[serving] replay: batch path')
-    b = Batch(48 << 30, max_slots=min(nreq, 1024))
-    lat_batch = np.full(nreq, np.nan)
-    slot_of = {}
-    nxt = 0
-    done = 0
-    pending = []
-    t0 = time.perf_counter()
-    while done < nreq:
-        now = time.perf_counter() - t0
-        while nxt < nreq and arrivals[nxt] <= now:
-            pending.append(nxt)
-            nxt += 1
-        still = []
-        for k in pending:
-            try:
-                slot_of[b.admit(reqs[k], max_steps=steps)] = k
-            except CgksError as e:
-                if e.code != CGKS_EBUSY:
-                    raise
-                still.append(k)
-        pending = still
-        if not slot_of:
-            if nxt < nreq:
-                wait_until(t0 + arrivals[nxt])
-            continue
-        b.run(steps_per_run)
-        for s in list(slot_of):
-            st = b.poll(s)[0]
-            if st in (SLOT_DONE, SLOT_FAILED):
-                if st == SLOT_FAILED:
-                    raise RuntimeError('request %d failed' % slot_of[s])
-                b.read(s)
-                b.release(s)
-                k = slot_of.pop(s)
-                lat_batch[k] = time.perf_counter() - t0 - arrivals[k]
-                done += 1
-    span_batch = time.perf_counter() - t0
-    b.close()
+    lat_batch, span_batch = batch_replay(arrivals)
+    log('[serving] batch capacity (all requests at once)')
+    _, span_cap = batch_replay(np.zeros(nreq))
+    capacity = nreq / span_cap
+    rate_low = 0.7 * capacity
+    arrivals_low = arrivals * (rate / rate_low)
+    log('[serving] replay: batch path at %.2f /s (0.7 x capacity %.2f)' % (rate_low, capacity))
+    lat_low, span_low = batch_replay(arrivals_low)
 
     def pct(a, q):
         return float(np.percentile(a, q))
@@ -233,6 +247,9 @@ def serving(nreq, steps_per_run=10):
                    'steps_per_run': steps_per_run},
         'batched': {'solves_per_s': nreq / span_batch, 'p50_s': pct(lat_batch, 50), 'p99_s': pct(lat_batch, 99),
                     'span_s': span_batch},
+        'batched_capacity_solves_per_s': capacity,
+        'batched_at_70pct_capacity': {'arrival_rate_per_s': rate_low, 'solves_per_s': nreq / span_low,
+                                      'p50_s': pct(lat_low, 50), 'p99_s': pct(lat_low, 99), 'span_s': span_low},
         'plain': {'closed_loop_solves_per_s': closed, 'solves_per_s': nreq / span_plain,
                   'p50_s': pct(lat_plain, 50), 'p99_s': pct(lat_plain, 99), 'span_s': span_plain},
         'arrival_rate_per_s': rate,
