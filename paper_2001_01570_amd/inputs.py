@@ -381,6 +381,27 @@ def viscous_shock_vortex_2d(nx: int = 700, ny: int = 600, Ms: float = 1.2, Mv: f
                    meta=dict(Ms=Ms, Mv=Mv, Re=Re, downstream=(r2, U2, 0.0, p2), upstream=(1.0, U1, 0.0, p1)))
 
 
+def shock_reflection_2d(nx: int = 200, ny: int = 50, t_end: float = 50.0, cfl: float = 0.3) -> Problem:
+    """Regular shock reflection of Sec. 4.4 on [0,4]x[0,1]: a Mach 2.9 stream
+    (rho, U, V, p) = (1, 2.9, 0, 1/gamma) enters on the left, the state behind
+    an oblique shock that meets the bottom wall at 29 degrees enters on the top
+    (1.69997, 2.61934, -0.50632, 1.52819; Rankine-Hugoniot), slip wall at the
+    bottom, free flow on the right; the domain starts at the left state."""
+    left = (1.0, 2.9, 0.0, 1.0 / GAMMA)
+    top = (1.69997, 2.61934, -0.50632, 1.52819)
+
+    def prim(x, y, sx, sy):
+        one = np.ones_like(np.asarray(x, dtype=np.float64) + 0.0 * np.asarray(y))
+        return left[0] * one, left[1] * one, left[2] * one, left[3] * one
+
+    fields = _cell_fields_2d(prim, 0.0, 4.0, 0.0, 1.0, nx, ny)
+    inflow = np.zeros((4, 4))
+    inflow[0] = left
+    inflow[3] = top
+    return Problem('shock_reflection_2d', 2, nx, ny, 0.0, 4.0, 0.0, 1.0, fields, bc=(INFLOW, FREE, WALL, INFLOW),
+                   inflow_prim=inflow, cfl=cfl, t_end=t_end)
+
+
 def serving_request(k: int) -> Problem:
     """Request k of the serving workload: periodic [-1,1]^2, background
     (1,0,0,1/gamma), a Gaussian acoustic pulse (amplitude log-uniform in

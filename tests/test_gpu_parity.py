@@ -365,6 +365,56 @@ def test_viscous_shock_vortex_sound_pressure_range(row):
     assert s.counters()['guard_w0'] == 0 and s.counters()['guard_weno'] == 0
 
 
+def _oblique_shock(M, beta, g=1.4):
+    """textbook oblique-shock relations: density ratio, pressure ratio,
+    deflection angle and downstream Mach number for shock angle beta"""
+    Mn = M * math.sin(beta)
+    rr = (g + 1) * Mn * Mn / ((g - 1) * Mn * Mn + 2)
+    pr = 1 + 2 * g / (g + 1) * (Mn * Mn - 1)
+    theta = math.atan(2 / math.tan(beta) * (Mn * Mn - 1) / (M * M * (g + math.cos(2 * beta)) + 2))
+    Mn2 = math.sqrt(((g - 1) * Mn * Mn + 2) / (2 * g * Mn * Mn - (g - 1)))
+    return rr, pr, theta, Mn2 / math.sin(beta - theta)
+
+
+def test_regular_shock_reflection_steady_state():
+    """Sec. 4.4 regular shock reflection (Mach 2.9, 29 degrees, 200 x 50):
+    no guard fires; by t = 25 the field is steady except for a small unsteady
+    patch where the wall meets the free outflow (the paper's own residue
+    likewise stalls for this case); along y = 0.51 the plateaus match the
+    textbook oblique-shock states to 0.2 % and both shocks cross within half
+    a cell of their exact positions."""
+    from scipy.optimize import brentq
+    g = 1.4
+    b1 = math.radians(29.0)
+    r2, _, th, M2 = _oblique_shock(2.9, b1)
+    br = brentq(lambda b: _oblique_shock(M2, b)[2] - th, math.asin(1 / M2) + 1e-9, math.radians(60))
+    r3 = r2 * _oblique_shock(M2, br)[0]
+    p = I.shock_reflection_2d(200, 50)
+    s = solver(p)
+    s.advance_to(25.0)
+    r25 = s.state[0].copy()
+    s.advance_to(30.0)
+    r = s.state[0]
+    assert s.counters()['guard_w0'] == 0 and s.counters()['guard_weno'] == 0
+    assert np.abs(r - r25).mean() < 1e-4
+    y = 25.5 / 50
+    row = r[25]
+    x = (np.arange(200) + 0.5) * 0.02
+    assert abs(row[(x > 1.2) & (x < 2.6)].mean() / r2 - 1) < 2e-3
+    assert abs(row[(x > 3.2) & (x < 3.9)].mean() / r3 - 1) < 2e-3
+
+    def crossing(level, lo, hi):
+        xm = x[:-1]
+        k = np.nonzero((xm > lo) & (xm < hi) & (row[:-1] < level) & (row[1:] >= level))[0][0]
+        return x[k] + 0.02 * (level - row[k]) / (row[k + 1] - row[k])
+    x_inc = (1 - y) / math.tan(b1)
+    x_ref = 1 / math.tan(b1) + y / math.tan(br - th)
+    say('shock reflection: plateaus', row[(x > 1.2) & (x < 2.6)].mean(), r2, row[(x > 3.2) & (x < 3.9)].mean(), r3,
+        'crossings', crossing(0.5 * (1 + r2), 0.3, 1.5), x_inc, crossing(0.5 * (r2 + r3), 2.5, 3.5), x_ref)
+    assert abs(crossing(0.5 * (1 + r2), 0.3, 1.5) - x_inc) < 0.01
+    assert abs(crossing(0.5 * (r2 + r3), 2.5, 3.5) - x_ref) < 0.01
+
+
 def test_tam_webb_step_counts():
     p = I.tam_webb_2d(200)
     s = solver(p)
