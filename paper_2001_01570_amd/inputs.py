@@ -21,6 +21,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+
+from scipy.special import erf as _erf
 from typing import Callable, List, Optional, Sequence
 
 import numpy as np
@@ -400,6 +402,49 @@ def shock_reflection_2d(nx: int = 200, ny: int = 50, t_end: float = 50.0, cfl: f
     inflow[3] = top
     return Problem('shock_reflection_2d', 2, nx, ny, 0.0, 4.0, 0.0, 1.0, fields, bc=(INFLOW, FREE, WALL, INFLOW),
                    inflow_prim=inflow, cfl=cfl, t_end=t_end)
+
+
+def plane_pulse(n: int = 300, ny: int = 0, eps: float = 1e-4, b: float = 0.08, mu: float = 0.0,
+                cfl: float = 0.3) -> Problem:
+    """Plane pressure pulse of Sec. 4.6 on [-5,5] (x [0,1] in 2D, ny > 0):
+    rho = 1, U = V = 0, p = 1/gamma + eps exp(-ln2 (x/b)^2); free flow at
+    x = +-5 (the waves stay inside for t < 4), periodic in y.  exact(t) is the
+    linear inviscid solution: two acoustic halves moving at +-1 (the sound
+    speed) and an entropy wave at rest, -eps f(x) in density."""
+    g = GAMMA
+    a = math.sqrt(math.log(2.0)) / b
+    x0, x1 = -5.0, 5.0
+    dx = (x1 - x0) / n
+    xl = x0 + np.arange(n) * dx
+    xr = xl + dx
+
+    def favg(s):          # cell averages of f(x - s)
+        return math.sqrt(math.pi) / (2 * a) * (_erf(a * (xr - s)) - _erf(a * (xl - s))) / dx
+
+    def fpt(x):
+        return np.exp(-(a * x) ** 2)
+
+    def fields_at(t):
+        pa = 0.5 * eps * (favg(t) + favg(-t))                    # pressure (acoustic)
+        ra = pa - eps * favg(0.0)                                 # density: acoustic + entropy
+        dpa = 0.5 * eps * (fpt(xr - t) - fpt(xl - t) + fpt(xr + t) - fpt(xl + t)) / dx
+        dra = dpa - eps * (fpt(xr) - fpt(xl)) / dx
+        # momentum of the two acoustic halves: rho U = (p_right-moving - p_left-moving) / c
+        mu_ = 0.5 * eps * (favg(t) - favg(-t))
+        dmu = 0.5 * eps * (fpt(xr - t) - fpt(xl - t) - fpt(xr + t) + fpt(xl + t)) / dx
+        rows = [1.0 + ra, mu_, (1.0 / g + pa) / (g - 1.0), dra, dmu, dpa / (g - 1.0)]
+        if ny <= 0:
+            return np.array(rows)
+        out = np.zeros((12, ny, n))
+        for k, src in zip((0, 1, 3, 4, 5, 7), rows):
+            out[k] = src
+        return out
+
+    if ny <= 0:
+        return Problem('plane_pulse_1d', 1, n, 1, x0, x1, 0.0, 1.0, fields_at(0.0), bc=(FREE, FREE, PERIODIC, PERIODIC),
+                       cfl=cfl, mu=mu, exact=fields_at, meta=dict(eps=eps))
+    return Problem('plane_pulse_2d', 2, n, ny, x0, x1, 0.0, 1.0, fields_at(0.0), bc=(FREE, FREE, PERIODIC, PERIODIC),
+                   cfl=cfl, mu=mu, exact=fields_at, meta=dict(eps=eps))
 
 
 def serving_request(k: int) -> Problem:

@@ -415,6 +415,24 @@ def test_regular_shock_reflection_steady_state():
     assert abs(crossing(0.5 * (r2 + r3), 2.5, 3.5) - x_ref) < 0.01
 
 
+def test_plane_pressure_pulse_2d():
+    """Sec. 4.6 plane pressure pulse at the paper's 300 x 30: the 2D run
+    matches linear acoustics plus the entropy wave like the 1D oracle does
+    (errors relative to the amplitude below 5e-4 at t = 0.5, 2e-3 at t = 3),
+    and stays invariant in y."""
+    from tests.test_oracle_scheme import _pulse_errors
+    p = I.plane_pulse(300, ny=30)
+    s = solver(p)
+    for t, bar in ((0.5, 5e-4), (3.0, 2e-3)):
+        s.advance_to(t)
+        st = s.state
+        ex = p.exact(t)
+        assert np.abs(st - st[:, :1, :]).max() < 1e-15
+        e = _pulse_errors(st[[0, 1, 3], 0], ex[[0, 1, 3], 0], p.meta['eps'])
+        say('plane pulse t', t, 'errors / eps', e)
+        assert e.max() < bar, (t, e)
+
+
 def test_tam_webb_step_counts():
     p = I.tam_webb_2d(200)
     s = solver(p)

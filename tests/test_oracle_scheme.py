@@ -286,6 +286,27 @@ def test_noslip_channel_decays_at_the_navier_stokes_rate():
     assert abs(slip) > 100 * e2
 
 
+def _pulse_errors(st, ex, eps, g=1.4):
+    """max |error| / eps of density, momentum and pressure"""
+    pr = (g - 1) * (st[2] - 0.5 * st[1] ** 2 / st[0])
+    pe = (g - 1) * (ex[2] - 0.5 * ex[1] ** 2 / ex[0])
+    return np.array([np.abs(st[0] - ex[0]).max(), np.abs(st[1] - ex[1]).max(), np.abs(pr - pe).max()]) / eps
+
+
+def test_plane_pressure_pulse_is_linear_acoustics_plus_entropy():
+    """Sec. 4.6 plane pressure pulse (inviscid, 300 cells on [-5,5], about 2.4
+    cells per half-width): the pulse splits into two acoustic halves at the
+    sound speed and an entropy wave at rest (closed form of linear
+    acoustics); errors relative to the amplitude below 5e-4 at t = 0.5 and
+    2e-3 at t = 3."""
+    p = I.plane_pulse(300)
+    o = O.Oracle(p)
+    for t, bar in ((0.5, 5e-4), (3.0, 2e-3)):
+        o.advance_to(t)
+        e = _pulse_errors(o.state, p.exact(t), p.meta['eps'])
+        assert e.max() < bar, (t, e)
+
+
 def test_shock_entropy_config2_positive_and_bounded():
     p = I.shock_entropy_1d(400, t_end=1.8)
     o = O.Oracle(p)
