@@ -433,6 +433,25 @@ def test_plane_pressure_pulse_2d():
         assert e.max() < bar, (t, e)
 
 
+@pytest.mark.parametrize('b,err_bar,peak_bar', [(2.0, 1e-2, 2e-3), (1.5, 3e-2, 1.5e-2)])
+def test_gaussian_advection_over_400_cells(b, err_bar, peak_bar):
+    """Sec. 4.2: a density Gaussian of half-width b cells (b = 2 and 1.5, unit
+    mesh, CFL 0.3) advected 400 cells: against the exact translated profile
+    (the oracle's own errors on this run are 6.2e-3 and 2.0e-2; peaks 0.472
+    and 0.448 against 0.4726 and 0.4531)."""
+    p = I.gaussian_advection_1d(1800, -800.0, 1000.0, b, 400.0)
+    s = solver(p)
+    n = s.advance_to(400.0)
+    st = s.state
+    ex = p.exact(400.0)
+    err = np.abs(st[0] - ex[0]).max()
+    peak = st[0].max() - 1.0
+    say('gaussian b', b, 'steps', n, 'max err', err, 'peak', peak, ex[0].max() - 1.0)
+    assert 2900 <= n <= 2920
+    assert err < err_bar
+    assert abs(peak / (ex[0].max() - 1.0) - 1.0) < peak_bar
+
+
 def test_tam_webb_step_counts():
     p = I.tam_webb_2d(200)
     s = solver(p)
