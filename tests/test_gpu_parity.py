@@ -96,6 +96,23 @@ def test_1d_viscous_single_step_and_run():
     assert err.max() < TOL, err
 
 
+def test_1d_acoustic_wave_small_perturbation_full_run():
+    """Sec. 4.3: eps = 1e-5 on p = 101325, 16 cells, 10 domain lengths (~830
+    steps): the GPU's density perturbation equals the oracle's to 1e-7 of the
+    amplitude (rounding of the O(1) background, accumulated), and both are
+    within 4e-3 of the amplitude from the linear solution."""
+    p = I.acoustic_wave_1d(16)
+    s, o = solver(p), O.Oracle(p)
+    ns, no = s.advance_to(0.01), o.advance_to(0.01)
+    assert ns == no
+    amp = p.meta['eps'] * p.meta['rho_inf']
+    d = np.abs(s.state[0] - o.state[0]).max() / amp
+    e = np.abs(s.state[0] - p.exact(0.01)[0]).max() / amp
+    say('acoustic wave: GPU - oracle', d, 'GPU - linear solution', e)
+    assert d < 1e-7
+    assert e < 4e-3
+
+
 def test_1d_shock_tube_free_boundaries():
     p = I.shock_tube_1d(100)
     s, o = solver(p), O.Oracle(p)
