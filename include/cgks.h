@@ -162,8 +162,9 @@ int cgks_batch_create(size_t hbm_budget_bytes, int max_slots, void *hip_stream, 
  * state is copied, host or device pointer) that runs until t_end (> 0) or for
  * max_steps (> 0) steps, whichever comes first (one of them must be given).
  * Returns its slot.  CGKS_EBUSY: no free slot or no room in the arena;
- * CGKS_ENONPHYS: non-physical initial state; CGKS_EINVAL: bad configuration or
- * dim != 2.  A device pointer must be ready (its producer synchronized). */
+ * CGKS_ENONPHYS: non-physical initial state; CGKS_EINVAL: bad configuration,
+ * dim != 2 or FP32 storage (the batch runs FP64 storage).  A device pointer
+ * must be ready (its producer synchronized). */
 int cgks_batch_admit(cgks_batch *b, const cgks_config *cfg, const double *fields, int on_device,
                      double t_end, long max_steps, int *slot);
 

@@ -922,10 +922,20 @@ extern "C" void cgks_destroy(cgks_ctx* c) {
 extern "C" int cgks_set_profiling(cgks_ctx* c, int on) {
   if (!c) return CGKS_EINVAL;
   if (on && !c->events) {
-    c->events = new (std::nothrow) std::vector<hipEvent_t>(2 * kEventPairs);
-    c->ev_kind = new (std::nothrow) std::vector<int>(kEventPairs);
-    if (!c->events || !c->ev_kind) return CGKS_ENOMEM;
-    for (auto& e : *c->events) HIPCHK(hipEventCreate(&e));
+    auto* ev = new (std::nothrow) std::vector<hipEvent_t>(2 * kEventPairs, nullptr);
+    auto* kind = new (std::nothrow) std::vector<int>(kEventPairs);
+    bool ok = ev && kind;
+    for (size_t k = 0; ok && k < ev->size(); ++k) ok = hipEventCreate(&(*ev)[k]) == hipSuccess;
+    if (!ok) {                       // leave the context without profiling state
+      if (ev)
+        for (hipEvent_t e : *ev)
+          if (e) (void)hipEventDestroy(e);
+      delete ev;
+      delete kind;
+      return CGKS_ENOMEM;
+    }
+    c->events = ev;
+    c->ev_kind = kind;
   }
   if (on) {
     HIPCHK(hipStreamSynchronize(c->stream));
