@@ -2,6 +2,7 @@
 accumulation stay FP64.  The round trip rounds only the gradients; one step
 and many steps stay within stated bounds of the FP64 path (itself pinned to
 the oracle at 1e-12), measured relative to the perturbation amplitude."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -32,9 +33,19 @@ def test_round_trip_rounds_only_the_gradients():
     assert np.array_equal(g[4:], p.fields[4:].astype(np.float32).astype(np.float64))
 
 
+def _viscous_box():
+    p = I.acoustic_pulse_2d(40, seed=4, amp=0.05, half_width=0.3, ny=24)
+    p.fields[1] += 0.2 * p.fields[0]
+    p.fields[3] += 0.02 * p.fields[0]
+    p.fields[5] += 0.2 * p.fields[4]
+    p.fields[9] += 0.2 * p.fields[8]
+    return dataclasses.replace(p, mu=0.01, bc=(I.NOSLIP,) * 4)
+
+
 @pytest.mark.parametrize('mk,amp', [(lambda: I.acoustic_pulse_2d(64, seed=3, amp=1e-3, half_width=0.2), 1e-3),
-                                    (lambda: I.shock_vortex_2d(64, 32, Rc=0.12), 0.3)],
-                         ids=['pulse', 'shock_vortex'])
+                                    (lambda: I.shock_vortex_2d(64, 32, Rc=0.12), 0.3),
+                                    (_viscous_box, 0.125)],   # its largest perturbation (energy)
+                         ids=['pulse', 'shock_vortex', 'viscous_noslip'])
 def test_fp32_storage_error_against_fp64(mk, amp):
     from paper_2001_01570_amd.cgks import Solver, CGKS_FP32_STORAGE
     p = mk()
