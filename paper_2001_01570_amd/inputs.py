@@ -510,10 +510,12 @@ def serving_request(k: int) -> Problem:
                    meta=dict(k=k, amp=amp, Mv=Mv))
 
 
-def tam_webb_2d(n: int = 200, t_end: float = 28.45) -> Problem:
+def tam_webb_2d(n: int = 200, t_end: float = 28.45, L: float = 100.0, cfl: float = 0.3) -> Problem:
     """Sound, entropy and vorticity pulses on a uniform flow (Sec. 4.7):
-    [-100,100]^2, rho_inf = 1, U_inf = 0.5, Mach 0.5 (c_inf = 1, p_inf = 1/gamma),
-    CFL 0.3; periodic boundaries (no wave reaches them before t = 56.9)."""
+    [-L,L]^2 (the paper's L = 100), rho_inf = 1, U_inf = 0.5, Mach 0.5
+    (c_inf = 1, p_inf = 1/gamma), CFL 0.3; periodic boundaries: at L = 100 no
+    wave reaches them before t = 56.9, at L = 250 none reaches them, nor
+    any periodic image the window [-100,100]^2, before t = 100."""
     e1, e2, e3 = 1e-2, 1e-3, 4e-4
     a1 = math.log(2.0) / 9.0
     a2 = a3 = math.log(2.0) / 25.0
@@ -528,8 +530,8 @@ def tam_webb_2d(n: int = 200, t_end: float = 28.45) -> Problem:
         V = -e3 * np.exp(-a3 * r2) * (x - x2c)
         return rho, U, V, p
 
-    fields = _cell_fields_2d(prim, -100.0, 100.0, -100.0, 100.0, n, n)
-    return Problem('tam_webb_2d', 2, n, n, -100.0, 100.0, -100.0, 100.0, fields, cfl=0.3, t_end=t_end)
+    fields = _cell_fields_2d(prim, -L, L, -L, L, n, n)
+    return Problem('tam_webb_2d', 2, n, n, -L, L, -L, L, fields, cfl=cfl, t_end=t_end)
 
 
 def diagonal_wave_2d(n: int, eps: float = 0.2, t_end: float = 0.5, cfl: float = 0.3,
