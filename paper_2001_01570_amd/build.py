@@ -57,6 +57,21 @@ def count_operations(verbose: bool = False) -> str:
     return FLOPS_JSON
 
 
+RUN_SRC = os.path.join(PKG, 'csrc', 'cgks_run.c')
+RUN_EXE = os.path.join(PKG, 'cgks_run')
+
+
+def build_driver(verbose: bool = False) -> str:
+    """Compile cgks_run, the plain-C driver of the C ABI, against libcgks.so."""
+    cmd = ['gcc', '-std=c11', '-O2', '-Wall', '-I', os.path.join(ROOT, 'include'), RUN_SRC, '-L', PKG, '-lcgks',
+           '-Wl,-rpath,$ORIGIN', '-Wl,-rpath,/opt/rocm/lib', '-o', RUN_EXE + '.tmp']
+    if verbose:
+        print(' '.join(cmd), file=sys.stderr, flush=True)
+    subprocess.check_call(cmd)
+    os.replace(RUN_EXE + '.tmp', RUN_EXE)
+    return RUN_EXE
+
+
 def build(verbose: bool = False, extra=(), out: str = None) -> str:
     """Compile libcgks.so (out: alternative path, used for tuning variants)."""
     target = out or LIB
@@ -68,6 +83,7 @@ def build(verbose: bool = False, extra=(), out: str = None) -> str:
     os.replace(target + '.tmp', target)
     if out is None:
         count_operations(verbose)
+        build_driver(verbose)
     return target
 
 
