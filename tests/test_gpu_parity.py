@@ -343,6 +343,37 @@ def test_config3_full_size_ten_steps_sampled():
     assert worst < TOL, worst
 
 
+def test_largest_accepted_grid_single_step_sampled():
+    """11584^2 = 134.2 M cells, just under the library's limit of 2^31/16
+    cells (32-bit indexing of 16 face planes; ~86 GB of device buffers): one
+    step against the oracle on sampled windows at the corners, edges and
+    centre.  The state is analytic point data of a smooth periodic wave on a
+    moving background (the parity check does not need exact cell averages)."""
+    n = 11584
+    g = 1.4
+    x = (np.arange(n) + 0.5) / n
+    sx, cx = np.sin(2 * np.pi * x), np.cos(2 * np.pi * x)
+    f = np.empty((12, n, n))
+    amp, U, V = 1e-2, 0.1, -0.05
+    f[0] = 1.0 + amp * np.outer(sx, sx)             # rho(y, x)
+    f[1] = U * f[0]
+    f[2] = V * f[0]
+    f[3] = (1.0 / g) / (g - 1) + 0.5 * (U * U + V * V) * f[0]
+    k = 2 * np.pi * amp
+    f[4] = k * np.outer(sx, cx)                     # d/dx
+    f[8] = k * np.outer(cx, sx)                     # d/dy
+    for base, d in ((4, 4), (8, 8)):
+        f[base + 1] = U * f[d]
+        f[base + 2] = V * f[d]
+        f[base + 3] = 0.5 * (U * U + V * V) * f[d]
+    p = I.Problem('largest', 2, n, n, 0.0, 1.0, 0.0, 1.0, f, cfl=0.3)
+    wins = [(0, 0), (n - 8, n - 8), (n // 2, n // 2), (0, n - 8), (n - 8, 0), (3001, 7777)]
+    say('largest grid', n, 'x', n, 'windows', wins)
+    worst, s = _sampled(p, wins)
+    say('largest grid worst field error', worst)
+    del s, f
+
+
 def test_config4_full_size_single_step_sampled():
     p = I.shock_vortex_2d(2048, 1024)
     wins = [(0, 0), (508, 500), (254, 508), (2040, 1016), (1024, 0), (0, 1016), (250, 470)]
