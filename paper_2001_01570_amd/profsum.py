@@ -28,7 +28,10 @@ SHORT = [
     (r'k_faces2<1, 2\b', 'yfaces2'), (r'k_update2<1\b', 'update1'), (r'k_update2<2\b', 'update2'),
     (r'k_faces1<1\b', 'faces1'), (r'k_faces1<2\b', 'faces2'), (r'k_update1<1\b', 'update1_1d'),
     (r'k_update1<2\b', 'update2_1d'), (r'k_begin\b', 'begin'), (r'k_end\b', 'end'), (r'k_scan<4\b', 'scan'),
-    (r'k_scan<3\b', 'scan_1d'),
+    (r'k_scan<3\b', 'scan_1d'), (r'kb_faces<0, 1\b', 'b_xfaces1'), (r'kb_faces<1, 1\b', 'b_yfaces1'),
+    (r'kb_faces<0, 2\b', 'b_xfaces2'), (r'kb_faces<1, 2\b', 'b_yfaces2'), (r'kb_update<1\b', 'b_update1'),
+    (r'kb_update<2\b', 'b_update2'), (r'kb_begin\b', 'b_begin'), (r'kb_end\b', 'b_end'),
+    (r'k_to_storage32\b', 'to_fp32'), (r'k_from_storage32\b', 'from_fp32'),
 ]
 COPY_KERNEL = '__amd_rocclr_copyBuffer'
 
