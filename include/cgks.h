@@ -106,7 +106,11 @@ int cgks_advance_to(cgks_ctx *ctx, double t_end, long max_steps, long *steps_tak
 
 /* Exactly n steps of the rule (no end time); used to time fixed step counts.
  * On a capturable stream (not the legacy null stream) and with profiling
- * off, runs of 25 steps replay one captured HIP graph. */
+ * off, runs of 25 steps replay one captured HIP graph.
+ * 1D grids of at most 255 cells (with profiling off) run whole steps in one
+ * single-block launch instead, in cgks_step, cgks_step_dt, cgks_advance_to
+ * and cgks_run_steps alike: the same arithmetic, with results that agree with
+ * the separate launches to rounding. */
 int cgks_run_steps(cgks_ctx *ctx, long n);
 
 /* Copy the current state out (host or device pointer); t and step may be NULL. */
@@ -121,7 +125,8 @@ int cgks_last_bad_cell(const cgks_ctx *ctx, long *cell);
  * events in the stream).  cgks_kernel_times fills ms[k] (accumulated device
  * milliseconds) and calls[k] and returns the number of kinds, or an error.
  * Setting a nonzero mask clears the accumulators.  While profiling is on,
- * cgks_run_steps launches step by step instead of replaying its graph. */
+ * cgks_run_steps launches step by step instead of replaying its graph,
+ * and small 1D grids use the separate kernels, so that each can be timed. */
 int cgks_set_profiling(cgks_ctx *ctx, int mask);
 int cgks_kernel_times(cgks_ctx *ctx, double *ms, long *calls, int n);
 int cgks_counters(cgks_ctx *ctx, cgks_counters_t *out);

@@ -555,13 +555,13 @@ __global__ __launch_bounds__(256) void k_from_storage32(const double* src, doubl
 
 // ---------------------------------------------------------------- 1D
 
+// face f (0..nx) of one stage
 template <int STAGE>
-__global__ __launch_bounds__(256) void k_faces1(Geom G, Bufs B) {
+__device__ __forceinline__ void faces1_body(const Geom& G, const Bufs& B, int f) {
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
   const double dt = sc->dt;
   const double* S = STAGE == 1 ? B.S[sc->cur] : B.Ws;
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f > G.nx) return;
   const double h = G.dx;
   double Wc[4][3], Dc[4][3];
@@ -614,11 +614,16 @@ __global__ __launch_bounds__(256) void k_faces1(Geom G, Bufs B) {
 }
 
 template <int STAGE>
-__global__ __launch_bounds__(256) void k_update1(Geom G, Bufs B) {
+__global__ __launch_bounds__(256) void k_faces1(Geom G, Bufs B) {
+  faces1_body<STAGE>(G, B, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// cell i (0..nx-1) of one stage; returns the cell's CFL rate after stage 2 (else 0)
+template <int STAGE>
+__device__ __forceinline__ double update1_body(const Geom& G, const Bufs& B, int i) {
   Scalars* sc = B.sc;
-  if (!sc->active || sc->status != 0) return;
+  if (!sc->active || sc->status != 0) return 0.0;
   const double dt = sc->dt;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const size_t N = (size_t)G.nx;
   const size_t plane = N + 1;
   double lam = 0.0;
@@ -656,7 +661,50 @@ __global__ __launch_bounds__(256) void k_update1(Geom G, Bufs B) {
       else lam = cell_lambda<3>(Wn, G);
     }
   }
+  return lam;
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_update1(Geom G, Bufs B) {
+  // a step that does not run leaves the CFL partials of the last one that did
+  if (!B.sc->active || B.sc->status != 0) return;
+  const double lam = update1_body<STAGE>(G, B, blockIdx.x * blockDim.x + threadIdx.x);
   if (STAGE == 2) reduce_lambda(B.lam_part, blockIdx.x, lam);
+}
+
+// Small 1D grids: nsteps whole steps in one launch of one block.  The phases
+// of a step run in the order of the separate kernels (begin, faces 1,
+// update 1, faces 2, update 2, end) with block barriers in place of the
+// kernel boundaries, on the same device functions (the compiler may contract
+// a few operations differently here, so the results agree with the separate
+// launches to rounding, not always bitwise).  Every barrier is reached by every thread: the
+// bodies return early on their own, never around a barrier.  The CFL partials
+// are written per 256 cells, as by the update grid.
+__global__ __launch_bounds__(256) void k_steps1(Geom G, Bufs B, int nsteps, int nparts) {
+  __shared__ double red[4];
+  Scalars* sc = B.sc;
+  for (int s = 0; s < nsteps; ++s) {
+    begin_body(sc, B.lam_part, nparts);
+    __syncthreads();
+    for (int f = threadIdx.x; f <= G.nx; f += 256) faces1_body<1>(G, B, f);
+    __syncthreads();
+    for (int i = threadIdx.x; i < G.nx; i += 256) update1_body<1>(G, B, i);
+    __syncthreads();
+    for (int f = threadIdx.x; f <= G.nx; f += 256) faces1_body<2>(G, B, f);
+    __syncthreads();
+    for (int b = 0; b < nparts; ++b) {
+      double lam = update1_body<2>(G, B, b * 256 + (int)threadIdx.x);
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) lam = fmax(lam, __shfl_xor(lam, o, 64));
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lam;
+      __syncthreads();
+      if (threadIdx.x == 0 && sc->active && sc->status == 0)   // as k_update1: only a step that runs
+        B.lam_part[b] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      __syncthreads();
+    }
+    end_body(sc);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- batch
@@ -1071,13 +1119,41 @@ static void launch_step(cgks_ctx* c) {
   k_end<<<1, 64, 0, s>>>(c->B.sc);
 }
 
+// 1D grids of at most this many cells run whole steps in one single-block
+// launch (k_steps1) unless the kernels are being timed one by one: with one
+// face per thread (nx + 1 <= 256) a step takes 17 instead of 25 us at 100
+// cells; with two or more faces per thread the serial point evaluations cost
+// more than the separate launches (34 against 29 us at 400 cells).
+#ifndef CGKS_FUSED1D_MAX
+#define CGKS_FUSED1D_MAX 255
+#endif
+constexpr long kStepsPerLaunch1D = 4096;   // bound on one fused launch's duration
+
+static bool fused_1d(const cgks_ctx* c) {
+  return c->G.dim == 1 && c->G.nx <= CGKS_FUSED1D_MAX && !c->profiling;
+}
+
+// n steps queued on the context's stream
+static void launch_steps(cgks_ctx* c, long n) {
+  if (fused_1d(c)) {
+    const int nparts = (int)update_grid(c->G).x;
+    while (n > 0) {
+      const long k = n < kStepsPerLaunch1D ? n : kStepsPerLaunch1D;
+      k_steps1<<<1, 256, 0, c->stream>>>(c->G, c->B, (int)k, nparts);
+      n -= k;
+    }
+    return;
+  }
+  for (long k = 0; k < n; ++k) launch_step(c);
+}
+
 extern "C" int cgks_step_dt(cgks_ctx* c, double dt, double* dt_used) {
   if (!c) return CGKS_EINVAL;
   if (!c->has_state) return CGKS_ESTATE;
   int rc = push_params(c, INFINITY, dt > 0.0 ? dt : 0.0);
   if (rc) return rc;
   const long long before = c->host_sc->step;
-  launch_step(c);
+  launch_steps(c, 1);
   HIPCHK(hipGetLastError());
   rc = pull_scalars(c);
   if (rc) return rc;
@@ -1119,9 +1195,9 @@ extern "C" int cgks_run_steps(cgks_ctx* c, long n) {
   int rc = push_params(c, INFINITY, 0.0);
   if (rc) return rc;
   long k = 0;
-  if (n >= GRAPH_STEPS && !c->profiling && ensure_graph(c))
+  if (n >= GRAPH_STEPS && !c->profiling && !fused_1d(c) && ensure_graph(c))
     for (; k + GRAPH_STEPS <= n; k += GRAPH_STEPS) HIPCHK(hipGraphLaunch(c->exec, c->stream));
-  for (; k < n; ++k) launch_step(c);
+  launch_steps(c, n - k);
   HIPCHK(hipGetLastError());
   rc = pull_scalars(c);
   if (rc) return rc;
@@ -1140,7 +1216,7 @@ extern "C" int cgks_advance_to(cgks_ctx* c, double t_end, long max_steps, long* 
     long n = chunk;
     if (max_steps > 0) n = n < max_steps - launched ? n : max_steps - launched;
     if (n <= 0) break;
-    for (long k = 0; k < n; ++k) launch_step(c);
+    launch_steps(c, n);
     launched += n;
     HIPCHK(hipGetLastError());
     rc = pull_scalars(c);
