@@ -42,8 +42,12 @@ using Tile8x16 = Tile<8, 16>;
 using Tile4x32 = Tile<4, 32>;
 using Tile2x64 = Tile<2, 64>;
 constexpr int kTileShapes = 3;
-constexpr int TF = Tile8x16::F, TT = Tile8x16::T;   // the batched kernels' shape
-constexpr int NSEG = Tile8x16::NSEG;
+// the batched face kernels' tiles per direction: the shapes the tuner picks
+// for most grids from 64^2 to 2048^2 (x faces 4x32, y faces 2x64)
+template <int DIR> struct BatchTile { using T = Tile4x32; };
+template <> struct BatchTile<1> { using T = Tile2x64; };
+using BTX = BatchTile<0>::T;
+using BTY = BatchTile<1>::T;
 constexpr int NQ = 24;          // per segment: 5 quantities x 4 components + 4 reference values
 constexpr int FACE_THREADS = 256;   // one thread per Gauss point of the tile's face segments
 // waves per SIMD the face kernels are compiled for (register budget 512 / waves:
@@ -766,7 +770,8 @@ __global__ void kb_end(const SlotDev* slots, const BatchTable* tab) {
 template <int DIR, int STAGE>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces(const SlotDev* slots,
                                                                             const BatchTable* tab) {
-  __shared__ double lds[NQ][NSEG];
+  using TL = typename BatchTile<DIR>::T;
+  __shared__ double lds[NQ][TL::NSEG];
   const int n = tab->n;
   const int* pre = DIR == 0 ? tab->pre_x : tab->pre_y;
   const int item = xcd_item(pre[n]);
@@ -775,7 +780,7 @@ __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces(cons
   const SlotDev& sd = slots[tab->slot[k]];
   const int local = item - pre[k];
   const int w = DIR == 0 ? sd.gxw : sd.gyw;
-  faces2_body<DIR, STAGE>(sd.G, sd.B, local % w, local / w, lds);
+  faces2_body<DIR, STAGE, double, TL>(sd.G, sd.B, local % w, local / w, lds);
 }
 
 template <int STAGE>
@@ -1451,16 +1456,16 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   sd.B.FY = (double*)p; p += fy;
   sd.B.lam_part = (double*)p;
   sd.B.sc = b->d_sc + k;
-  sd.gxw = (G.nx + 1 + TF - 1) / TF;
-  sd.gyw = (G.nx + TT - 1) / TT;
+  sd.gxw = (G.nx + 1 + BTX::F - 1) / BTX::F;
+  sd.gyw = (G.nx + BTY::T - 1) / BTY::T;
   sd.guw = (int)gu.x;
   sd.nparts = (int)(gu.x * gu.y);
   in.used = 1;
   in.off = off;
   in.bytes = bytes;
   in.N = N;
-  in.nbx = sd.gxw * ((G.ny + TT - 1) / TT);
-  in.nby = sd.gyw * ((G.ny + 1 + TF - 1) / TF);
+  in.nbx = sd.gxw * ((G.ny + BTX::T - 1) / BTX::T);
+  in.nby = sd.gyw * ((G.ny + 1 + BTY::F - 1) / BTY::F);
   in.nbu = sd.nparts;
 
   Scalars& h = b->h_sc[k];
