@@ -31,7 +31,7 @@ SHORT = [
     (r'k_scan<3\b', 'scan_1d'), (r'kb_faces<0, 1\b', 'b_xfaces1'), (r'kb_faces<1, 1\b', 'b_yfaces1'),
     (r'kb_faces<0, 2\b', 'b_xfaces2'), (r'kb_faces<1, 2\b', 'b_yfaces2'), (r'kb_update<1\b', 'b_update1'),
     (r'kb_update<2\b', 'b_update2'), (r'kb_begin\b', 'b_begin'), (r'kb_end\b', 'b_end'),
-    (r'k_to_storage32\b', 'to_fp32'), (r'k_from_storage32\b', 'from_fp32'),
+    (r'k_to_storage32\b', 'to_fp32'), (r'k_from_storage32\b', 'from_fp32'), (r'k_steps1\b', 'steps_1d'),
 ]
 COPY_KERNEL = '__amd_rocclr_copyBuffer'
 
