@@ -179,10 +179,12 @@ def test_2d_diagonal_wave_order():
 
 def test_2d_spatial_order_with_dt_proportional_to_dx2():
     """The translated isentropic vortex with dt = 0.02 dx^2, so that the
-    fourth-order time error is negligible: the 2D step converges in space at
-    order about 8 (L1 9.9e-7 at n = 48; order 7.8 from n = 32), like the 1D
-    Table 1, although with a CFL-proportional step the 2D orders are those of
-    the time integration."""
+    fourth-order time error is negligible: on these coarse meshes the 2D step
+    converges in space at order about 8 (L1 9.9e-7 at n = 48; order 7.8 from
+    n = 32), like the 1D Table 1 (with a CFL-proportional step the 2D orders
+    are those of the time integration).  The order is pre-asymptotic: the
+    two-point quadrature along the faces and the quartic tangential
+    reconstruction take it towards 4 on finer meshes (n >= 96)."""
     errs = []
     for n in (32, 48):
         p = dataclasses.replace(I.vortex_translation_2d(n, t_end=0.5), fixed_dt=0.02 * (10.0 / n) ** 2)
