@@ -382,6 +382,36 @@ def test_config4_full_size_single_step_sampled():
     say('config4 worst field error', worst)
 
 
+def test_config4_runs_to_its_end_time_with_a_small_viscosity():
+    """The 2048x1024 Mach 1.1 shock-vortex case to its end time t = 0.8 with
+    mu = 1e-5 (a cell Reynolds number of about 130): no guard fires, the
+    density stays within the states of the interaction, and the stationary
+    shock stays at x = 0.5: the first density crossing of the rows lies within
+    a cell of it in the median and within 8 cells on every row (at t = 0.8 the
+    shock still carries the ripple the vortex left on it, -5.5 to +2.5 cells).  Inviscid, the run stops near
+    t = 0.37 on the growing grid-scale mode of the 2D step, which grid-scale
+    dissipation of this size controls."""
+    p = dataclasses.replace(I.shock_vortex_2d(), mu=1e-5)
+    s = solver(p)
+    n = s.advance_to(0.8)
+    g, t, _ = s.get_state()
+    c = s.counters()
+    say('C4 viscous to t = 0.8:', n, 'steps', c)
+    assert t == 0.8 and 7000 < n < 8000
+    assert c['guard_w0'] == 0 and c['guard_weno'] == 0
+    rho = g[0]
+    assert 0.95 < rho.min() and rho.max() < 1.3
+    dx = (p.x1 - p.x0) / p.nx
+    x = p.x0 + (np.arange(p.nx) + 0.5) * dx
+    mid = 0.5 * (1.0 + 1.169082)          # between the upstream and the Rankine-Hugoniot densities
+    off = []
+    for j in range(0, p.ny, 32):
+        k = np.nonzero((rho[j, :-1] < mid) & (rho[j, 1:] >= mid))[0]
+        assert len(k), j
+        off.append((x[k[0]] - 0.5) / dx)
+    assert abs(np.median(off)) <= 1.0 and np.abs(off).max() <= 8.0, off
+
+
 def test_viscous_shock_vortex_full_size_single_step_sampled():
     p = I.viscous_shock_vortex_2d()
     # shock at x = 0 (column 500), vortex at (2, 0) (column 550, row 300)
