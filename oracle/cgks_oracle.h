@@ -34,6 +34,8 @@ typedef struct {
   double weno_eps, tau_eps, tau_C;
   double fixed_dt;           /* 0 -> CFL rule, >0 -> fixed step */
   double mu;                 /* dynamic viscosity: 0 -> Euler, > 0 -> Navier-Stokes */
+  int gauss_points;          /* 2D: Gauss-Legendre points per face segment, 2 (0 means 2;
+                                quartic through 5 segment averages) or 4 (sextic through 7) */
 } orc_config;
 
 typedef struct orc_ctx orc_ctx;
@@ -92,6 +94,9 @@ void orc_flux_integral(int dim, double gamma, double tau, double tau_ce, double 
 /* Tangential quartic through 5 segment averages s[0..4] (segments -2..2):
  * value, first and second derivative (unit width) at eta. */
 void orc_quartic(const double *s, double eta, double *out3);
+/* The sextic through 7 unit-cell averages s[0..6] (offsets -3..3), at eta:
+ * (value, d/deta, d2/deta2). */
+void orc_sextic(const double *s, double eta, double *out3);
 
 #ifdef __cplusplus
 }

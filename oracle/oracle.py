@@ -35,7 +35,7 @@ class _Cfg(C.Structure):
                 ('gamma', C.c_double), ('cfl', C.c_double),
                 ('bc', C.c_int * 4), ('inflow_prim', (C.c_double * 4) * 4),
                 ('weno_eps', C.c_double), ('tau_eps', C.c_double), ('tau_C', C.c_double),
-                ('fixed_dt', C.c_double), ('mu', C.c_double)]
+                ('fixed_dt', C.c_double), ('mu', C.c_double), ('gauss_points', C.c_int)]
 
 
 class _Counters(C.Structure):
@@ -79,6 +79,7 @@ def lib():
         L.orc_gks_point.argtypes = [C.c_int] + [C.c_double] * 5 + [D] * 8 + [D] * 7
         L.orc_flux_integral.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [D] * 6
         L.orc_quartic.argtypes = [D, C.c_double, D]
+        L.orc_sextic.argtypes = [D, C.c_double, D]
         _lib = L
     return _lib
 
@@ -110,6 +111,7 @@ class Oracle:
             setattr(cfg, k, int(d[k]))
         for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt', 'mu'):
             setattr(cfg, k, float(d[k]))
+        cfg.gauss_points = int(d.get('gauss_points', 2))
         for s in range(4):
             cfg.bc[s] = int(d['bc'][s])
             for q in range(4):
@@ -239,4 +241,10 @@ def flux_integral(dim, gamma, tau, delta, W0, W0n, Wl, Wr, W0t=None, tau_ce=0.0)
 def quartic(s, eta):
     out = np.empty(3)
     lib().orc_quartic(_p(_vec(s, 5)), float(eta), _p(out))
+    return out
+
+
+def sextic(s, eta):
+    out = np.empty(3)
+    lib().orc_sextic(_p(_vec(s, 7)), float(eta), _p(out))
     return out

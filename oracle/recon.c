@@ -56,6 +56,7 @@ static const stencil_t STENCIL[7] = {
 };
 static double STENCIL_INV[7][25];
 static double QUARTIC_INV[25];
+static double SEXTIC_INV[49];
 static int recon_ready = 0;
 
 static double ipow(double x, int p) { double r = 1.0; for (int i = 0; i < p; ++i) r *= x; return r; }
@@ -83,6 +84,14 @@ __attribute__((constructor)) void orc_recon_init(void) {
     for (int p = 0; p < 5; ++p) B[r * 5 + p] = (ipow(hi, p + 1) - ipow(lo, p + 1)) / (p + 1);
   }
   orc_invert(5, B, QUARTIC_INV);
+  {
+    double B7[49];               /* cell r spans [r-7/2, r-5/2]: offsets -3..3 */
+    for (int r = 0; r < 7; ++r) {
+      double lo = r - 3.5, hi = r - 2.5;
+      for (int p = 0; p < 7; ++p) B7[r * 7 + p] = (ipow(hi, p + 1) - ipow(lo, p + 1)) / (p + 1);
+    }
+    orc_invert(7, B7, SEXTIC_INV);
+  }
   recon_ready = 1;
 }
 
@@ -138,6 +147,22 @@ double orc_weno_right(const double *Q, const double *D, double eps) {
   double Qm[4], Dm[4];
   for (int m = 0; m < 4; ++m) { Qm[m] = Q[3 - m]; Dm[m] = -D[3 - m]; }
   return orc_weno_left(Qm, Dm, eps, 0, 0, 0);
+}
+
+void orc_sextic(const double *s, double eta, double *out3) {
+  double c[7];
+  for (int p = 0; p < 7; ++p) {
+    double acc = 0.0;
+    for (int r = 0; r < 7; ++r) acc += SEXTIC_INV[p * 7 + r] * s[r];
+    c[p] = acc;
+  }
+  double v = 0.0, d1 = 0.0, d2 = 0.0;
+  for (int p = 0; p < 7; ++p) {
+    v += c[p] * ipow(eta, p);
+    if (p >= 1) d1 += c[p] * p * ipow(eta, p - 1);
+    if (p >= 2) d2 += c[p] * p * (p - 1) * ipow(eta, p - 2);
+  }
+  out3[0] = v; out3[1] = d1; out3[2] = d2;
 }
 
 void orc_quartic(const double *s, double eta, double *out3) {

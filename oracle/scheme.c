@@ -15,6 +15,8 @@
 struct orc_ctx {
   orc_config cfg;
   int nc, nf, gx, gy;
+  int ng;                /* ghost layers: 2, or 3 for the 7-segment tangential stencil */
+  int nl, npts;          /* 2D: tangential stencil lines (5 or 7) and Gauss points (2 or 4) */
   double dx, dy;
   double *U, *Us, *Un;   /* ghosted state, ghosted intermediate state, next state */
   double *P;             /* W + dt L + dt^2/6 L_t and the matching gradient part */
@@ -32,7 +34,7 @@ void orc_set_threads(int n) { nthreads_req = n; }
 static size_t fsize(const orc_ctx *c) { return (size_t)c->gx * c->gy; }
 static double *fld(const orc_ctx *c, double *base, int f) { return base + (size_t)f * fsize(c); }
 static size_t gidx(const orc_ctx *c, int i, int j) {
-  return c->cfg.dim == 2 ? (size_t)(j + 2) * c->gx + (i + 2) : (size_t)(i + 2);
+  return c->cfg.dim == 2 ? (size_t)(j + c->ng) * c->gx + (i + c->ng) : (size_t)(i + c->ng);
 }
 
 int orc_create(const orc_config *cfg, orc_ctx **out) {
@@ -45,6 +47,12 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   if ((cfg->bc[0] == ORC_PERIODIC) != (cfg->bc[1] == ORC_PERIODIC)) return ORC_EINVAL;
   if (cfg->dim == 2 && (cfg->bc[2] == ORC_PERIODIC) != (cfg->bc[3] == ORC_PERIODIC)) return ORC_EINVAL;
   if (!(cfg->mu >= 0.0) || !isfinite(cfg->mu)) return ORC_EINVAL;
+  const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
+  if (gp != 2 && !(gp == 4 && cfg->dim == 2)) return ORC_EINVAL;
+  /* the 7-segment stencil reaches 3 cells across a side: a wall mirrors 3 cells */
+  if (gp == 4)
+    for (int s = 0; s < 4; ++s)
+      if ((cfg->bc[s] == ORC_WALL || cfg->bc[s] == ORC_NOSLIP) && (s < 2 ? cfg->nx : cfg->ny) < 3) return ORC_EINVAL;
   orc_recon_init();
   orc_ctx *c = (orc_ctx *)calloc(1, sizeof *c);
   if (!c) return ORC_ENOMEM;
@@ -52,8 +60,12 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   if (cfg->dim == 1) c->cfg.ny = 1;
   c->nc = cfg->dim + 2;
   c->nf = cfg->dim == 2 ? 12 : 6;
-  c->gx = c->cfg.nx + 4;
-  c->gy = cfg->dim == 2 ? c->cfg.ny + 4 : 1;
+  c->cfg.gauss_points = gp;
+  c->npts = cfg->dim == 2 ? gp : 1;
+  c->nl = gp == 4 ? 7 : 5;
+  c->ng = gp == 4 ? 3 : 2;
+  c->gx = c->cfg.nx + 2 * c->ng;
+  c->gy = cfg->dim == 2 ? c->cfg.ny + 2 * c->ng : 1;
   c->dx = (cfg->x1 - cfg->x0) / cfg->nx;
   c->dy = cfg->dim == 2 ? (cfg->y1 - cfg->y0) / cfg->ny : 1.0;
   const size_t n = (size_t)c->nf * fsize(c);
@@ -159,7 +171,7 @@ static void ghost_copy(orc_ctx *c, double *G, size_t dst, size_t src, int side, 
 static void fill_ghosts(orc_ctx *c, double *G) {
   const int nx = c->cfg.nx, ny = c->cfg.ny;
   for (int j = 0; j < ny; ++j)
-    for (int k = 1; k <= 2; ++k) {
+    for (int k = 1; k <= c->ng; ++k) {
       int src_lo, src_hi;
       switch (c->cfg.bc[0]) {
         case ORC_PERIODIC: src_lo = ((-k) % nx + nx) % nx; break;
@@ -175,8 +187,8 @@ static void fill_ghosts(orc_ctx *c, double *G) {
       ghost_copy(c, G, gidx(c, nx - 1 + k, j), gidx(c, src_hi, j), 1, 0);
     }
   if (c->cfg.dim == 1) return;
-  for (int i = -2; i < nx + 2; ++i)
-    for (int k = 1; k <= 2; ++k) {
+  for (int i = -c->ng; i < nx + c->ng; ++i)
+    for (int k = 1; k <= c->ng; ++k) {
       int src_lo, src_hi;
       switch (c->cfg.bc[2]) {
         case ORC_PERIODIC: src_lo = ((-k) % ny + ny) % ny; break;
@@ -232,37 +244,53 @@ static void swap12(double *v) { double t = v[1]; v[1] = v[2]; v[2] = t; }
 
 typedef struct { long w0, weno; } guards_t;
 
-/* Evaluate one face.  lines[l][q][c]: stencil line l (tangential offset l-2,
- * only l=0 used in 1D), quantity q (P7, P7_n, P7_nn, W_l, W_r), component c;
- * the value quantities are deviations from ref.  rot: y-face (swap momenta).
- * Writes F, Ft, A, B (blocks of nc) averaged over the Gauss points. */
-static void face_eval(orc_ctx *c, double lines[5][5][4], const double *ref, const double *Wleft,
+/* Evaluate one face.  lines[l][q][c]: stencil line l (tangential offset
+ * l - nl/2, only l=0 used in 1D), quantity q (P7, P7_n, P7_nn, W_l, W_r),
+ * component c; the value quantities are deviations from ref.  rot: y-face
+ * (swap momenta).  Writes F, Ft, A, B (blocks of nc) averaged over the Gauss
+ * points with the Gauss-Legendre weights. */
+static void face_eval(orc_ctx *c, double lines[7][5][4], const double *ref, const double *Wleft,
                       const double *Wright, double dt, int final, int rot, double ht,
                       double *out, guards_t *gd) {
   const int dim = c->cfg.dim, nc = c->nc;
   const double gam = c->cfg.gamma;
-  const int npts = dim == 2 ? 2 : 1;
-  const double eta[2] = {-0.5 / sqrt(3.0), 0.5 / sqrt(3.0)};   /* 2-point Gauss-Legendre */
+  const int npts = c->npts, nl = c->nl;
+  /* Gauss-Legendre nodes and weights on the segment [-1/2, 1/2] (weights sum to 1) */
+  double eta[4], wgt[4];
+  if (npts == 4) {
+    const double a = 0.5 * sqrt(3.0 / 7.0 - 2.0 / 7.0 * sqrt(6.0 / 5.0));
+    const double b = 0.5 * sqrt(3.0 / 7.0 + 2.0 / 7.0 * sqrt(6.0 / 5.0));
+    const double wa = (18.0 + sqrt(30.0)) / 72.0, wb = (18.0 - sqrt(30.0)) / 72.0;
+    eta[0] = -b; eta[1] = -a; eta[2] = a; eta[3] = b;
+    wgt[0] = wb; wgt[1] = wa; wgt[2] = wa; wgt[3] = wb;
+  } else if (npts == 2) {
+    eta[0] = -0.5 / sqrt(3.0); eta[1] = 0.5 / sqrt(3.0);
+    wgt[0] = wgt[1] = 0.5;
+  } else {
+    eta[0] = 0.0; wgt[0] = 1.0;
+  }
+  /* the tangential polynomial through the nl segment averages */
+  void (*tang)(const double *, double, double *) = nl == 7 ? orc_sextic : orc_quartic;
   for (int k = 0; k < NF_FACE * nc; ++k) out[k] = 0.0;
   for (int g = 0; g < npts; ++g) {
     double W0d[4], W0[4], Wn[4], Wt_[4], Wnn[4], Wnt[4], Wtt_[4], Wl[4], Wr[4];
     for (int k = 0; k < nc; ++k) {
       if (dim == 2) {
-        double s[5], r3[3];
-        for (int l = 0; l < 5; ++l) s[l] = lines[l][0][k];
-        orc_quartic(s, eta[g], r3);
+        double s[7], r3[3];
+        for (int l = 0; l < nl; ++l) s[l] = lines[l][0][k];
+        tang(s, eta[g], r3);
         W0d[k] = r3[0]; Wt_[k] = r3[1] / ht; Wtt_[k] = r3[2] / (ht * ht);
-        for (int l = 0; l < 5; ++l) s[l] = lines[l][1][k];
-        orc_quartic(s, eta[g], r3);
+        for (int l = 0; l < nl; ++l) s[l] = lines[l][1][k];
+        tang(s, eta[g], r3);
         Wn[k] = r3[0]; Wnt[k] = r3[1] / ht;
-        for (int l = 0; l < 5; ++l) s[l] = lines[l][2][k];
-        orc_quartic(s, eta[g], r3);
+        for (int l = 0; l < nl; ++l) s[l] = lines[l][2][k];
+        tang(s, eta[g], r3);
         Wnn[k] = r3[0];
-        for (int l = 0; l < 5; ++l) s[l] = lines[l][3][k];
-        orc_quartic(s, eta[g], r3);
+        for (int l = 0; l < nl; ++l) s[l] = lines[l][3][k];
+        tang(s, eta[g], r3);
         Wl[k] = ref[k] + r3[0];
-        for (int l = 0; l < 5; ++l) s[l] = lines[l][4][k];
-        orc_quartic(s, eta[g], r3);
+        for (int l = 0; l < nl; ++l) s[l] = lines[l][4][k];
+        tang(s, eta[g], r3);
         Wr[k] = ref[k] + r3[0];
       } else {
         W0d[k] = lines[0][0][k]; Wn[k] = lines[0][1][k]; Wnn[k] = lines[0][2][k];
@@ -283,7 +311,7 @@ static void face_eval(orc_ctx *c, double lines[5][5][4], const double *ref, cons
                                       Wnt, Wtt_, Wl, Wr, F, Ft, Wt, Wtt, Nh, Nf, &tau, W0u);
     if (rot) { swap12(F); swap12(Ft); swap12(Wt); swap12(Wtt); swap12(Nh); swap12(Nf); swap12(W0u); }
     if (fired) { gd->w0++; for (int k = 0; k < nc; ++k) W0d[k] = W0u[k] - ref[k]; }
-    const double wg = 1.0 / npts;
+    const double wg = wgt[g];
     for (int k = 0; k < nc; ++k) {
       double A, B;
       if (!final) {
@@ -312,15 +340,15 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
   for (int j = 0; j < ny; ++j) {
     guards_t gd = {0, 0};
     for (int f = 0; f <= nx; ++f) {
-      double ref[4], Wlc[4], Wrc[4], lines[5][5][4];
+      double ref[4], Wlc[4], Wrc[4], lines[7][5][4];
       for (int k = 0; k < nc; ++k) {
         ref[k] = fld(c, (double *)G, k)[gidx(c, f - 1, j)];
         Wlc[k] = ref[k];
         Wrc[k] = fld(c, (double *)G, k)[gidx(c, f, j)];
       }
-      const int nl = dim == 2 ? 5 : 1;
+      const int nl = dim == 2 ? c->nl : 1;
       for (int l = 0; l < nl; ++l) {
-        const int jj = dim == 2 ? j + l - 2 : 0;
+        const int jj = dim == 2 ? j + l - nl / 2 : 0;
         for (int k = 0; k < nc; ++k) {
           double Q[4], D[4];
           for (int m = 0; m < 4; ++m) {
@@ -343,14 +371,14 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
     for (int f = 0; f <= ny; ++f) {
       guards_t gd = {0, 0};
       for (int i = 0; i < nx; ++i) {
-        double ref[4], Wlc[4], Wrc[4], lines[5][5][4];
+        double ref[4], Wlc[4], Wrc[4], lines[7][5][4];
         for (int k = 0; k < nc; ++k) {
           ref[k] = fld(c, (double *)G, k)[gidx(c, i, f - 1)];
           Wlc[k] = ref[k];
           Wrc[k] = fld(c, (double *)G, k)[gidx(c, i, f)];
         }
-        for (int l = 0; l < 5; ++l) {
-          const int ii = i + l - 2;
+        for (int l = 0; l < c->nl; ++l) {
+          const int ii = i + l - c->nl / 2;
           for (int k = 0; k < nc; ++k) {
             double Q[4], D[4];
             for (int m = 0; m < 4; ++m) {

@@ -100,6 +100,8 @@ def _torch():
 
 def make_config(prob, storage: int = CGKS_FP64) -> cgks_config:
     d = prob.config_dict()
+    if d.get('gauss_points', 2) != 2:
+        raise ValueError('the HIP kernels evaluate two Gauss points per face segment')
     cfg = cgks_config()
     for k in ('dim', 'nx', 'ny'):
         setattr(cfg, k, int(d[k]))

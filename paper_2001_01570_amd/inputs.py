@@ -54,6 +54,7 @@ class Problem:
     tau_eps: float = 0.01
     tau_C: float = 1.0
     mu: float = 0.0               # dynamic viscosity (0: Euler equations)
+    gauss_points: int = 2         # 2D: Gauss points per face segment (2: quartic on 5 segments, 4: sextic on 7)
     exact: Optional[Callable[[float], np.ndarray]] = None   # t -> exact fields (cell averages)
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -75,7 +76,7 @@ class Problem:
                     y1=self.y1, gamma=self.gamma, cfl=self.cfl, bc=list(self.bc),
                     inflow_prim=np.asarray(inflow, dtype=np.float64).tolist(),
                     weno_eps=self.weno_eps, tau_eps=self.tau_eps, tau_C=self.tau_C,
-                    fixed_dt=self.fixed_dt, mu=self.mu)
+                    fixed_dt=self.fixed_dt, mu=self.mu, gauss_points=self.gauss_points)
 
 
 # ---------------------------------------------------------------- helpers

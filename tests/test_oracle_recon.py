@@ -150,6 +150,23 @@ def test_right_value_is_the_mirror_image():
 
 
 @pytest.mark.parametrize('seed', range(3))
+def test_tangential_sextic_exact(seed):
+    """The 7-segment tangential polynomial (four Gauss points per face)
+    reproduces any sextic from its unit-cell averages at offsets -3..3:
+    value, first and second derivative at the 4-point Gauss-Legendre nodes."""
+    rng = np.random.default_rng(40 + seed)
+    P = np.polynomial.Polynomial(rng.normal(size=7))
+    I = P.integ()
+    s = np.array([I(m - 3 + 0.5) - I(m - 3 - 0.5) for m in range(7)])
+    nodes = np.polynomial.legendre.leggauss(4)[0] / 2.0
+    for eta in list(nodes) + [0.0]:
+        v, d1, d2 = O.sextic(s, eta)
+        assert v == pytest.approx(P(eta), abs=1e-11)
+        assert d1 == pytest.approx(P.deriv()(eta), abs=1e-10)
+        assert d2 == pytest.approx(P.deriv(2)(eta), abs=1e-9)
+
+
+@pytest.mark.parametrize('seed', range(3))
 def test_tangential_quartic_exact(seed):
     rng = np.random.default_rng(30 + seed)
     P = np.polynomial.Polynomial(rng.normal(size=5))

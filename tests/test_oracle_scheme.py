@@ -390,3 +390,58 @@ def test_nonphysical_state_is_rejected():
     bad[2, 3] = 0.1    # energy below kinetic energy: negative pressure
     with pytest.raises(O.OracleError):
         O.Oracle(I.Problem('bad', 1, 10, 1, 0.0, 2.0, 0.0, 1.0, bad))
+
+
+def _diag_l1(n, gp):
+    p = dataclasses.replace(I.diagonal_wave_2d(n, t_end=0.5, fixed_dt=0.5 * (2.0 / n) ** 2), gauss_points=gp)
+    o = O.Oracle(p, threads=8)
+    o.advance_to(0.5)
+    st, t, _ = o.get_state()
+    return I.density_errors(st, p.exact(t))[0]
+
+
+def test_four_gauss_points_make_the_2d_step_eighth_order():
+    """The 2D assembly is fourth order in space with two Gauss points per face
+    (exact for cubics only) and the 5-segment quartic; four Gauss-Legendre
+    points with the sextic through 7 segment averages restore order about 8.
+    Diagonal wave rho = 1 + 0.2 sin pi(x + y), p constant, dt = 0.5 dx^2 so
+    that the time error is negligible (1D: order 8 on the same wave)."""
+    e2 = [_diag_l1(n, 2) for n in (24, 32)]
+    e4 = [_diag_l1(n, 4) for n in (16, 24, 32)]
+    o2 = math.log(e2[0] / e2[1]) / math.log(32 / 24)
+    o4 = math.log(e4[1] / e4[2]) / math.log(32 / 24)
+    assert o2 < 5.0 and e2[1] > 1e-7, (e2, o2)          # 5.61e-7, 1.51e-7: order 4.6
+    assert o4 > 7.0 and e4[2] < 1.2e-9, (e4, o4)        # 1.38e-7, 7.87e-9, 9.40e-10: order 7.4
+
+
+def test_four_points_equal_two_points_on_a_flow_without_tangential_variation():
+    """Where nothing varies along a face, every Gauss point sees the same state
+    and both quadratures return it: the 1D density wave (p = 1) laid out in 2D,
+    one step."""
+    p = I.sine_wave_1d(32)
+    f1 = p.fields
+    ny = 8
+    fields = np.zeros((12, ny, p.nx))
+    for k, k2 in ((0, 0), (1, 1), (2, 3)):                # (rho, rhoU, rhoE) -> (rho, rhoU, rhoV = 0, rhoE)
+        fields[k2] = f1[k][None, :]
+        fields[4 + k2] = f1[3 + k][None, :]
+    out = []
+    for gp in (2, 4):
+        q = I.Problem('xonly', 2, p.nx, ny, p.x0, p.x1, 0.0, ny * (p.x1 - p.x0) / p.nx, fields,
+                      cfl=0.3, gauss_points=gp)
+        o = O.Oracle(q, threads=4)
+        o.step(o.cfl_dt())
+        out.append(o.state)
+    for f in range(12):                                   # scale: the largest field of the block
+        scale = np.abs(out[0][4 * (f // 4):4 * (f // 4) + 4]).max()
+        assert np.abs(out[0][f] - out[1][f]).max() <= 1e-14 * scale, f
+
+
+def test_gauss_point_configurations_rejected():
+    from oracle.oracle import OracleError
+    base = I.diagonal_wave_2d(8)
+    for bad in (dataclasses.replace(base, gauss_points=3),
+                dataclasses.replace(I.sine_wave_1d(16), gauss_points=4),
+                dataclasses.replace(I.uniform_2d(2, 8, prim=(1.0, 0.1, 0.0, 1.0), bc=(I.WALL,) * 4), gauss_points=4)):
+        with pytest.raises(OracleError):
+            O.Oracle(bad)
