@@ -73,6 +73,15 @@ typedef struct {
                                 collision time is mu/p + C|dp/sum p|*dt in both of
                                 its roles (Sec. 4, viscous form) and tau_eps is
                                 unused; CGKS_NOSLIP gives viscous walls              */
+  int gauss_points;          /* 2D: Gauss-Legendre points per face segment (the
+                                quadrature points along the interface of Sec. 2,
+                                their number not given there).  0 or 2: the
+                                quartic through 5 segment averages, two points
+                                (fourth order in space in 2D; the default).  4:
+                                the sextic through 7 segment averages, four
+                                points (eighth order in 2D; FP64 storage, walls
+                                need 3 cells across, not in the batch API,
+                                tile shape fixed)                                    */
 } cgks_config;
 
 typedef struct {

@@ -26,7 +26,7 @@ class cgks_config(C.Structure):
                 ('gamma', C.c_double), ('cfl', C.c_double),
                 ('bc', C.c_int * 4), ('inflow_prim', (C.c_double * 4) * 4),
                 ('weno_eps', C.c_double), ('tau_eps', C.c_double), ('tau_C', C.c_double),
-                ('fixed_dt', C.c_double), ('storage', C.c_int), ('mu', C.c_double)]
+                ('fixed_dt', C.c_double), ('storage', C.c_int), ('mu', C.c_double), ('gauss_points', C.c_int)]
 
 
 class cgks_counters_t(C.Structure):
@@ -100,8 +100,6 @@ def _torch():
 
 def make_config(prob, storage: int = CGKS_FP64) -> cgks_config:
     d = prob.config_dict()
-    if d.get('gauss_points', 2) != 2:
-        raise ValueError('the HIP kernels evaluate two Gauss points per face segment')
     cfg = cgks_config()
     for k in ('dim', 'nx', 'ny'):
         setattr(cfg, k, int(d[k]))
@@ -112,6 +110,7 @@ def make_config(prob, storage: int = CGKS_FP64) -> cgks_config:
         for q in range(4):
             cfg.inflow_prim[s][q] = float(d['inflow_prim'][s][q])
     cfg.storage = int(storage)
+    cfg.gauss_points = int(d.get('gauss_points', 2))
     return cfg
 
 

@@ -31,17 +31,23 @@ namespace cgks {
 // 256 threads (one per Gauss point).  Shapes differ in halo overhead ((T+4)/T
 // reconstructed line segments per face segment) and in the width of the rows
 // they read and write; the shape is chosen per direction at run time (tuned).
-template <int F_, int T_>
+// M Gauss points per segment (one thread each); the tangential stencil has
+// 2 HALO + 1 lines (2: the quartic through 5 segments with two points, 3: the
+// sextic through 7 with four).
+template <int F_, int T_, int M_ = 2, int HALO_ = 2>
 struct Tile {
-  static constexpr int F = F_, T = T_;
-  static constexpr int H = T_ + 4;          // tangential extent including the 2+2 halo
+  static constexpr int F = F_, T = T_, M = M_, HALO = HALO_;
+  static constexpr int H = T_ + 2 * HALO_;  // tangential extent including the halo
   static constexpr int NSEG = F_ * H;       // reconstructed line segments per tile
-  static_assert(2 * F_ * T_ == 256 && 32 % F_ == 0, "one 256-thread block per tile");
+  static_assert(M_ * F_ * T_ == 256 && (64 / M_) % F_ == 0, "one 256-thread block per tile");
 };
 using Tile8x16 = Tile<8, 16>;
 using Tile4x32 = Tile<4, 32>;
 using Tile2x64 = Tile<2, 64>;
 constexpr int kTileShapes = 3;
+// four Gauss points per segment with the 7-line stencil (x faces, y faces)
+using Tile4x16G4 = Tile<4, 16, 4, 3>;
+using Tile2x32G4 = Tile<2, 32, 4, 3>;
 // the batched face kernels' tiles per direction: the shapes the tuner picks
 // for most grids from 64^2 to 2048^2 (x faces 4x32, y faces 2x64)
 template <int DIR> struct BatchTile { using T = Tile4x32; };
@@ -346,7 +352,7 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 template <int DIR, int STAGE, class GT = double, class TL = Tile8x16>
 __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx, int by,
                                             double (*lds)[TL::NSEG]) {
-  constexpr int TF = TL::F, TT = TL::T, TH = TL::H, NSEG = TL::NSEG;
+  constexpr int TF = TL::F, TT = TL::T, TH = TL::H, NSEG = TL::NSEG, HALO = TL::HALO;
   Scalars* sc = B.sc;
   if (!sc->active || sc->status != 0) return;
   const double dt = sc->dt;
@@ -366,7 +372,7 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   // from the boundary skip the boundary rules, which map every index in
   // [-2, n + 1] into the grid.
   {
-    const int i0 = (DIR == 0 ? f0 : t0) - 2, j0 = (DIR == 0 ? t0 : f0) - 2;
+    const int i0 = DIR == 0 ? f0 - 2 : t0 - HALO, j0 = DIR == 0 ? t0 - HALO : f0 - 2;
     const bool interior = i0 >= 0 && j0 >= 0 && i0 + TH <= G.nx && j0 + TH <= G.ny;
     const size_t N = (size_t)G.nx * G.ny;
 #pragma unroll 1
@@ -375,8 +381,8 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
       int fl, tl, pos;
       if (DIR == 0) { tl = s / TF; fl = s % TF; pos = tl * TF + fl; }
       else { fl = s / TH; tl = s % TH; pos = fl * TH + tl; }
-      const int f = f0 + fl, ta = t0 - 2 + tl;
-      if (f > nn || ta > nt + 1) continue;
+      const int f = f0 + fl, ta = t0 - HALO + tl;
+      if (f > nn || ta > nt + HALO - 1) continue;
       double w[4], gd[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -408,23 +414,28 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   // banks), a half-wave covers 16 segments along x.  x faces: the two points in
   // the two half-waves (within a half-wave, reads of lines 2 or 4 rows apart
   // would share LDS banks), a half-wave covers 32/TF rows of TF faces.
+  // With four points (M = 4) the groups are quarter-waves (x faces) or 4
+  // adjacent lanes (y faces): point gp = 2 pr + mirror, pr 0 the inner pair
+  // of nodes, 1 the outer; the mirrored point reads the lines in reverse.
+  constexpr int M = TL::M, NL = 2 * HALO + 1, QW = 64 / M;
   int gp, fl, tl;
   if (DIR == 0) {
     const int lane = threadIdx.x & 63;
-    gp = lane >> 5;
+    gp = lane / QW;
     fl = lane % TF;
-    tl = (32 / TF) * (threadIdx.x >> 6) + (lane & 31) / TF;
+    tl = (QW / TF) * (threadIdx.x >> 6) + (lane % QW) / TF;
   } else {
-    gp = threadIdx.x & 1;
-    tl = (threadIdx.x >> 1) % TT;
-    fl = (threadIdx.x >> 1) / TT;
+    gp = threadIdx.x % M;
+    tl = (threadIdx.x / M) % TT;
+    fl = (threadIdx.x / M) / TT;
   }
-  constexpr int PAIR = DIR == 0 ? 32 : 1;   // lane distance of the two points of a segment
+  constexpr int PAIR = DIR == 0 ? QW : 1;   // lane distance of the two points of a pair
   const int f = f0 + fl, tt = t0 + tl;
   if (f > nn || tt >= nt) return;
+  const int mirror = gp & 1;
   const int lstride = DIR == 0 ? TF : 1;    // next stencil line in LDS
-  const int lfirst = (DIR == 0 ? tl * TF + fl : fl * TH + tl) + (gp ? 4 * lstride : 0);
-  const int lstep = gp ? -lstride : lstride;
+  const int lfirst = (DIR == 0 ? tl * TF + fl : fl * TH + tl) + (mirror ? (NL - 1) * lstride : 0);
+  const int lstep = mirror ? -lstride : lstride;
   auto get = [&](int q, int l) { return lds[q][lfirst + lstep * l]; };
   auto right_cell = [&](int k) {            // the cell right of the face, boundary rule applied
     double W[4];
@@ -435,13 +446,26 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   double acc[NO];
   int guard, nbad;
   const double inv_hn = DIR == 0 ? G.inv_dx : G.inv_dy, inv_ht = DIR == 0 ? G.inv_dy : G.inv_dx;
-  face_point<DIR, STAGE == 1>(get, right_cell, kTang[0], inv_hn, gp ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad);
+  if constexpr (M == 2) {
+    face_point<DIR, STAGE == 1>(get, right_cell, kTang[0], inv_hn, mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard,
+                                nbad);
+  } else {
+    const int pr = gp >> 1;
+    face_point<DIR, STAGE == 1>(get, right_cell, kTang7[pr], inv_hn, mirror ? -inv_ht : inv_ht, G.gas, dt, acc,
+                                guard, nbad, pr ? kGauss4Outer : kGauss4Inner);
+  }
   if (guard) atomicAdd(&sc->guard_w0, 1ull);
   if (nbad) atomicAdd(&sc->guard_weno, (unsigned long long)nbad);
 
-  // Gauss average over the two lanes of the segment; the first point's lane writes
+  // Gauss average over the lanes of the segment (each point weighted in
+  // face_point: the pair, then the two pairs); the first point's lane writes
 #pragma unroll
   for (int q = 0; q < NO; ++q) acc[q] += __shfl_xor(acc[q], PAIR, 64);
+  if constexpr (M == 4) {
+    constexpr int PAIRS = DIR == 0 ? 32 : 2;
+#pragma unroll
+    for (int q = 0; q < NO; ++q) acc[q] += __shfl_xor(acc[q], PAIRS, 64);
+  }
   if (gp) return;
   double* F = DIR == 0 ? B.FX : B.FY;
   // x faces: [q][row][face] (nx+1 per row); y faces: [q][face][column] (nx per row)
@@ -873,10 +897,12 @@ static int validate(const cgks_config* c) {
   if (!(c->weno_eps > 0.0) || !(c->tau_eps > 0.0) || c->tau_C < 0.0) return CGKS_EINVAL;
   if (!(c->mu >= 0.0) || !std::isfinite(c->mu)) return CGKS_EINVAL;
   if (c->storage != CGKS_FP64 && !(c->storage == CGKS_FP32_STORAGE && c->dim == 2)) return CGKS_EINVAL;
+  const int gp = c->gauss_points ? c->gauss_points : 2;
+  if (gp != 2 && !(gp == 4 && c->dim == 2 && c->storage == CGKS_FP64)) return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
     if (c->bc[s] < 0 || c->bc[s] > 4) return CGKS_EINVAL;
     const int n = s < 2 ? c->nx : c->ny;
-    if ((c->bc[s] == CGKS_WALL || c->bc[s] == CGKS_NOSLIP) && n < 2) return CGKS_EINVAL;
+    if ((c->bc[s] == CGKS_WALL || c->bc[s] == CGKS_NOSLIP) && n < (gp == 4 ? 3 : 2)) return CGKS_EINVAL;
     if (c->bc[s] == CGKS_INFLOW) {
       const double* q = c->inflow_prim[s];
       if (!(q[0] > 0.0) || !(q[3] > 0.0)) return CGKS_EINVAL;
@@ -929,6 +955,7 @@ extern "C" int cgks_create(const cgks_config* cfg, void* hip_stream, cgks_ctx** 
   std::memset(c, 0, sizeof *c);
   c->cfg = *cfg;
   if (cfg->dim == 1) c->cfg.ny = 1;
+  if (c->cfg.gauss_points == 0) c->cfg.gauss_points = 2;
   c->stream = (hipStream_t)hip_stream;
   Geom& G = c->G;
   make_geom(c->cfg, G);
@@ -1092,6 +1119,13 @@ static void launch_step(cgks_ctx* c) {
                                 : dim3((G.nx + TL::T - 1) / TL::T, (G.ny + 1 + TL::F - 1) / TL::F);
         timed(c, kind, [&] { k_faces2<DIR, STAGE, GT, TL><<<g, FACE_THREADS, 0, s>>>(G, B); });
       };
+      if (c->cfg.gauss_points == 4) {        // FP64 storage only (validated)
+        if constexpr (std::is_same_v<GT, double>) {
+          if constexpr (DIR == 0) go(Tile4x16G4());
+          else go(Tile2x32G4());
+        }
+        return;
+      }
       switch (c->tile[DIR]) {
         case 1: go(Tile4x32()); break;
         case 2: go(Tile2x64()); break;
@@ -1428,7 +1462,8 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   if (!b || !fields || !slot) return CGKS_EINVAL;
   int rc = validate(cfg);
   if (rc) return rc;
-  if (cfg->dim != 2 || cfg->storage != CGKS_FP64) return CGKS_EINVAL;
+  if (cfg->dim != 2 || cfg->storage != CGKS_FP64 || (cfg->gauss_points != 0 && cfg->gauss_points != 2))
+    return CGKS_EINVAL;
   if (!(t_end > 0.0) && max_steps <= 0) return CGKS_EINVAL;   // a request needs an end
   int k = 0;
   while (k < b->max_slots && b->info[k].used) ++k;

@@ -162,7 +162,9 @@ CGKS_HD __forceinline__ Line5 normal_line(double a, double c, double d, double A
 // the 2-point Gauss-Legendre nodes eta = -+1/(2 sqrt 3) of the segment
 // (value, d/deta, d2/deta2).  Weights derived symbolically.
 // ----------------------------------------------------------------------------
-struct TangW { double v[5], d1[5], d2[5]; };
+template <int NL>
+struct TangWT { double v[NL], d1[NL], d2[NL]; };
+using TangW = TangWT<5>;
 
 #define CGKS_TANG_WEIGHTS { \
   {{-0.028297119567088289478, 0.20139476939454598305, 0.99861111111111111111, -0.19954291754269413120, 0.027834156604125326515}, \
@@ -174,6 +176,24 @@ struct TangW { double v[5], d1[5], d2[5]; };
 }
 
 __constant__ static const TangW kTang[2] = CGKS_TANG_WEIGHTS;
+
+// The sextic through 7 segment averages (offsets -3..3) at the 4-point
+// Gauss-Legendre nodes eta = -a (inner) and -b (outer), a = 0.16999052179...,
+// b = 0.43056815579...; the nodes +a, +b read the lines in reverse order
+// (first-derivative weights with opposite sign).  Weights from the exact
+// rational inverse of the 7x7 segment-average matrix evaluated at the nodes;
+// Gauss weights (18 + sqrt 30)/72 (inner) and (18 - sqrt 30)/72 (outer) for
+// an average over the segment.
+#define CGKS_TANG7_WEIGHTS { \
+  {{0.00327670662777140150320, -0.0266359260617751224288, 0.0928282644451935365246, 1.08046056237311464266, -0.183384586025290289167, 0.0375843394851378397702, -0.00412936084415200886592}, \
+   {-0.0234994586764076403944, 0.217583386144768507063, -1.09415803665141890662, 0.524691359684989440382, 0.497541637759546521474, -0.139445386633782430552, 0.0172864983723045086499}, \
+   {-0.00808539123755721195341, -0.0258058754040666686056, 1.39474441702196471283, -2.98922056750361979378, 1.97853482298309596974, -0.390843887097514794698, 0.0406764812376977864692}}, \
+  {{0.00860109764472105523262, -0.0796691475531970354643, 0.415576982717297023337, 0.849155569794037932652, -0.245805403605616208498, 0.0591434746546156592307, -0.00700257365185842648992}, \
+   {-0.0153298262005816740398, 0.170954211803748928533, -1.34141626702514246895, 1.21722202742076867842, -0.0133313609372416838971, -0.0221303941025073900877, 0.00403160904095561002241}, \
+   {-0.0547477785057617936884, 0.399186600655063098459, 0.438830376399876995413, -2.22166378623787680486, 1.86135977135016436283, -0.480496021826951022910, 0.0575308381654851647508}}, \
+}
+__constant__ static const TangWT<7> kTang7[2] = CGKS_TANG7_WEIGHTS;
+constexpr double kGauss4Inner = 0.326072577431273071313, kGauss4Outer = 0.173927422568726928687;
 
 // ----------------------------------------------------------------------------
 // erfc and exp near zero.  The half-space moments take erfc(-s sqrt(lambda) U)
@@ -703,73 +723,74 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
 // normal and tangential cell widths.
 // ----------------------------------------------------------------------------
 // Offsets that move the value-type quantities of line l to the middle line's
-// reference: off[l] = ref(l) - ref(2); returns ref(2).
-template <class Get>
+// reference: off[l] = ref(l) - ref(NL/2); returns ref(NL/2).  NL = 5 (quartic)
+// or 7 (sextic) lines.
+template <int NL = 5, class Get>
 CGKS_HD __forceinline__ double tang_offsets(Get get, int k, double* off) {
-  const double rj = get(20 + k, 2);
+  const double rj = get(20 + k, NL / 2);
 #pragma unroll
-  for (int l = 0; l < 5; ++l) off[l] = get(20 + k, l) - rj;
+  for (int l = 0; l < NL; ++l) off[l] = get(20 + k, l) - rj;
   return rj;
 }
 
 // sum_l c[l] (get(q, l) + off[l]) (value-type quantity, off from tang_offsets)
-template <class Get>
+template <int NL = 5, class Get>
 CGKS_HD __forceinline__ double tang_value(Get get, const double* c, int q, const double* off) {
   double s = 0;
 #pragma unroll
-  for (int l = 0; l < 5; ++l) s += c[l] * (get(q, l) + off[l]);
+  for (int l = 0; l < NL; ++l) s += c[l] * (get(q, l) + off[l]);
   return s;
 }
 
 // sum_l c[l] get(q, l) (derivative-type quantity, no reference shift)
-template <class Get>
+template <int NL = 5, class Get>
 CGKS_HD __forceinline__ double tang_deriv(Get get, const double* c, int q) {
   double s = 0;
 #pragma unroll
-  for (int l = 0; l < 5; ++l) s += c[l] * get(q, l);
+  for (int l = 0; l < NL; ++l) s += c[l] * get(q, l);
   return s;
 }
 
-template <class Get>
-CGKS_HD __forceinline__ void tangential_point(Get get, const TangW& w, double hn, double ht,
+template <int NL, class Get>
+CGKS_HD __forceinline__ void tangential_point(Get get, const TangWT<NL>& w, double hn, double ht,
                                               PointIn<4>& in, double* dev, double* ref) {
   const double inv_ht = 1.0 / ht, inv_hn = 1.0 / hn;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    double off[5];
-    const double rj = tang_offsets(get, k, off);
-    const double v = tang_value(get, w.v, k, off);
+    double off[NL];
+    const double rj = tang_offsets<NL>(get, k, off);
+    const double v = tang_value<NL>(get, w.v, k, off);
     ref[k] = rj;
     dev[k] = v;
     in.W0[k] = rj + v;
-    in.Wn[k] = tang_deriv(get, w.v, 4 + k) * inv_hn;
-    in.Wnn[k] = tang_deriv(get, w.v, 8 + k) * inv_hn * inv_hn;
-    in.Wt[k] = tang_value(get, w.d1, k, off) * inv_ht;
-    in.Wnt[k] = tang_deriv(get, w.d1, 4 + k) * inv_hn * inv_ht;
-    in.Wtt[k] = tang_value(get, w.d2, k, off) * inv_ht * inv_ht;
-    in.Wl[k] = rj + tang_value(get, w.v, 12 + k, off);
-    in.Wr[k] = rj + tang_value(get, w.v, 16 + k, off);
+    in.Wn[k] = tang_deriv<NL>(get, w.v, 4 + k) * inv_hn;
+    in.Wnn[k] = tang_deriv<NL>(get, w.v, 8 + k) * inv_hn * inv_hn;
+    in.Wt[k] = tang_value<NL>(get, w.d1, k, off) * inv_ht;
+    in.Wnt[k] = tang_deriv<NL>(get, w.d1, 4 + k) * inv_hn * inv_ht;
+    in.Wtt[k] = tang_value<NL>(get, w.d2, k, off) * inv_ht * inv_ht;
+    in.Wl[k] = rj + tang_value<NL>(get, w.v, 12 + k, off);
+    in.Wr[k] = rj + tang_value<NL>(get, w.v, 16 + k, off);
   }
 }
 
-// Gauss average (weights 1/2) of the per-point face results.  Stage 1 keeps
+// Gauss average (weight wg of this point: 1/2 for two points) of the per-point face results.  Stage 1 keeps
 // F, F_t and the interface states at t + dt/2 (A) and the stage-n part of the
 // state at t + dt (B), both as deviations from the face reference (Sec. 2.2);
 // stage 2 keeps F_t and W_tt.
 template <int NC, bool FULL>
 CGKS_HD __forceinline__ void face_accumulate(double* acc, const PointOut<NC>& o, const double* dev,
-                                             const double* ref, double dt) {
+                                             const double* ref, double dt, double wg = 0.5) {
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     if constexpr (FULL) {
       const double d0 = o.guard ? o.W0[k] - ref[k] : dev[k];
-      acc[k] += 0.5 * o.F[k];
-      acc[NC + k] += 0.5 * o.Ft[k];
-      acc[2 * NC + k] += 0.5 * (d0 + 0.5 * dt * o.Wt[k] + dt * dt / 8.0 * o.Wtt[k] + o.Nh[k]);
-      acc[3 * NC + k] += 0.5 * (d0 + dt * o.Wt[k] + dt * dt / 6.0 * o.Wtt[k] + o.Nf[k]);
+      acc[k] += wg * o.F[k];
+      acc[NC + k] += wg * o.Ft[k];
+      acc[2 * NC + k] += wg * (d0 + 0.5 * dt * o.Wt[k] + dt * dt / 8.0 * o.Wtt[k] + o.Nh[k]);
+      acc[3 * NC + k] += wg * (d0 + dt * o.Wt[k] + dt * dt / 6.0 * o.Wtt[k] + o.Nf[k]);
     } else {
-      acc[k] += 0.5 * o.Ft[k];
-      acc[NC + k] += 0.5 * o.Wtt[k];
+      acc[k] += wg * o.Ft[k];
+      acc[NC + k] += wg * o.Wtt[k];
     }
   }
 }
@@ -787,9 +808,10 @@ CGKS_HD __forceinline__ void face_accumulate(double* acc, const PointOut<NC>& o,
 // DIR 1 (y faces) rotates the momenta so that the normal one comes first.
 // acc receives this point's half of the Gauss average (face_accumulate from
 // zero); guard / nbad count the equilibrium and WENO fallbacks.
-template <int DIR, bool FULL, class Get, class Right>
-CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, double inv_hn, double inv_ht,
-                                        const Gas& gas, double dt, double* acc, int& guard, int& nbad) {
+template <int DIR, bool FULL, int NL, class Get, class Right>
+CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<NL>& w, double inv_hn, double inv_ht,
+                                        const Gas& gas, double dt, double* acc, int& guard, int& nbad,
+                                        double wg = 0.5) {
   auto rot = [](double* v) {
     if (DIR == 1) { const double t = v[1]; v[1] = v[2]; v[2] = t; }
   };
@@ -800,11 +822,11 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
   double Wl[4], Wr[4], W0[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    double off[5];
-    const double rj = tang_offsets(get, k, off);
-    Wl[k] = rj + tang_value(get, w.v, 12 + k, off);
-    Wr[k] = rj + tang_value(get, w.v, 16 + k, off);
-    W0[k] = rj + tang_value(get, w.v, k, off);
+    double off[NL];
+    const double rj = tang_offsets<NL>(get, k, off);
+    Wl[k] = rj + tang_value<NL>(get, w.v, 12 + k, off);
+    Wr[k] = rj + tang_value<NL>(get, w.v, 16 + k, off);
+    W0[k] = rj + tang_value<NL>(get, w.v, k, off);
     CGKS_PIN(Wl[k]);
     CGKS_PIN(Wr[k]);
     CGKS_PIN(W0[k]);
@@ -813,7 +835,7 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
   nbad = 0;
   if (!admissible<4>(Wl, gas.gamma)) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Wl[k] = get(20 + k, 2);
+    for (int k = 0; k < 4; ++k) Wl[k] = get(20 + k, NL / 2);
     ++nbad;
   }
   if (!admissible<4>(Wr, gas.gamma)) {
@@ -842,10 +864,10 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
   double Wn[4], Wt[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    double off[5];
-    tang_offsets(get, k, off);
-    Wn[k] = tang_deriv(get, w.v, 4 + k) * inv_hn;
-    Wt[k] = tang_value(get, w.d1, k, off) * inv_ht;
+    double off[NL];
+    tang_offsets<NL>(get, k, off);
+    Wn[k] = tang_deriv<NL>(get, w.v, 4 + k) * inv_hn;
+    Wt[k] = tang_value<NL>(get, w.d1, k, off) * inv_ht;
     CGKS_PIN(Wn[k]);
     CGKS_PIN(Wt[k]);
     CGKS_BREAK();
@@ -870,11 +892,11 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
     double Wnn[4], Wnt[4], Wtt[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      double off[5];
-      tang_offsets(get, k, off);
-      Wnn[k] = tang_deriv(get, w.v, 8 + k) * inv_hn * inv_hn;
-      Wnt[k] = tang_deriv(get, w.d1, 4 + k) * inv_hn * inv_ht;
-      Wtt[k] = tang_value(get, w.d2, k, off) * inv_ht * inv_ht;
+      double off[NL];
+      tang_offsets<NL>(get, k, off);
+      Wnn[k] = tang_deriv<NL>(get, w.v, 8 + k) * inv_hn * inv_hn;
+      Wnt[k] = tang_deriv<NL>(get, w.d1, 4 + k) * inv_hn * inv_ht;
+      Wtt[k] = tang_value<NL>(get, w.d2, k, off) * inv_ht * inv_ht;
       CGKS_PIN(Wnn[k]);
       CGKS_PIN(Wnt[k]);
       CGKS_PIN(Wtt[k]);
@@ -913,9 +935,9 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
   double dev[4], ref[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    double off[5];
-    ref[k] = tang_offsets(get, k, off);
-    dev[k] = tang_value(get, w.v, k, off);
+    double off[NL];
+    ref[k] = tang_offsets<NL>(get, k, off);
+    dev[k] = tang_value<NL>(get, w.v, k, off);
     CGKS_PIN(ref[k]);
     CGKS_PIN(dev[k]);
     CGKS_BREAK();
@@ -923,7 +945,7 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangW& w, do
   constexpr int NO = FULL ? 16 : 8;
 #pragma unroll
   for (int q = 0; q < NO; ++q) acc[q] = 0.0;
-  face_accumulate<4, FULL>(acc, o, dev, ref, dt);
+  face_accumulate<4, FULL>(acc, o, dev, ref, dt, wg);
 }
 
 }  // namespace cgks

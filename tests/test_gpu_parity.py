@@ -174,6 +174,43 @@ TINY = [(1, 1, 'periodic'), (1, 5, 'periodic'), (3, 2, 'periodic'), (2, 9, 'wall
 def test_2d_degenerate_tiny_grids(nx, ny, kind):
     """Grids smaller than a tile and than the stencil (ghosts wrap onto or
     mirror the same few cells): one step against the oracle."""
+    _tiny(nx, ny, kind, 2)
+
+
+# four Gauss points per face segment with the 7-segment sextic (gauss_points = 4)
+G4 = [(name, (lambda mk=mk: dataclasses.replace(mk(), gauss_points=4))) for name, mk in CASES_2D + VISCOUS[-2:]]
+TINY4 = [(1, 1, 'periodic'), (2, 5, 'periodic'), (3, 3, 'walls'), (3, 4, 'noslip'), (5, 3, 'inflow')]
+
+
+@pytest.mark.parametrize('name,mk', G4[:-2], ids=['g4_' + c[0] for c in G4[:-2]])
+def test_2d_single_step_four_points(name, mk):
+    p = mk()
+    say('2d single step, four points', name, p.nx, p.ny)
+    e, dt, dtg = single_step(p, steps_before=2)
+    say(name, 'field errors', e)
+    assert dtg == pytest.approx(dt, rel=1e-13)
+    assert e.max() < TOL, e
+
+
+@pytest.mark.parametrize('nx,ny,kind', TINY4, ids=['g4_%dx%d-%s' % t for t in TINY4])
+def test_2d_degenerate_tiny_grids_four_points(nx, ny, kind):
+    """The 7-line stencil on grids smaller than it (walls need 3 cells)."""
+    _tiny(nx, ny, kind, 4)
+
+
+@pytest.mark.parametrize('name,mk', G4[:3] + G4[5:], ids=['g4_' + c[0] for c in G4[:3] + G4[5:]])
+def test_2d_multi_step_four_points(name, mk):
+    p = mk()
+    s, o = solver(p), O.Oracle(p, threads=8)
+    for _ in range(20):
+        dt = o.step()
+        s.step(dt)
+    err = scaled_errors(s.state, o.state, p.dx, p.dy)
+    say(name, 'four points, 20-step scaled errors', err)
+    assert err.max() < TOL, err
+
+
+def _tiny(nx, ny, kind, gp):
     p = I.acoustic_pulse_2d(max(nx, ny), seed=3, amp=0.05, half_width=0.3, ny=max(nx, ny))
     f = np.ascontiguousarray(p.fields[:, :ny, :nx])
     f[1] += 0.2 * f[0]
@@ -181,8 +218,8 @@ def test_2d_degenerate_tiny_grids(nx, ny, kind):
     bc = {'periodic': (I.PERIODIC,) * 4, 'walls': (I.WALL, I.WALL, I.PERIODIC, I.PERIODIC),
           'noslip': (I.NOSLIP,) * 4, 'inflow': (I.INFLOW, I.FREE, I.WALL, I.FREE)}[kind]
     q = I.Problem('tiny', 2, nx, ny, 0.0, nx * p.dx, 0.0, ny * p.dy, f, bc=bc,
-                  inflow_prim=((1.0, 0.3, 0.0, 0.7),) * 4, mu=0.01 if kind == 'noslip' else 0.0)
-    say('tiny', nx, ny, kind)
+                  inflow_prim=((1.0, 0.3, 0.0, 0.7),) * 4, mu=0.01 if kind == 'noslip' else 0.0, gauss_points=gp)
+    say('tiny', nx, ny, kind, 'gauss points', gp)
     e, dt, dtg = single_step(q)
     assert dtg == pytest.approx(dt, rel=1e-13)
     assert e.max() < TOL, e
