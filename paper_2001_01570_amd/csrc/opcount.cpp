@@ -82,6 +82,7 @@ static void emit(const char* name, const OpCounts& c, bool comma) {
 
 int main() {
   static const TangW host_tang[2] = CGKS_TANG_WEIGHTS;
+  static const TangWT<7> host_tang7[2] = CGKS_TANG7_WEIGHTS;
   const double gamma = 1.4;
   const Gas gas = make_gas(gamma, 2, 0.01, 1.0, 0.0);
   const double dt = 6e-4, hn = 1.0 / 512, ht = 1.0 / 512;
@@ -103,6 +104,21 @@ int main() {
   a = snap();
   tangential_point(get, host_tang[0], CD(hn), CD(ht), in, dev, ref);
   const OpCounts tang = diff(a, snap());
+  // the sextic through 7 segment averages (four Gauss points per segment)
+  CD lines7[24][7];
+  for (int q = 0; q < 24; ++q)
+    for (int l = 0; l < 7; ++l) lines7[q][l] = q >= 20 ? CD(1.0 + 1e-4 * l) : CD(1e-5 * (q + 1) * (l + 1));
+  for (int l = 0; l < 7; ++l) { lines7[20][l] = CD(1.0 + 1e-4 * l); lines7[23][l] = CD(1.8 + 1e-4 * l); }
+  auto get7 = [&](int q, int l) { return lines7[q][l]; };
+  {
+    PointIn<4> in7;
+    a = snap();
+    tangential_point(get7, host_tang7[0], CD(hn), CD(ht), in7, dev, ref);
+  }
+  const OpCounts tang7 = diff(a, snap());
+  a = snap();
+  tangential_point(get, host_tang[0], CD(hn), CD(ht), in, dev, ref);   // the input of the point counts below
+  (void)diff(a, snap());
   for (int k = 0; k < 4; ++k) { in.Wl[k] = in.W0[k] + CD(1e-9); in.Wr[k] = in.W0[k] - CD(1e-9); }
 
   PointOut<4> o;
@@ -124,17 +140,19 @@ int main() {
 
   // per face segment of a stage: 4 component reconstructions of its own line,
   // 2 Gauss points (tangential + evolution + accumulation)
-  auto seg = [&](const OpCounts& g, const OpCounts& ac) {
+  auto seg = [&](const OpCounts& g, const OpCounts& ac, const OpCounts& tg, long m) {
     OpCounts s;
-    s.add = 4 * recon.add + 2 * (tang.add + g.add + ac.add);
-    s.mul = 4 * recon.mul + 2 * (tang.mul + g.mul + ac.mul);
-    s.div = 4 * recon.div + 2 * (tang.div + g.div + ac.div);
-    s.sqrt_ = 4 * recon.sqrt_ + 2 * (tang.sqrt_ + g.sqrt_ + ac.sqrt_);
-    s.exp_ = 4 * recon.exp_ + 2 * (tang.exp_ + g.exp_ + ac.exp_);
-    s.erfc_ = 4 * recon.erfc_ + 2 * (tang.erfc_ + g.erfc_ + ac.erfc_);
+    s.add = 4 * recon.add + m * (tg.add + g.add + ac.add);
+    s.mul = 4 * recon.mul + m * (tg.mul + g.mul + ac.mul);
+    s.div = 4 * recon.div + m * (tg.div + g.div + ac.div);
+    s.sqrt_ = 4 * recon.sqrt_ + m * (tg.sqrt_ + g.sqrt_ + ac.sqrt_);
+    s.exp_ = 4 * recon.exp_ + m * (tg.exp_ + g.exp_ + ac.exp_);
+    s.erfc_ = 4 * recon.erfc_ + m * (tg.erfc_ + g.erfc_ + ac.erfc_);
     return s;
   };
-  const OpCounts seg1 = seg(gks1, acc1), seg2 = seg(gks2, acc2);
+  const OpCounts seg1 = seg(gks1, acc1, tang, 2), seg2 = seg(gks2, acc2, tang, 2);
+  // four Gauss points per segment with the 7-line stencil (gauss_points = 4)
+  const OpCounts seg1g4 = seg(gks1, acc1, tang7, 4), seg2g4 = seg(gks2, acc2, tang7, 4);
   // cell updates per component (see k_update2): stage 1: L, Lt (2 faces x 2 directions,
   // 4 sub, 2 div, 2 add each) 12 + 2 jump sub + W*, P (3 mul 2 add each ~ 10) +
   // 4 gradients (1 sub 1 add 1 div) 12 -> 36; stage 2: Lt 6 + W (2) + 2 gradients (1 sub 1 mul 1 div 1 add) 8 -> 16
@@ -149,7 +167,10 @@ int main() {
   emit("face_segment_stage1", seg1, true);
   emit("face_segment_stage2", seg2, true);
   emit("cell_update_stage1", up1, true);
-  emit("cell_update_stage2", up2, false);
+  emit("cell_update_stage2", up2, true);
+  emit("tangential_point_7", tang7, true);
+  emit("face_segment_stage1_4pt", seg1g4, true);
+  emit("face_segment_stage2_4pt", seg2g4, false);
   std::printf("  },\n");
   const long cell_step = 2 * flops(seg1) + 2 * flops(seg2) + flops(up1) + flops(up2);
   std::printf("  \"flops_per_cell_step\": %ld,\n", cell_step);
@@ -160,6 +181,14 @@ int main() {
   std::printf("    \"yfaces1\": {\"units\": \"(ny+1)*nx\", \"flops_per_unit\": %ld},\n", flops(seg1));
   std::printf("    \"xfaces2\": {\"units\": \"ny*(nx+1)\", \"flops_per_unit\": %ld},\n", flops(seg2));
   std::printf("    \"yfaces2\": {\"units\": \"(ny+1)*nx\", \"flops_per_unit\": %ld},\n", flops(seg2));
+  std::printf("    \"update1\": {\"units\": \"nx*ny\", \"flops_per_unit\": %ld},\n", flops(up1));
+  std::printf("    \"update2\": {\"units\": \"nx*ny\", \"flops_per_unit\": %ld}\n", flops(up2));
+  std::printf("  },\n");
+  std::printf("  \"per_launch_units_4pt\": {\n");
+  std::printf("    \"xfaces1\": {\"units\": \"ny*(nx+1)\", \"flops_per_unit\": %ld},\n", flops(seg1g4));
+  std::printf("    \"yfaces1\": {\"units\": \"(ny+1)*nx\", \"flops_per_unit\": %ld},\n", flops(seg1g4));
+  std::printf("    \"xfaces2\": {\"units\": \"ny*(nx+1)\", \"flops_per_unit\": %ld},\n", flops(seg2g4));
+  std::printf("    \"yfaces2\": {\"units\": \"(ny+1)*nx\", \"flops_per_unit\": %ld},\n", flops(seg2g4));
   std::printf("    \"update1\": {\"units\": \"nx*ny\", \"flops_per_unit\": %ld},\n", flops(up1));
   std::printf("    \"update2\": {\"units\": \"nx*ny\", \"flops_per_unit\": %ld}\n", flops(up2));
   std::printf("  }\n}\n");
