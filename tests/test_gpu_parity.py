@@ -603,3 +603,23 @@ def test_tam_webb_step_counts():
         total += s.advance_to(t_end)
         assert total == int(steps), (t_end, total)
         assert s.t == t_end
+
+
+def test_four_points_converge_at_order_eight_on_the_gpu_path():
+    """The diagonal wave (dt = 0.5 dx^2, t = 0.5) beyond the oracle pin's
+    sizes: four Gauss points converge at order about 7.5 (L1 9.40e-10 and
+    4.51e-11 at n = 32 and 48), two points at order about 4 (2.78e-8 at 48)."""
+    from paper_2001_01570_amd.cgks import Solver
+
+    def l1(n, gp):
+        p = dataclasses.replace(I.diagonal_wave_2d(n, t_end=0.5, fixed_dt=0.5 * (2.0 / n) ** 2), gauss_points=gp)
+        s = Solver(p)
+        s.advance_to(0.5)
+        st, t, _ = s.get_state()
+        return I.density_errors(st, p.exact(t))[0]
+
+    e4 = [l1(n, 4) for n in (32, 48)]
+    e2 = l1(48, 2)
+    order = math.log(e4[0] / e4[1]) / math.log(48 / 32)
+    say('four points: L1', e4, 'order', order, '; two points at 48:', e2)
+    assert order > 7.0 and e4[1] < 6e-11 and e2 > 1e-8
