@@ -91,9 +91,12 @@ def test_mirror_symmetry_1d():
     assert d.max() < 5e-14
 
 
+@pytest.mark.parametrize('gp', [2, 4])
 @pytest.mark.parametrize('bc', [I.PERIODIC, I.FREE, I.INFLOW])
-def test_free_stream_preserved(bc):
-    p = I.uniform_2d(10, 7, prim=(1.1, 0.3, -0.2, 0.8), bc=(bc,) * 4)
+def test_free_stream_preserved(bc, gp):
+    """A uniform moving state through every open boundary stays uniform (with
+    four Gauss points the stencil reaches the third ghost layer)."""
+    p = dataclasses.replace(I.uniform_2d(10, 7, prim=(1.1, 0.3, -0.2, 0.8), bc=(bc,) * 4), gauss_points=gp)
     o = O.Oracle(p, threads=2)
     for _ in range(3):
         o.step()
@@ -103,8 +106,11 @@ def test_free_stream_preserved(bc):
     assert np.abs(st[4:]).max() < 1e-13
 
 
-def test_free_stream_preserved_with_walls():
-    p = I.uniform_2d(8, 9, prim=(0.9, 0.0, 0.0, 1.3), bc=(I.WALL,) * 4)
+@pytest.mark.parametrize('gp,n', [(2, 8), (4, 8), (4, 3)])
+def test_free_stream_preserved_with_walls(gp, n):
+    """A fluid at rest between walls stays at rest, also with the 7-line stencil
+    mirrored through three ghost layers on a grid 3 cells across."""
+    p = dataclasses.replace(I.uniform_2d(n, 9, prim=(0.9, 0.0, 0.0, 1.3), bc=(I.WALL,) * 4), gauss_points=gp)
     o = O.Oracle(p, threads=2)
     for _ in range(3):
         o.step()
