@@ -237,9 +237,11 @@ def test_2d_multi_step(name, mk):
     assert err.max() < TOL, err
 
 
-def test_2d_wall_and_inflow_free_stream():
+@pytest.mark.parametrize('gp', [2, 4])
+def test_2d_wall_and_inflow_free_stream(gp):
     for bc in ((I.WALL,) * 4, (I.INFLOW, I.FREE, I.WALL, I.INFLOW)):
         p = I.uniform_2d(19, 13, prim=(0.9, 0.0, 0.0, 1.3) if bc[0] == I.WALL else (0.9, 0.4, 0.0, 1.3), bc=bc)
+        p = dataclasses.replace(p, gauss_points=gp)
         s = solver(p)
         for _ in range(3):
             s.step()
