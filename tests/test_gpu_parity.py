@@ -357,6 +357,18 @@ def test_config3_full_size_single_step_sampled():
     assert (np.abs(tot - tot0) / np.maximum(scale, 1.0)).max() < 1e-14
 
 
+def test_config3_full_size_single_step_sampled_four_points():
+    """The 1024^2 pulse with four Gauss points per face (the eighth-order 2D
+    assembly): one GPU step at full size, windows recomputed by the oracle
+    (6-cell margins for the 7-segment stencil)."""
+    p = dataclasses.replace(I.acoustic_pulse_2d(1024, seed=0), gauss_points=4)
+    cx, cy = p.meta['centre']
+    ic, jc = int((cx + 1.0) / p.dx), int((cy + 1.0) / p.dy)
+    wins = [(ic - 4, jc - 4), (0, 0), (1016, 1016), (500, 3)]
+    worst, _ = _sampled(p, [(i % 1024, j % 1024) for i, j in wins])
+    say('config3 four points, worst field error', worst)
+
+
 def test_config3_full_size_ten_steps_sampled():
     """Ten GPU steps at full size with the bench's kernels and tile shapes
     (stepped one by one to record each step size; the bench's graph replays

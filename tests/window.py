@@ -1,8 +1,9 @@
 """Oracle steps on a window of a large grid, for sampled parity at full size.
 
-A step reads cells within 4 of a cell (2 per stage), so a window with a 4k-cell
-margin on every artificial side reproduces k full-grid steps exactly on its
-core.  Sides where the window meets the real domain boundary keep the real
+A step reads cells within 4 of a cell (2 per stage; 6, 3 per stage, with four
+Gauss points and their 7-segment tangential stencil), so a window with a
+4k-cell (6k-cell) margin on every artificial side reproduces k full-grid steps
+exactly on its core.  Sides where the window meets the real domain boundary keep the real
 boundary condition; artificial sides use free-flow ghosts (never compared)."""
 import numpy as np
 
@@ -32,7 +33,7 @@ def window_step(prob, fields, i0, j0, size, dt, ulp_seed=None):
     conditioning of the FP64 step on that window."""
     bc = list(prob.bc)
     dts = list(dt) if np.ndim(dt) else [dt]
-    h = H * len(dts)
+    h = (6 if prob.gauss_points == 4 else H) * len(dts)
     ix, xlo, xhi, cx0, cx1 = _axis(i0, size, prob.nx, bc[0] == I.PERIODIC, bc[0], bc[1], h)
     iy, ylo, yhi, cy0, cy1 = _axis(j0, size, prob.ny, bc[2] == I.PERIODIC, bc[2], bc[3], h)
     patch = np.ascontiguousarray(fields[:, iy][:, :, ix])
@@ -42,7 +43,8 @@ def window_step(prob, fields, i0, j0, size, dt, ulp_seed=None):
     dx, dy = prob.dx, prob.dy
     p = I.Problem('window', 2, len(ix), len(iy), 0.0, dx * len(ix), 0.0, dy * len(iy), patch,
                   bc=(xlo, xhi, ylo, yhi), inflow_prim=prob.inflow_prim, gamma=prob.gamma, cfl=prob.cfl,
-                  weno_eps=prob.weno_eps, tau_eps=prob.tau_eps, tau_C=prob.tau_C, mu=prob.mu)
+                  weno_eps=prob.weno_eps, tau_eps=prob.tau_eps, tau_C=prob.tau_C, mu=prob.mu,
+                  gauss_points=prob.gauss_points)
     o = O.Oracle(p, threads=4)
     for d in dts:
         o.step(d)
