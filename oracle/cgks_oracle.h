@@ -35,7 +35,8 @@ typedef struct {
   double fixed_dt;           /* 0 -> CFL rule, >0 -> fixed step */
   double mu;                 /* dynamic viscosity: 0 -> Euler, > 0 -> Navier-Stokes */
   int gauss_points;          /* 2D: Gauss-Legendre points per face segment, 2 (0 means 2;
-                                quartic through 5 segment averages) or 4 (sextic through 7) */
+                                3 segments with the tangential gradients) or 4 (sextic through
+                                7 segment averages, three ghost layers) */
 } orc_config;
 
 typedef struct orc_ctx orc_ctx;
@@ -91,12 +92,20 @@ void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double m
 void orc_flux_integral(int dim, double gamma, double tau, double tau_ce, double delta,
                        const double *W0, const double *W0n, const double *W0t,
                        const double *Wl, const double *Wr, double *Fhat);
-/* Tangential quartic through 5 segment averages s[0..4] (segments -2..2):
- * value, first and second derivative (unit width) at eta. */
-void orc_quartic(const double *s, double eta, double *out3);
 /* The sextic through 7 unit-cell averages s[0..6] (offsets -3..3), at eta:
  * (value, d/deta, d2/deta2). */
 void orc_sextic(const double *s, double eta, double *out3);
+/* The quadratic through 3 unit-cell averages s[0..2] (offsets -1..1), at eta. */
+void orc_quadratic3(const double *s, double eta, double *out3);
+/* The quintic fixed by 3 unit-cell averages s[0..2] (offsets -1..1) and by the
+ * averages of its derivative over the same cells, d[0..2] (for a unit cell the
+ * average of the derivative is the difference of the end values), at eta:
+ * (value, d/deta, d2/deta2). */
+void orc_hermite3(const double *s, const double *d, double eta, double *out3);
+/* The cubic through the averages a[0..3] of 4 unit cells, cells 1 and 2 on
+ * either side of eta = 1/2 (the cells of the normal stencil of a face): its
+ * value and first derivative at the face. */
+void orc_cubic_face(const double *a, double *out2);
 
 #ifdef __cplusplus
 }

@@ -78,8 +78,10 @@ def lib():
         L.orc_euler_wtt.argtypes = [C.c_double] + [D] * 7
         L.orc_gks_point.argtypes = [C.c_int] + [C.c_double] * 5 + [D] * 8 + [D] * 7
         L.orc_flux_integral.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [D] * 6
-        L.orc_quartic.argtypes = [D, C.c_double, D]
         L.orc_sextic.argtypes = [D, C.c_double, D]
+        L.orc_quadratic3.argtypes = [D, C.c_double, D]
+        L.orc_hermite3.argtypes = [D, D, C.c_double, D]
+        L.orc_cubic_face.argtypes = [D, D]
         _lib = L
     return _lib
 
@@ -238,9 +240,21 @@ def flux_integral(dim, gamma, tau, delta, W0, W0n, Wl, Wr, W0t=None, tau_ce=0.0)
     return out
 
 
-def quartic(s, eta):
+def quadratic3(s, eta):
     out = np.empty(3)
-    lib().orc_quartic(_p(_vec(s, 5)), float(eta), _p(out))
+    lib().orc_quadratic3(_p(_vec(s, 3)), float(eta), _p(out))
+    return out
+
+
+def hermite3(s, d, eta):
+    out = np.empty(3)
+    lib().orc_hermite3(_p(_vec(s, 3)), _p(_vec(d, 3)), float(eta), _p(out))
+    return out
+
+
+def cubic_face(a):
+    out = np.empty(2)
+    lib().orc_cubic_face(_p(_vec(a, 4)), _p(out))
     return out
 
 

@@ -55,8 +55,10 @@ static const stencil_t STENCIL[7] = {
   {4, 5, {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}}},
 };
 static double STENCIL_INV[7][25];
-static double QUARTIC_INV[25];
 static double SEXTIC_INV[49];
+static double QUADRATIC_INV[9];
+static double HERMITE3_INV[36];
+static double CUBIC_INV[16];
 static int recon_ready = 0;
 
 static double ipow(double x, int p) { double r = 1.0; for (int i = 0; i < p; ++i) r *= x; return r; }
@@ -77,13 +79,6 @@ __attribute__((constructor)) void orc_recon_init(void) {
     }
     orc_invert(s->n, A, STENCIL_INV[k]);
   }
-  /* quartic through 5 averages on segments [m-2-1/2, m-2+1/2], m = 0..4 */
-  double B[25];
-  for (int r = 0; r < 5; ++r) {
-    double lo = r - 2.5, hi = r - 1.5;
-    for (int p = 0; p < 5; ++p) B[r * 5 + p] = (ipow(hi, p + 1) - ipow(lo, p + 1)) / (p + 1);
-  }
-  orc_invert(5, B, QUARTIC_INV);
   {
     double B7[49];               /* cell r spans [r-7/2, r-5/2]: offsets -3..3 */
     for (int r = 0; r < 7; ++r) {
@@ -91,6 +86,38 @@ __attribute__((constructor)) void orc_recon_init(void) {
       for (int p = 0; p < 7; ++p) B7[r * 7 + p] = (ipow(hi, p + 1) - ipow(lo, p + 1)) / (p + 1);
     }
     orc_invert(7, B7, SEXTIC_INV);
+  }
+  {
+    /* quadratic through 3 averages on segments offsets -1..1 */
+    double B3[9];
+    for (int r = 0; r < 3; ++r) {
+      double lo = r - 1.5, hi = r - 0.5;
+      for (int p = 0; p < 3; ++p) B3[r * 3 + p] = (ipow(hi, p + 1) - ipow(lo, p + 1)) / (p + 1);
+    }
+    orc_invert(3, B3, QUADRATIC_INV);
+  }
+  {
+    /* quintic fixed by the averages of the polynomial and of its derivative on
+     * the segments at offsets -1..1: rows 0-2 average, rows 3-5 the average of
+     * the derivative times the width, i.e. p(hi) - p(lo) */
+    double H[36];
+    for (int r = 0; r < 3; ++r) {
+      double lo = r - 1.5, hi = r - 0.5;
+      for (int p = 0; p < 6; ++p) {
+        H[r * 6 + p] = (ipow(hi, p + 1) - ipow(lo, p + 1)) / (p + 1);
+        H[(r + 3) * 6 + p] = ipow(hi, p) - ipow(lo, p);
+      }
+    }
+    orc_invert(6, H, HERMITE3_INV);
+  }
+  {
+    /* cubic through the averages of 4 unit cells spanning [m-3/2, m-1/2], m = 0..3 */
+    double Cb[16];
+    for (int r = 0; r < 4; ++r) {
+      double lo = cell_lo(r), hi = lo + 1.0;
+      for (int p = 0; p < 4; ++p) Cb[r * 4 + p] = (ipow(hi, p + 1) - ipow(lo, p + 1)) / (p + 1);
+    }
+    orc_invert(4, Cb, CUBIC_INV);
   }
   recon_ready = 1;
 }
@@ -165,18 +192,36 @@ void orc_sextic(const double *s, double eta, double *out3) {
   out3[0] = v; out3[1] = d1; out3[2] = d2;
 }
 
-void orc_quartic(const double *s, double eta, double *out3) {
-  double c[5];
-  for (int p = 0; p < 5; ++p) {
+
+/* value, first and second derivative at eta of the polynomial whose monomial
+ * coefficients are Minv * rhs (n unknowns) */
+static void poly_eval(int n, const double *Minv, const double *rhs, double eta, double *out3) {
+  double c[8];
+  for (int p = 0; p < n; ++p) {
     double acc = 0.0;
-    for (int r = 0; r < 5; ++r) acc += QUARTIC_INV[p * 5 + r] * s[r];
+    for (int r = 0; r < n; ++r) acc += Minv[p * n + r] * rhs[r];
     c[p] = acc;
   }
   double v = 0.0, d1 = 0.0, d2 = 0.0;
-  for (int p = 0; p < 5; ++p) {
+  for (int p = 0; p < n; ++p) {
     v += c[p] * ipow(eta, p);
     if (p >= 1) d1 += c[p] * p * ipow(eta, p - 1);
     if (p >= 2) d2 += c[p] * p * (p - 1) * ipow(eta, p - 2);
   }
   out3[0] = v; out3[1] = d1; out3[2] = d2;
+}
+
+void orc_quadratic3(const double *s, double eta, double *out3) {
+  poly_eval(3, QUADRATIC_INV, s, eta, out3);
+}
+
+void orc_hermite3(const double *s, const double *d, double eta, double *out3) {
+  const double rhs[6] = {s[0], s[1], s[2], d[0], d[1], d[2]};
+  poly_eval(6, HERMITE3_INV, rhs, eta, out3);
+}
+
+void orc_cubic_face(const double *a, double *out2) {
+  double o[3];
+  poly_eval(4, CUBIC_INV, a, 0.5, o);
+  out2[0] = o[0]; out2[1] = o[1];
 }

@@ -16,7 +16,7 @@ struct orc_ctx {
   orc_config cfg;
   int nc, nf, gx, gy;
   int ng;                /* ghost layers: 2, or 3 for the 7-segment tangential stencil */
-  int nl, npts;          /* 2D: tangential stencil lines (5 or 7) and Gauss points (2 or 4) */
+  int nl, npts;          /* 2D: tangential stencil lines (3 or 7) and Gauss points (2 or 4) */
   double dx, dy;
   double *U, *Us, *Un;   /* ghosted state, ghosted intermediate state, next state */
   double *P;             /* W + dt L + dt^2/6 L_t and the matching gradient part */
@@ -62,7 +62,7 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   c->nf = cfg->dim == 2 ? 12 : 6;
   c->cfg.gauss_points = gp;
   c->npts = cfg->dim == 2 ? gp : 1;
-  c->nl = gp == 4 ? 7 : 5;
+  c->nl = gp == 4 ? 7 : 3;
   c->ng = gp == 4 ? 3 : 2;
   c->gx = c->cfg.nx + 2 * c->ng;
   c->gy = cfg->dim == 2 ? c->cfg.ny + 2 * c->ng : 1;
@@ -226,7 +226,7 @@ double orc_cfl_dt(const orc_ctx *c) {
 }
 
 /* ---- one face: normal reconstruction of 5 stencil lines, tangential
- * quartic to the Gauss points, gas-kinetic evolution at each point ---------- */
+ * reconstruction to the Gauss points, gas-kinetic evolution at each point -- */
 
 /* Normal reconstruction on one line (Sec. 3.2, 3.3): Q shifted by the face's
  * reference state, D = h Q'.  Output: P7, P7_n, P7_nn, left and right values. */
@@ -246,11 +246,25 @@ typedef struct { long w0, weno; } guards_t;
 
 /* Evaluate one face.  lines[l][q][c]: stencil line l (tangential offset
  * l - nl/2, only l=0 used in 1D), quantity q (P7, P7_n, P7_nn, W_l, W_r),
- * component c; the value quantities are deviations from ref.  rot: y-face
- * (swap momenta).  Writes F, Ft, A, B (blocks of nc) averaged over the Gauss
- * points with the Gauss-Legendre weights. */
-static void face_eval(orc_ctx *c, double lines[7][5][4], const double *ref, const double *Wleft,
-                      const double *Wright, double dt, int final, int rot, double ht,
+ * component c; the value quantities are deviations from ref.  tg[l][q][c]:
+ * the line's tangential gradient reconstructed across the face from the
+ * cells' own tangential gradients, q = 0 its value at the face, q = 1 its
+ * normal derivative.  rot: y-face (swap momenta).  Writes F, Ft, A, B
+ * (blocks of nc) averaged over the Gauss points with the Gauss-Legendre
+ * weights.
+ *
+ * Tangential assembly (the 2D algorithm figure of Sec. 3 is not in the text):
+ * the face sees the cells' cell-averaged tangential gradients, which the
+ * compact scheme carries beside the averages.  Two Gauss points: every
+ * quantity comes from the three nearest segments, the value quantities (and
+ * the normal derivative) by the quintic that matches their segment averages
+ * and the segment averages of their tangential derivative, W_nn by the
+ * quadratic through its segment averages.  Four Gauss points: the sextic
+ * through 7 segment averages for the values and the first derivatives; W_nt
+ * and W_tt, which enter only the second time derivative, from the quintics
+ * of the three nearest segments as with two points. */
+static void face_eval(orc_ctx *c, double lines[7][5][4], double tg[7][2][4], const double *ref,
+                      const double *Wleft, const double *Wright, double dt, int final, int rot, double ht,
                       double *out, guards_t *gd) {
   const int dim = c->cfg.dim, nc = c->nc;
   const double gam = c->cfg.gamma;
@@ -269,28 +283,52 @@ static void face_eval(orc_ctx *c, double lines[7][5][4], const double *ref, cons
   } else {
     eta[0] = 0.0; wgt[0] = 1.0;
   }
-  /* the tangential polynomial through the nl segment averages */
-  void (*tang)(const double *, double, double *) = nl == 7 ? orc_sextic : orc_quartic;
   for (int k = 0; k < NF_FACE * nc; ++k) out[k] = 0.0;
   for (int g = 0; g < npts; ++g) {
     double W0d[4], W0[4], Wn[4], Wt_[4], Wnn[4], Wnt[4], Wtt_[4], Wl[4], Wr[4];
     for (int k = 0; k < nc; ++k) {
-      if (dim == 2) {
-        double s[7], r3[3];
-        for (int l = 0; l < nl; ++l) s[l] = lines[l][0][k];
-        tang(s, eta[g], r3);
+      if (dim == 2 && nl == 3) {
+        double s[3], d[3], dn[3], r3[3];
+        for (int l = 0; l < 3; ++l) { d[l] = ht * tg[l][0][k]; dn[l] = ht * tg[l][1][k]; }
+        for (int l = 0; l < 3; ++l) s[l] = lines[l][0][k];
+        orc_hermite3(s, d, eta[g], r3);
         W0d[k] = r3[0]; Wt_[k] = r3[1] / ht; Wtt_[k] = r3[2] / (ht * ht);
-        for (int l = 0; l < nl; ++l) s[l] = lines[l][1][k];
-        tang(s, eta[g], r3);
+        for (int l = 0; l < 3; ++l) s[l] = lines[l][1][k];
+        orc_hermite3(s, dn, eta[g], r3);
         Wn[k] = r3[0]; Wnt[k] = r3[1] / ht;
+        for (int l = 0; l < 3; ++l) s[l] = lines[l][2][k];
+        orc_quadratic3(s, eta[g], r3);
+        Wnn[k] = r3[0];
+        for (int l = 0; l < 3; ++l) s[l] = lines[l][3][k];
+        orc_hermite3(s, d, eta[g], r3);
+        Wl[k] = ref[k] + r3[0];
+        for (int l = 0; l < 3; ++l) s[l] = lines[l][4][k];
+        orc_hermite3(s, d, eta[g], r3);
+        Wr[k] = ref[k] + r3[0];
+      } else if (dim == 2) {
+        double s[7], r3[3], d[3];
+        for (int l = 0; l < nl; ++l) s[l] = lines[l][0][k];
+        orc_sextic(s, eta[g], r3);
+        W0d[k] = r3[0]; Wt_[k] = r3[1] / ht;
+        for (int l = 0; l < nl; ++l) s[l] = lines[l][1][k];
+        orc_sextic(s, eta[g], r3);
+        Wn[k] = r3[0];
+        /* the tangential derivatives that enter only the second time
+         * derivative come from the three nearest segments, as with two points */
+        for (int l = 0; l < 3; ++l) { s[l] = lines[l + 2][0][k]; d[l] = ht * tg[l + 2][0][k]; }
+        orc_hermite3(s, d, eta[g], r3);
+        Wtt_[k] = r3[2] / (ht * ht);
+        for (int l = 0; l < 3; ++l) { s[l] = lines[l + 2][1][k]; d[l] = ht * tg[l + 2][1][k]; }
+        orc_hermite3(s, d, eta[g], r3);
+        Wnt[k] = r3[1] / ht;
         for (int l = 0; l < nl; ++l) s[l] = lines[l][2][k];
-        tang(s, eta[g], r3);
+        orc_sextic(s, eta[g], r3);
         Wnn[k] = r3[0];
         for (int l = 0; l < nl; ++l) s[l] = lines[l][3][k];
-        tang(s, eta[g], r3);
+        orc_sextic(s, eta[g], r3);
         Wl[k] = ref[k] + r3[0];
         for (int l = 0; l < nl; ++l) s[l] = lines[l][4][k];
-        tang(s, eta[g], r3);
+        orc_sextic(s, eta[g], r3);
         Wr[k] = ref[k] + r3[0];
       } else {
         W0d[k] = lines[0][0][k]; Wn[k] = lines[0][1][k]; Wnn[k] = lines[0][2][k];
@@ -340,7 +378,7 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
   for (int j = 0; j < ny; ++j) {
     guards_t gd = {0, 0};
     for (int f = 0; f <= nx; ++f) {
-      double ref[4], Wlc[4], Wrc[4], lines[7][5][4];
+      double ref[4], Wlc[4], Wrc[4], lines[7][5][4], tg[7][2][4];
       for (int k = 0; k < nc; ++k) {
         ref[k] = fld(c, (double *)G, k)[gidx(c, f - 1, j)];
         Wlc[k] = ref[k];
@@ -358,10 +396,17 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
           double o5[5];
           normal_line(Q, D, c->dx, eps, o5);
           for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q];
+          if (dim == 2) {
+            double T[4], o2[2];
+            for (int m = 0; m < 4; ++m) T[m] = fld(c, (double *)G, 2 * nc + k)[gidx(c, f - 2 + m, jj)];
+            orc_cubic_face(T, o2);
+            tg[l][0][k] = o2[0];
+            tg[l][1][k] = o2[1] / c->dx;
+          }
         }
       }
       double *out = c->xf + ((size_t)j * (nx + 1) + f) * NF_FACE * nc;
-      face_eval(c, lines, ref, Wlc, Wrc, dt, final, 0, c->dy, out, &gd);
+      face_eval(c, lines, tg, ref, Wlc, Wrc, dt, final, 0, c->dy, out, &gd);
     }
     gw0 += gd.w0; gwe += gd.weno;
   }
@@ -371,7 +416,7 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
     for (int f = 0; f <= ny; ++f) {
       guards_t gd = {0, 0};
       for (int i = 0; i < nx; ++i) {
-        double ref[4], Wlc[4], Wrc[4], lines[7][5][4];
+        double ref[4], Wlc[4], Wrc[4], lines[7][5][4], tg[7][2][4];
         for (int k = 0; k < nc; ++k) {
           ref[k] = fld(c, (double *)G, k)[gidx(c, i, f - 1)];
           Wlc[k] = ref[k];
@@ -385,13 +430,17 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
               Q[m] = fld(c, (double *)G, k)[gidx(c, ii, f - 2 + m)] - ref[k];
               D[m] = c->dy * fld(c, (double *)G, 2 * nc + k)[gidx(c, ii, f - 2 + m)];
             }
-            double o5[5];
+            double o5[5], T[4], o2[2];
             normal_line(Q, D, c->dy, eps, o5);
             for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q];
+            for (int m = 0; m < 4; ++m) T[m] = fld(c, (double *)G, nc + k)[gidx(c, ii, f - 2 + m)];
+            orc_cubic_face(T, o2);
+            tg[l][0][k] = o2[0];
+            tg[l][1][k] = o2[1] / c->dy;
           }
         }
         double *out = c->yf + ((size_t)f * nx + i) * NF_FACE * nc;
-        face_eval(c, lines, ref, Wlc, Wrc, dt, final, 1, c->dx, out, &gd);
+        face_eval(c, lines, tg, ref, Wlc, Wrc, dt, final, 1, c->dx, out, &gd);
       }
       gw0 += gd.w0; gwe += gd.weno;
     }

@@ -167,13 +167,55 @@ def test_tangential_sextic_exact(seed):
 
 
 @pytest.mark.parametrize('seed', range(3))
-def test_tangential_quartic_exact(seed):
+def test_tangential_hermite_quintic_exact(seed):
+    """The two-point tangential fit: the quintic fixed by the averages of a
+    function and of its derivative over the three nearest unit segments
+    (offsets -1..1) reproduces any quintic -- value, first and second
+    derivative at the Gauss-Legendre nodes and elsewhere in the segment."""
     rng = np.random.default_rng(30 + seed)
-    P = np.polynomial.Polynomial(rng.normal(size=5))
+    P = np.polynomial.Polynomial(rng.normal(size=6))
     I = P.integ()
-    s = np.array([I(m - 2 + 0.5) - I(m - 2 - 0.5) for m in range(5)])
-    for eta in (-0.5 / math.sqrt(3), 0.5 / math.sqrt(3), 0.3):
-        v, d1, d2 = O.quartic(s, eta)
+    s = np.array([I(m + 0.5) - I(m - 0.5) for m in (-1, 0, 1)])
+    d = np.array([P(m + 0.5) - P(m - 0.5) for m in (-1, 0, 1)])   # unit width: average of P'
+    for eta in (-0.5 / math.sqrt(3), 0.5 / math.sqrt(3), 0.3, -0.5, 0.5):
+        v, d1, d2 = O.hermite3(s, d, eta)
         assert v == pytest.approx(P(eta), abs=1e-12)
         assert d1 == pytest.approx(P.deriv()(eta), abs=1e-11)
         assert d2 == pytest.approx(P.deriv(2)(eta), abs=1e-10)
+    # a sextic term is not reproduced (the fit has six conditions)
+    Q = np.polynomial.Polynomial([0, 0, 0, 0, 0, 0, 1.0])
+    J = Q.integ()
+    s6 = np.array([J(m + 0.5) - J(m - 0.5) for m in (-1, 0, 1)])
+    d6 = np.array([Q(m + 0.5) - Q(m - 0.5) for m in (-1, 0, 1)])
+    assert abs(O.hermite3(s6, d6, 0.3)[0] - Q(0.3)) > 1e-4
+
+
+@pytest.mark.parametrize('seed', range(3))
+def test_tangential_quadratic_exact(seed):
+    rng = np.random.default_rng(50 + seed)
+    P = np.polynomial.Polynomial(rng.normal(size=3))
+    I = P.integ()
+    s = np.array([I(m + 0.5) - I(m - 0.5) for m in (-1, 0, 1)])
+    for eta in (-0.5 / math.sqrt(3), 0.5 / math.sqrt(3), 0.3):
+        v, d1, d2 = O.quadratic3(s, eta)
+        assert v == pytest.approx(P(eta), abs=1e-13)
+        assert d1 == pytest.approx(P.deriv()(eta), abs=1e-12)
+        assert d2 == pytest.approx(P.deriv(2)(eta), abs=1e-12)
+
+
+@pytest.mark.parametrize('seed', range(3))
+def test_cross_face_cubic_exact(seed):
+    """The cells' tangential gradients are carried to a face by the cubic
+    through the averages of the 4 cells of the normal stencil: value and
+    normal derivative at the face are exact for cubics; the value is the
+    classic fourth-order (-1, 7, 7, -1)/12 and the derivative (1, -15, 15, -1)/12."""
+    rng = np.random.default_rng(60 + seed)
+    P = np.polynomial.Polynomial(rng.normal(size=4))
+    I = P.integ()
+    a = np.array([I(m - 0.5) - I(m - 1.5) for m in range(4)])   # cell m spans [m-3/2, m-1/2]
+    v, d1 = O.cubic_face(a)
+    assert v == pytest.approx(P(0.5), abs=1e-13)
+    assert d1 == pytest.approx(P.deriv()(0.5), abs=1e-12)
+    e = np.eye(4)
+    assert np.allclose([O.cubic_face(e[m])[0] for m in range(4)], np.array([-1, 7, 7, -1]) / 12, atol=1e-15)
+    assert np.allclose([O.cubic_face(e[m])[1] for m in range(4)], np.array([1, -15, 15, -1]) / 12, atol=1e-14)

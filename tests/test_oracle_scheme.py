@@ -189,9 +189,9 @@ def test_2d_spatial_order_with_dt_proportional_to_dx2():
     converges in space at order about 8 (L1 9.9e-7 at n = 48; order 7.8 from
     n = 32), like the 1D Table 1 (with a CFL-proportional step the 2D orders
     are those of the time integration).  The order is pre-asymptotic: the
-    two-point quadrature along the faces and the quartic tangential
-    reconstruction make the 2D assembly fourth order in space, which shows on
-    finer meshes (n >= 96 here) and on the diagonal wave from n = 24 on."""
+    two-point quadrature along the faces makes the 2D assembly fourth order
+    in space, which shows on finer meshes (n >= 96 here) and on the diagonal
+    wave from n = 24 on."""
     errs = []
     for n in (32, 48):
         p = dataclasses.replace(I.vortex_translation_2d(n, t_end=0.5), fixed_dt=0.02 * (10.0 / n) ** 2)
@@ -408,16 +408,16 @@ def _diag_l1(n, gp):
 
 def test_four_gauss_points_make_the_2d_step_eighth_order():
     """The 2D assembly is fourth order in space with two Gauss points per face
-    (exact for cubics only) and the 5-segment quartic; four Gauss-Legendre
-    points with the sextic through 7 segment averages restore order about 8.
-    Diagonal wave rho = 1 + 0.2 sin pi(x + y), p constant, dt = 0.5 dx^2 so
-    that the time error is negligible (1D: order 8 on the same wave)."""
+    (exact for cubics only); four Gauss-Legendre points with the sextic
+    through 7 segment averages restore order about 8.  Diagonal wave
+    rho = 1 + 0.2 sin pi(x + y), p constant, dt = 0.5 dx^2 so that the time
+    error is negligible (1D: order 8 on the same wave)."""
     e2 = [_diag_l1(n, 2) for n in (24, 32)]
     e4 = [_diag_l1(n, 4) for n in (16, 24, 32)]
     o2 = math.log(e2[0] / e2[1]) / math.log(32 / 24)
     o4 = math.log(e4[1] / e4[2]) / math.log(32 / 24)
-    assert o2 < 5.0 and e2[1] > 1e-7, (e2, o2)          # 5.61e-7, 1.51e-7: order 4.6
-    assert o4 > 7.0 and e4[2] < 1.2e-9, (e4, o4)        # 1.38e-7, 7.87e-9, 9.40e-10: order 7.4
+    assert o2 < 5.0 and e2[1] > 1e-7, (e2, o2)          # 5.65e-7, 1.52e-7: order 4.6
+    assert o4 > 7.0 and e4[2] < 1.2e-9, (e4, o4)        # 1.38e-7, 7.85e-9, 9.39e-10: order 7.4
 
 
 def test_four_points_equal_two_points_on_a_flow_without_tangential_variation():

@@ -1,23 +1,90 @@
-"""The 2D step on a fluid at rest at CFL 0.15: inputs 1e-10 apart (relative,
-on the gradients) stay apart by no more than a small multiple of that after
-300 steps (no growing mode in this regime; at CFL 0.3 the step as read grows
-an odd-even mode of the gradient fields, documented with its measurements)."""
+"""Linear stability of the 2D step at the CFL numbers of Sec. 4.
+
+Sec. 4 runs every test at CFL >= 0.3 (0.5 for inviscid flow in Sec. 3), so a
+small perturbation of a uniform state must not grow over a run of a few
+hundred steps at those CFL numbers.  These pins fix the 2D assembly against
+that requirement: with the x faces blind to the cells' y-gradients (the
+reading this oracle used before), the linearised step about rest has spectral
+radius 1.067 at CFL 0.3 -- a checkerboard of d(rhoU)/dx + d(rhoV)/dy fed by
+the cell averages through both directions -- and 500 steps amplify rounding
+by ~1e14.  With the cells' tangential gradients entering the faces the
+radius is 1 + O(dt^2) (9.3e-5 at CFL 0.3 on the 8 x 8 grid below).
+"""
+import dataclasses
+
 import numpy as np
+import pytest
 
 from oracle import oracle as O
 from paper_2001_01570_amd import inputs as I
 
+GAMMA = 1.4
 
-def test_rest_state_pulse_is_stable_at_cfl_0_15():
-    p = I.acoustic_pulse_2d(32, seed=0, amp=1e-3, half_width=0.2, cfl=0.15)
-    rng = np.random.default_rng(1)
-    f2 = p.fields.copy()
-    f2[4:] *= 1 + 1e-10 * rng.standard_normal(f2[4:].shape)
-    q = I.Problem(p.name, 2, p.nx, p.ny, p.x0, p.x1, p.y0, p.y1, f2, bc=p.bc, cfl=p.cfl)
-    a, b = O.Oracle(p, threads=8), O.Oracle(q, threads=8)
-    d0 = np.abs(a.state - b.state).max()
-    for _ in range(300):
+
+def _uniform(n, U, cfl, gp):
+    base = I.uniform_2d(n, n, prim=(1.0, U, 0.0, 1.0 / GAMMA))
+    return dataclasses.replace(base, cfl=cfl, gauss_points=gp)
+
+
+def _perturbed(p, amp, seed):
+    """uniform state plus noise: amp on the averages, amp/dx on the gradients
+    (the scale of a gradient of noise of size amp), so that the difference of
+    two runs measures growth and not the first step's re-scaling"""
+    rng = np.random.default_rng(seed)
+    dx = (p.x1 - p.x0) / p.nx
+    f = p.fields.copy()
+    f[:4] += amp * rng.standard_normal(f[:4].shape)
+    f[4:] += amp / dx * rng.standard_normal(f[4:].shape)
+    return dataclasses.replace(p, fields=f)
+
+
+def _growth(p, steps, amp=1e-8, seed=1):
+    a = O.Oracle(p, threads=8)
+    b = O.Oracle(_perturbed(p, amp, seed), threads=8)
+    d = []
+    for _ in range(steps):
         dt = a.step()
         b.step(dt)
-    d = np.abs(a.state - b.state).max()
-    assert d < 20 * d0, (d0, d)
+        d.append(np.abs(a.state - b.state).max())
+    return np.array(d)
+
+
+@pytest.mark.parametrize('gp,U', [(2, 0.0), (4, 0.0), (2, 0.5)])
+def test_perturbation_of_a_uniform_state_stays_bounded_over_500_steps_at_cfl_0_3(gp, U):
+    """16 x 16 periodic, fluid at rest (and moving at Mach 0.5), noise of
+    1e-8: after the first steps have mapped the noise onto the scheme's own
+    modes, the difference of the two runs grows by at most 3x over the next
+    400 steps (measured: at most 1.29x, 1.31x and 1.38x, ending at 1.15x,
+    1.19x and 0.83x)."""
+    d = _growth(_uniform(16, U, 0.3, gp), 500)
+    ref = d[99]
+    assert np.isfinite(d).all()
+    assert d[100:].max() < 3.0 * ref, (ref, d[100:].max(), d[-1])
+
+
+def _jacobian_radius(p, eps=1e-7):
+    o = O.Oracle(p, threads=1)
+    dt = o.cfl_dt()
+    f0 = p.fields.copy()
+    o.step(dt)
+    s0 = o.state.reshape(-1)
+    J = np.empty((f0.size, f0.size))
+    flat = f0.reshape(-1)
+    for c in range(f0.size):
+        f = flat.copy()
+        f[c] += eps
+        o.set_state(f.reshape(f0.shape))
+        o.step(dt)
+        J[:, c] = (o.state.reshape(-1) - s0) / eps
+    return np.abs(np.linalg.eigvals(J)).max()
+
+
+@pytest.mark.parametrize('cfl,bound', [(0.15, 1.0 + 4e-4), (0.3, 1.0 + 2e-4), (0.5, 1.0 + 1e-6)])
+def test_linearised_step_about_rest_has_no_growing_mode_of_order_dt(cfl, bound):
+    """Spectral radius of the step's Jacobian (central differences about the
+    fluid at rest, 8 x 8 periodic, every wave number pi m/4): measured
+    1 + 2.3e-4, 1 + 9.3e-5 and 1 + 5e-9 at CFL 0.15, 0.3 and 0.5 -- growth
+    of order dt^2 per step, from the second time derivative of the interface
+    state, which a run of a few thousand steps does not see."""
+    r = _jacobian_radius(_uniform(8, 0.0, cfl, 2))
+    assert r < bound, r
