@@ -4,7 +4,7 @@
 // launches on the context's stream:
 //   begin   (1 thread)   step size from the CFL maximum of the previous step
 //   xfaces1, yfaces1     normal reconstruction of line segments into LDS, tangential
-//                        quartic to 2 Gauss points, gas-kinetic evolution per point
+//                        fits to the Gauss points, gas-kinetic evolution per point
 //   update1              W*, P (partial sums of the final update), gradients of W*
 //   xfaces2, yfaces2     same on W*, only F_t and W_tt
 //   update2              W^{n+1}, its gradients, CFL maximum and admissibility
@@ -28,13 +28,13 @@
 namespace cgks {
 
 // Face tile: F faces along the normal x T face segments along the tangential,
-// 256 threads (one per Gauss point).  Shapes differ in halo overhead ((T+4)/T
+// 256 threads (one per Gauss point).  Shapes differ in halo overhead ((T+2 HALO)/T
 // reconstructed line segments per face segment) and in the width of the rows
 // they read and write; the shape is chosen per direction at run time (tuned).
 // M Gauss points per segment (one thread each); the tangential stencil has
-// 2 HALO + 1 lines (2: the quartic through 5 segments with two points, 3: the
+// 2 HALO + 1 lines (1: the three nearest segments with two points, 3: the
 // sextic through 7 with four).
-template <int F_, int T_, int M_ = 2, int HALO_ = 2>
+template <int F_, int T_, int M_ = 2, int HALO_ = 1>
 struct Tile {
   static constexpr int F = F_, T = T_, M = M_, HALO = HALO_;
   static constexpr int H = T_ + 2 * HALO_;  // tangential extent including the halo
@@ -54,7 +54,7 @@ template <int DIR> struct BatchTile { using T = Tile4x32; };
 template <> struct BatchTile<1> { using T = Tile2x64; };
 using BTX = BatchTile<0>::T;
 using BTY = BatchTile<1>::T;
-constexpr int NQ = 24;          // per segment: 5 quantities x 4 components + 4 reference values
+constexpr int NQ = 32;          // per segment: 5 quantities x 4 components, 4 reference values, 2 x 4 tangential-gradient data
 constexpr int FACE_THREADS = 256;   // one thread per Gauss point of the tile's face segments
 // waves per SIMD the face kernels are compiled for (register budget 512 / waves:
 // 168 at 3; the latency of the point evaluation needs the occupancy more than
@@ -184,17 +184,19 @@ __device__ __forceinline__ void load_cell(const double* S, const Geom& G, int i,
   if constexpr (NC == 4) apply_rule<NC>(G, ky, 2 + sy, 1, dir, W, Gd);
 }
 
-// one component k of W and of its gradient along dir at cell (i, j), ghosts included (2D)
+// one component k of W and of its gradients along dir (gn) and along the other
+// axis (gt) at cell (i, j), ghosts included (2D)
 template <class GT>
 __device__ __forceinline__ void load_comp(const double* S, const Geom& G, int i, int j, int dir, int k,
-                                          double& w, double& gd) {
+                                          double& w, double& gn, double& gt) {
   int kx, sx = 0, ky, sy = 0;
   const int si = src_index(i, G.nx, G.bc[0], G.bc[1], kx, sx);
   const int sj = src_index(j, G.ny, G.bc[2], G.bc[3], ky, sy);
   const size_t N = (size_t)G.nx * G.ny;
   const size_t id = (size_t)sj * G.nx + si;
   w = S[k * N + id];
-  gd = grad_planes<GT>(S, N, 4)[(4 * dir + k) * N + id];
+  gn = grad_planes<GT>(S, N, 4)[(4 * dir + k) * N + id];
+  gt = grad_planes<GT>(S, N, 4)[(4 * (1 - dir) + k) * N + id];
   // rules applied to one component: x rule, then y rule
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -202,14 +204,17 @@ __device__ __forceinline__ void load_comp(const double* S, const Geom& G, int i,
     if (kind < 0 || kind == CGKS_PERIODIC) continue;
     const int side = a == 0 ? sx : 2 + sy;
     if (kind == CGKS_FREE) {
-      gd = 0.0;
+      gn = 0.0;
+      gt = 0.0;
     } else if (kind == CGKS_INFLOW) {
       w = G.inflow[side][k];
-      gd = 0.0;
-    } else {  // walls about axis a
+      gn = 0.0;
+      gt = 0.0;
+    } else {  // walls about axis a: the gradient along a has the opposite parity
       const double par = wall_parity<4>(kind, a, k);
       w *= par;
-      gd *= dir == a ? -par : par;
+      gn *= dir == a ? -par : par;
+      gt *= dir == a ? par : -par;
     }
   }
 }
@@ -328,10 +333,11 @@ __global__ __launch_bounds__(256) void k_scan(Geom G, Bufs B) {
 // DIR 1: y faces (normal y, tangential x, momenta swapped for the evolution).
 // Tile: TF faces x TT segments, 256 threads, small enough in LDS and registers
 // for two blocks per CU (one block's reconstruction overlaps the other's point
-// evaluation).  Phase 1 reconstructs TF x (TT+4) line segments (each shifted
-// by its own reference cell) into LDS; phase 2 runs one Gauss point per
-// thread: tangential quartic, gas-kinetic evolution, Gauss average over the
-// lane pair.
+// evaluation).  Phase 1 reconstructs TF x (TT + 2 HALO) line segments (each
+// shifted by its own reference cell), with the cells' tangential gradients
+// carried across the face, into LDS; phase 2 runs one Gauss point per thread:
+// tangential fits, gas-kinetic evolution, Gauss average over the lanes of the
+// segment.
 // Tile of this block when consecutive blocks go round-robin to the XCDs: each
 // XCD (its own L2) gets a contiguous run of tiles in row-major order, so the
 // stencil halos shared by neighbouring tiles are fetched into one L2.
@@ -383,7 +389,7 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
       else { fl = s / TH; tl = s % TH; pos = fl * TH + tl; }
       const int f = f0 + fl, ta = t0 - HALO + tl;
       if (f > nn || ta > nt + HALO - 1) continue;
-      double w[4], gd[4];
+      double w[4], gd[4], gt[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int i = DIR == 0 ? f - 2 + m : ta, j = DIR == 0 ? ta : f - 2 + m;
@@ -391,8 +397,9 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
           const size_t id = (size_t)j * G.nx + i;
           w[m] = S[k * N + id];
           gd[m] = grad_planes<GT>(S, N, 4)[(4 * DIR + k) * N + id];
+          gt[m] = grad_planes<GT>(S, N, 4)[(4 * (1 - DIR) + k) * N + id];
         } else {
-          load_comp<GT>(S, G, i, j, DIR, k, w[m], gd[m]);
+          load_comp<GT>(S, G, i, j, DIR, k, w[m], gd[m], gt[m]);
         }
       }
       const double ref = w[1];
@@ -404,12 +411,18 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
       lds[3 * 4 + k][pos] = L.wl;
       lds[4 * 4 + k][pos] = L.wr;
       lds[20 + k][pos] = ref;
+      // the cells' tangential gradient carried across the face by the cubic
+      // through the 4 stencil cells: value and (unit-width) normal derivative
+      double hT, hTN;
+      cross_face(gt[0], gt[1], gt[2], gt[3], ht, hT, hTN);
+      lds[24 + k][pos] = hT;
+      lds[28 + k][pos] = hTN;
     }
   }
   __syncthreads();
 
   // phase 2: one Gauss point per thread (face_point); the second point reads
-  // the 5 stencil lines in reverse order.  y faces: the two points of a segment
+  // the stencil lines in reverse order.  y faces: the two points of a segment
   // in adjacent lanes (their reads of a line row coincide or fall in different
   // banks), a half-wave covers 16 segments along x.  x faces: the two points in
   // the two half-waves (within a half-wave, reads of lines 2 or 4 rows apart
@@ -446,13 +459,15 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   double acc[NO];
   int guard, nbad;
   const double inv_hn = DIR == 0 ? G.inv_dx : G.inv_dy, inv_ht = DIR == 0 ? G.inv_dy : G.inv_dx;
+  const double dsg = mirror ? -1.0 : 1.0;
   if constexpr (M == 2) {
-    face_point<DIR, STAGE == 1>(get, right_cell, kTang[0], inv_hn, mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard,
-                                nbad);
+    face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[0], kHerm2[0], dsg, inv_hn, mirror ? -inv_ht : inv_ht,
+                                    G.gas, dt, acc, guard, nbad);
   } else {
     const int pr = gp >> 1;
-    face_point<DIR, STAGE == 1>(get, right_cell, kTang7[pr], inv_hn, mirror ? -inv_ht : inv_ht, G.gas, dt, acc,
-                                guard, nbad, pr ? kGauss4Outer : kGauss4Inner);
+    face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[pr], kHerm4[pr], dsg, inv_hn,
+                                    mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad,
+                                    pr ? kGauss4Outer : kGauss4Inner);
   }
   if (guard) atomicAdd(&sc->guard_w0, 1ull);
   if (nbad) atomicAdd(&sc->guard_weno, (unsigned long long)nbad);

@@ -157,25 +157,75 @@ CGKS_HD __forceinline__ Line5 normal_line(double a, double c, double d, double A
   return r;
 }
 
-// ----------------------------------------------------------------------------
-// Tangential quartic through 5 segment averages (offsets -2..2) evaluated at
-// the 2-point Gauss-Legendre nodes eta = -+1/(2 sqrt 3) of the segment
-// (value, d/deta, d2/deta2).  Weights derived symbolically.
-// ----------------------------------------------------------------------------
-template <int NL>
-struct TangWT { double v[NL], d1[NL], d2[NL]; };
-using TangW = TangWT<5>;
-
-#define CGKS_TANG_WEIGHTS { \
-  {{-0.028297119567088289478, 0.20139476939454598305, 0.99861111111111111111, -0.19954291754269413120, 0.027834156604125326515}, \
-   {0.11540834828831254247, -1.0836418610813963855, 0.76980035891950101935, 0.24969147225193694785, -0.051258318378354124194}, \
-   {0.061004233964073107794, 1.0446581987385204511, -2.5, 1.6220084679281462156, -0.22767090063073977446}}, \
-  {{0.027834156604125326515, -0.19954291754269413120, 0.99861111111111111111, 0.20139476939454598305, -0.028297119567088289478}, \
-   {0.051258318378354124194, -0.24969147225193694785, -0.76980035891950101935, 1.0836418610813963855, -0.11540834828831254247}, \
-   {-0.22767090063073977446, 1.6220084679281462156, -2.5, 1.0446581987385204511, 0.061004233964073107794}}, \
+// The cells' tangential gradient g of the 4 stencil cells carried across the
+// face by the cubic through their averages: ht T (value at the face) and
+// ht TN (its normal derivative at unit normal width), times the tangential
+// width ht (the data of the tangential fits are width x derivative).
+CGKS_HD __forceinline__ void cross_face(double g0, double g1, double g2, double g3, double ht, double& hT,
+                                        double& hTN) {
+  hT = ht * ((7.0 * (g1 + g2) - (g0 + g3)) * (1.0 / 12.0));
+  hTN = ht * ((15.0 * (g2 - g1) + (g0 - g3)) * (1.0 / 12.0));
 }
 
-__constant__ static const TangW kTang[2] = CGKS_TANG_WEIGHTS;
+// ----------------------------------------------------------------------------
+// Tangential fits (2D).  A face segment sees the stencil lines of the
+// neighbouring segments and, for each line, the cells' own tangential
+// gradient carried across the face (the cubic through the 4 cells of the
+// normal stencil: its value T and normal derivative TN at the face).
+// Two Gauss points: every quantity at a point comes from the three nearest
+// segments (offsets -1..1): the quintic that matches the segment averages s_l
+// and the segment averages of the tangential derivative (data d_l = width
+// times average derivative), or for W_nn the quadratic through the averages.
+// Weights at the nodes eta = -+1/(2 sqrt 3) (unit width; the kernels use the
+// first and reach the second by mirroring):
+//   p(eta) = sum v_l s_l + vd_l d_l, p' = sum d1_l s_l + d1d_l d_l,
+//   p'' = sum d2_l s_l + d2d_l d_l, quadratic(eta) = sum q_l s_l.
+// The mirrored node reads the segments in reverse order; its derivative data
+// then change sign.  Four Gauss points: the same quintics at the 4-point
+// nodes give W_nt and W_tt (the sextic below gives the rest).  Weights from
+// the exact inverse of the 6x6 (3x3) condition matrix evaluated at the nodes
+// (csrc/tangential_weights.py).
+// ----------------------------------------------------------------------------
+struct HermWT { double v[3], vd[3], d1[3], d1d[3], d2[3], d2d[3], q[3]; };
+
+#define CGKS_HERM2_WEIGHTS { \
+  {{-0.07540507117498404449950279, 0.9944444444444444444444444, 0.08096062673053960005505834}, \
+   {-0.01665330702328691625202201, -0.4089564406759849165273137, -0.01943108480106469402979979}, \
+   {-0.6944086473878967252606736, 1.347150628109126783854680, -0.6527419807212300585940069}, \
+   {-0.1993945341743196992808274, 0.9722222222222222222222222, 0.1855056452854308103919385}, \
+   {4.886751345948128822545744, -4.0, -0.8867513459481288225457439}, \
+   {1.173575314054563391927340, 4.426352063787130861236807, 0.1735753140545633919273402}, \
+   {0.1443375672974064411272872, 1.0, -0.1443375672974064411272872}}, \
+  {{0.08096062673053960005505834, 0.9944444444444444444444444, -0.07540507117498404449950279}, \
+   {0.01943108480106469402979979, 0.4089564406759849165273137, 0.01665330702328691625202201}, \
+   {0.6527419807212300585940069, -1.347150628109126783854680, 0.6944086473878967252606736}, \
+   {0.1855056452854308103919385, 0.9722222222222222222222222, -0.1993945341743196992808274}, \
+   {-0.8867513459481288225457439, -4.0, 4.886751345948128822545744}, \
+   {-0.1735753140545633919273402, -4.426352063787130861236807, -1.173575314054563391927340}, \
+   {-0.1443375672974064411272872, 1.0, 0.1443375672974064411272872}} \
+}
+// inner (-a) and outer (-b) nodes of the 4-point rule
+#define CGKS_HERM4_WEIGHTS { \
+  {{-0.1248240833561131699440749, 1.124426413335020227523364, 0.0003976700210929424207106109}, \
+   {-0.03210351457762360623395334, -0.2660001747648614712891579, 0.002891414172850832756992869}, \
+   {-0.1526899822820735562383774, 0.8303038958212636973409479, -0.6776139135391901411025705}, \
+   {-0.06231166909995143542794097, 1.404385843338815739450934, 0.1828497570182522808412001}, \
+   {4.165330030890955969267389, -4.653238670008856194497662, 0.4879086391179002252302731}, \
+   {1.106222711005295206895935, 2.791595304766893427494077, -0.2203966239991328903528958}, \
+   {0.05777698297917839142993050, 1.054436555834071349541472, -0.1122135388132497409714024}}, \
+  {{0.07355769190377441281049170, 0.7667300492500137860820779, 0.1597122588462118011074304}, \
+   {0.02308107005580096648563723, -0.4972776892026319862157708, -0.04252610359263265617877837}, \
+   {-1.408829046621189383642094, 1.833550488515874427317954, -0.4247214418946850436758601}, \
+   {-0.3560936766249800353899954, 0.2418726600625448047667532, 0.1301134118359308906570084}, \
+   {5.034219542738118133817983, -2.775332758562572376930909, -2.258886784175545756887074}, \
+   {0.9787827549958941217382635, 5.723207196203161835693985, 0.5911163757146079332728091}, \
+   {0.2663118796250726281005321, 0.8979443965468810314109091, -0.1642562761719536595114412}} \
+}
+__constant__ static const HermWT kHerm2[2] = CGKS_HERM2_WEIGHTS;
+__constant__ static const HermWT kHerm4[2] = CGKS_HERM4_WEIGHTS;
+
+template <int NL>
+struct TangWT { double v[NL], d1[NL], d2[NL]; };
 
 // The sextic through 7 segment averages (offsets -3..3) at the 4-point
 // Gauss-Legendre nodes eta = -a (inner) and -b (outer), a = 0.16999052179...,
@@ -714,18 +764,21 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
 }
 
 // ----------------------------------------------------------------------------
-// Tangential reconstruction of one face point from the 5 stencil lines of its
-// face segment (offsets -2..2).  get(q, l) returns quantity q of line l:
-// q = 4*j + k for j = (P7, h P7_n, h^2 P7_nn, WENO left, WENO right) and
-// component k (each shifted by the line's own reference cell), q = 20 + k the
-// reference cell average.  Value-type quantities are moved to the face
-// segment's reference (the middle line) before the quartic; hn, ht are the
-// normal and tangential cell widths.
+// Tangential reconstruction of one face point from the NL stencil lines of its
+// face segment (offsets -NL/2..NL/2; NL = 3 with two Gauss points, 7 with
+// four).  get(q, l) returns quantity q of line l: q = 4*j + k for
+// j = (P7, hn P7_n, hn^2 P7_nn, WENO left, WENO right) and component k (each
+// shifted by the line's own reference cell), q = 20 + k the reference cell
+// average, q = 24 + k the line's tangential gradient at the face times ht
+// (ht T) and q = 28 + k its normal derivative times hn ht (hn ht TN).
+// Value-type quantities are moved to the face segment's reference (the
+// middle line) before the fit; hn, ht are the normal and tangential cell
+// widths.  dsg = -1 when get presents the lines in reverse order (the
+// mirrored Gauss point: the derivative data change sign).
 // ----------------------------------------------------------------------------
 // Offsets that move the value-type quantities of line l to the middle line's
-// reference: off[l] = ref(l) - ref(NL/2); returns ref(NL/2).  NL = 5 (quartic)
-// or 7 (sextic) lines.
-template <int NL = 5, class Get>
+// reference: off[l] = ref(l) - ref(NL/2); returns ref(NL/2).
+template <int NL, class Get>
 CGKS_HD __forceinline__ double tang_offsets(Get get, int k, double* off) {
   const double rj = get(20 + k, NL / 2);
 #pragma unroll
@@ -734,7 +787,7 @@ CGKS_HD __forceinline__ double tang_offsets(Get get, int k, double* off) {
 }
 
 // sum_l c[l] (get(q, l) + off[l]) (value-type quantity, off from tang_offsets)
-template <int NL = 5, class Get>
+template <int NL, class Get>
 CGKS_HD __forceinline__ double tang_value(Get get, const double* c, int q, const double* off) {
   double s = 0;
 #pragma unroll
@@ -743,7 +796,7 @@ CGKS_HD __forceinline__ double tang_value(Get get, const double* c, int q, const
 }
 
 // sum_l c[l] get(q, l) (derivative-type quantity, no reference shift)
-template <int NL = 5, class Get>
+template <int NL, class Get>
 CGKS_HD __forceinline__ double tang_deriv(Get get, const double* c, int q) {
   double s = 0;
 #pragma unroll
@@ -751,25 +804,92 @@ CGKS_HD __forceinline__ double tang_deriv(Get get, const double* c, int q) {
   return s;
 }
 
+// The three-segment quintic over the middle lines of an NL-line stencil:
+// value-type quantity q (averages, with the offsets) and its tangential
+// derivative data qd; ws/wd: weights of the averages and of the data.
 template <int NL, class Get>
-CGKS_HD __forceinline__ void tangential_point(Get get, const TangWT<NL>& w, double hn, double ht,
-                                              PointIn<4>& in, double* dev, double* ref) {
+CGKS_HD __forceinline__ double herm_value(Get get, const double* ws, const double* wd, int q, int qd,
+                                          const double* off, double dsg) {
+  constexpr int L0 = NL / 2 - 1;
+  double s = 0, d = 0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    s += ws[l] * (get(q, L0 + l) + off[L0 + l]);
+    d += wd[l] * get(qd, L0 + l);
+  }
+  return s + dsg * d;
+}
+
+// the same for a derivative-type quantity (no reference shift)
+template <int NL, class Get>
+CGKS_HD __forceinline__ double herm_deriv(Get get, const double* ws, const double* wd, int q, int qd, double dsg) {
+  constexpr int L0 = NL / 2 - 1;
+  double s = 0, d = 0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    s += ws[l] * get(q, L0 + l);
+    d += wd[l] * get(qd, L0 + l);
+  }
+  return s + dsg * d;
+}
+
+// The point quantities of component k (h: quintic weights at this node; w7:
+// sextic weights, used when NL = 7).  Value-type results are deviations from
+// the middle line's reference.
+template <int NL>
+struct TangEval {
+  const TangWT<7>& w7;
+  const HermWT& h;
+  double dsg;
+  template <class Get> CGKS_HD __forceinline__ double W0(Get get, int k, const double* off) const {
+    if constexpr (NL == 3) return herm_value<3>(get, h.v, h.vd, k, 24 + k, off, dsg);
+    else return tang_value<NL>(get, w7.v, k, off);
+  }
+  template <class Get> CGKS_HD __forceinline__ double side(Get get, int q, int k, const double* off) const {
+    if constexpr (NL == 3) return herm_value<3>(get, h.v, h.vd, q, 24 + k, off, dsg);
+    else return tang_value<NL>(get, w7.v, q, off);
+  }
+  template <class Get> CGKS_HD __forceinline__ double Wt(Get get, int k, const double* off) const {
+    if constexpr (NL == 3) return herm_value<3>(get, h.d1, h.d1d, k, 24 + k, off, dsg);
+    else return tang_value<NL>(get, w7.d1, k, off);
+  }
+  template <class Get> CGKS_HD __forceinline__ double Wtt(Get get, int k, const double* off) const {
+    return herm_value<NL>(get, h.d2, h.d2d, k, 24 + k, off, dsg);
+  }
+  template <class Get> CGKS_HD __forceinline__ double Wn(Get get, int k) const {
+    if constexpr (NL == 3) return herm_deriv<3>(get, h.v, h.vd, 4 + k, 28 + k, dsg);
+    else return tang_deriv<NL>(get, w7.v, 4 + k);
+  }
+  template <class Get> CGKS_HD __forceinline__ double Wnt(Get get, int k) const {
+    return herm_deriv<NL>(get, h.d1, h.d1d, 4 + k, 28 + k, dsg);
+  }
+  template <class Get> CGKS_HD __forceinline__ double Wnn(Get get, int k) const {
+    if constexpr (NL == 3) return tang_deriv<3>(get, h.q, 8 + k);
+    else return tang_deriv<NL>(get, w7.v, 8 + k);
+  }
+};
+
+// All inputs of the point evaluation at once (host checks and operation count).
+template <int NL, class Get>
+CGKS_HD __forceinline__ void tangential_point(Get get, const TangWT<7>& w7, const HermWT& h, double dsg, double hn,
+                                              double ht, PointIn<4>& in, double* dev, double* ref) {
   const double inv_ht = 1.0 / ht, inv_hn = 1.0 / hn;
+  const TangEval<NL> te{w7, h, dsg};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     double off[NL];
     const double rj = tang_offsets<NL>(get, k, off);
-    const double v = tang_value<NL>(get, w.v, k, off);
+    const double v = te.W0(get, k, off);
     ref[k] = rj;
     dev[k] = v;
     in.W0[k] = rj + v;
-    in.Wn[k] = tang_deriv<NL>(get, w.v, 4 + k) * inv_hn;
-    in.Wnn[k] = tang_deriv<NL>(get, w.v, 8 + k) * inv_hn * inv_hn;
-    in.Wt[k] = tang_value<NL>(get, w.d1, k, off) * inv_ht;
-    in.Wnt[k] = tang_deriv<NL>(get, w.d1, 4 + k) * inv_hn * inv_ht;
-    in.Wtt[k] = tang_value<NL>(get, w.d2, k, off) * inv_ht * inv_ht;
-    in.Wl[k] = rj + tang_value<NL>(get, w.v, 12 + k, off);
-    in.Wr[k] = rj + tang_value<NL>(get, w.v, 16 + k, off);
+    in.Wn[k] = te.Wn(get, k) * inv_hn;
+    in.Wnn[k] = te.Wnn(get, k) * inv_hn * inv_hn;
+    in.Wt[k] = te.Wt(get, k, off) * inv_ht;
+    in.Wnt[k] = te.Wnt(get, k) * inv_hn * inv_ht;
+    in.Wtt[k] = te.Wtt(get, k, off) * inv_ht * inv_ht;
+    in.Wl[k] = rj + te.side(get, 12 + k, k, off);
+    in.Wr[k] = rj + te.side(get, 16 + k, k, off);
   }
 }
 
@@ -798,20 +918,20 @@ CGKS_HD __forceinline__ void face_accumulate(double* acc, const PointOut<NC>& o,
 // One Gauss point of a 2D face segment, evaluated phase by phase so that few
 // values are live at a time: every tangential quantity is evaluated from the
 // line data right before the phase that first needs it (the reference/deviation
-// pair of the final state is re-read at the end).  get(q, l) as for
-// tangential_point, with the weights w; inv_hn, inv_ht: inverse normal and
-// tangential cell widths, inv_ht negated when get presents the lines in
-// reverse order (the other Gauss point: same value and second-derivative
-// weights mirrored, first-derivative weights mirrored with opposite sign).
+// pair of the final state is re-read at the end).  get(q, l), w7, h and dsg
+// as for tangential_point; inv_hn, inv_ht: inverse normal and tangential cell
+// widths, inv_ht negated (and dsg = -1) when get presents the lines in
+// reverse order (the other Gauss point: the same fits mirrored).
 // right(k): average of the cell right of the face (fallback of an inadmissible
 // right WENO state; the left one falls back to the reference cell).
 // DIR 1 (y faces) rotates the momenta so that the normal one comes first.
-// acc receives this point's half of the Gauss average (face_accumulate from
-// zero); guard / nbad count the equilibrium and WENO fallbacks.
+// acc receives this point's share wg of the Gauss average (face_accumulate
+// from zero); guard / nbad count the equilibrium and WENO fallbacks.
 template <int DIR, bool FULL, int NL, class Get, class Right>
-CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<NL>& w, double inv_hn, double inv_ht,
-                                        const Gas& gas, double dt, double* acc, int& guard, int& nbad,
-                                        double wg = 0.5) {
+CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<7>& w7, const HermWT& h, double dsg,
+                                        double inv_hn, double inv_ht, const Gas& gas, double dt, double* acc,
+                                        int& guard, int& nbad, double wg = 0.5) {
+  const TangEval<NL> te{w7, h, dsg};
   auto rot = [](double* v) {
     if (DIR == 1) { const double t = v[1]; v[1] = v[2]; v[2] = t; }
   };
@@ -824,9 +944,9 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<NL>& 
   for (int k = 0; k < 4; ++k) {
     double off[NL];
     const double rj = tang_offsets<NL>(get, k, off);
-    Wl[k] = rj + tang_value<NL>(get, w.v, 12 + k, off);
-    Wr[k] = rj + tang_value<NL>(get, w.v, 16 + k, off);
-    W0[k] = rj + tang_value<NL>(get, w.v, k, off);
+    Wl[k] = rj + te.side(get, 12 + k, k, off);
+    Wr[k] = rj + te.side(get, 16 + k, k, off);
+    W0[k] = rj + te.W0(get, k, off);
     CGKS_PIN(Wl[k]);
     CGKS_PIN(Wr[k]);
     CGKS_PIN(W0[k]);
@@ -866,8 +986,8 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<NL>& 
   for (int k = 0; k < 4; ++k) {
     double off[NL];
     tang_offsets<NL>(get, k, off);
-    Wn[k] = tang_deriv<NL>(get, w.v, 4 + k) * inv_hn;
-    Wt[k] = tang_value<NL>(get, w.d1, k, off) * inv_ht;
+    Wn[k] = te.Wn(get, k) * inv_hn;
+    Wt[k] = te.Wt(get, k, off) * inv_ht;
     CGKS_PIN(Wn[k]);
     CGKS_PIN(Wt[k]);
     CGKS_BREAK();
@@ -894,9 +1014,9 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<NL>& 
     for (int k = 0; k < 4; ++k) {
       double off[NL];
       tang_offsets<NL>(get, k, off);
-      Wnn[k] = tang_deriv<NL>(get, w.v, 8 + k) * inv_hn * inv_hn;
-      Wnt[k] = tang_deriv<NL>(get, w.d1, 4 + k) * inv_hn * inv_ht;
-      Wtt[k] = tang_value<NL>(get, w.d2, k, off) * inv_ht * inv_ht;
+      Wnn[k] = te.Wnn(get, k) * inv_hn * inv_hn;
+      Wnt[k] = te.Wnt(get, k) * inv_hn * inv_ht;
+      Wtt[k] = te.Wtt(get, k, off) * inv_ht * inv_ht;
       CGKS_PIN(Wnn[k]);
       CGKS_PIN(Wnt[k]);
       CGKS_PIN(Wtt[k]);
@@ -937,7 +1057,7 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<NL>& 
   for (int k = 0; k < 4; ++k) {
     double off[NL];
     ref[k] = tang_offsets<NL>(get, k, off);
-    dev[k] = tang_value<NL>(get, w.v, k, off);
+    dev[k] = te.W0(get, k, off);
     CGKS_PIN(ref[k]);
     CGKS_PIN(dev[k]);
     CGKS_BREAK();

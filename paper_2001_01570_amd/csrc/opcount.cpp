@@ -5,13 +5,14 @@
 // and divisions are counted (a fused multiply-add is a multiplication plus an
 // addition, i.e. 2 flops), square roots, exponentials and complementary error
 // functions separately.  Counting runs the device building blocks the kernels
-// run (reconstruction, tangential quartic, point evolution, Gauss average),
+// run (reconstruction, tangential fits, point evolution, Gauss average),
 // each tangential quantity once per point, on a smooth representative state
 // (no guard fires, both WENO sides evaluated).
 //
 // Units:  x- or y-face segment of one stage (4 normal reconstructions of its
-// own line, 2 Gauss points: tangential quartic, gas-kinetic evolution, Gauss
-// average) and one cell update.  The kernels' halo recomputation of stencil
+// own line with the cells' tangential gradients carried across the face, 2
+// Gauss points: tangential fits, gas-kinetic evolution, Gauss average) and
+// one cell update.  The kernels' halo recomputation of stencil
 // lines and the face kernels' second read of each point's reference state are
 // not algorithmic work and are not counted.
 //
@@ -81,8 +82,9 @@ static void emit(const char* name, const OpCounts& c, bool comma) {
 }
 
 int main() {
-  static const TangW host_tang[2] = CGKS_TANG_WEIGHTS;
   static const TangWT<7> host_tang7[2] = CGKS_TANG7_WEIGHTS;
+  static const HermWT host_herm2[2] = CGKS_HERM2_WEIGHTS;
+  static const HermWT host_herm4[2] = CGKS_HERM4_WEIGHTS;
   const double gamma = 1.4;
   const Gas gas = make_gas(gamma, 2, 0.01, 1.0, 0.0);
   const double dt = 6e-4, hn = 1.0 / 512, ht = 1.0 / 512;
@@ -91,33 +93,37 @@ int main() {
   OpCounts a = snap();
   Line5 L = normal_line(CD(1.1e-4), CD(-0.9e-4), CD(2.1e-4), CD(0.5e-4), CD(-0.7e-4), CD(1.3e-4), CD(0.2e-4), CD(1e-6));
   (void)L;
+  CD hT, hTN;
+  cross_face(CD(0.3), CD(-0.2), CD(0.25), CD(0.1), CD(ht), hT, hTN);
   const OpCounts recon = diff(a, snap());
 
-  // tangential quartic to one Gauss point (4 components)
-  CD lines[24][5];
-  for (int q = 0; q < 24; ++q)
-    for (int l = 0; l < 5; ++l) lines[q][l] = q >= 20 ? CD(1.0 + 1e-4 * l) : CD(1e-5 * (q + 1) * (l + 1));
-  for (int l = 0; l < 5; ++l) { lines[20][l] = CD(1.0 + 1e-4 * l); lines[23][l] = CD(1.8 + 1e-4 * l); }
+  // tangential fits to one Gauss point (4 components): three segments
+  CD lines[32][3];
+  for (int q = 0; q < 32; ++q)
+    for (int l = 0; l < 3; ++l) lines[q][l] = CD(1e-5 * (q + 1) * (l + 1));
+  for (int l = 0; l < 3; ++l)
+    for (int k = 0; k < 4; ++k) lines[20 + k][l] = CD((k == 3 ? 1.8 : 1.0) + 1e-4 * l);
   auto get = [&](int q, int l) { return lines[q][l]; };
   PointIn<4> in;
   CD dev[4], ref[4];
   a = snap();
-  tangential_point(get, host_tang[0], CD(hn), CD(ht), in, dev, ref);
+  tangential_point<3>(get, host_tang7[0], host_herm2[0], CD(1.0), CD(hn), CD(ht), in, dev, ref);
   const OpCounts tang = diff(a, snap());
   // the sextic through 7 segment averages (four Gauss points per segment)
-  CD lines7[24][7];
-  for (int q = 0; q < 24; ++q)
-    for (int l = 0; l < 7; ++l) lines7[q][l] = q >= 20 ? CD(1.0 + 1e-4 * l) : CD(1e-5 * (q + 1) * (l + 1));
-  for (int l = 0; l < 7; ++l) { lines7[20][l] = CD(1.0 + 1e-4 * l); lines7[23][l] = CD(1.8 + 1e-4 * l); }
+  CD lines7[32][7];
+  for (int q = 0; q < 32; ++q)
+    for (int l = 0; l < 7; ++l) lines7[q][l] = CD(1e-5 * (q + 1) * (l + 1));
+  for (int l = 0; l < 7; ++l)
+    for (int k = 0; k < 4; ++k) lines7[20 + k][l] = CD((k == 3 ? 1.8 : 1.0) + 1e-4 * l);
   auto get7 = [&](int q, int l) { return lines7[q][l]; };
   {
     PointIn<4> in7;
     a = snap();
-    tangential_point(get7, host_tang7[0], CD(hn), CD(ht), in7, dev, ref);
+    tangential_point<7>(get7, host_tang7[0], host_herm4[0], CD(1.0), CD(hn), CD(ht), in7, dev, ref);
   }
   const OpCounts tang7 = diff(a, snap());
   a = snap();
-  tangential_point(get, host_tang[0], CD(hn), CD(ht), in, dev, ref);   // the input of the point counts below
+  tangential_point<3>(get, host_tang7[0], host_herm2[0], CD(1.0), CD(hn), CD(ht), in, dev, ref);   // the input of the point counts below
   (void)diff(a, snap());
   for (int k = 0; k < 4; ++k) { in.Wl[k] = in.W0[k] + CD(1e-9); in.Wr[k] = in.W0[k] - CD(1e-9); }
 
@@ -138,8 +144,9 @@ int main() {
   face_accumulate<4, false>(acc, o, dev, ref, CD(dt));
   const OpCounts acc2 = diff(a, snap());
 
-  // per face segment of a stage: 4 component reconstructions of its own line,
-  // 2 Gauss points (tangential + evolution + accumulation)
+  // per face segment of a stage: 4 component reconstructions of its own line
+  // (with the tangential gradients carried across the face), M Gauss points
+  // (tangential fits + evolution + accumulation)
   auto seg = [&](const OpCounts& g, const OpCounts& ac, const OpCounts& tg, long m) {
     OpCounts s;
     s.add = 4 * recon.add + m * (tg.add + g.add + ac.add);
@@ -160,7 +167,7 @@ int main() {
   up1.add = 4 * 20; up1.mul = 4 * 8; up1.div = 4 * 8;
   up2.add = 4 * 8; up2.mul = 4 * 4; up2.div = 4 * 4;
   std::printf("{\n  \"units\": {\n");
-  emit("recon_line_component", recon, true);
+  emit("recon_line_component", recon, true);   // normal reconstruction + cross_face
   emit("tangential_point", tang, true);
   emit("gks_point_stage1", gks1, true);
   emit("gks_point_stage2", gks2, true);
