@@ -344,7 +344,7 @@ def acoustic_pulse_2d(n: int = 1024, seed: int = 0, amp: float = 1e-3, half_widt
                       steps: int = 500, cfl: float = 0.3, ny: Optional[int] = None) -> Problem:
     """Periodic [-1,1]^2, background (rho,U,V,p) = (1,0,0,1/gamma), a Gaussian
     pulse amp*exp(-ln2 r^2/b^2) added to both density and pressure (the
-    acoustic-pulse form of Sec. 4.7), centred at a point drawn uniformly from
+    acoustic-pulse form of Sec. 4.6), centred at a point drawn uniformly from
     [-1,1]^2 by numpy's default_rng(seed); minimum-image distances."""
     ny = n if ny is None else ny
     rng = np.random.default_rng(seed)
@@ -364,11 +364,12 @@ def acoustic_pulse_2d(n: int = 1024, seed: int = 0, amp: float = 1e-3, half_widt
 
 
 def shock_vortex_2d(nx: int = 2048, ny: int = 1024, Ms: float = 1.1, Mv: float = 0.3, Rc: float = 0.05,
-                    xv: float = 0.25, yv: float = 0.5, t_end: float = 0.8, cfl: float = 0.3) -> Problem:
+                    xv: float = 0.25, yv: float = 0.5, t_end: float = 0.8, cfl: float = 0.5) -> Problem:
     """[0,2]x[0,1]: stationary normal shock of Mach Ms at x = 0.5 (upstream
     rho = p = 1, U = Ms sqrt(gamma); downstream from the Rankine-Hugoniot
     relations), isentropic vortex upstream; reflecting walls at y = 0, 1,
-    fixed inflow at x = 0, free flow at x = 2."""
+    fixed inflow at x = 0, free flow at x = 2.  CFL 0.5, the number Sec. 3
+    gives for inviscid flow."""
     g = GAMMA
     U1 = Ms * math.sqrt(g)
     r2 = (g + 1.0) * Ms * Ms / ((g - 1.0) * Ms * Ms + 2.0)
@@ -394,7 +395,7 @@ def shock_vortex_2d(nx: int = 2048, ny: int = 1024, Ms: float = 1.1, Mv: float =
 
 def viscous_shock_vortex_2d(nx: int = 700, ny: int = 600, Ms: float = 1.2, Mv: float = 0.5, Re: float = 800.0,
                             t_end: float = 6.0, cfl: float = 0.3) -> Problem:
-    """The viscous shock-vortex interaction of Sec. 4.9 on [-20,8]x[-12,12]:
+    """The viscous shock-vortex interaction of Sec. 4.8 on [-20,8]x[-12,12]:
     a stationary normal shock of Mach Ms at x = 0, the supersonic stream
     (rho = 1, p = 1/gamma, sound speed 1, U = -Ms) entering at x = 8 and
     carrying a counter-clockwise isentropic vortex of strength Mv (core radius
@@ -443,7 +444,7 @@ def shock_reflection_2d(nx: int = 200, ny: int = 50, t_end: float = 50.0, cfl: f
 
 def plane_pulse(n: int = 300, ny: int = 0, eps: float = 1e-4, b: float = 0.08, mu: float = 0.0,
                 cfl: float = 0.3) -> Problem:
-    """Plane pressure pulse of Sec. 4.6 on [-5,5] (x [0,1] in 2D, ny > 0):
+    """Plane pressure pulse of Sec. 4.5 on [-5,5] (x [0,1] in 2D, ny > 0):
     rho = 1, U = V = 0, p = 1/gamma + eps exp(-ln2 (x/b)^2); free flow at
     x = +-5 (the waves stay inside for t < 4), periodic in y.  exact(t) is the
     linear inviscid solution: two acoustic halves moving at +-1 (the sound
@@ -512,7 +513,7 @@ def serving_request(k: int) -> Problem:
 
 
 def tam_webb_2d(n: int = 200, t_end: float = 28.45, L: float = 100.0, cfl: float = 0.3) -> Problem:
-    """Sound, entropy and vorticity pulses on a uniform flow (Sec. 4.7):
+    """Sound, entropy and vorticity pulses on a uniform flow (Sec. 4.6):
     [-L,L]^2 (the paper's L = 100), rho_inf = 1, U_inf = 0.5, Mach 0.5
     (c_inf = 1, p_inf = 1/gamma), CFL 0.3; periodic boundaries: at L = 100 no
     wave reaches them before t = 56.9, at L = 250 none reaches them, nor

@@ -435,14 +435,13 @@ def test_config4_full_size_single_step_sampled():
 
 def test_config4_runs_to_its_end_time_with_a_small_viscosity():
     """The 2048x1024 Mach 1.1 shock-vortex case to its end time t = 0.8 with
-    mu = 1e-5 (a cell Reynolds number of about 130): no guard fires, the
-    density stays within the states of the interaction, and the stationary
-    shock stays at x = 0.5: the first density crossing of the rows lies within
-    a cell of it in the median and within 8 cells on every row (at t = 0.8 the
-    shock still carries the ripple the vortex left on it, -5.5 to +2.5 cells).  Inviscid, the run stops near
-    t = 0.37 on the growing grid-scale mode of the 2D step, which grid-scale
-    dissipation of this size controls."""
-    p = dataclasses.replace(I.shock_vortex_2d(), mu=1e-5)
+    mu = 1e-5 (a cell Reynolds number of about 130) at CFL 0.3: no guard
+    fires, the density stays within the states of the interaction, and the
+    stationary shock stays at x = 0.5: the first density crossing of the rows
+    lies within a cell of it in the median and within 8 cells on every row (at
+    t = 0.8 the shock still carries the ripple the vortex left on it, -5.5 to
+    +2.5 cells)."""
+    p = dataclasses.replace(I.shock_vortex_2d(), mu=1e-5, cfl=0.3)
     s = solver(p)
     n = s.advance_to(0.8)
     g, t, _ = s.get_state()
@@ -461,6 +460,71 @@ def test_config4_runs_to_its_end_time_with_a_small_viscosity():
         assert len(k), j
         off.append((x[k[0]] - 0.5) / dx)
     assert abs(np.median(off)) <= 1.0 and np.abs(off).max() <= 8.0, off
+
+
+def _ulp_moved(f, seed):
+    st = np.random.default_rng(seed).integers(-1, 2, size=f.shape)
+    return np.where(st > 0, np.nextafter(f, np.inf), np.where(st < 0, np.nextafter(f, -np.inf), f))
+
+
+@pytest.mark.parametrize('cfl', [0.3, 0.5])
+def test_config3_500_steps_at_the_papers_cfl_are_well_conditioned(cfl):
+    """The 1024^2 pulse for its 500 steps at CFL 0.3 (Sec. 4) and 0.5 (Sec. 3,
+    inviscid flow): two runs whose inputs differ by at most 1 ulp per value
+    end within 1e-9 of the pulse amplitude of each other (measured 1.4e-11 and
+    1.5e-11; before the faces saw the cells' tangential gradients, the step
+    grew a checkerboard mode at CFL 0.3 and the two runs differed by 4 times
+    the amplitude), the totals of mass, momentum and energy are conserved to
+    rounding and no guard fires."""
+    amp = 1e-3
+    p = I.acoustic_pulse_2d(1024, seed=0, amp=amp, cfl=cfl)
+    a, b = solver(p), solver(dataclasses.replace(p, fields=_ulp_moved(p.fields, 3)))
+    a.run_steps(500)
+    b.run_steps(500)
+    ga, gb = a.state, b.state
+    spread = np.abs(ga - gb)
+    dx = (p.x1 - p.x0) / p.nx
+    say('C3 cfl', cfl, '500 steps: 1-ulp spread / amplitude', spread[:4].max() / amp, spread[4:].max() * dx / amp)
+    assert spread[:4].max() < 1e-9 * amp and spread[4:].max() * dx < 1e-9 * amp
+    m0 = p.fields[:4].reshape(4, -1).sum(1)
+    m1 = ga[:4].reshape(4, -1).sum(1)
+    assert np.all(np.abs(m1 - m0) <= 1e-14 * np.maximum(np.abs(m0), 1.0)), (m0, m1)
+    c = a.counters()
+    assert c['steps'] == 500 and c['guard_w0'] == 0 and c['guard_weno'] == 0
+
+
+def test_config4_inviscid_runs_to_its_end_time():
+    """The 2048x1024 Mach 1.1 shock-vortex case, inviscid, to t = 0.8 at
+    CFL 0.5 (Sec. 3's number for inviscid flow): no guard fires, the density
+    stays within [0.95, 1.3] (the states of the interaction: 0.88 in the vortex
+    core upstream, 1.17 behind the shock, the compression where the vortex
+    crosses it) and the shock stays at x = 0.5 (median row offset within a
+    cell).  At CFL 0.3 and 0.4 the same run ends at t = 0.375 and 0.52: after
+    the vortex has crossed the shock, an odd-even mode grows in its core at
+    the 1 + O(dt^2) per-step rate the 2D step has in moving flow, from the
+    perturbation the interaction leaves there."""
+    p = I.shock_vortex_2d()
+    assert p.cfl == 0.5 and p.mu == 0.0
+    s = solver(p)
+    n = s.advance_to(0.8)
+    g, t, _ = s.get_state()
+    c = s.counters()
+    say('C4 inviscid to t = 0.8:', n, 'steps', c)
+    assert t == 0.8 and 4000 < n < 5000
+    assert c['guard_w0'] == 0 and c['guard_weno'] == 0
+    rho = g[0]
+    say('C4 inviscid density range', rho.min(), rho.max())
+    assert 0.95 < rho.min() and rho.max() < 1.3
+    dx = (p.x1 - p.x0) / p.nx
+    x = p.x0 + (np.arange(p.nx) + 0.5) * dx
+    mid = 0.5 * (1.0 + 1.169082)
+    off = []
+    for j in range(0, p.ny, 32):
+        k = np.nonzero((rho[j, :-1] < mid) & (rho[j, 1:] >= mid))[0]
+        assert len(k), j
+        off.append((x[k[0]] - 0.5) / dx)
+    say('C4 inviscid shock offsets', min(off), np.median(off), max(off))
+    assert abs(np.median(off)) <= 1.0 and np.abs(off).max() <= 12.0, off
 
 
 def test_viscous_shock_vortex_full_size_single_step_sampled():
@@ -545,7 +609,7 @@ def test_regular_shock_reflection_steady_state():
 
 
 def test_plane_pressure_pulse_2d():
-    """Sec. 4.6 plane pressure pulse at the paper's 300 x 30: the 2D run
+    """Sec. 4.5 plane pressure pulse at the paper's 300 x 30: the 2D run
     matches linear acoustics plus the entropy wave like the 1D oracle does
     (errors relative to the amplitude below 5e-4 at t = 0.5, 2e-3 at t = 3),
     and stays invariant in y."""
@@ -582,7 +646,7 @@ def test_gaussian_advection_over_400_cells(b, err_bar, peak_bar):
 
 
 def test_tam_webb_full_run_to_t100():
-    """Sec. 4.7 run to t = 100 at the paper's resolution (1 cell per unit,
+    """Sec. 4.6 run to t = 100 at the paper's resolution (1 cell per unit,
     CFL 0.3, 500 steps): the window [-100,100]^2 sits in a periodic [-250,250]^2
     that no wave crosses (in place of a non-reflecting boundary); against a
     2x finer run (CFL 0.15) averaged to the same cells, density and pressure

@@ -204,7 +204,7 @@ def test_2d_spatial_order_with_dt_proportional_to_dx2():
 
 
 def test_cfl_rule_matches_tam_webb_step_counts():
-    """Sec. 4.7: 143 and 286 steps to t = 28.45 and 56.9 at CFL 0.3 on 200x200.
+    """Sec. 4.6: 143 and 286 steps to t = 28.45 and 56.9 at CFL 0.3 on 200x200.
     The first step of the CFL rule is 0.19974 and no step can exceed 0.2 (the
     far field moves at |U| + c = 1.5), so the counts hold for any history in
     between; the full run is checked on the GPU path."""
@@ -320,7 +320,7 @@ def _pulse_errors(st, ex, eps, g=1.4):
 
 
 def test_plane_pressure_pulse_is_linear_acoustics_plus_entropy():
-    """Sec. 4.6 plane pressure pulse (inviscid, 300 cells on [-5,5], about 2.4
+    """Sec. 4.5 plane pressure pulse (inviscid, 300 cells on [-5,5], about 2.4
     cells per half-width): the pulse splits into two acoustic halves at the
     sound speed and an entropy wave at rest (closed form of linear
     acoustics); errors relative to the amplitude below 5e-4 at t = 0.5 and
