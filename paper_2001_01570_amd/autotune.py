@@ -4,9 +4,11 @@
 
 For each grid size it times every tile shape (HIP events around each face
 launch, two stages, over a few steps of the acoustic-pulse workload) and
-keeps the fastest shape per direction; the table (tuning.json, with the
-digest of the HIP sources it was measured on) is read by every 2D context at
-creation.  A table from other sources, or no table, leaves the default shape.
+keeps the fastest shape per direction.  It writes tuning.json (the timings,
+with the digest of the HIP sources they were measured on) and
+csrc/tuning_table.h, the table the library compiles in: every 2D context
+(and every step without allocation) takes the entry nearest in cell count.
+Rebuild the library after tuning.
 """
 from __future__ import annotations
 
@@ -19,31 +21,6 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(PKG, 'tuning.json')
 SHAPES = {0: '8x16', 1: '4x32', 2: '2x64'}
-
-_table = None
-
-
-def _load():
-    global _table
-    if _table is None:
-        _table = {}
-        if os.path.exists(TABLE):
-            from .build import source_digest
-            with open(TABLE) as f:
-                t = json.load(f)
-            if t.get('source_digest') == source_digest():
-                _table = t
-    return _table
-
-
-def tiles_for(nx: int, ny: int):
-    """(x shape, y shape) for a grid: the entry nearest in cell count (log scale)."""
-    entries = _load().get('entries', [])
-    if not entries:
-        return 0, 0
-    e = min(entries, key=lambda e: abs(math.log(e['nx'] * e['ny']) - math.log(nx * ny)))
-    return e['x'], e['y']
-
 
 def tune(n: int, steps: int = 20, rounds: int = 3):
     """Fastest shape per direction on an n x n grid: every shape is timed in
@@ -87,9 +64,31 @@ def main(argv=None):
         print('[autotune] %d^2: x %s, y %s  %s' % (n, SHAPES[e['x']], SHAPES[e['y']], e['ms_per_step']),
               file=sys.stderr, flush=True)
         entries.append(e)
+    digest = source_digest()
     with open(a.out + '.tmp', 'w') as f:
-        json.dump({'source_digest': source_digest(), 'shapes': SHAPES, 'entries': entries}, f, indent=1)
+        json.dump({'source_digest': digest, 'shapes': SHAPES, 'entries': entries}, f, indent=1)
     os.replace(a.out + '.tmp', a.out)
+    write_header(entries, digest)
+
+
+HEADER = os.path.join(PKG, 'csrc', 'tuning_table.h')
+
+
+def write_header(entries, digest, path=HEADER):
+    rows = '\n'.join('    {%d, %d, %d, %d},' % (e['nx'], e['ny'], e['x'], e['y']) for e in entries)
+    text = ('// Face tile shapes per direction by grid size, written by the autotuner\n'
+            '// (python -m paper_2001_01570_amd.autotune) from its timings on the GPU;\n'
+            '// the library applies the entry nearest in cell count (log scale) when a 2D\n'
+            '// context is created.  Shapes: 0 = 8x16, 1 = 4x32, 2 = 2x64.\n'
+            '// Sources digest the timings were taken on: %s\n'
+            '#pragma once\n'
+            'namespace cgks {\n'
+            'struct TuneEntry { int nx, ny, x, y; };\n'
+            'constexpr TuneEntry kTuneTable[] = {\n%s\n};\n'
+            '}  // namespace cgks\n' % (digest, rows))
+    with open(path + '.tmp', 'w') as f:
+        f.write(text)
+    os.replace(path + '.tmp', path)
 
 
 if __name__ == '__main__':

@@ -135,9 +135,6 @@ class Solver:
         if rc:
             raise CgksError(rc, 'cgks_create')
         self.h = h
-        if prob.dim == 2:
-            from . import autotune
-            self.set_tiles(*autotune.tiles_for(prob.nx, prob.ny))
         if load_state:
             self.set_state(prob.fields, 0.0)
 

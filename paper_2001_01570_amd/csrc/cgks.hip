@@ -24,6 +24,7 @@
 
 #include "cgks.h"
 #include "cgks_device.h"
+#include "tuning_table.h"
 
 namespace cgks {
 
@@ -960,6 +961,17 @@ static void free_bufs(cgks_ctx* c) {
   if (c->host_sc) (void)hipHostFree(c->host_sc);
 }
 
+// Face tile shapes of a 2D grid: the tuned entry nearest in cell count (log scale).
+static void tuned_tiles(int nx, int ny, int* tile) {
+  const double lc = std::log((double)nx * (double)ny);
+  double best = INFINITY;
+  tile[0] = tile[1] = 0;
+  for (const TuneEntry& e : kTuneTable) {
+    const double d = std::fabs(std::log((double)e.nx * (double)e.ny) - lc);
+    if (d < best) { best = d; tile[0] = e.x; tile[1] = e.y; }
+  }
+}
+
 extern "C" int cgks_create(const cgks_config* cfg, void* hip_stream, cgks_ctx** out) {
   if (!out) return CGKS_EINVAL;
   *out = nullptr;
@@ -997,6 +1009,7 @@ extern "C" int cgks_create(const cgks_config* cfg, void* hip_stream, cgks_ctx** 
     return CGKS_ENOMEM;
   }
   std::memset(c->host_sc, 0, sizeof(Scalars));
+  if (cfg->dim == 2) tuned_tiles(G.nx, G.ny, c->tile);
   *out = c;
   return CGKS_OK;
 }
@@ -1117,14 +1130,16 @@ extern "C" int cgks_set_state(cgks_ctx* c, const double* fields, int on_device, 
   return CGKS_OK;
 }
 
-static void launch_step(cgks_ctx* c) {
-  const Geom& G = c->G;
-  hipStream_t s = c->stream;
+// The launches of one step on stream s for geometry G and buffers B.  run(kind,
+// launch) issues each kernel launch (the context brackets them with events
+// while profiling).  gp: Gauss points; tiles: face tile shape per direction.
+template <class Run>
+static void launch_step_on(const Geom& G, const Bufs& B, int gp, int storage, const int* tiles, hipStream_t s,
+                           Run&& run) {
   const dim3 gu = update_grid(G);
-  k_begin<<<1, 256, 0, s>>>(c->B.sc, c->B.lam_part, (int)(gu.x * gu.y));
+  k_begin<<<1, 256, 0, s>>>(B.sc, B.lam_part, (int)(gu.x * gu.y));
   if (G.dim == 2) {
-    const Bufs B = c->B;
-    // one direction's face kernel of one stage with the context's tile shape
+    // one direction's face kernel of one stage with the given tile shape
     auto faces = [&](auto dir, auto stage, auto gt, int kind) {
       constexpr int DIR = decltype(dir)::value, STAGE = decltype(stage)::value;
       using GT = decltype(gt);
@@ -1132,16 +1147,16 @@ static void launch_step(cgks_ctx* c) {
         using TL = decltype(tl);
         const dim3 g = DIR == 0 ? dim3((G.nx + 1 + TL::F - 1) / TL::F, (G.ny + TL::T - 1) / TL::T)
                                 : dim3((G.nx + TL::T - 1) / TL::T, (G.ny + 1 + TL::F - 1) / TL::F);
-        timed(c, kind, [&] { k_faces2<DIR, STAGE, GT, TL><<<g, FACE_THREADS, 0, s>>>(G, B); });
+        run(kind, [&] { k_faces2<DIR, STAGE, GT, TL><<<g, FACE_THREADS, 0, s>>>(G, B); });
       };
-      if (c->cfg.gauss_points == 4) {        // FP64 storage only (validated)
+      if (gp == 4) {        // FP64 storage only (validated)
         if constexpr (std::is_same_v<GT, double>) {
           if constexpr (DIR == 0) go(Tile4x16G4());
           else go(Tile2x32G4());
         }
         return;
       }
-      switch (c->tile[DIR]) {
+      switch (tiles[DIR]) {
         case 1: go(Tile4x32()); break;
         case 2: go(Tile2x64()); break;
         default: go(Tile8x16()); break;
@@ -1155,22 +1170,26 @@ static void launch_step(cgks_ctx* c) {
       using GT = decltype(gt);
       faces(D0(), S1(), gt, 0);
       faces(D1(), S1(), gt, 1);
-      timed(c, 2, [&] { k_update2<1, GT><<<gu, 256, 0, s>>>(G, B); });
+      run(2, [&] { k_update2<1, GT><<<gu, 256, 0, s>>>(G, B); });
       faces(D0(), S2(), gt, 3);
       faces(D1(), S2(), gt, 4);
-      timed(c, 5, [&] { k_update2<2, GT><<<gu, 256, 0, s>>>(G, B); });
+      run(5, [&] { k_update2<2, GT><<<gu, 256, 0, s>>>(G, B); });
     };
-    if (c->cfg.storage == CGKS_FP32_STORAGE) stage_kernels(0.0f);
+    if (storage == CGKS_FP32_STORAGE) stage_kernels(0.0f);
     else stage_kernels(0.0);
   } else {
     const unsigned nf = (unsigned)((G.nx + 1 + 255) / 256);
-    const Bufs B = c->B;
-    timed(c, 0, [&] { k_faces1<1><<<nf, 256, 0, s>>>(G, B); });
-    timed(c, 1, [&] { k_update1<1><<<gu, 256, 0, s>>>(G, B); });
-    timed(c, 2, [&] { k_faces1<2><<<nf, 256, 0, s>>>(G, B); });
-    timed(c, 3, [&] { k_update1<2><<<gu, 256, 0, s>>>(G, B); });
+    run(0, [&] { k_faces1<1><<<nf, 256, 0, s>>>(G, B); });
+    run(1, [&] { k_update1<1><<<gu, 256, 0, s>>>(G, B); });
+    run(2, [&] { k_faces1<2><<<nf, 256, 0, s>>>(G, B); });
+    run(3, [&] { k_update1<2><<<gu, 256, 0, s>>>(G, B); });
   }
-  k_end<<<1, 64, 0, s>>>(c->B.sc);
+  k_end<<<1, 64, 0, s>>>(B.sc);
+}
+
+static void launch_step(cgks_ctx* c) {
+  launch_step_on(c->G, c->B, c->cfg.gauss_points, c->cfg.storage, c->tile, c->stream,
+                 [c](int kind, auto&& launch) { timed(c, kind, launch); });
 }
 
 // 1D grids of at most this many cells run whole steps in one single-block
