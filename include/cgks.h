@@ -148,6 +148,31 @@ int cgks_set_tiles(cgks_ctx *ctx, int x_shape, int y_shape);
 void cgks_destroy(cgks_ctx *ctx);
 const char *cgks_strerror(int code);
 
+/* ---- One step without allocation ------------------------------------------
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One step of
+ * the configuration's problem (as cgks_step / cgks_step_dt on a context with
+ * that configuration and state) from the device state `in` to the device
+ * state `out`: both device pointers of nf * nx * ny doubles in the layout
+ * above, distinct buffers; `in` is only read.  dt > 0: a step of that size;
+ * otherwise the configuration's rule (CFL or fixed_dt).  The intermediate
+ * buffers of the step live in a static device array of the library, one per
+ * GPU for the life of the process, sized for CGKS_NOALLOC_MAX_CELLS cells:
+ * larger grids, FP32 storage or in == out return CGKS_EINVAL.  The call
+ * allocates nothing; it runs on the current device, and hip_stream (NULL: the
+ * null stream) must belong to it.  Every call on one GPU uses that GPU's one
+ * array: calls that overlap on a GPU (other streams or host threads) race and
+ * must be serialised by the caller.
+ * dt_used == NULL: the work is only queued on hip_stream (no host
+ * synchronisation, so the call can be captured into a graph), and a
+ * non-physical result is not reported.  Otherwise the call waits for the step
+ * and returns CGKS_ENONPHYS if the input or the result has a non-physical
+ * cell (out then holds no valid state), else stores the step size. */
+#define CGKS_NOALLOC_MAX_CELLS 65536
+int cgks_step_noalloc(const cgks_config *cfg, const double *in, double *out, double dt, void *hip_stream,
+                      double *dt_used);
+
 /* ---- Batch: many independent 2D problems advanced together (serving) ------
  *
  * Same scheme and kernels as a context; the requests of a serving workload

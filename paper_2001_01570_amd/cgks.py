@@ -87,6 +87,7 @@ def load():
     L.cgks_batch_release.argtypes = [C.c_void_p, C.c_int]
     L.cgks_batch_destroy.argtypes = [C.c_void_p]
     L.cgks_batch_destroy.restype = None
+    L.cgks_step_noalloc.argtypes = [C.POINTER(cgks_config), C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, _D]
     _lib = L
     return L
 
@@ -235,6 +236,30 @@ class Solver:
             raise CgksError(k, 'cgks_kernel_times')
         names = KERNEL_NAMES_2D if self.dim == 2 else KERNEL_NAMES_1D
         return {names[i]: (ms[i], calls[i]) for i in range(min(k, len(names)))}
+
+
+NOALLOC_MAX_CELLS = 65536
+
+
+def step_noalloc(prob, fields_in, fields_out, dt: float = 0.0, stream=None, wait: bool = True):
+    """One step with cgks_step_noalloc (no device allocation): fields_in and
+    fields_out are distinct contiguous float64 CUDA tensors of the state
+    shape.  wait=True: waits and returns the step size (raises on a
+    non-physical result); wait=False: only queues the work, returns None."""
+    torch = _torch()
+    shape = (6, prob.nx) if prob.dim == 1 else (12, prob.ny, prob.nx)
+    for f in (fields_in, fields_out):
+        assert isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float64
+        assert tuple(f.shape) == shape and f.is_contiguous()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    used = C.c_double()
+    rc = load().cgks_step_noalloc(C.byref(make_config(prob)), C.c_void_p(fields_in.data_ptr()),
+                                  C.c_void_p(fields_out.data_ptr()), float(dt), C.c_void_p(stream.cuda_stream),
+                                  C.byref(used) if wait else None)
+    if rc:
+        raise CgksError(rc, 'cgks_step_noalloc')
+    return used.value if wait else None
 
 
 SLOT_FREE, SLOT_RUNNING, SLOT_DONE, SLOT_FAILED = 0, 1, 2, 3

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <type_traits>
 #include <new>
 #include <vector>
@@ -1354,6 +1355,113 @@ extern "C" const char* cgks_strerror(int code) {
     case CGKS_ESTATE: return "no state loaded";
     default: return "unknown error";
   }
+}
+
+// ============================================================== step without allocation
+
+// Scratch of cgks_step_noalloc: the intermediate state, the partial final
+// update, the face results, the CFL partials and the step scalars of one step
+// of at most CGKS_NOALLOC_MAX_CELLS cells (2D: 12 + 12 fields of 8 bytes,
+// 16 x 2 face planes, a partial per 256 cells; 1D needs less).  One copy per
+// GPU, for the life of the process.  Host code never passes the symbol itself:
+// it takes the device address from hipGetSymbolAddress (per device).
+constexpr size_t kScratchBytes = (size_t)600 * CGKS_NOALLOC_MAX_CELLS + ((size_t)1 << 16);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// the device address of this device's scratch (looked up once per device)
+static int scratch_on_device(unsigned char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return CGKS_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return CGKS_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return CGKS_OK;
+}
+
+// every field of the step scalars (the scratch keeps the last call's contents)
+__global__ void k_noalloc_init(Scalars* sc, double cfl, double fixed_dt, double dt_override) {
+  if (threadIdx.x != 0) return;
+  sc->prm.t_end = INFINITY;
+  sc->prm.dt_override = dt_override;
+  sc->prm.max_step = LLONG_MAX;
+  sc->t = 0.0;
+  sc->dt = 0.0;
+  sc->cfl = cfl;
+  sc->fixed_dt = fixed_dt;
+  sc->last_dt = 0.0;
+  sc->bad_cell = ULLONG_MAX;
+  sc->guard_w0 = 0;
+  sc->guard_weno = 0;
+  sc->step = 0;
+  sc->status = 0;
+  sc->active = 0;
+  sc->last = 0;
+  sc->cur = 0;
+}
+
+extern "C" int cgks_step_noalloc(const cgks_config* cfg, const double* in, double* out, double dt, void* hip_stream,
+                                 double* dt_used) {
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!in || !out || in == out || cfg->storage != CGKS_FP64) return CGKS_EINVAL;
+  cgks_config cf = *cfg;
+  if (cf.dim == 1) cf.ny = 1;
+  if (cf.gauss_points == 0) cf.gauss_points = 2;
+  Geom G;
+  make_geom(cf, G);
+  const size_t N = (size_t)G.nx * G.ny;
+  if (N > (size_t)CGKS_NOALLOC_MAX_CELLS) return CGKS_EINVAL;
+  const size_t nf = cf.dim == 2 ? 12 : 6;
+  const dim3 gu = update_grid(G);
+  // carve the scratch: each piece 256-byte aligned
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
+  const size_t o_ws = take(nf * N * sizeof(double));
+  const size_t o_p = take(nf * N * sizeof(double));
+  const size_t o_fx = take(cf.dim == 2 ? (size_t)16 * G.ny * (G.nx + 1) * sizeof(double)
+                                       : (size_t)12 * (G.nx + 1) * sizeof(double));
+  const size_t o_fy = take(cf.dim == 2 ? (size_t)16 * (G.ny + 1) * G.nx * sizeof(double) : sizeof(double));
+  const size_t o_lam = take((size_t)gu.x * gu.y * sizeof(double));
+  const size_t o_sc = take(sizeof(Scalars));
+  if (off > kScratchBytes) return CGKS_EINVAL;
+  unsigned char* base = nullptr;
+  rc = scratch_on_device(&base);
+  if (rc) return rc;
+  Bufs B;
+  B.S[0] = const_cast<double*>(in);   // only read: the step writes S[cur ^ 1] = out
+  B.S[1] = out;
+  B.Ws = reinterpret_cast<double*>(base + o_ws);
+  B.P = reinterpret_cast<double*>(base + o_p);
+  B.FX = reinterpret_cast<double*>(base + o_fx);
+  B.FY = reinterpret_cast<double*>(base + o_fy);
+  B.lam_part = reinterpret_cast<double*>(base + o_lam);
+  B.sc = reinterpret_cast<Scalars*>(base + o_sc);
+  hipStream_t s = (hipStream_t)hip_stream;
+  int tiles[2] = {0, 0};
+  if (cf.dim == 2) tuned_tiles(G.nx, G.ny, tiles);
+  k_noalloc_init<<<1, 64, 0, s>>>(B.sc, cf.cfl, cf.fixed_dt, dt > 0.0 ? dt : 0.0);
+  if (cf.dim == 2) k_scan<4><<<gu, 256, 0, s>>>(G, B);
+  else k_scan<3><<<gu, 256, 0, s>>>(G, B);
+  launch_step_on(G, B, cf.gauss_points, cf.storage, tiles, s, [](int, auto&& launch) { launch(); });
+  HIPCHK(hipGetLastError());
+  if (!dt_used) return CGKS_OK;
+  Scalars h;
+  HIPCHK(hipMemcpyAsync(&h, B.sc, sizeof h, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h.status) return h.status;
+  if (h.step != 1) return CGKS_EDEVICE;
+  *dt_used = h.last_dt;
+  return CGKS_OK;
 }
 
 // ============================================================== batch (serving)
