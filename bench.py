@@ -42,47 +42,58 @@ def load_flops():
         return json.load(f)
 
 
-def cpu_baseline(prob, target_s=10.0):
+def cpu_baseline(prob, target_s=10.0, threads=None):
     """The oracle, as it stands, timed on this host: one MSMD step of a
-    horizontal band of the same workload (full width, periodic in x) with a
-    4-row margin, rows counted only in the band's exact core.  The band height
-    is chosen from a 16-row probe so that the timed step takes about target_s
+    horizontal band of the same workload (full width, every parameter of the
+    problem kept, free-flow rows beyond the band) with a margin of 4 rows
+    (6 with four Gauss points: a step reads 2, resp. 3, cells per stage);
+    rows are counted only in the band's exact core.  The band height is
+    chosen from a 16-row probe so that the timed step takes about target_s
     seconds; if the whole grid takes less, consecutive steps of it are timed
-    until about target_s.  Threads: the host cores this process may use, at
-    most 16 (one GPU's share of a host)."""
+    until about target_s.  threads: the host cores this process may use, at
+    most 16 (one GPU's share of a host), or the given number."""
     import numpy as np
     from oracle import oracle as O
     from paper_2001_01570_amd import inputs as I
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, 'sched_getaffinity') else os.cpu_count()
-    threads = max(1, min(threads, 16))
+    if threads is None:
+        threads = len(os.sched_getaffinity(0)) if hasattr(os, 'sched_getaffinity') else os.cpu_count()
+        threads = max(1, min(threads, 16))
+    margin = 6 if prob.gauss_points == 4 else 4
 
     def band_step(rows, steps=1):
-        if rows == prob.ny:              # the whole periodic grid
+        if rows == prob.ny:              # the whole grid
             p = prob
         else:
             j0 = prob.ny // 2 - rows // 2
-            iy = np.arange(j0 - 4, j0 + rows + 4) % prob.ny
-            band = np.ascontiguousarray(prob.fields[:, iy, :])
-            p = I.Problem('band', 2, prob.nx, len(iy), prob.x0, prob.x1, 0.0, prob.dy * len(iy), band,
-                          bc=(I.PERIODIC, I.PERIODIC, I.FREE, I.FREE), cfl=prob.cfl)
+            idx = np.arange(j0 - margin, j0 + rows + margin)
+            if prob.bc[2] == I.PERIODIC:
+                idx %= prob.ny
+            else:
+                idx = np.clip(idx, 0, prob.ny - 1)
+            band = np.ascontiguousarray(prob.fields[:, idx, :])
+            p = dataclasses.replace(prob, ny=len(idx), fields=band, y0=0.0, y1=prob.dy * len(idx),
+                                    bc=(prob.bc[0], prob.bc[1], I.FREE, I.FREE))
         o = O.Oracle(p, threads=threads)
+        dt = o.cfl_dt()
         t0 = time.perf_counter()
         for _ in range(steps):
-            o.step(o.cfl_dt())
+            o.step(dt)
         return time.perf_counter() - t0
 
     probe = band_step(16)
-    rows = int(min(prob.ny, max(16, 24 * target_s / max(probe, 1e-6) - 8)))   # the probe computes 24 rows
+    rows_probe = 16 + 2 * margin
+    rows = int(min(prob.ny, max(16, rows_probe * target_s / max(probe, 1e-6) - 2 * margin)))
     steps = 1
     if rows == prob.ny:
-        steps = max(1, int(round(target_s / (probe * (prob.ny + 8) / 24))))
+        steps = max(1, int(round(target_s / (probe * (prob.ny + 2 * margin) / rows_probe))))
     el = band_step(rows, steps)
     cells = prob.nx * rows * steps
     what = ('%d MSMD step%s of the whole %dx%d workload' % (steps, 's' if steps > 1 else '', prob.nx, prob.ny)
             if rows == prob.ny else
-            '1 MSMD step of a %dx%d band (+4-row margins) of the %dx%d workload' % (prob.nx, rows, prob.nx, prob.ny))
+            '1 MSMD step of a %dx%d band (+%d-row margins) of the %dx%d workload'
+            % (prob.nx, rows, margin, prob.nx, prob.ny))
     return dict(value=cells / el, unit='cell-updates/s', cores=threads, kind='oracle',
-                sample='%s, %.1f s on %d threads' % (what, el, threads))
+                sample='%s, %.1f s on %d thread%s' % (what, el, threads, 's' if threads > 1 else ''))
 
 
 def launch_units(kernel, nx, ny):
@@ -117,9 +128,20 @@ def _make_request(k):
     return k, p
 
 
-def serving(nreq, steps_per_run=10):
-    """Serving workload: nreq independent requests (inputs.serving_request:
-    side 64..512, pulse + vortex, 200 steps each).  (1) the plain path closed
+def serving_requests(nreq):
+    """The serving workload's requests (inputs.serving_request: side 64..512,
+    pulse + vortex, 200 steps each), generated in worker processes.  Call it
+    before anything touches the GPU (the workers are started by spawn)."""
+    from multiprocessing import get_context
+    log('[serving] generating %d requests' % nreq)
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, 'sched_getaffinity') else 4))
+    with get_context('spawn').Pool(workers) as pool:
+        reqs = dict(pool.map(_make_request, range(nreq)))
+    return [reqs[k] for k in range(nreq)]
+
+
+def serving(reqs, steps_per_run=10):
+    """Serving workload over the requests reqs.  (1) the plain path closed
     loop (one context per request: create, load from host, 200 steps, read to
     host) gives the rate r; (2) Poisson arrivals at 2r (default_rng(7)) are
     replayed in real time through the plain path (FIFO, one request at a time)
@@ -128,16 +150,9 @@ def serving(nreq, steps_per_run=10):
     (3) The batch's own capacity c (every request admitted at once), and a
     second batch replay with the same draws at 0.7c, where the queue stays
     short and the latency is the steady-state one.
-    Latency = completion - arrival."""
+    Latency = completion - arrival.  Returns the figures as a dict."""
     import numpy as np
-    from multiprocessing import get_context
-
-    # inputs first, in worker processes started before anything touches the GPU
-    log('[serving] generating %d requests' % nreq)
-    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, 'sched_getaffinity') else 4))
-    with get_context('spawn').Pool(workers) as pool:
-        reqs = dict(pool.map(_make_request, range(nreq)))
-    reqs = [reqs[k] for k in range(nreq)]
+    nreq = len(reqs)
     steps = reqs[0].steps
 
     import torch
@@ -233,14 +248,11 @@ def serving(nreq, steps_per_run=10):
     def pct(a, q):
         return float(np.percentile(a, q))
     cells = sum(p.nx * p.ny for p in reqs)
-    out = {
+    return {
         'metric': 'solves/s (serving, Poisson arrivals at 2x the plain closed-loop rate)',
         'value': nreq / span_batch,
         'unit': 'solves/s',
-        'n_gpus': 1,
         'higher_is_better': True,
-        'dtype': 'f64',
-        'data': 'synthetic',
         'config': {'workload': '%d serving requests (sides 64-512, pulse + vortex, %d steps each, default_rng(1000+k)),'
                                ' arrivals default_rng(7)' % (nreq, steps), 'cells_total': cells,
                    'steps_per_run': steps_per_run},
@@ -252,8 +264,8 @@ def serving(nreq, steps_per_run=10):
         'plain': {'closed_loop_solves_per_s': closed, 'solves_per_s': nreq / span_plain,
                   'p50_s': pct(lat_plain, 50), 'p99_s': pct(lat_plain, 99), 'span_s': span_plain},
         'arrival_rate_per_s': rate,
+        'batched_over_plain': (nreq / span_batch) / (nreq / span_plain),
     }
-    print(json.dumps(out), flush=True)
 
 
 def fp32_storage(args):
@@ -312,8 +324,11 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--copy-calibration', type=int, default=0, metavar='MIB',
                     help='also run one plain device copy of this many MiB (reference for HBM byte counters)')
-    ap.add_argument('--serving', type=int, default=0, metavar='R',
-                    help='instead: the serving workload with R requests (Poisson arrivals), batched vs per-request')
+    ap.add_argument('--serving', type=int, default=256, metavar='R',
+                    help='serving requests measured after the headline (Poisson arrivals, batched vs per-request), '
+                         'reported in the same JSON line; 0: none')
+    ap.add_argument('--serving-only', action='store_true',
+                    help='only the serving workload (its own JSON line)')
     ap.add_argument('--gauss-points', type=int, choices=(2, 4), default=2,
                     help='Gauss points per face segment in 2D (4: the eighth-order 2D assembly with the 7-segment '
                          'sextic; the headline uses 2)')
@@ -323,8 +338,11 @@ def main():
     if args.gpus != 1:
         print('bench.py measures one GPU: the solver runs on a single MI355X (use --gpus 1).', file=sys.stderr)
         sys.exit(2)
-    if args.serving:
-        serving(args.serving)
+    reqs = serving_requests(args.serving) if args.serving and not args.fp32_storage else None
+    if args.serving_only:
+        out = serving(reqs)
+        out.update({'n_gpus': 1, 'dtype': 'f64', 'data': 'synthetic'})
+        print(json.dumps(out), flush=True)
         return
     if args.fp32_storage:
         fp32_storage(args)
@@ -408,11 +426,23 @@ def main():
                 'traffic': measured_traffic(name, prob.nx, prob.ny) if args.gauss_points == 2 else None,
                 'avg_ms': avg_s * 1e3, 'flops_per_launch': alg}
 
+    s.close()
+    serv = None
+    if reqs:
+        log('[bench] serving: %d requests' % len(reqs))
+        serv = serving(reqs)
+        log('[bench] serving: batched %.2f solves/s (p50 %.3f s, p99 %.3f s), plain %.2f solves/s'
+            % (serv['batched']['solves_per_s'], serv['batched']['p50_s'], serv['batched']['p99_s'],
+               serv['plain']['solves_per_s']))
+
     cpu = None
     if not args.no_cpu_baseline:
-        log('[bench] oracle CPU baseline')
+        log('[bench] oracle CPU baseline (all cores, then one thread)')
         cpu = cpu_baseline(prob)
         log('[bench] cpu', cpu)
+        one = cpu_baseline(prob, threads=1)
+        log('[bench] cpu 1 thread', one)
+        cpu['single_thread'] = {'value': one['value'], 'cores': 1, 'sample': one['sample']}
 
     out = {
         'metric': 'cell-updates/s per MSMD step (2D FP64)',
@@ -431,6 +461,7 @@ def main():
         'roofline': roof,
         'kernel_ms_per_launch_probe': {k: v[0] / max(v[1], 1) for k, v in probe.items()},
         'cpu_baseline': cpu,
+        'serving': serv,
     }
     print(json.dumps(out), flush=True)
 
