@@ -86,6 +86,25 @@ void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double m
                    const double *Wl, const double *Wr,
                    double *F, double *Ft, double *Wt, double *Wtt,
                    double *Nh, double *Nf, double *tau);
+/* orc_gks_point with the positivity guard of the equilibrium state reported:
+ * returns 1 when W0 was inadmissible and the kinetic collision state of the
+ * two sides took its place; W0used (nc) receives the state actually used. */
+int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double mu, double dt,
+                    const double *W0, const double *W0n, const double *W0t,
+                    const double *W0nn, const double *W0nt, const double *W0tt,
+                    const double *Wl, const double *Wr,
+                    double *F, double *Ft, double *Wt, double *Wtt,
+                    double *Nh, double *Nf, double *tau, double *W0used);
+/* One 1D face of a stage as the scheme evaluates it (Sec. 2.2, 3.2, 3.3), for
+ * the face between cells 1 and 2 of a 4-cell line: cells[f * 4 + m] is field
+ * f (the 6 fields of the 1D layout) of cell m.  The reference state of the
+ * face is cell 1.  out (12): F, F_t, A, B in blocks of 3 -- A, B the stage's
+ * interface-state terms (stage 1: at t + dt/2 and the stage-n part at
+ * t + dt; stage 2, final = 1: W_tt and 0), as deviations from cell 1.
+ * guards[0]: equilibrium-state guard fired (0/1); guards[1]: inadmissible
+ * WENO point states replaced by the adjacent cell average (0..2). */
+void orc_face_1d(const orc_config *cfg, const double *cells, double dt, int final,
+                 double *out, long *guards);
 /* The same evolution evaluated as the time integral of the interface flux over
  * [0, delta]: Fhat(delta), with tau in the exponentials and tau_ce in the
  * Chapman-Enskog term (exposed for the extraction tests). */

@@ -77,6 +77,9 @@ def lib():
         L.orc_slope.argtypes = [C.c_int, C.c_double, D, D, D]
         L.orc_euler_wtt.argtypes = [C.c_double] + [D] * 7
         L.orc_gks_point.argtypes = [C.c_int] + [C.c_double] * 5 + [D] * 8 + [D] * 7
+        L.orc_gks_point_g.argtypes = [C.c_int] + [C.c_double] * 5 + [D] * 8 + [D] * 8
+        L.orc_gks_point_g.restype = C.c_int
+        L.orc_face_1d.argtypes = [C.POINTER(_Cfg), D, C.c_double, C.c_int, D, C.POINTER(C.c_long)]
         L.orc_flux_integral.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [D] * 6
         L.orc_sextic.argtypes = [D, C.c_double, D]
         L.orc_quadratic3.argtypes = [D, C.c_double, D]
@@ -229,6 +232,42 @@ def gks_point(dim, gamma, dt, W0, W0n, W0nn, Wl, Wr, W0t=None, W0nt=None, W0tt=N
     r = dict(zip(names, outs))
     r['tau'] = float(tau[0])
     return r
+
+
+def gks_point_guarded(dim, gamma, dt, W0, W0n, W0nn, Wl, Wr, W0t=None, W0nt=None, W0tt=None,
+                      tau_eps=0.01, tau_C=1.0, mu=0.0):
+    """gks_point, also reporting whether the equilibrium-state guard fired
+    ('fired') and the equilibrium state actually used ('W0used')."""
+    nc = dim + 2
+    z = np.zeros(nc)
+    ins = [_vec(v, nc) for v in (W0, W0n, z if W0t is None else W0t, W0nn, z if W0nt is None else W0nt,
+                                 z if W0tt is None else W0tt, Wl, Wr)]
+    outs = [np.empty(nc) for _ in range(6)]
+    tau = np.empty(1)
+    used = np.empty(nc)
+    fired = lib().orc_gks_point_g(int(dim), float(gamma), float(tau_eps), float(tau_C), float(mu), float(dt),
+                                  *[_p(a) for a in ins], *[_p(a) for a in outs], _p(tau), _p(used))
+    r = dict(zip(('F', 'Ft', 'Wt', 'Wtt', 'Nh', 'Nf'), outs))
+    r.update(tau=float(tau[0]), fired=int(fired), W0used=used)
+    return r
+
+
+def face_1d(prob, cells, dt, final=False):
+    """One 1D face as a stage of the scheme evaluates it: cells (6, 4) holds
+    the 6 fields of the four cells of its stencil; the face lies between
+    cells 1 and 2.  Returns (out (4, 3): F, F_t, A, B as deviations from
+    cell 1; (equilibrium guard fired, WENO fallbacks))."""
+    cfg = _Cfg()
+    d = prob.config_dict()
+    for k in ('dim', 'nx', 'ny'):
+        setattr(cfg, k, int(d[k]))
+    for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt', 'mu'):
+        setattr(cfg, k, float(d[k]))
+    a = _vec(cells, 24)
+    out = np.empty(12)
+    g = (C.c_long * 2)()
+    lib().orc_face_1d(C.byref(cfg), _p(a), float(dt), int(bool(final)), _p(out), g)
+    return out.reshape(4, 3), (int(g[0]), int(g[1]))
 
 
 def flux_integral(dim, gamma, tau, delta, W0, W0n, Wl, Wr, W0t=None, tau_ce=0.0):

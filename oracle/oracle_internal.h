@@ -20,12 +20,4 @@ int orc_maxw_init(int dim, double gamma, const double *W, int half, orc_maxw *g)
 int orc_admissible(int dim, double gamma, const double *W);
 double orc_pressure(int dim, double gamma, const double *W);
 
-/* one interface point; returns 1 when the equilibrium-state guard fired */
-int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double mu, double dt,
-                    const double *W0, const double *W0n, const double *W0t,
-                    const double *W0nn, const double *W0nt, const double *W0tt,
-                    const double *Wl, const double *Wr,
-                    double *F, double *Ft, double *Wt, double *Wtt,
-                    double *Nh, double *Nf, double *tau, double *W0used);
-
 #endif

@@ -368,13 +368,44 @@ static void face_eval(orc_ctx *c, double lines[7][5][4], double tg[7][2][4], con
   }
 }
 
+void orc_face_1d(const orc_config *cfg, const double *cells, double dt, int final,
+                 double *out, long *guards) {
+  orc_ctx c;
+  memset(&c, 0, sizeof c);
+  c.cfg = *cfg;
+  c.cfg.dim = 1;
+  c.nc = 3;
+  c.npts = 1;
+  c.nl = 1;
+  orc_recon_init();
+  const double h = (cfg->x1 - cfg->x0) / cfg->nx;
+  double ref[4] = {0, 0, 0, 0}, Wlc[4] = {0, 0, 0, 0}, Wrc[4] = {0, 0, 0, 0};
+  double lines[7][5][4], tg[7][2][4];
+  memset(tg, 0, sizeof tg);
+  for (int k = 0; k < 3; ++k) {
+    ref[k] = Wlc[k] = cells[k * 4 + 1];
+    Wrc[k] = cells[k * 4 + 2];
+    double Q[4], D[4], o5[5];
+    for (int m = 0; m < 4; ++m) {
+      Q[m] = cells[k * 4 + m] - ref[k];
+      D[m] = h * cells[(3 + k) * 4 + m];
+    }
+    normal_line(Q, D, h, cfg->weno_eps, o5);
+    for (int q = 0; q < 5; ++q) lines[0][q][k] = o5[q];
+  }
+  guards_t gd = {0, 0};
+  face_eval(&c, lines, tg, ref, Wlc, Wrc, dt, final, 0, 1.0, out, &gd);
+  guards[0] = gd.w0;
+  guards[1] = gd.weno;
+}
+
 /* all faces of one stage on the ghosted state G */
 static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guards_t *gd_total) {
   const int nx = c->cfg.nx, ny = c->cfg.ny, nc = c->nc, dim = c->cfg.dim;
   const double eps = c->cfg.weno_eps;
   long gw0 = 0, gwe = 0;
   /* x faces: face f between cells f-1 and f, reference = cell f-1 of the same row */
-#pragma omp parallel for schedule(dynamic) reduction(+ : gw0, gwe) if (nthreads_req != 1)
+#pragma omp parallel for schedule(dynamic) reduction(+ : gw0, gwe) if (nthreads_req != 1 && ny > 1)
   for (int j = 0; j < ny; ++j) {
     guards_t gd = {0, 0};
     for (int f = 0; f <= nx; ++f) {
@@ -458,7 +489,7 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
 static void stage_update(orc_ctx *c, const double *G, double dt, int final, double *dst) {
   const int nx = c->cfg.nx, ny = c->cfg.ny, nc = c->nc, dim = c->cfg.dim;
   const int B = NF_FACE * nc;
-#pragma omp parallel for if (nthreads_req != 1)
+#pragma omp parallel for if (nthreads_req != 1 && ny > 1)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const double *xl = c->xf + ((size_t)j * (nx + 1) + i) * B;

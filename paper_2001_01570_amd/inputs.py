@@ -247,6 +247,51 @@ def shock_tube_1d(n: int = 100, t_end: float = 0.16, cfl: float = 0.3) -> Proble
                    cfl=cfl, t_end=t_end, meta=dict(left=left, right=right, x_diaphragm=0.5))
 
 
+def riemann_1d(left, right, n: int, x0: float = 0.0, x1: float = 1.0, x_d: float = 0.5, t_end: float = 0.1,
+               cfl: float = 0.3) -> Problem:
+    """Riemann problem with primitive states left = (rho, U, p) for x < x_d and
+    right for x > x_d, free-flow boundaries."""
+    def cons(x, side):
+        x = np.asarray(x, dtype=np.float64)
+        is_left = (x < x_d) | ((x == x_d) & (np.asarray(side) < 0))
+        st = [np.where(is_left, a, b) for a, b in zip(left, right)]
+        return prim_to_cons(st[0], st[1], 0.0 * st[1], st[2], GAMMA, 1)
+
+    fields = _cell_fields_1d(cons, x0, x1, n)
+    return Problem('riemann_1d', 1, n, 1, x0, x1, 0.0, 1.0, fields, bc=(FREE, FREE, PERIODIC, PERIODIC),
+                   cfl=cfl, t_end=t_end, meta=dict(left=tuple(left), right=tuple(right), x_diaphragm=x_d))
+
+
+def expansion_1d(n: int, U: float = 1.5, rho: float = 1.0, p: float = 0.4, cfl: float = 0.3) -> Problem:
+    """Periodic [0, 1] with (rho, -U, p) for x < 1/2 and (rho, U, p) for
+    x > 1/2: two rarefactions leave a near-vacuum behind them at x = 1/2 (the
+    double-rarefaction Riemann problem of the test suites for positivity) and
+    the two streams collide at x = 0 (two shocks)."""
+    def cons(x, side):
+        x = np.asarray(x, dtype=np.float64)
+        right = (x > 0.5) | ((x == 0.5) & (np.asarray(side) > 0))
+        return prim_to_cons(rho + 0.0 * x, np.where(right, U, -U), 0.0 * x, p + 0.0 * x, GAMMA, 1)
+
+    fields = _cell_fields_1d(cons, 0.0, 1.0, n)
+    return Problem('expansion_1d', 1, n, 1, 0.0, 1.0, 0.0, 1.0, fields, bc=(PERIODIC,) * 4, cfl=cfl,
+                   meta=dict(U=U, rho=rho, p=p))
+
+
+def expansion_2d(nx: int, ny: int = 0, U: float = 1.25, amp: float = 0.1, rho: float = 1.0, p: float = 0.4,
+                 cfl: float = 0.3, gauss_points: int = 2) -> Problem:
+    """The 1D expansion made two-dimensional: periodic [0, 1]^2, U = -U left of
+    the curve x = 1/2 + amp sin(2 pi y) and +U right of it, V = 0."""
+    ny = ny or nx
+
+    def prim(x, y, sx, sy):
+        right = x > 0.5 + amp * np.sin(2.0 * np.pi * y)
+        return rho + 0.0 * x, np.where(right, U, -U), 0.0 * x, p + 0.0 * x
+
+    fields = _cell_fields_2d(prim, 0.0, 1.0, 0.0, 1.0, nx, ny)
+    return Problem('expansion_2d', 2, nx, ny, 0.0, 1.0, 0.0, 1.0, fields, bc=(PERIODIC,) * 4, cfl=cfl,
+                   gauss_points=gauss_points, meta=dict(U=U, amp=amp, rho=rho, p=p))
+
+
 def stationary_shock_1d(n: int = 128, Ms: float = 1.1, t_end: float = 0.5, cfl: float = 0.3) -> Problem:
     """Normal shock of Mach Ms at rest at x = 0.5 on [0, 1]: upstream rho = p = 1,
     U = Ms sqrt(gamma), downstream from the Rankine-Hugoniot relations (the
