@@ -444,6 +444,92 @@ CGKS_HD __forceinline__ void mom_psi(const Mom<NC>& M, int n, int m, double* out
   mom_psi_a<NC>(M, n, m, one, out);
 }
 
+// Moments of the slope terms of one Maxwellian.  With the expansions
+// a_n . psi and a_t . psi of the normal and tangential slopes, the slope
+// polynomial P = u (a_n . psi) + v (a_t . psi) collects into
+//   P = c_u u + c_uu u^2 + c_uv u v + c_v v + c_vv v^2 + A u e + B v e,
+//   e = u^2 + v^2 + xi^2,  c_u = a_n0, c_uu = a_n1, c_uv = a_n2 + a_t1,
+//   c_v = a_t0, c_vv = a_t2, A = a_n3 / 2, B = a_t3 / 2
+// (1D: P = c_u u + c_uu u^2 + A u e, e = u^2 + xi^2).  Su = <u psi P>
+// (always) and, with PSI, Sp = <psi P>, from the products
+// E(a, b) = <u^a><v^b> of the moment table, each formed once, and the
+// moments of e and e^2 (<xi^2> = x1, <xi^4> = x2; E(0, 0) = <u^0> is the mass
+// fraction of a half space):
+//   <u^a v^b e>   = E(a+2,b) + E(a,b+2) + x1 E(a,b),
+//   <u^a v^b e^2> = E(a+4,b) + 2 E(a+2,b+2) + E(a,b+4) + 2 x1 (E(a+2,b) + E(a,b+2)) + x2 E(a,b).
+// The same sums as mom_psi_a over the two slopes, with every product of the
+// moment table formed once.
+template <int NC, bool PSI>
+CGKS_HD __forceinline__ void slope_moments(const Mom<NC>& M, const double* an, const double* at, double* Sp,
+                                           double* Su) {
+  const double* mu = M.mu;
+  const double x1 = M.x1, x2 = M.x2;
+  if constexpr (NC == 4) {
+    const double* mv = M.mv;
+    // the moment table (a >= 1, b >= 1)
+    const double E11 = mu[1] * mv[1], E12 = mu[1] * mv[2], E13 = mu[1] * mv[3], E14 = mu[1] * mv[4];
+    const double E21 = mu[2] * mv[1], E22 = mu[2] * mv[2], E23 = mu[2] * mv[3];
+    const double E31 = mu[3] * mv[1], E32 = mu[3] * mv[2];
+    const double E41 = mu[4] * mv[1];
+    // <u^a v^b e>
+    const double eM11 = fma(x1, E11, E31 + E13), eM20 = fma(x1, mu[2], mu[4] + E22);
+    const double eM30 = fma(x1, mu[3], mu[5] + E32), eM21 = fma(x1, E21, E41 + E23);
+    const double eM12 = fma(x1, E12, E32 + E14);
+    const double eM10 = fma(x1, mu[1], mu[3] + E12);
+    const double cu = an[0], cuu = an[1], cuv = an[2] + at[1], cv = at[0], cvv = at[2];
+    const double A = 0.5 * an[3], B = 0.5 * at[3];
+    // <u^a v^b P> = cu E(a+1,b) + cuu E(a+2,b) + cuv E(a+1,b+1) + cv E(a,b+1) + cvv E(a,b+2)
+    //               + A <u^(a+1) v^b e> + B <u^a v^(b+1) e>
+    const double S1 = cu * mu[2] + cuu * mu[3] + cuv * E21 + cv * E11 + cvv * E12 + A * eM20 + B * eM11;
+    const double E15 = mu[1] * mv[5], E24 = mu[2] * mv[4], E33 = mu[3] * mv[3], E42 = mu[4] * mv[2];
+    const double E51 = mu[5] * mv[1];
+    const double T1 = cu * mu[3] + cuu * mu[4] + cuv * E31 + cv * E21 + cvv * E22 + A * eM30 + B * eM21;
+    const double T2 = cu * E21 + cuu * E31 + cuv * E22 + cv * E12 + cvv * E13 + A * eM21 + B * eM12;
+    // <u e P>: <u^a v^b e^2> for (a, b) = (2, 0), (1, 1)
+    const double e2M20 = mu[6] + 2.0 * E42 + E24 + 2.0 * x1 * (mu[4] + E22) + x2 * mu[2];
+    const double e2M11 = E51 + 2.0 * E33 + E15 + 2.0 * x1 * (E31 + E13) + x2 * E11;
+    const double T3 = cu * eM20 + cuu * eM30 + cuv * eM21 + cv * eM11 + cvv * eM12 + A * e2M20 + B * e2M11;
+    Su[0] = S1;
+    Su[1] = T1;
+    Su[2] = T2;
+    Su[3] = 0.5 * T3;
+    if constexpr (PSI) {
+      // E(0, b) = <u^0> <v^b>: <u^0> is the mass fraction of a half space
+      const double E01 = mu[0] * mv[1], E02 = mu[0] * mv[2], E03 = mu[0] * mv[3], E04 = mu[0] * mv[4],
+                   E05 = mu[0] * mv[5];
+      const double eM01 = fma(x1, E01, E21 + E03), eM02 = fma(x1, E02, E22 + E04);
+      const double S0 = cu * mu[1] + cuu * mu[2] + cuv * E11 + cv * E01 + cvv * E02 + A * eM10 + B * eM01;
+      const double S2 = cu * E11 + cuu * E21 + cuv * E12 + cv * E02 + cvv * E03 + A * eM11 + B * eM02;
+      const double e2M10 = mu[5] + 2.0 * E32 + E14 + 2.0 * x1 * (mu[3] + E12) + x2 * mu[1];
+      const double e2M01 = E41 + 2.0 * E23 + E05 + 2.0 * x1 * (E21 + E03) + x2 * E01;
+      const double S3 = cu * eM10 + cuu * eM20 + cuv * eM11 + cv * eM01 + cvv * eM02 + A * e2M10 + B * e2M01;
+      Sp[0] = S0;
+      Sp[1] = S1;
+      Sp[2] = S2;
+      Sp[3] = 0.5 * S3;
+    }
+  } else {
+    (void)at;
+    const double cu = an[0], cuu = an[1], A = 0.5 * an[2];
+    const double eM1 = fma(x1, mu[1], mu[3]), eM2 = fma(x1, mu[2], mu[4]), eM3 = fma(x1, mu[3], mu[5]);
+    const double S1 = cu * mu[2] + cuu * mu[3] + A * eM2;
+    const double T1 = cu * mu[3] + cuu * mu[4] + A * eM3;
+    const double e2M2 = mu[6] + 2.0 * x1 * mu[4] + x2 * mu[2];
+    const double T3 = cu * eM2 + cuu * eM3 + A * e2M2;
+    Su[0] = S1;
+    Su[1] = T1;
+    Su[2] = 0.5 * T3;
+    if constexpr (PSI) {
+      const double S0 = cu * mu[1] + cuu * mu[2] + A * eM1;
+      const double e2M1 = mu[5] + 2.0 * x1 * mu[3] + x2 * mu[1];
+      const double S3 = cu * eM1 + cuu * eM2 + A * e2M1;
+      Sp[0] = S0;
+      Sp[1] = S1;
+      Sp[2] = 0.5 * S3;
+    }
+  }
+}
+
 // Exact Euler first and second time derivatives at a point (Cauchy-Kowalewski
 // in primitive variables) and the flux time derivative dF/dt along the
 // solution.  2D form; the 1D case has no y dependence and V = 0.
@@ -581,7 +667,7 @@ CGKS_HD __forceinline__ void side_terms(const double* Ws, int side, const double
                                         const Gas& g, SideSums<NC>& acc) {
   Mom<NC> m;
   moments<NC>(Ws, g, side, m);
-  double bn[NC], an[NC], at[NC], t1[NC], t2[NC];
+  double bn[NC], an[NC], at[NC] = {}, t1[NC], t2[NC];
   const double ir = m.ir;
 #pragma unroll
   for (int k = 0; k < NC; ++k) bn[k] = Wn[k] * ir;
@@ -591,29 +677,37 @@ CGKS_HD __forceinline__ void side_terms(const double* Ws, int side, const double
     for (int k = 0; k < NC; ++k) bn[k] = Wt[k] * ir;
     slope<NC>(m, g, bn, at);
   }
-  mom_psi<NC>(m, 1, 0, t1);                   // <u psi>
+  // <u psi> and, with FULL, <psi>
+  if constexpr (NC == 4) {
+    t1[0] = m.mu[1];
+    t1[1] = m.mu[2];
+    t1[2] = m.mu[1] * m.mv[1];
+    t1[3] = 0.5 * fma(m.x1, m.mu[1], m.mu[3] + m.mu[1] * m.mv[2]);
+  } else {
+    t1[0] = m.mu[1];
+    t1[1] = m.mu[2];
+    t1[2] = 0.5 * fma(m.x1, m.mu[1], m.mu[3]);
+  }
 #pragma unroll
   for (int k = 0; k < NC; ++k) acc.M4[k] += m.rho * t1[k];
-  mom_psi_a<NC>(m, 2, 0, an, t1);             // <u^2 psi a_n>
-  if constexpr (NC == 4) {
-    mom_psi_a<NC>(m, 1, 1, at, t2);           // <u v psi a_t>
-#pragma unroll
-    for (int k = 0; k < NC; ++k) t1[k] += t2[k];
-  }
+  // the slope terms: <u psi P> and <psi P>, P = u (a_n . psi) + v (a_t . psi)
+  slope_moments<NC, FULL>(m, an, at, t2, t1);
 #pragma unroll
   for (int k = 0; k < NC; ++k) acc.D35[k] -= m.rho * t1[k];
   if constexpr (FULL) {
-    mom_psi<NC>(m, 0, 0, t1);                 // <psi>
 #pragma unroll
-    for (int k = 0; k < NC; ++k) acc.Slr[k] += m.rho * t1[k];
-    mom_psi_a<NC>(m, 1, 0, an, t1);           // <u psi a_n>
+    for (int k = 0; k < NC; ++k) acc.Salr[k] += m.rho * t2[k];
+    double t0[NC];
+    t0[0] = m.mu[0];
+    t0[1] = m.mu[1];
     if constexpr (NC == 4) {
-      mom_psi_a<NC>(m, 0, 1, at, t2);         // <v psi a_t>
-#pragma unroll
-      for (int k = 0; k < NC; ++k) t1[k] += t2[k];
+      t0[2] = m.mu[0] * m.mv[1];
+      t0[3] = 0.5 * fma(m.mu[0], m.mv[2] + m.x1, m.mu[2]);
+    } else {
+      t0[2] = 0.5 * fma(m.mu[0], m.x1, m.mu[2]);
     }
 #pragma unroll
-    for (int k = 0; k < NC; ++k) acc.Salr[k] += m.rho * t1[k];
+    for (int k = 0; k < NC; ++k) acc.Slr[k] += m.rho * t0[k];
   }
 }
 
@@ -641,21 +735,17 @@ CGKS_HD __forceinline__ void equilibrium_terms(const double* W0, const double* W
                                                double tau_ce, const double* M2, double* D35, double* Fce) {
   Mom<NC> m;
   moments<NC>(W0, g, 0, m);
-  double bn[NC], an[NC], t1[NC];
+  double bn[NC], an[NC], at[NC] = {}, t1[NC];
   const double ir = m.ir;
 #pragma unroll
   for (int k = 0; k < NC; ++k) bn[k] = Wn[k] * ir;
   slope<NC>(m, g, bn, an);
-  mom_psi_a<NC>(m, 2, 0, an, t1);
   if constexpr (NC == 4) {
-    double at[NC], t2[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) bn[k] = Wt[k] * ir;
     slope<NC>(m, g, bn, at);
-    mom_psi_a<NC>(m, 1, 1, at, t2);
-#pragma unroll
-    for (int k = 0; k < NC; ++k) t1[k] += t2[k];
   }
+  slope_moments<NC, false>(m, an, at, nullptr, t1);     // <u psi (a_n u + a_t v)>
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     const double m3 = m.rho * t1[k];

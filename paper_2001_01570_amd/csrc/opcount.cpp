@@ -21,33 +21,80 @@
 
 #include <cmath>
 #include <cstdio>
+#include <map>
+#include <tuple>
+#include <utility>
 
 struct OpCounts {
   long add = 0, mul = 0, div = 0, sqrt_ = 0, exp_ = 0, erfc_ = 0;
 };
 static OpCounts g_ops;
 
+// Value numbering: every value carries an id; an operation on operands that
+// have been combined the same way before within the unit being counted (the
+// same operation on the same ids; + and * commutative) yields the earlier
+// value and is not counted again, as common-subexpression elimination would
+// keep it.  So a product written twice in the source is one operation.
+// Literal constants are numbered by value, inputs each get their own id.
 // An operation with an exact 0 operand (additions, multiplications) or an
 // exact +-1 factor is structural (a unit vector, an initial accumulator) and
 // is folded by the compiler: it is not counted.  The representative state has
-// no zero data, so only structural constants are skipped.
-inline bool trivial_add(double a, double b) { return a == 0.0 || b == 0.0; }
-inline bool trivial_mul(double a, double b) {
-  return a == 0.0 || b == 0.0 || a == 1.0 || b == 1.0 || a == -1.0 || b == -1.0;
+// no zero data, so only structural constants are skipped.  Negation and
+// fabs are operand modifiers and not counted.
+enum { OP_ADD = 1, OP_SUB, OP_MUL, OP_DIV, OP_NEG, OP_ABS, OP_SQRT, OP_EXP, OP_ERFC };
+static std::map<std::tuple<int, long, long>, long> g_vn;
+static std::map<double, long> g_lit;
+static long g_next_id = 1;
+inline long lit_id(double x) {
+  auto it = g_lit.find(x);
+  if (it != g_lit.end()) return it->second;
+  return g_lit[x] = g_next_id++;
 }
 struct CD {
   double v;
-  constexpr CD(double x = 0.0) : v(x) {}
-  CD& operator+=(const CD& o) { if (!trivial_add(v, o.v)) ++g_ops.add; v += o.v; return *this; }
-  CD& operator-=(const CD& o) { if (!trivial_add(v, o.v)) ++g_ops.add; v -= o.v; return *this; }
-  CD& operator*=(const CD& o) { if (!trivial_mul(v, o.v)) ++g_ops.mul; v *= o.v; return *this; }
-  CD& operator/=(const CD& o) { ++g_ops.div; v /= o.v; return *this; }
+  long id;
+  constexpr CD(double x = 0.0) : v(x), id(0) {}   // a literal: numbered by its value where used
+  constexpr CD(double x, long i) : v(x), id(i) {}
+  static CD input(double x) { return CD(x, g_next_id++); }
+  CD& operator+=(const CD& o);
+  CD& operator-=(const CD& o);
+  CD& operator*=(const CD& o);
+  CD& operator/=(const CD& o);
 };
-inline CD operator+(const CD& a, const CD& b) { if (!trivial_add(a.v, b.v)) ++g_ops.add; return CD(a.v + b.v); }
-inline CD operator-(const CD& a, const CD& b) { if (!trivial_add(a.v, b.v)) ++g_ops.add; return CD(a.v - b.v); }
-inline CD operator*(const CD& a, const CD& b) { if (!trivial_mul(a.v, b.v)) ++g_ops.mul; return CD(a.v * b.v); }
-inline CD operator/(const CD& a, const CD& b) { ++g_ops.div; return CD(a.v / b.v); }
-inline CD operator-(const CD& a) { return CD(-a.v); }
+// the result of op on (a, b); counter incremented only for a new value
+inline CD vn(int op, const CD& a, const CD& b, double r, long* counter) {
+  long ia = a.id ? a.id : lit_id(a.v), ib = b.id ? b.id : lit_id(b.v);
+  if ((op == OP_ADD || op == OP_MUL) && ia > ib) std::swap(ia, ib);
+  auto key = std::make_tuple(op, ia, ib);
+  auto it = g_vn.find(key);
+  if (it != g_vn.end()) return CD(r, it->second);
+  if (counter) ++*counter;
+  const long id = g_next_id++;
+  g_vn[key] = id;
+  return CD(r, id);
+}
+inline CD operator+(const CD& a, const CD& b) {
+  if (a.v == 0.0) return b;
+  if (b.v == 0.0) return a;
+  return vn(OP_ADD, a, b, a.v + b.v, &g_ops.add);
+}
+inline CD operator-(const CD& a, const CD& b) {
+  if (b.v == 0.0) return a;
+  return vn(OP_SUB, a, b, a.v - b.v, a.v == 0.0 ? nullptr : &g_ops.add);
+}
+inline CD operator*(const CD& a, const CD& b) {
+  if (a.v == 0.0 || b.v == 0.0) return CD(0.0);
+  if (a.v == 1.0) return b;
+  if (b.v == 1.0) return a;
+  if (a.v == -1.0 || b.v == -1.0) return vn(OP_MUL, a, b, a.v * b.v, nullptr);
+  return vn(OP_MUL, a, b, a.v * b.v, &g_ops.mul);
+}
+inline CD operator/(const CD& a, const CD& b) { return vn(OP_DIV, a, b, a.v / b.v, &g_ops.div); }
+inline CD operator-(const CD& a) { return vn(OP_NEG, a, a, -a.v, nullptr); }
+inline CD& CD::operator+=(const CD& o) { return *this = *this + o; }
+inline CD& CD::operator-=(const CD& o) { return *this = *this - o; }
+inline CD& CD::operator*=(const CD& o) { return *this = *this * o; }
+inline CD& CD::operator/=(const CD& o) { return *this = *this / o; }
 inline bool operator<(const CD& a, const CD& b) { return a.v < b.v; }
 inline bool operator>(const CD& a, const CD& b) { return a.v > b.v; }
 inline bool operator<=(const CD& a, const CD& b) { return a.v <= b.v; }
@@ -55,10 +102,11 @@ inline bool operator>=(const CD& a, const CD& b) { return a.v >= b.v; }
 inline bool operator==(const CD& a, const CD& b) { return a.v == b.v; }
 inline bool operator!=(const CD& a, const CD& b) { return a.v != b.v; }
 inline bool operator!(const CD& a) { return !a.v; }
-inline CD fabs(const CD& a) { return CD(std::fabs(a.v)); }
-inline CD sqrt(const CD& a) { ++g_ops.sqrt_; return CD(std::sqrt(a.v)); }
-inline CD exp(const CD& a) { ++g_ops.exp_; return CD(std::exp(a.v)); }
-inline CD erfc(const CD& a) { ++g_ops.erfc_; return CD(std::erfc(a.v)); }
+inline CD fma(const CD& a, const CD& b, const CD& c) { return a * b + c; }
+inline CD fabs(const CD& a) { return vn(OP_ABS, a, a, std::fabs(a.v), nullptr); }
+inline CD sqrt(const CD& a) { return vn(OP_SQRT, a, a, std::sqrt(a.v), &g_ops.sqrt_); }
+inline CD exp(const CD& a) { return vn(OP_EXP, a, a, std::exp(a.v), &g_ops.exp_); }
+inline CD erfc(const CD& a) { return vn(OP_ERFC, a, a, std::erfc(a.v), &g_ops.erfc_); }
 
 #define CGKS_OPCOUNT
 #define double CD
@@ -67,7 +115,10 @@ inline CD erfc(const CD& a) { ++g_ops.erfc_; return CD(std::erfc(a.v)); }
 
 using namespace cgks;
 
-static OpCounts snap() { return g_ops; }
+static OpCounts snap() {   // start of a unit: values of earlier units are not reused
+  g_vn.clear();
+  return g_ops;
+}
 static OpCounts diff(const OpCounts& a, const OpCounts& b) {
   OpCounts d;
   d.add = b.add - a.add; d.mul = b.mul - a.mul; d.div = b.div - a.div;
@@ -91,57 +142,58 @@ int main() {
 
   // one normal reconstruction (one line, one component)
   OpCounts a = snap();
-  Line5 L = normal_line(CD(1.1e-4), CD(-0.9e-4), CD(2.1e-4), CD(0.5e-4), CD(-0.7e-4), CD(1.3e-4), CD(0.2e-4), CD(1e-6));
+  Line5 L = normal_line(CD::input(1.1e-4), CD::input(-0.9e-4), CD::input(2.1e-4), CD::input(0.5e-4), CD::input(-0.7e-4),
+                        CD::input(1.3e-4), CD::input(0.2e-4), CD::input(1e-6));
   (void)L;
   CD hT, hTN;
-  cross_face(CD(0.3), CD(-0.2), CD(0.25), CD(0.1), CD(ht), hT, hTN);
+  cross_face(CD::input(0.3), CD::input(-0.2), CD::input(0.25), CD::input(0.1), CD::input(ht), hT, hTN);
   const OpCounts recon = diff(a, snap());
 
   // tangential fits to one Gauss point (4 components): three segments
   CD lines[32][3];
   for (int q = 0; q < 32; ++q)
-    for (int l = 0; l < 3; ++l) lines[q][l] = CD(1e-5 * (q + 1) * (l + 1));
+    for (int l = 0; l < 3; ++l) lines[q][l] = CD::input(1e-5 * (q + 1) * (l + 1));
   for (int l = 0; l < 3; ++l)
-    for (int k = 0; k < 4; ++k) lines[20 + k][l] = CD((k == 3 ? 1.8 : 1.0) + 1e-4 * l);
+    for (int k = 0; k < 4; ++k) lines[20 + k][l] = CD::input((k == 3 ? 1.8 : 1.0) + 1e-4 * l);
   auto get = [&](int q, int l) { return lines[q][l]; };
   PointIn<4> in;
   CD dev[4], ref[4];
   a = snap();
-  tangential_point<3>(get, host_tang7[0], host_herm2[0], CD(1.0), CD(hn), CD(ht), in, dev, ref);
+  tangential_point<3>(get, host_tang7[0], host_herm2[0], CD(1.0), CD::input(hn), CD::input(ht), in, dev, ref);
   const OpCounts tang = diff(a, snap());
   // the sextic through 7 segment averages (four Gauss points per segment)
   CD lines7[32][7];
   for (int q = 0; q < 32; ++q)
-    for (int l = 0; l < 7; ++l) lines7[q][l] = CD(1e-5 * (q + 1) * (l + 1));
+    for (int l = 0; l < 7; ++l) lines7[q][l] = CD::input(1e-5 * (q + 1) * (l + 1));
   for (int l = 0; l < 7; ++l)
-    for (int k = 0; k < 4; ++k) lines7[20 + k][l] = CD((k == 3 ? 1.8 : 1.0) + 1e-4 * l);
+    for (int k = 0; k < 4; ++k) lines7[20 + k][l] = CD::input((k == 3 ? 1.8 : 1.0) + 1e-4 * l);
   auto get7 = [&](int q, int l) { return lines7[q][l]; };
   {
     PointIn<4> in7;
     a = snap();
-    tangential_point<7>(get7, host_tang7[0], host_herm4[0], CD(1.0), CD(hn), CD(ht), in7, dev, ref);
+    tangential_point<7>(get7, host_tang7[0], host_herm4[0], CD(1.0), CD::input(hn), CD::input(ht), in7, dev, ref);
   }
   const OpCounts tang7 = diff(a, snap());
   a = snap();
-  tangential_point<3>(get, host_tang7[0], host_herm2[0], CD(1.0), CD(hn), CD(ht), in, dev, ref);   // the input of the point counts below
+  tangential_point<3>(get, host_tang7[0], host_herm2[0], CD(1.0), CD::input(hn), CD::input(ht), in, dev, ref);   // the input of the point counts below
   (void)diff(a, snap());
-  for (int k = 0; k < 4; ++k) { in.Wl[k] = in.W0[k] + CD(1e-9); in.Wr[k] = in.W0[k] - CD(1e-9); }
+  for (int k = 0; k < 4; ++k) { in.Wl[k] = CD::input(in.W0[k].v + 1e-9); in.Wr[k] = CD::input(in.W0[k].v - 1e-9); }
 
   PointOut<4> o;
   a = snap();
-  gks_point<4, true>(in, gas, CD(dt), o);
+  gks_point<4, true>(in, gas, CD::input(dt), o);
   const OpCounts gks1 = diff(a, snap());
   a = snap();
-  gks_point<4, false>(in, gas, CD(dt), o);
+  gks_point<4, false>(in, gas, CD::input(dt), o);
   const OpCounts gks2 = diff(a, snap());
 
   CD acc[16];
   for (int q = 0; q < 16; ++q) acc[q] = CD(0.0);
   a = snap();
-  face_accumulate<4, true>(acc, o, dev, ref, CD(dt));
+  face_accumulate<4, true>(acc, o, dev, ref, CD::input(dt));
   const OpCounts acc1 = diff(a, snap());
   a = snap();
-  face_accumulate<4, false>(acc, o, dev, ref, CD(dt));
+  face_accumulate<4, false>(acc, o, dev, ref, CD::input(dt));
   const OpCounts acc2 = diff(a, snap());
 
   // per face segment of a stage: 4 component reconstructions of its own line
