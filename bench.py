@@ -140,13 +140,14 @@ def serving_requests(nreq):
     return [reqs[k] for k in range(nreq)]
 
 
-def serving(reqs, steps_per_run=10):
+def serving(reqs, steps_per_run=None):
     """Serving workload over the requests reqs.  (1) the plain path closed
     loop (one context per request: create, load from host, 200 steps, read to
     host) gives the rate r; (2) Poisson arrivals at 2r (default_rng(7)) are
     replayed in real time through the plain path (FIFO, one request at a time)
     and through the batch API (admit on arrival, advance all running requests
-    steps_per_run steps per graph replay, read and release on completion).
+    steps_per_run steps per graph replay -- by default the autotuner's
+    figure -- read and release on completion).
     (3) The batch's own capacity c (every request admitted at once), and a
     second batch replay with the same draws at 0.7c, where the queue stays
     short and the latency is the steady-state one.
@@ -156,8 +157,10 @@ def serving(reqs, steps_per_run=10):
     steps = reqs[0].steps
 
     import torch
-    from paper_2001_01570_amd.cgks import Batch, Solver, SLOT_DONE, SLOT_FAILED, CgksError, CGKS_EBUSY
+    from paper_2001_01570_amd.cgks import Batch, Solver, SLOT_DONE, SLOT_FAILED, CgksError, CGKS_EBUSY, batch_tuning
     torch.cuda.init()
+    if steps_per_run is None:        # the autotuner's steps per graph replay
+        steps_per_run = batch_tuning()[2]
 
     def plain_solve(p):
         s = Solver(p)

@@ -79,9 +79,8 @@ typedef struct {
                                 quartic through 5 segment averages, two points
                                 (fourth order in space in 2D; the default).  4:
                                 the sextic through 7 segment averages, four
-                                points (eighth order in 2D; FP64 storage, walls
-                                need 3 cells across, not in the batch API,
-                                tile shape fixed)                                    */
+                                points (eighth order in 2D; walls need 3 cells
+                                across; tile shape fixed)                            */
 } cgks_config;
 
 typedef struct {
@@ -200,10 +199,12 @@ int cgks_batch_create(size_t hbm_budget_bytes, int max_slots, void *hip_stream, 
 /* Admit a 2D problem (configuration and initial state as for a context; the
  * state is copied, host or device pointer) that runs until t_end (> 0) or for
  * max_steps (> 0) steps, whichever comes first (one of them must be given).
- * Returns its slot.  CGKS_EBUSY: no free slot or no room in the arena;
- * CGKS_ENONPHYS: non-physical initial state; CGKS_EINVAL: bad configuration,
- * dim != 2 or FP32 storage (the batch runs FP64 storage).  A device pointer
- * must be ready (its producer synchronized). */
+ * Any configuration a 2D context accepts is admitted: two or four Gauss
+ * points, FP64 or FP32 gradient storage; slots of each such kind share their
+ * own face launches, so a mix of kinds runs in one step.  Returns its slot.
+ * CGKS_EBUSY: no free slot or no room in the arena; CGKS_ENONPHYS:
+ * non-physical initial state; CGKS_EINVAL: bad configuration or dim != 2.  A
+ * device pointer must be ready (its producer synchronized). */
 int cgks_batch_admit(cgks_batch *b, const cgks_config *cfg, const double *fields, int on_device,
                      double t_end, long max_steps, int *slot);
 
@@ -215,6 +216,16 @@ int cgks_batch_poll(cgks_batch *b, int slot, int *state, double *t, long *step);
 
 /* Copy a slot's current state out (layout as for a context). */
 int cgks_batch_read(cgks_batch *b, int slot, double *fields_out, int on_device);
+
+/* Face tile shapes (as for cgks_set_tiles) of the two-point FP64 slots;
+ * only while no slot is admitted (CGKS_ESTATE otherwise).  A new batch takes
+ * the autotuner's shapes.  Results do not depend on the shapes. */
+int cgks_batch_set_tiles(cgks_batch *b, int x_shape, int y_shape);
+
+/* The autotuner's batch entry: tile shapes of the two-point FP64 slots and
+ * the steps per cgks_batch_run that gave the serving mix its highest rate
+ * (any pointer may be NULL). */
+int cgks_batch_tuning(int *x_shape, int *y_shape, int *steps_per_run);
 
 /* Free a slot and return its memory to the arena. */
 int cgks_batch_release(cgks_batch *b, int slot);

@@ -85,6 +85,8 @@ def load():
     L.cgks_batch_poll.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), _D, C.POINTER(C.c_long)]
     L.cgks_batch_read.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
     L.cgks_batch_release.argtypes = [C.c_void_p, C.c_int]
+    L.cgks_batch_set_tiles.argtypes = [C.c_void_p, C.c_int, C.c_int]
+    L.cgks_batch_tuning.argtypes = [C.POINTER(C.c_int)] * 3
     L.cgks_batch_destroy.argtypes = [C.c_void_p]
     L.cgks_batch_destroy.restype = None
     L.cgks_step_noalloc.argtypes = [C.POINTER(cgks_config), C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, _D]
@@ -265,6 +267,13 @@ def step_noalloc(prob, fields_in, fields_out, dt: float = 0.0, stream=None, wait
 SLOT_FREE, SLOT_RUNNING, SLOT_DONE, SLOT_FAILED = 0, 1, 2, 3
 
 
+def batch_tuning():
+    """The library's tuned batch entry: (x tile shape, y tile shape, steps per run)."""
+    x, y, n = C.c_int(), C.c_int(), C.c_int()
+    load().cgks_batch_tuning(C.byref(x), C.byref(y), C.byref(n))
+    return x.value, y.value, n.value
+
+
 class Batch:
     """Many independent 2D problems advanced together (see cgks_batch_* in
     include/cgks.h).  Slots are admitted with a configuration (a Problem) and
@@ -294,11 +303,15 @@ class Batch:
 
     def admit(self, prob, fields=None, t_end: float = 0.0, max_steps: int = 0) -> int:
         """Returns the slot; raises CgksError (code CGKS_EBUSY when full)."""
+        return self.admit_storage(prob, CGKS_FP64, fields, t_end, max_steps)
+
+    def admit_storage(self, prob, storage: int, fields=None, t_end: float = 0.0, max_steps: int = 0) -> int:
+        """admit with the gradient storage given (CGKS_FP64 or CGKS_FP32_STORAGE)."""
         torch = _torch()
         fields = prob.fields if fields is None else fields
         shape = (12, prob.ny, prob.nx) if prob.dim == 2 else (6, prob.nx)   # the library rejects dim 1
         slot = C.c_int()
-        cfg = make_config(prob)
+        cfg = make_config(prob, storage)
         if isinstance(fields, torch.Tensor) and fields.is_cuda:
             assert tuple(fields.shape) == shape and fields.dtype == torch.float64
             f = fields.contiguous()
@@ -338,6 +351,12 @@ class Batch:
         if rc:
             raise CgksError(rc, 'cgks_batch_read')
         return out
+
+    def set_tiles(self, x_shape: int, y_shape: int):
+        """Face tile shapes of the two-point FP64 slots (before any admit); speed only."""
+        rc = load().cgks_batch_set_tiles(self.h, int(x_shape), int(y_shape))
+        if rc:
+            raise CgksError(rc, 'cgks_batch_set_tiles')
 
     def release(self, slot: int):
         rc = load().cgks_batch_release(self.h, int(slot))

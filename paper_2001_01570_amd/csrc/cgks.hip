@@ -50,12 +50,6 @@ constexpr int kTileShapes = 3;
 // four Gauss points per segment with the 7-line stencil (x faces, y faces)
 using Tile4x16G4 = Tile<4, 16, 4, 3>;
 using Tile2x32G4 = Tile<2, 32, 4, 3>;
-// the batched face kernels' tiles per direction: the shapes the tuner picks
-// for most grids from 64^2 to 2048^2 (x faces 4x32, y faces 2x64)
-template <int DIR> struct BatchTile { using T = Tile4x32; };
-template <> struct BatchTile<1> { using T = Tile2x64; };
-using BTX = BatchTile<0>::T;
-using BTY = BatchTile<1>::T;
 constexpr int NQ = 32;          // per segment: 5 quantities x 4 components, 4 reference values, 2 x 4 tangential-gradient data
 constexpr int FACE_THREADS = 256;   // one thread per Gauss point of the tile's face segments
 // waves per SIMD the face kernels are compiled for (register budget 512 / waves:
@@ -759,22 +753,41 @@ __global__ __launch_bounds__(256) void k_steps1(Geom G, Bufs B, int nsteps, int 
 // all running slots, one block each.  Its grid is a power-of-two bucket of
 // the list's length (blocks past the end return at once), so the list may
 // change between runs without a new graph until it outgrows its bucket.
-// Within a run each slot keeps its own step size, time and status.
+// Within a run each slot keeps its own step size, time and status.  Slots
+// of each kind (Gauss points x gradient storage) have face work lists of
+// their own, launched with that kind's kernels; the updates have one list per
+// storage.
 constexpr int kMaxSlots = 1024;
 
 struct SlotDev {
   Geom G;
   Bufs B;
-  int gxw, gyw, guw;   // blocks along the first grid axis: x-face, y-face and update grids
+  int gw[2];           // tiles along the first axis of the x-face and y-face grids
+  int guw;             // blocks along x of the update grid
   int nparts;          // CFL partial maxima (update blocks)
 };
 
-// Running slots: work item i of a kind belongs to the k-th of them when
-// pre[k] <= i < pre[k + 1] (x-face tiles, y-face tiles, update blocks).
-struct BatchTable {
+// Slot kinds: the face kernels differ by Gauss points and gradient storage.
+enum { BK_G2 = 0, BK_G4 = 1, BK_G2_F32 = 2, BK_G4_F32 = 3, BK_KINDS = 4 };
+
+// Running slots of one kind: work item i of a face direction belongs to the
+// k-th of them when pre[dir][k] <= i < pre[dir][k + 1] (face tiles).
+struct FaceList {
   int n;
   int slot[kMaxSlots];
-  int pre_x[kMaxSlots + 1], pre_y[kMaxSlots + 1], pre_u[kMaxSlots + 1];
+  int pre[2][kMaxSlots + 1];
+};
+// Running slots of one storage (0: FP64, 1: FP32 gradients): update blocks.
+struct UpdateList {
+  int n;
+  int slot[kMaxSlots];
+  int pre[kMaxSlots + 1];
+};
+struct BatchTable {
+  int n;               // every running slot (step begin and end)
+  int slot[kMaxSlots];
+  FaceList face[BK_KINDS];
+  UpdateList upd[2];
 };
 
 __device__ __forceinline__ int find_slot(const int* pre, int n, int b) {
@@ -808,31 +821,33 @@ __global__ void kb_end(const SlotDev* slots, const BatchTable* tab) {
   end_body(slots[tab->slot[blockIdx.x]].B.sc);
 }
 
-template <int DIR, int STAGE>
+// Face tiles of the slots of one kind (tile shape TL, gradient storage GT).
+template <int DIR, int STAGE, class GT, class TL>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces(const SlotDev* slots,
-                                                                            const BatchTable* tab) {
-  using TL = typename BatchTile<DIR>::T;
+                                                                            const BatchTable* tab, int kind) {
   __shared__ double lds[NQ][TL::NSEG];
-  const int n = tab->n;
-  const int* pre = DIR == 0 ? tab->pre_x : tab->pre_y;
+  const FaceList& L = tab->face[kind];
+  const int n = L.n;
+  const int* pre = L.pre[DIR];
   const int item = xcd_item(pre[n]);
   if (item < 0) return;
   const int k = find_slot(pre, n, item);
-  const SlotDev& sd = slots[tab->slot[k]];
+  const SlotDev& sd = slots[L.slot[k]];
   const int local = item - pre[k];
-  const int w = DIR == 0 ? sd.gxw : sd.gyw;
-  faces2_body<DIR, STAGE, double, TL>(sd.G, sd.B, local % w, local / w, lds);
+  const int w = sd.gw[DIR];
+  faces2_body<DIR, STAGE, GT, TL>(sd.G, sd.B, local % w, local / w, lds);
 }
 
-template <int STAGE>
-__global__ __launch_bounds__(256) void kb_update(const SlotDev* slots, const BatchTable* tab) {
-  const int n = tab->n;
+template <int STAGE, class GT>
+__global__ __launch_bounds__(256) void kb_update(const SlotDev* slots, const BatchTable* tab, int storage) {
+  const UpdateList& L = tab->upd[storage];
+  const int n = L.n;
   const int item = blockIdx.x;
-  if (item >= tab->pre_u[n]) return;
-  const int k = find_slot(tab->pre_u, n, item);
-  const SlotDev& sd = slots[tab->slot[k]];
-  const int local = item - tab->pre_u[k];
-  update2_body<STAGE>(sd.G, sd.B, local % sd.guw, local / sd.guw, local);
+  if (item >= L.pre[n]) return;
+  const int k = find_slot(L.pre, n, item);
+  const SlotDev& sd = slots[L.slot[k]];
+  const int local = item - L.pre[k];
+  update2_body<STAGE, GT>(sd.G, sd.B, local % sd.guw, local / sd.guw, local);
 }
 
 }  // namespace cgks
@@ -915,7 +930,7 @@ static int validate(const cgks_config* c) {
   if (!(c->mu >= 0.0) || !std::isfinite(c->mu)) return CGKS_EINVAL;
   if (c->storage != CGKS_FP64 && !(c->storage == CGKS_FP32_STORAGE && c->dim == 2)) return CGKS_EINVAL;
   const int gp = c->gauss_points ? c->gauss_points : 2;
-  if (gp != 2 && !(gp == 4 && c->dim == 2 && c->storage == CGKS_FP64)) return CGKS_EINVAL;
+  if (gp != 2 && !(gp == 4 && c->dim == 2)) return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
     if (c->bc[s] < 0 || c->bc[s] > 4) return CGKS_EINVAL;
     const int n = s < 2 ? c->nx : c->ny;
@@ -1150,11 +1165,9 @@ static void launch_step_on(const Geom& G, const Bufs& B, int gp, int storage, co
                                 : dim3((G.nx + TL::T - 1) / TL::T, (G.ny + 1 + TL::F - 1) / TL::F);
         run(kind, [&] { k_faces2<DIR, STAGE, GT, TL><<<g, FACE_THREADS, 0, s>>>(G, B); });
       };
-      if (gp == 4) {        // FP64 storage only (validated)
-        if constexpr (std::is_same_v<GT, double>) {
-          if constexpr (DIR == 0) go(Tile4x16G4());
-          else go(Tile2x32G4());
-        }
+      if (gp == 4) {
+        if constexpr (DIR == 0) go(Tile4x16G4());
+        else go(Tile2x32G4());
         return;
       }
       switch (tiles[DIR]) {
@@ -1511,8 +1524,24 @@ struct SlotInfo {
   int used = 0;
   size_t off = 0, bytes = 0;
   size_t N = 0;
-  int nbx = 0, nby = 0, nbu = 0;   // blocks of the x-face, y-face and update grids
+  int kind = 0;                    // BK_*
+  int nb[2] = {0, 0}, nbu = 0;     // blocks of the x-face, y-face and update grids
 };
+
+// Face tile shape of a kind per direction: two points with FP64 storage use
+// the batch's tuned shapes (0 = 8x16, 1 = 4x32, 2 = 2x64), FP32 storage 4x32
+// and 2x64, four points the four-point tiles.
+struct TileDims { int F, T; };
+static TileDims kind_tile(int kind, int dir, const int* tile) {
+  if (kind == BK_G4 || kind == BK_G4_F32)
+    return dir == 0 ? TileDims{Tile4x16G4::F, Tile4x16G4::T} : TileDims{Tile2x32G4::F, Tile2x32G4::T};
+  const int shape = kind == BK_G2 ? tile[dir] : (dir == 0 ? 1 : 2);
+  switch (shape) {
+    case 1: return TileDims{Tile4x32::F, Tile4x32::T};
+    case 2: return TileDims{Tile2x64::F, Tile2x64::T};
+    default: return TileDims{Tile8x16::F, Tile8x16::T};
+  }
+}
 
 }  // namespace
 
@@ -1530,9 +1559,11 @@ struct cgks_batch {
   std::vector<SlotInfo> info;
   std::vector<int> table;           // running slots in the current table
   int dirty = 1;                    // a slot was admitted or released since the table was built
-  int cap_n = 0, cap_x = 0, cap_y = 0, cap_u = 0;   // grid buckets of the captured graph
+  int cap_n = 0;                    // grid bucket of the begin/end launches
+  int tile[2] = {1, 2};             // face tile shapes of the two-point FP64 slots
   hipGraphExec_t exec = nullptr;
   int graph_steps = 0;
+  int cap_f[BK_KINDS][2] = {}, cap_u2[2] = {};   // face and update grid buckets per kind / storage
 };
 
 static int slot_state(const cgks_batch* b, int k) {
@@ -1591,6 +1622,8 @@ extern "C" int cgks_batch_create(size_t hbm_budget_bytes, int max_slots, void* h
     return CGKS_ENOMEM;
   }
   b->arena.free_[0] = b->arena.size;
+  b->tile[0] = kBatchTune.x;
+  b->tile[1] = kBatchTune.y;
   b->h_slots.assign(max_slots, SlotDev());
   b->info.assign(max_slots, SlotInfo());
   std::memset(b->h_sc, 0, sizeof(Scalars) * max_slots);
@@ -1604,8 +1637,7 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   if (!b || !fields || !slot) return CGKS_EINVAL;
   int rc = validate(cfg);
   if (rc) return rc;
-  if (cfg->dim != 2 || cfg->storage != CGKS_FP64 || (cfg->gauss_points != 0 && cfg->gauss_points != 2))
-    return CGKS_EINVAL;
+  if (cfg->dim != 2) return CGKS_EINVAL;
   if (!(t_end > 0.0) && max_steps <= 0) return CGKS_EINVAL;   // a request needs an end
   int k = 0;
   while (k < b->max_slots && b->info[k].used) ++k;
@@ -1613,6 +1645,9 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
 
   SlotDev& sd = b->h_slots[k];
   SlotInfo& in = b->info[k];
+  const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
+  const int f32 = cfg->storage == CGKS_FP32_STORAGE;
+  const int kind = gp == 4 ? (f32 ? BK_G4_F32 : BK_G4) : (f32 ? BK_G2_F32 : BK_G2);
   make_geom(*cfg, sd.G);
   const Geom& G = sd.G;
   const size_t N = (size_t)G.nx * G.ny;
@@ -1633,16 +1668,18 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   sd.B.FY = (double*)p; p += fy;
   sd.B.lam_part = (double*)p;
   sd.B.sc = b->d_sc + k;
-  sd.gxw = (G.nx + 1 + BTX::F - 1) / BTX::F;
-  sd.gyw = (G.nx + BTY::T - 1) / BTY::T;
+  const TileDims tx = kind_tile(kind, 0, b->tile), ty = kind_tile(kind, 1, b->tile);
+  sd.gw[0] = (G.nx + 1 + tx.F - 1) / tx.F;
+  sd.gw[1] = (G.nx + ty.T - 1) / ty.T;
   sd.guw = (int)gu.x;
   sd.nparts = (int)(gu.x * gu.y);
   in.used = 1;
   in.off = off;
   in.bytes = bytes;
   in.N = N;
-  in.nbx = sd.gxw * ((G.ny + BTX::T - 1) / BTX::T);
-  in.nby = sd.gyw * ((G.ny + 1 + BTY::F - 1) / BTY::F);
+  in.kind = kind;
+  in.nb[0] = sd.gw[0] * ((G.ny + tx.T - 1) / tx.T);
+  in.nb[1] = sd.gw[1] * ((G.ny + 1 + ty.F - 1) / ty.F);
   in.nbu = sd.nparts;
 
   Scalars& h = b->h_sc[k];
@@ -1653,10 +1690,20 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   h.cfl = cfg->cfl;
   h.fixed_dt = cfg->fixed_dt;
   h.bad_cell = ULLONG_MAX;
-  bool ok = hipMemcpyAsync(sd.B.S[0], fields, 12 * N * sizeof(double),
-                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, b->stream) == hipSuccess &&
-            hipMemcpyAsync(b->d_sc + k, &h, sizeof h, hipMemcpyHostToDevice, b->stream) == hipSuccess &&
-            hipMemcpyAsync(b->d_slots + k, &sd, sizeof sd, hipMemcpyHostToDevice, b->stream) == hipSuccess;
+  bool ok;
+  if (f32) {   // staged in W* (free between steps), then converted to the storage layout
+    ok = hipMemcpyAsync(sd.B.Ws, fields, 12 * N * sizeof(double),
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, b->stream) == hipSuccess;
+    if (ok) {
+      k_to_storage32<<<(unsigned)((N + 255) / 256), 256, 0, b->stream>>>(sd.B.Ws, sd.B.S[0], N);
+      ok = hipGetLastError() == hipSuccess;
+    }
+  } else {
+    ok = hipMemcpyAsync(sd.B.S[0], fields, 12 * N * sizeof(double),
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, b->stream) == hipSuccess;
+  }
+  ok = ok && hipMemcpyAsync(b->d_sc + k, &h, sizeof h, hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+       hipMemcpyAsync(b->d_slots + k, &sd, sizeof sd, hipMemcpyHostToDevice, b->stream) == hipSuccess;
   if (ok) {
     k_scan<4><<<gu, 256, 0, b->stream>>>(sd.G, sd.B);
     ok = hipGetLastError() == hipSuccess &&
@@ -1673,8 +1720,8 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   return CGKS_OK;
 }
 
-// Work list of the running slots (the graph reads it from device memory and
-// needs no new capture while each list stays in its grid bucket).
+// Work lists of the running slots (the graph reads them from device memory
+// and needs no new capture while each list stays in its grid bucket).
 static int refresh_table(cgks_batch* b) {
   std::vector<int> run;
   for (int k = 0; k < b->max_slots; ++k)
@@ -1685,46 +1732,92 @@ static int refresh_table(cgks_batch* b) {
   b->table = run;
   BatchTable& t = *b->h_tab;
   t.n = (int)run.size();
-  t.pre_x[0] = t.pre_y[0] = t.pre_u[0] = 0;
+  for (int q = 0; q < BK_KINDS; ++q) t.face[q].n = t.face[q].pre[0][0] = t.face[q].pre[1][0] = 0;
+  for (int q = 0; q < 2; ++q) t.upd[q].n = t.upd[q].pre[0] = 0;
   for (int i = 0; i < t.n; ++i) {
     const SlotInfo& in = b->info[run[i]];
     t.slot[i] = run[i];
-    t.pre_x[i + 1] = t.pre_x[i] + in.nbx;
-    t.pre_y[i + 1] = t.pre_y[i] + in.nby;
-    t.pre_u[i + 1] = t.pre_u[i] + in.nbu;
+    FaceList& F = t.face[in.kind];
+    F.slot[F.n] = run[i];
+    F.pre[0][F.n + 1] = F.pre[0][F.n] + in.nb[0];
+    F.pre[1][F.n + 1] = F.pre[1][F.n] + in.nb[1];
+    ++F.n;
+    UpdateList& U = t.upd[in.kind >= BK_G2_F32];
+    U.slot[U.n] = run[i];
+    U.pre[U.n + 1] = U.pre[U.n] + in.nbu;
+    ++U.n;
   }
-  // grids: power-of-two buckets; a new graph only when a list leaves its bucket
-  // (buckets are multiples of NXCD and >= NXCD * ceil(len / NXCD), as the
-  // face kernels' XCD mapping needs)
+  // grids: power-of-two buckets (0 for an empty list: its launches are left
+  // out); a new graph only when a list leaves its bucket (buckets are
+  // multiples of NXCD and >= NXCD * ceil(len / NXCD), as the face kernels'
+  // XCD mapping needs)
   auto bucket = [](int len, int cap) {
+    if (len == 0) return 0;
     const int need = (len + NXCD - 1) / NXCD * NXCD;
     if (cap > 0 && need <= cap && 4 * need > cap) return cap;
     int c = 64;
     while (c < need) c *= 2;
     return c;
   };
-  const int cn = bucket(t.n, b->cap_n), cx = bucket(t.pre_x[t.n], b->cap_x);
-  const int cy = bucket(t.pre_y[t.n], b->cap_y), cu = bucket(t.pre_u[t.n], b->cap_u);
-  if (cn != b->cap_n || cx != b->cap_x || cy != b->cap_y || cu != b->cap_u) {
-    drop_graph(b);
-    b->cap_n = cn; b->cap_x = cx; b->cap_y = cy; b->cap_u = cu;
-  }
+  bool changed = false;
+  auto rebucket = [&](int len, int& cap) {
+    const int c = bucket(len, cap);
+    changed |= c != cap;
+    cap = c;
+  };
+  rebucket(t.n, b->cap_n);
+  for (int q = 0; q < BK_KINDS; ++q)
+    for (int d = 0; d < 2; ++d) rebucket(t.face[q].pre[d][t.face[q].n], b->cap_f[q][d]);
+  for (int q = 0; q < 2; ++q) rebucket(t.upd[q].pre[t.upd[q].n], b->cap_u2[q]);
+  if (changed) drop_graph(b);
   HIPCHK(hipMemcpyAsync(b->d_tab, &t, sizeof t, hipMemcpyHostToDevice, b->stream));
   return CGKS_OK;
 }
 
-// One step of every running slot: eight launches of fixed size.
+// One step of every running slot: begin, the face kernels of each kind present
+// and the updates of each storage present for both stages, end.
 static void launch_batch_step(cgks_batch* b) {
   hipStream_t s = b->stream;
   const SlotDev* sl = b->d_slots;
   const BatchTable* t = b->d_tab;
   kb_begin<<<b->cap_n, 256, 0, s>>>(sl, t);
-  kb_faces<0, 1><<<b->cap_x, FACE_THREADS, 0, s>>>(sl, t);
-  kb_faces<1, 1><<<b->cap_y, FACE_THREADS, 0, s>>>(sl, t);
-  kb_update<1><<<b->cap_u, 256, 0, s>>>(sl, t);
-  kb_faces<0, 2><<<b->cap_x, FACE_THREADS, 0, s>>>(sl, t);
-  kb_faces<1, 2><<<b->cap_y, FACE_THREADS, 0, s>>>(sl, t);
-  kb_update<2><<<b->cap_u, 256, 0, s>>>(sl, t);
+  using D0 = std::integral_constant<int, 0>;
+  using D1 = std::integral_constant<int, 1>;
+  auto faces = [&](auto dir, auto stage) {
+    constexpr int DIR = decltype(dir)::value, STAGE = decltype(stage)::value;
+    for (int q = 0; q < BK_KINDS; ++q) {
+      const int g = b->cap_f[q][DIR];
+      if (!g) continue;
+      auto go = [&](auto gt, auto tl) {
+        kb_faces<DIR, STAGE, decltype(gt), decltype(tl)><<<g, FACE_THREADS, 0, s>>>(sl, t, q);
+      };
+      if (q == BK_G4 || q == BK_G4_F32) {
+        if (q == BK_G4) { if constexpr (DIR == 0) go(0.0, Tile4x16G4()); else go(0.0, Tile2x32G4()); }
+        else { if constexpr (DIR == 0) go(0.0f, Tile4x16G4()); else go(0.0f, Tile2x32G4()); }
+      } else if (q == BK_G2_F32) {
+        if constexpr (DIR == 0) go(0.0f, Tile4x32()); else go(0.0f, Tile2x64());
+      } else {
+        switch (b->tile[DIR]) {
+          case 1: go(0.0, Tile4x32()); break;
+          case 2: go(0.0, Tile2x64()); break;
+          default: go(0.0, Tile8x16()); break;
+        }
+      }
+    }
+  };
+  auto updates = [&](auto stage) {
+    constexpr int STAGE = decltype(stage)::value;
+    if (b->cap_u2[0]) kb_update<STAGE, double><<<b->cap_u2[0], 256, 0, s>>>(sl, t, 0);
+    if (b->cap_u2[1]) kb_update<STAGE, float><<<b->cap_u2[1], 256, 0, s>>>(sl, t, 1);
+  };
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  faces(D0(), S1());
+  faces(D1(), S1());
+  updates(S1());
+  faces(D0(), S2());
+  faces(D1(), S2());
+  updates(S2());
   kb_end<<<b->cap_n, 64, 0, s>>>(sl, t);
 }
 
@@ -1770,9 +1863,37 @@ extern "C" int cgks_batch_read(cgks_batch* b, int slot, double* fields_out, int 
   if (!b || !fields_out || slot < 0 || slot >= b->max_slots) return CGKS_EINVAL;
   if (!b->info[slot].used) return CGKS_ESTATE;
   const SlotDev& sd = b->h_slots[slot];
-  HIPCHK(hipMemcpyAsync(fields_out, sd.B.S[b->h_sc[slot].cur], 12 * b->info[slot].N * sizeof(double),
-                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));
+  const size_t N = b->info[slot].N;
+  const double* S = sd.B.S[b->h_sc[slot].cur];
+  if (b->info[slot].kind >= BK_G2_F32) {
+    // converted to FP64 straight into a device output, else via W* (free between steps)
+    double* dst = on_device ? fields_out : sd.B.Ws;
+    k_from_storage32<<<(unsigned)((N + 255) / 256), 256, 0, b->stream>>>(S, dst, N);
+    HIPCHK(hipGetLastError());
+    if (!on_device)
+      HIPCHK(hipMemcpyAsync(fields_out, sd.B.Ws, 12 * N * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  } else {
+    HIPCHK(hipMemcpyAsync(fields_out, S, 12 * N * sizeof(double),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));
+  }
   HIPCHK(hipStreamSynchronize(b->stream));
+  return CGKS_OK;
+}
+
+extern "C" int cgks_batch_set_tiles(cgks_batch* b, int x_shape, int y_shape) {
+  if (!b || x_shape < 0 || x_shape >= kTileShapes || y_shape < 0 || y_shape >= kTileShapes) return CGKS_EINVAL;
+  for (int k = 0; k < b->max_slots; ++k)
+    if (b->info[k].used) return CGKS_ESTATE;
+  b->tile[0] = x_shape;
+  b->tile[1] = y_shape;
+  drop_graph(b);
+  return CGKS_OK;
+}
+
+extern "C" int cgks_batch_tuning(int* x_shape, int* y_shape, int* steps_per_run) {
+  if (x_shape) *x_shape = kBatchTune.x;
+  if (y_shape) *y_shape = kBatchTune.y;
+  if (steps_per_run) *steps_per_run = kBatchTune.steps;
   return CGKS_OK;
 }
 

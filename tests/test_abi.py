@@ -87,7 +87,6 @@ def test_create_rejects_invalid_configurations_before_touching_the_device():
 
     assert rc(base, nx=0) == EINVAL
     assert rc(base, gauss_points=3) == EINVAL                       # two or four points only
-    assert rc(base, gauss_points=4, storage=CGKS_FP32_STORAGE) == EINVAL
     assert rc(I.sine_wave_1d(16), gauss_points=4) == EINVAL         # 2D only
     assert rc(I.uniform_2d(2, 8, bc=(I.WALL,) * 4), gauss_points=4) == EINVAL   # walls: 3 cells across
     assert rc(base, ny=0) == EINVAL

@@ -170,3 +170,82 @@ def test_batch_slot_reused_by_another_grid():
     assert np.array_equal(b.read(sc), rc.get_state()[0])
     assert np.array_equal(b.read(sd), rd.get_state()[0])
     b.close()
+
+
+def _kinds():
+    """One problem of every slot kind: two and four Gauss points, FP64 and FP32
+    gradient storage (walls and inflow among them)."""
+    from paper_2001_01570_amd.cgks import CGKS_FP32_STORAGE
+    g4 = lambda p: dataclasses.replace(p, gauss_points=4)
+    return [(I.acoustic_pulse_2d(48, seed=5, amp=1e-3, half_width=0.2, ny=33), 0),
+            (g4(I.shock_vortex_2d(64, 32, Rc=0.12)), 0),
+            (g4(I.acoustic_pulse_2d(37, seed=4, amp=0.05, half_width=0.3, ny=21)), 0),
+            (I.vortex_translation_2d(24), CGKS_FP32_STORAGE),
+            (g4(I.acoustic_pulse_2d(40, seed=2, amp=1e-3, half_width=0.2, ny=24)), CGKS_FP32_STORAGE),
+            (I.shock_vortex_2d(64, 32, Rc=0.12), 0)]
+
+
+def test_batch_of_mixed_kinds_equals_separate_contexts():
+    """Slots of all four kinds in one batch (their own face launches in the
+    same graph): every replay bitwise equal to separate contexts of the same
+    configuration, a slot index reused by another kind included."""
+    from paper_2001_01570_amd.cgks import Batch, Solver
+    kinds = _kinds()
+    say('mixed batch', [(p.name, p.gauss_points, st) for p, st in kinds])
+    b = Batch(1 * GiB, max_slots=8)
+    slots = [b.admit_storage(p, st, max_steps=6) for p, st in kinds]
+    refs = [Solver(p, storage=st) for p, st in kinds]
+    for rnd in range(2):
+        b.run(3)
+        for r in refs:
+            r.run_steps(3)
+        for (p, st), s, r in zip(kinds, slots, refs):
+            g = b.read(s)
+            e, te, ne = r.get_state()
+            assert b.poll(s)[2] == ne == 3 * (rnd + 1)
+            assert np.array_equal(g, e), (p.name, p.gauss_points, st, rnd, np.abs(g - e).max())
+    # slot 0 (two points, FP64) taken by a four-point FP32 problem
+    b.release(slots[0])
+    p, st = kinds[4]
+    s = b.admit_storage(p, st, max_steps=2)
+    assert s == slots[0]
+    b.run(2)
+    r = Solver(p, storage=st)
+    r.run_steps(2)
+    assert np.array_equal(b.read(s), r.get_state()[0])
+    b.close()
+
+
+def test_batch_four_point_slot_matches_the_oracle():
+    from paper_2001_01570_amd.cgks import Batch
+    p = dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), gauss_points=4)
+    o = O.Oracle(p, threads=8)
+    b = Batch(GiB // 4, max_slots=2)
+    s = b.admit(p, max_steps=1)
+    b.run(1)
+    dt = b.poll(s)[1]
+    o.step(dt)
+    e = field_errors(b.read(s), o.state)
+    say('four-point batch slot vs oracle', e)
+    assert e.max() < 1e-12
+    b.close()
+
+
+@pytest.mark.parametrize('tiles', [(0, 0), (1, 2), (2, 1)])
+def test_batch_tile_shapes_do_not_change_results(tiles):
+    from paper_2001_01570_amd.cgks import Batch, Solver, CgksError, CGKS_ESTATE, batch_tuning
+    x, y, n = batch_tuning()
+    assert 0 <= x <= 2 and 0 <= y <= 2 and n >= 1
+    probs = problems()[:3]
+    b = Batch(GiB // 2, max_slots=4)
+    b.set_tiles(*tiles)
+    slots = [b.admit(p, max_steps=3) for p in probs]
+    with pytest.raises(CgksError) as ex:       # not while slots are admitted
+        b.set_tiles(0, 0)
+    assert ex.value.code == CGKS_ESTATE
+    b.run(3)
+    for p, s in zip(probs, slots):
+        r = Solver(p)
+        r.run_steps(3)
+        assert np.array_equal(b.read(s), r.get_state()[0]), (p.name, tiles)
+    b.close()

@@ -44,8 +44,14 @@ def _viscous_box():
 
 @pytest.mark.parametrize('mk,amp', [(lambda: I.acoustic_pulse_2d(64, seed=3, amp=1e-3, half_width=0.2), 1e-3),
                                     (lambda: I.shock_vortex_2d(64, 32, Rc=0.12), 0.3),
-                                    (_viscous_box, 0.125)],   # its largest perturbation (energy)
-                         ids=['pulse', 'shock_vortex', 'viscous_noslip'])
+                                    (_viscous_box, 0.125),    # its largest perturbation (energy)
+                                    (lambda: dataclasses.replace(I.acoustic_pulse_2d(64, seed=3, amp=1e-3,
+                                                                                     half_width=0.2),
+                                                                 gauss_points=4), 1e-3),
+                                    (lambda: dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12),
+                                                                 gauss_points=4), 0.3)],
+                         ids=['pulse', 'shock_vortex', 'viscous_noslip', 'pulse_four_points',
+                              'shock_vortex_four_points'])
 def test_fp32_storage_error_against_fp64(mk, amp):
     from paper_2001_01570_amd.cgks import Solver, CGKS_FP32_STORAGE
     p = mk()
