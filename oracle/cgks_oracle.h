@@ -37,6 +37,10 @@ typedef struct {
   int gauss_points;          /* 2D: Gauss-Legendre points per face segment, 2 (0 means 2;
                                 3 segments with the tangential gradients) or 4 (sextic through
                                 7 segment averages, three ghost layers) */
+  int side_slopes;           /* slopes of the two non-equilibrium sides: 0 the linear
+                                reconstruction's derivatives (the scheme as read); 1 (1D
+                                only, an evaluated variant) the WENO-weighted derivatives of
+                                the candidate polynomials of each side */
 } orc_config;
 
 typedef struct orc_ctx orc_ctx;
@@ -68,6 +72,10 @@ void orc_p7(const double *Q, const double *D, double *out);
 double orc_weno_left(const double *Q, const double *D, double eps,
                      double *cand, double *beta, double *weights);
 double orc_weno_right(const double *Q, const double *D, double eps);
+/* The same with *dval = h * d/dx at x_{i+1/2} of the WENO combination of the
+ * candidate polynomials (their slopes combined with the nonlinear weights). */
+double orc_weno_left_d(const double *Q, const double *D, double eps, double *dval);
+double orc_weno_right_d(const double *Q, const double *D, double eps, double *dval);
 /* Moments <u^n v^m xi^(2k)> of a (half-)Maxwellian; half = 0 full, +1 u>0, -1 u<0. */
 double orc_moment(int dim, double gamma, double U, double V, double lambda,
                   int half, int n, int m, int k);
@@ -88,13 +96,16 @@ void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double m
                    double *Nh, double *Nf, double *tau);
 /* orc_gks_point with the positivity guard of the equilibrium state reported:
  * returns 1 when W0 was inadmissible and the kinetic collision state of the
- * two sides took its place; W0used (nc) receives the state actually used. */
+ * two sides took its place; W0used (nc) receives the state actually used.
+ * Wln, Wrn: normal slopes of the two non-equilibrium sides (NULL: W0n, the
+ * scheme as read). */
 int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double mu, double dt,
                     const double *W0, const double *W0n, const double *W0t,
                     const double *W0nn, const double *W0nt, const double *W0tt,
                     const double *Wl, const double *Wr,
                     double *F, double *Ft, double *Wt, double *Wtt,
-                    double *Nh, double *Nf, double *tau, double *W0used);
+                    double *Nh, double *Nf, double *tau, double *W0used,
+                    const double *Wln, const double *Wrn);
 /* One 1D face of a stage as the scheme evaluates it (Sec. 2.2, 3.2, 3.3), for
  * the face between cells 1 and 2 of a 4-cell line: cells[f * 4 + m] is field
  * f (the 6 fields of the 1D layout) of cell m.  The reference state of the

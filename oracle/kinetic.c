@@ -205,7 +205,8 @@ typedef struct {
  * state's own Maxwellian; A0 follows from the compatibility condition
  * <psi (a_n u + a_t v + A)>_g0 = 0, eq. (compatibility). */
 static void iface_setup(int dim, double gamma, const double *W0, const double *W0n,
-                        const double *W0t, const double *Wl, const double *Wr, iface_t *s) {
+                        const double *W0t, const double *Wl, const double *Wr,
+                        const double *Wln, const double *Wrn, iface_t *s) {
   const int nc = dim + 2;
   s->dim = dim; s->nc = nc;
   double b[4] = {0.0, 0.0, 0.0, 0.0};
@@ -216,9 +217,11 @@ static void iface_setup(int dim, double gamma, const double *W0, const double *W
   orc_maxw_init(dim, gamma, Wr, -1, &s->gr_half);
   for (int c = 0; c < nc; ++c) b[c] = W0n[c] / W0[0];
   solve_slope(&s->g0, b, s->an0);
-  for (int c = 0; c < nc; ++c) b[c] = W0n[c] / Wl[0];
+  if (!Wln) Wln = W0n;
+  if (!Wrn) Wrn = W0n;
+  for (int c = 0; c < nc; ++c) b[c] = Wln[c] / Wl[0];
   solve_slope(&s->gl_full, b, s->anl);
-  for (int c = 0; c < nc; ++c) b[c] = W0n[c] / Wr[0];
+  for (int c = 0; c < nc; ++c) b[c] = Wrn[c] / Wr[0];
   solve_slope(&s->gr_full, b, s->anr);
   if (dim == 2) {
     for (int c = 0; c < nc; ++c) b[c] = W0t[c] / W0[0];
@@ -319,7 +322,7 @@ void orc_flux_integral(int dim, double gamma, double tau, double tau_ce, double 
                        const double *W0, const double *W0n, const double *W0t,
                        const double *Wl, const double *Wr, double *Fhat) {
   iface_t s;
-  iface_setup(dim, gamma, W0, W0n, W0t, Wl, Wr, &s);
+  iface_setup(dim, gamma, W0, W0n, W0t, Wl, Wr, 0, 0, &s);
   fhat(&s, tau, tau_ce, delta, Fhat);
 }
 
@@ -328,7 +331,8 @@ int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double 
                     const double *W0nn, const double *W0nt, const double *W0tt,
                     const double *Wl, const double *Wr,
                     double *F, double *Ft, double *Wt, double *Wtt,
-                    double *Nh, double *Nf, double *tau_out, double *W0used) {
+                    double *Nh, double *Nf, double *tau_out, double *W0used,
+                    const double *Wln, const double *Wrn) {
   const int nc = dim + 2;
   double W0[4];
   int fired = 0;
@@ -353,7 +357,7 @@ int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double 
 
   iface_t s;
   double zero[4] = {0, 0, 0, 0};
-  iface_setup(dim, gamma, W0, W0n, dim == 2 ? W0t : zero, Wl, Wr, &s);
+  iface_setup(dim, gamma, W0, W0n, dim == 2 ? W0t : zero, Wl, Wr, Wln, Wrn, &s);
 
   /* flux extraction (Sec. 2.2): F(t) ~ F + Ft t fitted to the time integrals
    * over [0, dt/2] and [0, dt], Fhat(dt/2) = F dt/2 + Ft dt^2/8 and
@@ -423,5 +427,5 @@ void orc_gks_point(int dim, double gamma, double tau_eps, double tau_C, double m
                    double *F, double *Ft, double *Wt, double *Wtt,
                    double *Nh, double *Nf, double *tau) {
   orc_gks_point_g(dim, gamma, tau_eps, tau_C, mu, dt, W0, W0n, W0t, W0nn, W0nt, W0tt, Wl, Wr,
-                  F, Ft, Wt, Wtt, Nh, Nf, tau, 0);
+                  F, Ft, Wt, Wtt, Nh, Nf, tau, 0, 0, 0);
 }

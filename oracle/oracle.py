@@ -35,7 +35,8 @@ class _Cfg(C.Structure):
                 ('gamma', C.c_double), ('cfl', C.c_double),
                 ('bc', C.c_int * 4), ('inflow_prim', (C.c_double * 4) * 4),
                 ('weno_eps', C.c_double), ('tau_eps', C.c_double), ('tau_C', C.c_double),
-                ('fixed_dt', C.c_double), ('mu', C.c_double), ('gauss_points', C.c_int)]
+                ('fixed_dt', C.c_double), ('mu', C.c_double), ('gauss_points', C.c_int),
+                ('side_slopes', C.c_int)]
 
 
 class _Counters(C.Structure):
@@ -77,7 +78,11 @@ def lib():
         L.orc_slope.argtypes = [C.c_int, C.c_double, D, D, D]
         L.orc_euler_wtt.argtypes = [C.c_double] + [D] * 7
         L.orc_gks_point.argtypes = [C.c_int] + [C.c_double] * 5 + [D] * 8 + [D] * 7
-        L.orc_gks_point_g.argtypes = [C.c_int] + [C.c_double] * 5 + [D] * 8 + [D] * 8
+        L.orc_gks_point_g.argtypes = [C.c_int] + [C.c_double] * 5 + [D] * 8 + [D] * 8 + [D] * 2
+        L.orc_weno_left_d.argtypes = [D, D, C.c_double, D]
+        L.orc_weno_left_d.restype = C.c_double
+        L.orc_weno_right_d.argtypes = [D, D, C.c_double, D]
+        L.orc_weno_right_d.restype = C.c_double
         L.orc_gks_point_g.restype = C.c_int
         L.orc_face_1d.argtypes = [C.POINTER(_Cfg), D, C.c_double, C.c_int, D, C.POINTER(C.c_long)]
         L.orc_flux_integral.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double] + [D] * 6
@@ -109,8 +114,11 @@ class OracleError(RuntimeError):
 class Oracle:
     """The oracle solver for one problem (see paper_2001_01570_amd.inputs.Problem)."""
 
-    def __init__(self, prob, threads: int = 0):
+    def __init__(self, prob, threads: int = 0, side_slopes: int = 0):
+        """side_slopes = 1 (1D): the evaluated variant whose non-equilibrium
+        sides take the WENO-weighted slopes of their candidates."""
         cfg = _Cfg()
+        cfg.side_slopes = int(side_slopes)
         d = prob.config_dict()
         for k in ('dim', 'nx', 'ny'):
             setattr(cfg, k, int(d[k]))
@@ -201,6 +209,15 @@ def weno_right(Q, D_, eps=1e-6):
     return lib().orc_weno_right(_p(_vec(Q, 4)), _p(_vec(D_, 4)), float(eps))
 
 
+def weno_slopes(Q, D_, eps=1e-6):
+    """(left value, h * left slope, right value, h * right slope): the WENO
+    values with the candidates' slopes combined by the same weights."""
+    dl, dr = C.c_double(), C.c_double()
+    vl = lib().orc_weno_left_d(_p(_vec(Q, 4)), _p(_vec(D_, 4)), float(eps), C.byref(dl))
+    vr = lib().orc_weno_right_d(_p(_vec(Q, 4)), _p(_vec(D_, 4)), float(eps), C.byref(dr))
+    return vl, dl.value, vr, dr.value
+
+
 def moment(dim, gamma, U, V, lam, half, n, m=0, k=0):
     return lib().orc_moment(int(dim), float(gamma), float(U), float(V), float(lam), int(half), int(n), int(m), int(k))
 
@@ -246,7 +263,7 @@ def gks_point_guarded(dim, gamma, dt, W0, W0n, W0nn, Wl, Wr, W0t=None, W0nt=None
     tau = np.empty(1)
     used = np.empty(nc)
     fired = lib().orc_gks_point_g(int(dim), float(gamma), float(tau_eps), float(tau_C), float(mu), float(dt),
-                                  *[_p(a) for a in ins], *[_p(a) for a in outs], _p(tau), _p(used))
+                                  *[_p(a) for a in ins], *[_p(a) for a in outs], _p(tau), _p(used), None, None)
     r = dict(zip(('F', 'Ft', 'Wt', 'Wtt', 'Nh', 'Nf'), outs))
     r.update(tau=float(tau[0]), fired=int(fired), W0used=used)
     return r

@@ -147,11 +147,30 @@ static double beta_of(int k, const double *Q, const double *D) {
   return beta;
 }
 
+/* h * d/dx at x_{i+1/2} of the polynomial of candidate k (the sub-stencils of
+ * eq. (sub-stencil); candidate 1 is the quadratic on Q_{i-1}, Q_i, Q_{i+1}, the
+ * same polynomial as candidate 3). */
+static double candidate_slope(int k, const double *Q, const double *D) {
+  const int ks = k == 1 ? 3 : k;
+  const stencil_t *s = &STENCIL[ks];
+  double rhs[5];
+  for (int r = 0; r < s->n; ++r) rhs[r] = s->c[r].kind == 0 ? Q[s->c[r].cell] : D[s->c[r].cell];
+  double d = 0.0;
+  for (int p = 1; p < s->n; ++p) {
+    double acc = 0.0;
+    for (int r = 0; r < s->n; ++r) acc += STENCIL_INV[ks][p * s->n + r] * rhs[r];
+    d += acc * p * ipow(0.5, p - 1);
+  }
+  return d;
+}
+
 /* Left value of the WENO-Z reconstruction, eqs. (right-left), (WENO-Z-w), (tau).
  * The data are first shifted by Q_i: the reconstruction commutes with adding a
- * constant, and the shift keeps the indicators free of cancellation. */
-double orc_weno_left(const double *Qin, const double *D, double eps,
-                     double *cand, double *beta, double *weights) {
+ * constant, and the shift keeps the indicators free of cancellation.  dval
+ * (may be NULL): the candidates' slopes h * q_k'(x_{i+1/2}) combined with the
+ * same nonlinear weights (the evaluated variant of the side slopes). */
+static double weno_left_impl(const double *Qin, const double *D, double eps,
+                             double *cand, double *beta, double *weights, double *dval) {
   double Q[4], q[7], b[7], w[7];
   const double ref = Qin[1];
   for (int m = 0; m < 4; ++m) Q[m] = Qin[m] - ref;
@@ -162,18 +181,41 @@ double orc_weno_left(const double *Qin, const double *D, double eps,
   for (int k = 0; k < 7; ++k) { w[k] = DK[k] * (1.0 + zref / (b[k] + eps)); asum += w[k]; }
   double val = 0.0;
   for (int k = 0; k < 7; ++k) { w[k] /= asum; val += w[k] * q[k]; }
+  if (dval) {
+    double d = 0.0;
+    for (int k = 0; k < 7; ++k) d += w[k] * candidate_slope(k, Q, D);
+    *dval = d;
+  }
   if (cand) for (int k = 0; k < 7; ++k) cand[k] = q[k] + ref;
   if (beta) memcpy(beta, b, sizeof b);
   if (weights) memcpy(weights, w, sizeof w);
   return val + ref;
 }
 
+double orc_weno_left(const double *Qin, const double *D, double eps,
+                     double *cand, double *beta, double *weights) {
+  return weno_left_impl(Qin, D, eps, cand, beta, weights, 0);
+}
+
+double orc_weno_left_d(const double *Q, const double *D, double eps, double *dval) {
+  return weno_left_impl(Q, D, eps, 0, 0, 0, dval);
+}
+
 /* Right value at x_{i+1/2}: the left procedure applied to the stencil mirrored
- * about the interface (cells reversed, slopes negated). */
+ * about the interface (cells reversed, slopes negated); its slope changes sign
+ * with the mirror. */
 double orc_weno_right(const double *Q, const double *D, double eps) {
   double Qm[4], Dm[4];
   for (int m = 0; m < 4; ++m) { Qm[m] = Q[3 - m]; Dm[m] = -D[3 - m]; }
-  return orc_weno_left(Qm, Dm, eps, 0, 0, 0);
+  return weno_left_impl(Qm, Dm, eps, 0, 0, 0, 0);
+}
+
+double orc_weno_right_d(const double *Q, const double *D, double eps, double *dval) {
+  double Qm[4], Dm[4], d;
+  for (int m = 0; m < 4; ++m) { Qm[m] = Q[3 - m]; Dm[m] = -D[3 - m]; }
+  const double v = weno_left_impl(Qm, Dm, eps, 0, 0, 0, &d);
+  *dval = -d;
+  return v;
 }
 
 void orc_sextic(const double *s, double eta, double *out3) {

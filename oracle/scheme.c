@@ -47,6 +47,7 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   if ((cfg->bc[0] == ORC_PERIODIC) != (cfg->bc[1] == ORC_PERIODIC)) return ORC_EINVAL;
   if (cfg->dim == 2 && (cfg->bc[2] == ORC_PERIODIC) != (cfg->bc[3] == ORC_PERIODIC)) return ORC_EINVAL;
   if (!(cfg->mu >= 0.0) || !isfinite(cfg->mu)) return ORC_EINVAL;
+  if (cfg->side_slopes != 0 && !(cfg->side_slopes == 1 && cfg->dim == 1)) return ORC_EINVAL;
   const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
   if (gp != 2 && !(gp == 4 && cfg->dim == 2)) return ORC_EINVAL;
   /* the 7-segment stencil reaches 3 cells across a side: a wall mirrors 3 cells */
@@ -230,14 +231,22 @@ double orc_cfl_dt(const orc_ctx *c) {
 
 /* Normal reconstruction on one line (Sec. 3.2, 3.3): Q shifted by the face's
  * reference state, D = h Q'.  Output: P7, P7_n, P7_nn, left and right values. */
-static void normal_line(const double *Q, const double *D, double h, double eps, double *o5) {
+static void normal_line(const double *Q, const double *D, double h, double eps, double *o5, double *sd) {
   double p[3];
   orc_p7(Q, D, p);
   o5[0] = p[0];
   o5[1] = p[1] / h;
   o5[2] = p[2] / (h * h);
-  o5[3] = orc_weno_left(Q, D, eps, 0, 0, 0);
-  o5[4] = orc_weno_right(Q, D, eps);
+  if (sd) {   /* the side-slope variant: the WENO-weighted slopes of both sides too */
+    double dl, dr;
+    o5[3] = orc_weno_left_d(Q, D, eps, &dl);
+    o5[4] = orc_weno_right_d(Q, D, eps, &dr);
+    sd[0] = dl / h;
+    sd[1] = dr / h;
+  } else {
+    o5[3] = orc_weno_left(Q, D, eps, 0, 0, 0);
+    o5[4] = orc_weno_right(Q, D, eps);
+  }
 }
 
 static void swap12(double *v) { double t = v[1]; v[1] = v[2]; v[2] = t; }
@@ -265,7 +274,7 @@ typedef struct { long w0, weno; } guards_t;
  * of the three nearest segments as with two points. */
 static void face_eval(orc_ctx *c, double lines[7][5][4], double tg[7][2][4], const double *ref,
                       const double *Wleft, const double *Wright, double dt, int final, int rot, double ht,
-                      double *out, guards_t *gd) {
+                      double (*sslope)[4], double *out, guards_t *gd) {
   const int dim = c->cfg.dim, nc = c->nc;
   const double gam = c->cfg.gamma;
   const int npts = c->npts, nl = c->nl;
@@ -337,16 +346,27 @@ static void face_eval(orc_ctx *c, double lines[7][5][4], double tg[7][2][4], con
       }
       W0[k] = ref[k] + W0d[k];
     }
+    /* side slopes of the evaluated variant (1D): the WENO-weighted ones; a
+     * side that falls back to the cell average takes the linear slope */
+    double Wln[4], Wrn[4];
+    if (sslope) for (int k = 0; k < nc; ++k) { Wln[k] = sslope[0][k]; Wrn[k] = sslope[1][k]; }
     /* inadmissible nonlinear states fall back to the adjacent cell average */
-    if (!orc_admissible(dim, gam, Wl)) { for (int k = 0; k < nc; ++k) Wl[k] = Wleft[k]; gd->weno++; }
-    if (!orc_admissible(dim, gam, Wr)) { for (int k = 0; k < nc; ++k) Wr[k] = Wright[k]; gd->weno++; }
+    if (!orc_admissible(dim, gam, Wl)) {
+      for (int k = 0; k < nc; ++k) { Wl[k] = Wleft[k]; Wln[k] = Wn[k]; }
+      gd->weno++;
+    }
+    if (!orc_admissible(dim, gam, Wr)) {
+      for (int k = 0; k < nc; ++k) { Wr[k] = Wright[k]; Wrn[k] = Wn[k]; }
+      gd->weno++;
+    }
     if (rot) {
       swap12(W0); swap12(Wn); swap12(Wt_); swap12(Wnn); swap12(Wnt); swap12(Wtt_);
       swap12(Wl); swap12(Wr);
     }
     double F[4], Ft[4], Wt[4], Wtt[4], Nh[4], Nf[4], tau, W0u[4];
     const int fired = orc_gks_point_g(dim, gam, c->cfg.tau_eps, c->cfg.tau_C, c->cfg.mu, dt, W0, Wn, Wt_, Wnn,
-                                      Wnt, Wtt_, Wl, Wr, F, Ft, Wt, Wtt, Nh, Nf, &tau, W0u);
+                                      Wnt, Wtt_, Wl, Wr, F, Ft, Wt, Wtt, Nh, Nf, &tau, W0u,
+                                      sslope ? Wln : 0, sslope ? Wrn : 0);
     if (rot) { swap12(F); swap12(Ft); swap12(Wt); swap12(Wtt); swap12(Nh); swap12(Nf); swap12(W0u); }
     if (fired) { gd->w0++; for (int k = 0; k < nc; ++k) W0d[k] = W0u[k] - ref[k]; }
     const double wg = wgt[g];
@@ -380,7 +400,7 @@ void orc_face_1d(const orc_config *cfg, const double *cells, double dt, int fina
   orc_recon_init();
   const double h = (cfg->x1 - cfg->x0) / cfg->nx;
   double ref[4] = {0, 0, 0, 0}, Wlc[4] = {0, 0, 0, 0}, Wrc[4] = {0, 0, 0, 0};
-  double lines[7][5][4], tg[7][2][4];
+  double lines[7][5][4], tg[7][2][4], sslope[2][4] = {{0}};
   memset(tg, 0, sizeof tg);
   for (int k = 0; k < 3; ++k) {
     ref[k] = Wlc[k] = cells[k * 4 + 1];
@@ -390,11 +410,14 @@ void orc_face_1d(const orc_config *cfg, const double *cells, double dt, int fina
       Q[m] = cells[k * 4 + m] - ref[k];
       D[m] = h * cells[(3 + k) * 4 + m];
     }
-    normal_line(Q, D, h, cfg->weno_eps, o5);
+    double sd[2] = {0.0, 0.0};
+    normal_line(Q, D, h, cfg->weno_eps, o5, cfg->side_slopes ? sd : 0);
     for (int q = 0; q < 5; ++q) lines[0][q][k] = o5[q];
+    sslope[0][k] = sd[0];
+    sslope[1][k] = sd[1];
   }
   guards_t gd = {0, 0};
-  face_eval(&c, lines, tg, ref, Wlc, Wrc, dt, final, 0, 1.0, out, &gd);
+  face_eval(&c, lines, tg, ref, Wlc, Wrc, dt, final, 0, 1.0, cfg->side_slopes ? sslope : 0, out, &gd);
   guards[0] = gd.w0;
   guards[1] = gd.weno;
 }
@@ -409,7 +432,8 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
   for (int j = 0; j < ny; ++j) {
     guards_t gd = {0, 0};
     for (int f = 0; f <= nx; ++f) {
-      double ref[4], Wlc[4], Wrc[4], lines[7][5][4], tg[7][2][4];
+      double ref[4], Wlc[4], Wrc[4], lines[7][5][4], tg[7][2][4], sslope[2][4];
+      const int side = dim == 1 && c->cfg.side_slopes;
       for (int k = 0; k < nc; ++k) {
         ref[k] = fld(c, (double *)G, k)[gidx(c, f - 1, j)];
         Wlc[k] = ref[k];
@@ -424,9 +448,10 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
             Q[m] = fld(c, (double *)G, k)[gidx(c, f - 2 + m, jj)] - ref[k];
             D[m] = c->dx * fld(c, (double *)G, nc + k)[gidx(c, f - 2 + m, jj)];
           }
-          double o5[5];
-          normal_line(Q, D, c->dx, eps, o5);
+          double o5[5], sd[2];
+          normal_line(Q, D, c->dx, eps, o5, side ? sd : 0);
           for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q];
+          if (side) { sslope[0][k] = sd[0]; sslope[1][k] = sd[1]; }
           if (dim == 2) {
             double T[4], o2[2];
             for (int m = 0; m < 4; ++m) T[m] = fld(c, (double *)G, 2 * nc + k)[gidx(c, f - 2 + m, jj)];
@@ -437,7 +462,7 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
         }
       }
       double *out = c->xf + ((size_t)j * (nx + 1) + f) * NF_FACE * nc;
-      face_eval(c, lines, tg, ref, Wlc, Wrc, dt, final, 0, c->dy, out, &gd);
+      face_eval(c, lines, tg, ref, Wlc, Wrc, dt, final, 0, c->dy, side ? sslope : 0, out, &gd);
     }
     gw0 += gd.w0; gwe += gd.weno;
   }
@@ -462,7 +487,7 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
               D[m] = c->dy * fld(c, (double *)G, 2 * nc + k)[gidx(c, ii, f - 2 + m)];
             }
             double o5[5], T[4], o2[2];
-            normal_line(Q, D, c->dy, eps, o5);
+            normal_line(Q, D, c->dy, eps, o5, 0);
             for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q];
             for (int m = 0; m < 4; ++m) T[m] = fld(c, (double *)G, nc + k)[gidx(c, ii, f - 2 + m)];
             orc_cubic_face(T, o2);
@@ -471,7 +496,7 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
           }
         }
         double *out = c->yf + ((size_t)f * nx + i) * NF_FACE * nc;
-        face_eval(c, lines, tg, ref, Wlc, Wrc, dt, final, 1, c->dx, out, &gd);
+        face_eval(c, lines, tg, ref, Wlc, Wrc, dt, final, 1, c->dx, 0, out, &gd);
       }
       gw0 += gd.w0; gwe += gd.weno;
     }

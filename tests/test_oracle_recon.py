@@ -219,3 +219,30 @@ def test_cross_face_cubic_exact(seed):
     e = np.eye(4)
     assert np.allclose([O.cubic_face(e[m])[0] for m in range(4)], np.array([-1, 7, 7, -1]) / 12, atol=1e-15)
     assert np.allclose([O.cubic_face(e[m])[1] for m in range(4)], np.array([1, -15, 15, -1]) / 12, atol=1e-14)
+
+
+def test_weno_weighted_slopes_exact_on_quadratics():
+    """The evaluated side-slope variant: every candidate reproduces quadratics,
+    and the nonlinear weights sum to one, so the WENO-weighted slopes of both
+    sides equal the exact derivative of a quadratic at the interface (and the
+    values its exact value), whatever the weights; on a jump the left slope
+    comes from the smooth side."""
+    rng = np.random.default_rng(11)
+    xc = np.array([-1.0, 0.0, 1.0, 2.0])     # centres of cells i-1 .. i+2 (width 1, interface at 1/2)
+    for _ in range(20):
+        a, b, c = rng.standard_normal(3)
+        q = lambda x: a + b * x + c * x * x
+        Q = a + b * xc + c * (xc * xc + 1.0 / 12.0)       # cell averages
+        D = q(xc + 0.5) - q(xc - 0.5)
+        vl, dl, vr, dr = O.weno_slopes(Q, D)
+        exact_d = b + 2.0 * c * 0.5
+        scale = abs(a) + abs(b) + abs(c)
+        assert abs(vl - q(0.5)) < 1e-13 * scale and abs(vr - q(0.5)) < 1e-13 * scale
+        assert abs(dl - exact_d) < 1e-12 * scale and abs(dr - exact_d) < 1e-12 * scale
+    # a jump between cells 2 and 3 (right of the interface's right cell): the
+    # left side's slope is the smooth part's (here linear: slope 0.3)
+    Q = np.array([1.0 - 0.3, 1.0, 1.0 + 0.3, 5.0])
+    D = np.array([0.3, 0.3, 0.3, 0.0])
+    vl, dl, _, _ = O.weno_slopes(Q, D)
+    lin = O.p7(Q - Q[1], D)[1]                   # the linear derivative sees the jump
+    assert abs(dl - 0.3) < 0.05 * abs(lin - 0.3) and abs(vl - 1.15) < 0.05 * abs(O.p7(Q - Q[1], D)[0] + Q[1] - 1.15)
