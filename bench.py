@@ -429,6 +429,13 @@ def main():
                 'traffic': measured_traffic(name, prob.nx, prob.ny) if args.gauss_points == 2 else None,
                 'avg_ms': avg_s * 1e3, 'flops_per_launch': alg}
 
+    # the whole step: algorithmic flops per cell and step times the rate
+    step = None
+    if flops is not None and args.gauss_points == 2:
+        fc = flops['flops_per_cell_step']
+        step = {'flops_per_cell_step': fc, 'tflops': fc * value / 1e12,
+                'frac_of_fp64_peak': fc * value / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
+
     s.close()
     serv = None
     if reqs:
@@ -463,6 +470,7 @@ def main():
         'config': {'workload': workload, 'cells': cells, 'seed': 0},
         'roofline': roof,
         'kernel_ms_per_launch_probe': {k: v[0] / max(v[1], 1) for k, v in probe.items()},
+        'whole_step': step,
         'cpu_baseline': cpu,
         'serving': serv,
     }
