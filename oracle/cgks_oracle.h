@@ -41,6 +41,10 @@ typedef struct {
                                 reconstruction's derivatives (the scheme as read); 1 (1D
                                 only, an evaluated variant) the WENO-weighted derivatives of
                                 the candidate polynomials of each side */
+  int char_vars;             /* variables of the nonlinear (WENO-Z) reconstruction: 0
+                                conservative, 1 characteristic (Sec. 3.2: the eigenvectors
+                                of the normal flux Jacobian at the mean of the two cells
+                                beside the face, per stencil line) */
 } orc_config;
 
 typedef struct orc_ctx orc_ctx;
@@ -116,6 +120,17 @@ int orc_gks_point_g(int dim, double gamma, double tau_eps, double tau_C, double 
  * WENO point states replaced by the adjacent cell average (0..2). */
 void orc_face_1d(const orc_config *cfg, const double *cells, double dt, int final,
                  double *out, long *guards);
+/* Characteristic variables (Sec. 3.2).  orc_char_basis: right eigenvectors
+ * R[i * nc + j] (component i of wave j; waves u - c, u (, u), u + c) of the
+ * Jacobian of the Euler flux in the first direction at W, and L = R^-1 (row
+ * major); -1 if W is not admissible.  orc_weno_char: the WENO-Z left and
+ * right states of one line reconstructed in the characteristic variables of
+ * Wm; Q[k * 4 + m], D[k * 4 + m] as for orc_weno_left per component k; the
+ * states as deviations, per component; returns 0 (conservative variables
+ * used) when Wm is not admissible, else 1. */
+int orc_char_basis(int dim, double gamma, const double *W, double *L, double *R);
+int orc_weno_char(int dim, double gamma, double eps, const double *Wm, const double *Q, const double *D,
+                  double *wl, double *wr);
 /* The same evolution evaluated as the time integral of the interface flux over
  * [0, delta]: Fhat(delta), with tau in the exponentials and tau_ce in the
  * Chapman-Enskog term (exposed for the extraction tests). */

@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, 'liboracle.so')
-SOURCES = ['linalg.c', 'recon.c', 'kinetic.c', 'scheme.c']
+SOURCES = ['linalg.c', 'recon.c', 'kinetic.c', 'charvars.c', 'scheme.c']
 
 
 def build(verbose: bool = False) -> str:
@@ -36,7 +36,7 @@ class _Cfg(C.Structure):
                 ('bc', C.c_int * 4), ('inflow_prim', (C.c_double * 4) * 4),
                 ('weno_eps', C.c_double), ('tau_eps', C.c_double), ('tau_C', C.c_double),
                 ('fixed_dt', C.c_double), ('mu', C.c_double), ('gauss_points', C.c_int),
-                ('side_slopes', C.c_int)]
+                ('side_slopes', C.c_int), ('char_vars', C.c_int)]
 
 
 class _Counters(C.Structure):
@@ -90,6 +90,10 @@ def lib():
         L.orc_quadratic3.argtypes = [D, C.c_double, D]
         L.orc_hermite3.argtypes = [D, D, C.c_double, D]
         L.orc_cubic_face.argtypes = [D, D]
+        L.orc_char_basis.argtypes = [C.c_int, C.c_double, D, D, D]
+        L.orc_char_basis.restype = C.c_int
+        L.orc_weno_char.argtypes = [C.c_int, C.c_double, C.c_double, D, D, D, D, D]
+        L.orc_weno_char.restype = C.c_int
         _lib = L
     return _lib
 
@@ -125,6 +129,7 @@ class Oracle:
         for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt', 'mu'):
             setattr(cfg, k, float(d[k]))
         cfg.gauss_points = int(d.get('gauss_points', 2))
+        cfg.char_vars = int(d.get('recon_vars', 0))
         for s in range(4):
             cfg.bc[s] = int(d['bc'][s])
             for q in range(4):
@@ -280,11 +285,35 @@ def face_1d(prob, cells, dt, final=False):
         setattr(cfg, k, int(d[k]))
     for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt', 'mu'):
         setattr(cfg, k, float(d[k]))
+    cfg.char_vars = int(d.get('recon_vars', 0))
     a = _vec(cells, 24)
     out = np.empty(12)
     g = (C.c_long * 2)()
     lib().orc_face_1d(C.byref(cfg), _p(a), float(dt), int(bool(final)), _p(out), g)
     return out.reshape(4, 3), (int(g[0]), int(g[1]))
+
+
+def char_basis(dim, gamma, W):
+    """(L, R): the left (rows) and right (columns) eigenvectors of the Euler
+    flux Jacobian in the first direction at W (waves u - c, u (, u), u + c);
+    None if W is not admissible."""
+    nc = dim + 2
+    L_, R_ = np.empty(nc * nc), np.empty(nc * nc)
+    if lib().orc_char_basis(int(dim), float(gamma), _p(_vec(W, nc)), _p(L_), _p(R_)) != 0:
+        return None
+    return L_.reshape(nc, nc), R_.reshape(nc, nc)
+
+
+def weno_char(dim, gamma, Wm, Q, D_, eps=1e-6):
+    """WENO-Z left and right states of one line in the characteristic
+    variables of Wm: Q, D_ (nc, 4) per component as for weno_left.  Returns
+    (wl, wr, used) with used = False when Wm is not admissible (then the
+    states are the componentwise ones)."""
+    nc = dim + 2
+    wl, wr = np.empty(nc), np.empty(nc)
+    used = lib().orc_weno_char(int(dim), float(gamma), float(eps), _p(_vec(Wm, nc)), _p(_vec(Q, 4 * nc)),
+                               _p(_vec(D_, 4 * nc)), _p(wl), _p(wr))
+    return wl, wr, bool(used)
 
 
 def flux_integral(dim, gamma, tau, delta, W0, W0n, Wl, Wr, W0t=None, tau_ce=0.0):

@@ -48,6 +48,7 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   if (cfg->dim == 2 && (cfg->bc[2] == ORC_PERIODIC) != (cfg->bc[3] == ORC_PERIODIC)) return ORC_EINVAL;
   if (!(cfg->mu >= 0.0) || !isfinite(cfg->mu)) return ORC_EINVAL;
   if (cfg->side_slopes != 0 && !(cfg->side_slopes == 1 && cfg->dim == 1)) return ORC_EINVAL;
+  if (cfg->char_vars != 0 && (cfg->char_vars != 1 || cfg->side_slopes)) return ORC_EINVAL;
   const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
   if (gp != 2 && !(gp == 4 && cfg->dim == 2)) return ORC_EINVAL;
   /* the 7-segment stencil reaches 3 cells across a side: a wall mirrors 3 cells */
@@ -251,6 +252,42 @@ static void normal_line(const double *Q, const double *D, double h, double eps, 
 
 static void swap12(double *v) { double t = v[1]; v[1] = v[2]; v[2] = t; }
 
+/* All components of one stencil line.  Q[k][m], D[k][m]: component k of cell
+ * m (cells i-1..i+2 of the line, face between i and i+1) as the deviation
+ * from the face's reference state and h times the normal derivative.
+ * o5[q][k]: the normal_line outputs of component k; sd[s][k] the side slopes
+ * of the evaluated variant (sd != NULL).  With characteristic variables the
+ * WENO-Z states are reconstructed in the characteristic variables of the
+ * mean Wm of cells i and i+1 (rot: y face, whose normal momentum is
+ * component 2). */
+static void line_all(const orc_config *cfg, int nc, double Q[4][4], double D[4][4], double h, const double *Wm,
+                     int rot, double o5[5][4], double (*sd)[4]) {
+  for (int k = 0; k < nc; ++k) {
+    double o[5], s2[2] = {0.0, 0.0};
+    normal_line(Q[k], D[k], h, cfg->weno_eps, o, sd ? s2 : 0);
+    for (int q = 0; q < 5; ++q) o5[q][k] = o[q];
+    if (sd) { sd[0][k] = s2[0]; sd[1][k] = s2[1]; }
+  }
+  if (cfg->char_vars) {
+    double Qc[16], Dc[16], Wr[4], wl[4], wr[4];
+    const int dim = nc - 2;
+    for (int k = 0; k < nc; ++k) {
+      Wr[k] = Wm[k];
+      for (int m = 0; m < 4; ++m) { Qc[4 * k + m] = Q[k][m]; Dc[4 * k + m] = D[k][m]; }
+    }
+    if (rot) {
+      swap12(Wr);
+      for (int m = 0; m < 4; ++m) {
+        double t = Qc[4 + m]; Qc[4 + m] = Qc[8 + m]; Qc[8 + m] = t;
+        t = Dc[4 + m]; Dc[4 + m] = Dc[8 + m]; Dc[8 + m] = t;
+      }
+    }
+    orc_weno_char(dim, cfg->gamma, cfg->weno_eps, Wr, Qc, Dc, wl, wr);
+    if (rot) { swap12(wl); swap12(wr); }
+    for (int k = 0; k < nc; ++k) { o5[3][k] = wl[k]; o5[4][k] = wr[k]; }
+  }
+}
+
 typedef struct { long w0, weno; } guards_t;
 
 /* Evaluate one face.  lines[l][q][c]: stencil line l (tangential offset
@@ -402,20 +439,19 @@ void orc_face_1d(const orc_config *cfg, const double *cells, double dt, int fina
   double ref[4] = {0, 0, 0, 0}, Wlc[4] = {0, 0, 0, 0}, Wrc[4] = {0, 0, 0, 0};
   double lines[7][5][4], tg[7][2][4], sslope[2][4] = {{0}};
   memset(tg, 0, sizeof tg);
+  double Q[4][4], D[4][4], Wm[4], o5[5][4];
   for (int k = 0; k < 3; ++k) {
     ref[k] = Wlc[k] = cells[k * 4 + 1];
     Wrc[k] = cells[k * 4 + 2];
-    double Q[4], D[4], o5[5];
+    Wm[k] = 0.5 * (Wlc[k] + Wrc[k]);
     for (int m = 0; m < 4; ++m) {
-      Q[m] = cells[k * 4 + m] - ref[k];
-      D[m] = h * cells[(3 + k) * 4 + m];
+      Q[k][m] = cells[k * 4 + m] - ref[k];
+      D[k][m] = h * cells[(3 + k) * 4 + m];
     }
-    double sd[2] = {0.0, 0.0};
-    normal_line(Q, D, h, cfg->weno_eps, o5, cfg->side_slopes ? sd : 0);
-    for (int q = 0; q < 5; ++q) lines[0][q][k] = o5[q];
-    sslope[0][k] = sd[0];
-    sslope[1][k] = sd[1];
   }
+  line_all(cfg, 3, Q, D, h, Wm, 0, o5, cfg->side_slopes ? sslope : 0);
+  for (int q = 0; q < 5; ++q)
+    for (int k = 0; k < 3; ++k) lines[0][q][k] = o5[q][k];
   guards_t gd = {0, 0};
   face_eval(&c, lines, tg, ref, Wlc, Wrc, dt, final, 0, 1.0, cfg->side_slopes ? sslope : 0, out, &gd);
   guards[0] = gd.w0;
@@ -425,7 +461,6 @@ void orc_face_1d(const orc_config *cfg, const double *cells, double dt, int fina
 /* all faces of one stage on the ghosted state G */
 static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guards_t *gd_total) {
   const int nx = c->cfg.nx, ny = c->cfg.ny, nc = c->nc, dim = c->cfg.dim;
-  const double eps = c->cfg.weno_eps;
   long gw0 = 0, gwe = 0;
   /* x faces: face f between cells f-1 and f, reference = cell f-1 of the same row */
 #pragma omp parallel for schedule(dynamic) reduction(+ : gw0, gwe) if (nthreads_req != 1 && ny > 1)
@@ -442,16 +477,18 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
       const int nl = dim == 2 ? c->nl : 1;
       for (int l = 0; l < nl; ++l) {
         const int jj = dim == 2 ? j + l - nl / 2 : 0;
+        double Q[4][4], D[4][4], Wm[4], o5[5][4];
         for (int k = 0; k < nc; ++k) {
-          double Q[4], D[4];
+          const double *Gk = fld(c, (double *)G, k);
           for (int m = 0; m < 4; ++m) {
-            Q[m] = fld(c, (double *)G, k)[gidx(c, f - 2 + m, jj)] - ref[k];
-            D[m] = c->dx * fld(c, (double *)G, nc + k)[gidx(c, f - 2 + m, jj)];
+            Q[k][m] = Gk[gidx(c, f - 2 + m, jj)] - ref[k];
+            D[k][m] = c->dx * fld(c, (double *)G, nc + k)[gidx(c, f - 2 + m, jj)];
           }
-          double o5[5], sd[2];
-          normal_line(Q, D, c->dx, eps, o5, side ? sd : 0);
-          for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q];
-          if (side) { sslope[0][k] = sd[0]; sslope[1][k] = sd[1]; }
+          Wm[k] = 0.5 * (Gk[gidx(c, f - 1, jj)] + Gk[gidx(c, f, jj)]);
+        }
+        line_all(&c->cfg, nc, Q, D, c->dx, Wm, 0, o5, side ? sslope : 0);
+        for (int k = 0; k < nc; ++k) {
+          for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q][k];
           if (dim == 2) {
             double T[4], o2[2];
             for (int m = 0; m < 4; ++m) T[m] = fld(c, (double *)G, 2 * nc + k)[gidx(c, f - 2 + m, jj)];
@@ -480,15 +517,19 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
         }
         for (int l = 0; l < c->nl; ++l) {
           const int ii = i + l - c->nl / 2;
+          double Q[4][4], D[4][4], Wm[4], o5[5][4];
           for (int k = 0; k < nc; ++k) {
-            double Q[4], D[4];
+            const double *Gk = fld(c, (double *)G, k);
             for (int m = 0; m < 4; ++m) {
-              Q[m] = fld(c, (double *)G, k)[gidx(c, ii, f - 2 + m)] - ref[k];
-              D[m] = c->dy * fld(c, (double *)G, 2 * nc + k)[gidx(c, ii, f - 2 + m)];
+              Q[k][m] = Gk[gidx(c, ii, f - 2 + m)] - ref[k];
+              D[k][m] = c->dy * fld(c, (double *)G, 2 * nc + k)[gidx(c, ii, f - 2 + m)];
             }
-            double o5[5], T[4], o2[2];
-            normal_line(Q, D, c->dy, eps, o5, 0);
-            for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q];
+            Wm[k] = 0.5 * (Gk[gidx(c, ii, f - 1)] + Gk[gidx(c, ii, f)]);
+          }
+          line_all(&c->cfg, nc, Q, D, c->dy, Wm, 1, o5, 0);
+          for (int k = 0; k < nc; ++k) {
+            double T[4], o2[2];
+            for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q][k];
             for (int m = 0; m < 4; ++m) T[m] = fld(c, (double *)G, nc + k)[gidx(c, ii, f - 2 + m)];
             orc_cubic_face(T, o2);
             tg[l][0][k] = o2[0];

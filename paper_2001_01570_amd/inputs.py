@@ -55,6 +55,7 @@ class Problem:
     tau_C: float = 1.0
     mu: float = 0.0               # dynamic viscosity (0: Euler equations)
     gauss_points: int = 2         # 2D: Gauss points per face segment (2: quartic on 5 segments, 4: sextic on 7)
+    recon_vars: int = 0           # variables of the WENO-Z states: 0 conservative, 1 characteristic
     exact: Optional[Callable[[float], np.ndarray]] = None   # t -> exact fields (cell averages)
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -76,7 +77,8 @@ class Problem:
                     y1=self.y1, gamma=self.gamma, cfl=self.cfl, bc=list(self.bc),
                     inflow_prim=np.asarray(inflow, dtype=np.float64).tolist(),
                     weno_eps=self.weno_eps, tau_eps=self.tau_eps, tau_C=self.tau_C,
-                    fixed_dt=self.fixed_dt, mu=self.mu, gauss_points=self.gauss_points)
+                    fixed_dt=self.fixed_dt, mu=self.mu, gauss_points=self.gauss_points,
+                    recon_vars=self.recon_vars)
 
 
 # ---------------------------------------------------------------- helpers
