@@ -52,6 +52,15 @@ enum { CGKS_PERIODIC = 0, CGKS_FREE = 1, CGKS_WALL = 2, CGKS_INFLOW = 3, CGKS_NO
  * tau/exp evaluation stay FP64.  Fields cross the boundary in FP64 either way
  * (the gradients are rounded to FP32 on set_state). */
 enum { CGKS_FP64 = 0, CGKS_FP32_STORAGE = 1 };
+/* Variables of the nonlinear reconstruction (Sec. 3.2: the compact
+ * reconstruction acts on conservative or characteristic variables).
+ * CGKS_CHARACTERISTIC: on every stencil line the WENO-Z left and right
+ * states are reconstructed in the coordinates of the right eigenvectors of
+ * the Euler flux Jacobian normal to the face, at the mean of the two cells
+ * beside the face (eigenvectors scaled to a first entry of 1), and projected
+ * back; a line whose mean state is not admissible keeps the conservative
+ * variables.  The linear reconstruction is the same either way. */
+enum { CGKS_CONSERVATIVE = 0, CGKS_CHARACTERISTIC = 1 };
 
 typedef struct cgks_ctx cgks_ctx;
 
@@ -81,6 +90,8 @@ typedef struct {
                                 the sextic through 7 segment averages, four
                                 points (eighth order in 2D; walls need 3 cells
                                 across; tile shape fixed)                            */
+  int recon_vars;            /* CGKS_CONSERVATIVE (0, the default) or
+                                CGKS_CHARACTERISTIC, for the WENO-Z states           */
 } cgks_config;
 
 typedef struct {

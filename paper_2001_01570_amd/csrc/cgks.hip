@@ -69,6 +69,7 @@ struct Geom {
   int bc[4];
   double inflow[4][4];   // conservative inflow state per side
   Gas gas;
+  int charv;             // WENO-Z states in characteristic variables
 };
 
 struct Params {          // written by the host before a batch of steps
@@ -351,7 +352,7 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 // Tile (bx, by) of the face grid of one direction: DIR 0 tiles (faces, rows),
 // DIR 1 tiles (columns, faces).
 // lds: the kernel's LDS tile, NQ rows of NSEG line segments.
-template <int DIR, int STAGE, class GT = double, class TL = Tile8x16>
+template <int DIR, int STAGE, class GT = double, class TL = Tile8x16, bool CH = false>
 __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx, int by,
                                             double (*lds)[TL::NSEG]) {
   constexpr int TF = TL::F, TT = TL::T, TH = TL::H, NSEG = TL::NSEG, HALO = TL::HALO;
@@ -376,6 +377,7 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   {
     const int i0 = DIR == 0 ? f0 - 2 : t0 - HALO, j0 = DIR == 0 ? t0 - HALO : f0 - 2;
     const bool interior = i0 >= 0 && j0 >= 0 && i0 + TH <= G.nx && j0 + TH <= G.ny;
+    constexpr bool charv = CH;
     const size_t N = (size_t)G.nx * G.ny;
 #pragma unroll 1
     for (int item = threadIdx.x; item < NSEG * 4; item += FACE_THREADS) {
@@ -399,13 +401,17 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
         }
       }
       const double ref = w[1];
-      const Line5 L = normal_line(w[0] - ref, w[2] - ref, w[3] - ref, hn * gd[0], hn * gd[1], hn * gd[2],
-                                  hn * gd[3], G.eps);
-      lds[0 * 4 + k][pos] = L.v;
-      lds[1 * 4 + k][pos] = L.vn;
-      lds[2 * 4 + k][pos] = L.vnn;
-      lds[3 * 4 + k][pos] = L.wl;
-      lds[4 * 4 + k][pos] = L.wr;
+      const double a = w[0] - ref, c = w[2] - ref, d = w[3] - ref;
+      const double A = hn * gd[0], Bq = hn * gd[1], C = hn * gd[2], D = hn * gd[3];
+      double v, vn, vnn;
+      p7_shifted(a, c, d, A, Bq, C, D, v, vn, vnn);
+      lds[0 * 4 + k][pos] = v;
+      lds[1 * 4 + k][pos] = vn;
+      lds[2 * 4 + k][pos] = vnn;
+      if constexpr (!charv) {
+        lds[3 * 4 + k][pos] = weno_left(a, c, d, A, Bq, C, D, G.eps);
+        lds[4 * 4 + k][pos] = weno_left(d - c, -c, a - c, -D, -C, -Bq, -A, G.eps) + c;
+      }
       lds[20 + k][pos] = ref;
       // the cells' tangential gradient carried across the face by the cubic
       // through the 4 stencil cells: value and (unit-width) normal derivative
@@ -413,6 +419,49 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
       cross_face(gt[0], gt[1], gt[2], gt[3], ht, hT, hTN);
       lds[24 + k][pos] = hT;
       lds[28 + k][pos] = hTN;
+    }
+    // characteristic variables: the WENO-Z states of each line segment from
+    // all four components (normal momentum first on y faces)
+    if constexpr (charv) {
+#pragma unroll 1
+      for (int s = threadIdx.x; s < NSEG; s += FACE_THREADS) {
+        int fl, tl, pos;
+        if (DIR == 0) { tl = s / TF; fl = s % TF; pos = tl * TF + fl; }
+        else { fl = s / TH; tl = s % TH; pos = fl * TH + tl; }
+        const int f = f0 + fl, ta = t0 - HALO + tl;
+        if (f > nn || ta > nt + HALO - 1) continue;
+        double Wc[4][4], Dc[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int i = DIR == 0 ? f - 2 + m : ta, j = DIR == 0 ? ta : f - 2 + m;
+          load_cell<4, GT>(S, G, i, j, DIR, Wc[m], Dc[m]);
+          if (DIR == 1) {
+            double t = Wc[m][1]; Wc[m][1] = Wc[m][2]; Wc[m][2] = t;
+            t = Dc[m][1]; Dc[m][1] = Dc[m][2]; Dc[m][2] = t;
+          }
+        }
+        double Wm[4], L[4][4], R[4][4], a[4], c[4], d[4], A[4], Bq[4], C[4], D[4], wl[4], wr[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double ref = Wc[1][k];
+          Wm[k] = 0.5 * (Wc[1][k] + Wc[2][k]);
+          a[k] = Wc[0][k] - ref; c[k] = Wc[2][k] - ref; d[k] = Wc[3][k] - ref;
+          A[k] = hn * Dc[0][k]; Bq[k] = hn * Dc[1][k]; C[k] = hn * Dc[2][k]; D[k] = hn * Dc[3][k];
+        }
+        if (!char_basis<4>(Wm, G.gas.gamma, L, R)) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) L[i][j] = R[i][j] = i == j ? 1.0 : 0.0;
+        }
+        weno_char<4>(L, R, a, c, d, A, Bq, C, D, G.eps, wl, wr);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int ks = DIR == 1 && (k == 1 || k == 2) ? 3 - k : k;
+          lds[3 * 4 + ks][pos] = wl[k];
+          lds[4 * 4 + ks][pos] = wr[k];
+        }
+      }
     }
   }
   __syncthreads();
@@ -486,12 +535,12 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   for (int q = 0; q < NO; ++q) F[q * plane + idx] = acc[q];
 }
 
-template <int DIR, int STAGE, class GT, class TL>
+template <int DIR, int STAGE, class GT, class TL, bool CH>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom G, Bufs B) {
   __shared__ double lds[NQ][TL::NSEG];
   int bx, by;
   xcd_tile(bx, by);
-  faces2_body<DIR, STAGE, GT, TL>(G, B, bx, by, lds);
+  faces2_body<DIR, STAGE, GT, TL, CH>(G, B, bx, by, lds);
 }
 
 // ---------------------------------------------------------------- 2D update
@@ -620,6 +669,28 @@ __device__ __forceinline__ void faces1_body(const Geom& G, const Bufs& B, int f)
     in.Wt[k] = 0.0; in.Wnt[k] = 0.0; in.Wtt[k] = 0.0;
     in.Wl[k] = ref + L.wl;
     in.Wr[k] = ref + L.wr;
+  }
+  if (G.charv) {   // the WENO-Z states in the characteristic variables of the mean of cells i, i+1
+    double Wm[3], L[3][3], R[3][3], a[3], c[3], d[3], A[3], Bv[3], C[3], D[3], wl[3], wr[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double ref = Wc[1][k];
+      Wm[k] = 0.5 * (Wc[1][k] + Wc[2][k]);
+      a[k] = Wc[0][k] - ref; c[k] = Wc[2][k] - ref; d[k] = Wc[3][k] - ref;
+      A[k] = h * Dc[0][k]; Bv[k] = h * Dc[1][k]; C[k] = h * Dc[2][k]; D[k] = h * Dc[3][k];
+    }
+    if (!char_basis<3>(Wm, G.gas.gamma, L, R)) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) L[i][j] = R[i][j] = i == j ? 1.0 : 0.0;
+    }
+    weno_char<3>(L, R, a, c, d, A, Bv, C, D, G.eps, wl, wr);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      in.Wl[k] = Wc[1][k] + wl[k];
+      in.Wr[k] = Wc[1][k] + wr[k];
+    }
   }
   int gweno = 0;
   if (!admissible<3>(in.Wl, G.gas.gamma)) {
@@ -767,8 +838,13 @@ struct SlotDev {
   int nparts;          // CFL partial maxima (update blocks)
 };
 
-// Slot kinds: the face kernels differ by Gauss points and gradient storage.
-enum { BK_G2 = 0, BK_G4 = 1, BK_G2_F32 = 2, BK_G4_F32 = 3, BK_KINDS = 4 };
+// Slot kinds: the face kernels differ by Gauss points (bit 0: four),
+// gradient storage (bit 1: FP32) and the variables of the WENO-Z states
+// (bit 2: characteristic).
+enum { BK_G2 = 0, BK_G4 = 1, BK_G2_F32 = 2, BK_G4_F32 = 3, BK_CHAR = 4, BK_KINDS = 8 };
+constexpr bool kind_g4(int kind) { return kind & 1; }
+constexpr bool kind_f32(int kind) { return kind & 2; }
+constexpr bool kind_char(int kind) { return kind & BK_CHAR; }
 
 // Running slots of one kind: work item i of a face direction belongs to the
 // k-th of them when pre[dir][k] <= i < pre[dir][k + 1] (face tiles).
@@ -821,8 +897,9 @@ __global__ void kb_end(const SlotDev* slots, const BatchTable* tab) {
   end_body(slots[tab->slot[blockIdx.x]].B.sc);
 }
 
-// Face tiles of the slots of one kind (tile shape TL, gradient storage GT).
-template <int DIR, int STAGE, class GT, class TL>
+// Face tiles of the slots of one kind (tile shape TL, gradient storage GT,
+// characteristic variables CH).
+template <int DIR, int STAGE, class GT, class TL, bool CH>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces(const SlotDev* slots,
                                                                             const BatchTable* tab, int kind) {
   __shared__ double lds[NQ][TL::NSEG];
@@ -835,7 +912,7 @@ __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces(cons
   const SlotDev& sd = slots[L.slot[k]];
   const int local = item - pre[k];
   const int w = sd.gw[DIR];
-  faces2_body<DIR, STAGE, GT, TL>(sd.G, sd.B, local % w, local / w, lds);
+  faces2_body<DIR, STAGE, GT, TL, CH>(sd.G, sd.B, local % w, local / w, lds);
 }
 
 template <int STAGE, class GT>
@@ -931,6 +1008,7 @@ static int validate(const cgks_config* c) {
   if (c->storage != CGKS_FP64 && !(c->storage == CGKS_FP32_STORAGE && c->dim == 2)) return CGKS_EINVAL;
   const int gp = c->gauss_points ? c->gauss_points : 2;
   if (gp != 2 && !(gp == 4 && c->dim == 2)) return CGKS_EINVAL;
+  if (c->recon_vars != CGKS_CONSERVATIVE && c->recon_vars != CGKS_CHARACTERISTIC) return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
     if (c->bc[s] < 0 || c->bc[s] > 4) return CGKS_EINVAL;
     const int n = s < 2 ? c->nx : c->ny;
@@ -956,6 +1034,7 @@ static void make_geom(const cgks_config& cfg, Geom& G) {
   G.inv_dx = 1.0 / G.dx;
   G.inv_dy = 1.0 / G.dy;
   G.eps = cfg.weno_eps;
+  G.charv = cfg.recon_vars == CGKS_CHARACTERISTIC;
   G.gas = make_gas(cfg.gamma, cfg.dim, cfg.tau_eps, cfg.tau_C, cfg.mu);
   for (int s = 0; s < 4; ++s) {
     G.bc[s] = s < 2 * cfg.dim ? cfg.bc[s] : CGKS_PERIODIC;
@@ -1159,21 +1238,28 @@ static void launch_step_on(const Geom& G, const Bufs& B, int gp, int storage, co
     auto faces = [&](auto dir, auto stage, auto gt, int kind) {
       constexpr int DIR = decltype(dir)::value, STAGE = decltype(stage)::value;
       using GT = decltype(gt);
-      auto go = [&](auto tl) {
+      auto go = [&](auto tl, auto ch) {
         using TL = decltype(tl);
+        constexpr bool CH = decltype(ch)::value;
         const dim3 g = DIR == 0 ? dim3((G.nx + 1 + TL::F - 1) / TL::F, (G.ny + TL::T - 1) / TL::T)
                                 : dim3((G.nx + TL::T - 1) / TL::T, (G.ny + 1 + TL::F - 1) / TL::F);
-        run(kind, [&] { k_faces2<DIR, STAGE, GT, TL><<<g, FACE_THREADS, 0, s>>>(G, B); });
+        run(kind, [&] { k_faces2<DIR, STAGE, GT, TL, CH><<<g, FACE_THREADS, 0, s>>>(G, B); });
       };
+      using CV = std::false_type;
+      using CC = std::true_type;
       if (gp == 4) {
-        if constexpr (DIR == 0) go(Tile4x16G4());
-        else go(Tile2x32G4());
+        if (G.charv) { if constexpr (DIR == 0) go(Tile4x16G4(), CC()); else go(Tile2x32G4(), CC()); }
+        else { if constexpr (DIR == 0) go(Tile4x16G4(), CV()); else go(Tile2x32G4(), CV()); }
+        return;
+      }
+      if (G.charv) {   // characteristic variables: one tile shape per direction
+        if constexpr (DIR == 0) go(Tile4x32(), CC()); else go(Tile2x64(), CC());
         return;
       }
       switch (tiles[DIR]) {
-        case 1: go(Tile4x32()); break;
-        case 2: go(Tile2x64()); break;
-        default: go(Tile8x16()); break;
+        case 1: go(Tile4x32(), CV()); break;
+        case 2: go(Tile2x64(), CV()); break;
+        default: go(Tile8x16(), CV()); break;
       }
     };
     using D0 = std::integral_constant<int, 0>;
@@ -1528,12 +1614,13 @@ struct SlotInfo {
   int nb[2] = {0, 0}, nbu = 0;     // blocks of the x-face, y-face and update grids
 };
 
-// Face tile shape of a kind per direction: two points with FP64 storage use
-// the batch's tuned shapes (0 = 8x16, 1 = 4x32, 2 = 2x64), FP32 storage 4x32
-// and 2x64, four points the four-point tiles.
+// Face tile shape of a kind per direction: two points with FP64 storage and
+// conservative variables use the batch's tuned shapes (0 = 8x16, 1 = 4x32,
+// 2 = 2x64), the other two-point kinds 4x32 and 2x64, four points the
+// four-point tiles.
 struct TileDims { int F, T; };
 static TileDims kind_tile(int kind, int dir, const int* tile) {
-  if (kind == BK_G4 || kind == BK_G4_F32)
+  if (kind_g4(kind))
     return dir == 0 ? TileDims{Tile4x16G4::F, Tile4x16G4::T} : TileDims{Tile2x32G4::F, Tile2x32G4::T};
   const int shape = kind == BK_G2 ? tile[dir] : (dir == 0 ? 1 : 2);
   switch (shape) {
@@ -1647,7 +1734,8 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   SlotInfo& in = b->info[k];
   const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
   const int f32 = cfg->storage == CGKS_FP32_STORAGE;
-  const int kind = gp == 4 ? (f32 ? BK_G4_F32 : BK_G4) : (f32 ? BK_G2_F32 : BK_G2);
+  const int kind = (gp == 4 ? BK_G4 : BK_G2) | (f32 ? BK_G2_F32 : 0) |
+                   (cfg->recon_vars == CGKS_CHARACTERISTIC ? BK_CHAR : 0);
   make_geom(*cfg, sd.G);
   const Geom& G = sd.G;
   const size_t N = (size_t)G.nx * G.ny;
@@ -1742,7 +1830,7 @@ static int refresh_table(cgks_batch* b) {
     F.pre[0][F.n + 1] = F.pre[0][F.n] + in.nb[0];
     F.pre[1][F.n + 1] = F.pre[1][F.n] + in.nb[1];
     ++F.n;
-    UpdateList& U = t.upd[in.kind >= BK_G2_F32];
+    UpdateList& U = t.upd[kind_f32(in.kind)];
     U.slot[U.n] = run[i];
     U.pre[U.n + 1] = U.pre[U.n] + in.nbu;
     ++U.n;
@@ -1788,19 +1876,29 @@ static void launch_batch_step(cgks_batch* b) {
     for (int q = 0; q < BK_KINDS; ++q) {
       const int g = b->cap_f[q][DIR];
       if (!g) continue;
-      auto go = [&](auto gt, auto tl) {
-        kb_faces<DIR, STAGE, decltype(gt), decltype(tl)><<<g, FACE_THREADS, 0, s>>>(sl, t, q);
+      auto go = [&](auto gt, auto tl, auto ch) {
+        kb_faces<DIR, STAGE, decltype(gt), decltype(tl), decltype(ch)::value><<<g, FACE_THREADS, 0, s>>>(sl, t, q);
       };
-      if (q == BK_G4 || q == BK_G4_F32) {
-        if (q == BK_G4) { if constexpr (DIR == 0) go(0.0, Tile4x16G4()); else go(0.0, Tile2x32G4()); }
-        else { if constexpr (DIR == 0) go(0.0f, Tile4x16G4()); else go(0.0f, Tile2x32G4()); }
-      } else if (q == BK_G2_F32) {
-        if constexpr (DIR == 0) go(0.0f, Tile4x32()); else go(0.0f, Tile2x64());
+      // the tile shapes of kind_tile
+      auto go_ch = [&](auto ch) {
+        if (kind_g4(q)) {
+          if (!kind_f32(q)) { if constexpr (DIR == 0) go(0.0, Tile4x16G4(), ch); else go(0.0, Tile2x32G4(), ch); }
+          else { if constexpr (DIR == 0) go(0.0f, Tile4x16G4(), ch); else go(0.0f, Tile2x32G4(), ch); }
+        } else if (kind_f32(q)) {
+          if constexpr (DIR == 0) go(0.0f, Tile4x32(), ch); else go(0.0f, Tile2x64(), ch);
+        } else {
+          if constexpr (DIR == 0) go(0.0, Tile4x32(), ch); else go(0.0, Tile2x64(), ch);
+        }
+      };
+      if (kind_char(q)) {
+        go_ch(std::true_type());
+      } else if (q != BK_G2) {
+        go_ch(std::false_type());
       } else {
         switch (b->tile[DIR]) {
-          case 1: go(0.0, Tile4x32()); break;
-          case 2: go(0.0, Tile2x64()); break;
-          default: go(0.0, Tile8x16()); break;
+          case 1: go(0.0, Tile4x32(), std::false_type()); break;
+          case 2: go(0.0, Tile2x64(), std::false_type()); break;
+          default: go(0.0, Tile8x16(), std::false_type()); break;
         }
       }
     }
@@ -1865,7 +1963,7 @@ extern "C" int cgks_batch_read(cgks_batch* b, int slot, double* fields_out, int 
   const SlotDev& sd = b->h_slots[slot];
   const size_t N = b->info[slot].N;
   const double* S = sd.B.S[b->h_sc[slot].cur];
-  if (b->info[slot].kind >= BK_G2_F32) {
+  if (kind_f32(b->info[slot].kind)) {
     // converted to FP64 straight into a device output, else via W* (free between steps)
     double* dst = on_device ? fields_out : sd.B.Ws;
     k_from_storage32<<<(unsigned)((N + 255) / 256), 256, 0, b->stream>>>(S, dst, N);

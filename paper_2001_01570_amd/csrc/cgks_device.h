@@ -157,6 +157,95 @@ CGKS_HD __forceinline__ Line5 normal_line(double a, double c, double d, double A
   return r;
 }
 
+// ----------------------------------------------------------------------------
+// Characteristic variables (Sec. 3.2: the reconstruction may act on the
+// conservative or on the characteristic variables).  Per line and face, the
+// WENO-Z states are reconstructed in the coordinates of the right
+// eigenvectors of the Jacobian of the Euler flux normal to the face at the
+// mean of the two cells beside it; P7 is linear and needs no change.
+// At a state W (normal momentum first) with velocity (u, v), sound speed c,
+// total enthalpy H, q2 = u^2 + v^2 and b = (gamma - 1)/c^2 the waves
+// u - c, u (2D: twice), u + c have the right eigenvectors (columns of R)
+//   (1, u - c, v, H - u c), (1, u, v, q2/2), (0, 0, 1, v), (1, u + c, v, H + u c)
+// and L = R^-1 has the rows
+//   (b q2/4 + u/(2c), -b u/2 - 1/(2c), -b v/2, b/2),  (1 - b q2/2, b u, b v, -b),
+//   (-v, 0, 1, 0),  (b q2/4 - u/(2c), -b u/2 + 1/(2c), -b v/2, b/2)
+// (NC = 3: without v and the shear wave).  The scaling of the eigenvectors
+// matters (the WENO-Z weights are not scale invariant): first entry 1, and
+// the shear wave's v entry 1.  Returns false when W is not admissible; the
+// line then keeps the conservative variables.
+// ----------------------------------------------------------------------------
+template <int NC>
+CGKS_HD __forceinline__ bool char_basis(const double* W, double gamma, double (&L)[NC][NC], double (&R)[NC][NC]) {
+  if (!(W[0] > 0.0)) return false;
+  const double rho = W[0];
+  const double u = W[1] / rho;
+  const double v = NC == 4 ? W[2] / rho : 0.0;
+  const double q2 = u * u + v * v;
+  const double p = (gamma - 1.0) * (W[NC - 1] - 0.5 * rho * q2);
+  if (!(p > 0.0) || !(p < INFINITY) || !(rho < INFINITY)) return false;
+  const double c = sqrt(gamma * p / rho);
+  const double H = (W[NC - 1] + p) / rho;
+  const double b = (gamma - 1.0) / (c * c);
+  const double hc = 0.5 / c;
+  constexpr int E = NC - 1;   // energy component, and the u + c wave
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) { L[i][j] = 0.0; R[i][j] = 0.0; }
+  R[0][0] = 1.0; R[1][0] = u - c; R[E][0] = H - u * c;
+  R[0][1] = 1.0; R[1][1] = u;     R[E][1] = 0.5 * q2;
+  R[0][E] = 1.0; R[1][E] = u + c; R[E][E] = H + u * c;
+  L[0][0] = 0.25 * b * q2 + u * hc; L[0][1] = -0.5 * b * u - hc; L[0][E] = 0.5 * b;
+  L[1][0] = 1.0 - 0.5 * b * q2;     L[1][1] = b * u;             L[1][E] = -b;
+  L[E][0] = 0.25 * b * q2 - u * hc; L[E][1] = -0.5 * b * u + hc; L[E][E] = 0.5 * b;
+  if constexpr (NC == 4) {
+    R[2][0] = v; R[2][1] = v; R[2][E] = v; R[2][2] = 1.0; R[E][2] = v;
+    L[0][2] = -0.5 * b * v; L[1][2] = b * v; L[E][2] = -0.5 * b * v;
+    L[2][0] = -v; L[2][2] = 1.0;
+  }
+  return true;
+}
+
+// The WENO-Z left and right states of one line in characteristic variables:
+// a, c, d (cells i-1, i+1, i+2 minus cell i) and A..D (h Q' of cells i-1..i+2)
+// per component are projected with L, reconstructed per characteristic
+// component (the right state mirrored as in normal_line) and projected back
+// with R; wl, wr are deviations from cell i.
+template <int NC>
+CGKS_HD __forceinline__ void weno_char(const double (&L)[NC][NC], const double (&R)[NC][NC], const double* a,
+                                       const double* c, const double* d, const double* A, const double* B,
+                                       const double* C, const double* D, double eps, double* wl, double* wr) {
+  double cl[NC], cr[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    double x[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      x[0] += L[j][k] * a[k];
+      x[1] += L[j][k] * c[k];
+      x[2] += L[j][k] * d[k];
+      x[3] += L[j][k] * A[k];
+      x[4] += L[j][k] * B[k];
+      x[5] += L[j][k] * C[k];
+      x[6] += L[j][k] * D[k];
+    }
+    cl[j] = weno_left(x[0], x[1], x[2], x[3], x[4], x[5], x[6], eps);
+    cr[j] = weno_left(x[2] - x[1], -x[1], x[0] - x[1], -x[6], -x[5], -x[4], -x[3], eps) + x[1];
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    double sl = 0.0, sr = 0.0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      sl += R[k][j] * cl[j];
+      sr += R[k][j] * cr[j];
+    }
+    wl[k] = sl;
+    wr[k] = sr;
+  }
+}
+
 // The cells' tangential gradient g of the 4 stencil cells carried across the
 // face by the cubic through their averages: ht T (value at the face) and
 // ht TN (its normal derivative at unit normal width), times the tangential

@@ -103,6 +103,8 @@ def test_create_rejects_invalid_configurations_before_touching_the_device():
     assert rc(base, bc=(5, 5, 0, 0)) == EINVAL                    # unknown boundary kind
     assert rc(base, bc=(0, 1, 0, 0)) == EINVAL                    # periodic on one side only
     assert rc(base, storage=7) == EINVAL
+    assert rc(base, recon_vars=2) == EINVAL                       # conservative or characteristic
+    assert rc(base, recon_vars=-1) == EINVAL
     assert rc(I.sine_wave_1d(8), storage=CGKS_FP32_STORAGE) == EINVAL   # FP32 storage is 2D only
     walled = dataclasses.replace(base, bc=(I.WALL, I.WALL, I.NOSLIP, I.NOSLIP))
     assert rc(walled, nx=1) == EINVAL                             # a wall needs 2 cells to mirror
