@@ -335,6 +335,9 @@ def main():
     ap.add_argument('--gauss-points', type=int, choices=(2, 4), default=2,
                     help='Gauss points per face segment in 2D (4: the eighth-order 2D assembly with the 7-segment '
                          'sextic; the headline uses 2)')
+    ap.add_argument('--recon-vars', choices=('conservative', 'characteristic'), default='conservative',
+                    help='variables of the WENO-Z states (the headline: conservative); the flop count covers '
+                         'the conservative kernels only, so the roofline is left out for characteristic')
     ap.add_argument('--fp32-storage', action='store_true',
                     help='instead: the same workload with FP32 storage of the gradients, and its error vs FP64')
     args = ap.parse_args()
@@ -368,6 +371,10 @@ def main():
     if args.gauss_points != 2:
         prob = dataclasses.replace(prob, gauss_points=args.gauss_points)
         workload += ', %d Gauss points per face segment' % args.gauss_points
+    charv = args.recon_vars == 'characteristic'
+    if charv:
+        prob = dataclasses.replace(prob, recon_vars=1)
+        workload += ', WENO-Z states in characteristic variables'
     fields = torch.from_numpy(prob.fields).to('cuda')
     torch.cuda.synchronize()
     s = Solver(prob, load_state=False)
@@ -418,7 +425,7 @@ def main():
     flops = load_flops()
     roof = None
     units_key = 'per_launch_units' if args.gauss_points == 2 else 'per_launch_units_4pt'
-    if flops is not None and name in flops.get(units_key, {}):
+    if flops is not None and name in flops.get(units_key, {}) and not charv:
         unit = flops[units_key][name]
         nunits = launch_units(name, prob.nx, prob.ny)
         alg = unit['flops_per_unit'] * nunits
@@ -431,7 +438,7 @@ def main():
 
     # the whole step: algorithmic flops per cell and step times the rate
     step = None
-    if flops is not None and args.gauss_points == 2:
+    if flops is not None and args.gauss_points == 2 and not charv:
         fc = flops['flops_per_cell_step']
         step = {'flops_per_cell_step': fc, 'tflops': fc * value / 1e12,
                 'frac_of_fp64_peak': fc * value / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
