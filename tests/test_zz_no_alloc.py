@@ -2,7 +2,7 @@
 (cgks_step_dt) on the same input and step size, through the C ABI: two calls
 in a row, the second on a smaller grid (the shared scratch keeps the first
 call's contents), 2D and 1D, four Gauss points, the queued (no wait) form,
-and its error paths."""
+characteristic variables, and its error paths."""
 import dataclasses
 import sys
 
@@ -63,6 +63,10 @@ def test_walls_inflow_viscous_and_four_points():
     _check(p)
     _check(dataclasses.replace(I.shock_vortex_2d(64, 32), mu=1e-3))
     _check(dataclasses.replace(I.diagonal_wave_2d(24), gauss_points=4))
+    # WENO-Z states in characteristic variables (the kernel instances of their own)
+    _check(dataclasses.replace(I.shock_vortex_2d(64, 32), recon_vars=1))
+    _check(dataclasses.replace(I.shock_vortex_2d(48, 24), recon_vars=1, gauss_points=4))
+    _check(dataclasses.replace(I.shock_tube_1d(100), recon_vars=1))
 
 
 def test_one_dimensional_and_fixed_step():
