@@ -153,7 +153,10 @@ int cgks_counters(cgks_ctx *ctx, cgks_counters_t *out);
 /* Tile shape of the face kernels per direction: 0 = 8 faces x 16 segments,
  * 1 = 4 x 32, 2 = 2 x 64 (faces along the normal x segments along the face).
  * Results do not depend on the shape (each face is computed alike); the
- * choice only changes speed and is made by the autotuner's table. */
+ * choice only changes speed and is made by the autotuner's table.  It
+ * applies to two-point FP64 and FP32 configurations with conservative
+ * variables; four points and characteristic variables use one fixed shape
+ * per direction. */
 int cgks_set_tiles(cgks_ctx *ctx, int x_shape, int y_shape);
 void cgks_destroy(cgks_ctx *ctx);
 const char *cgks_strerror(int code);
@@ -211,8 +214,9 @@ int cgks_batch_create(size_t hbm_budget_bytes, int max_slots, void *hip_stream, 
  * state is copied, host or device pointer) that runs until t_end (> 0) or for
  * max_steps (> 0) steps, whichever comes first (one of them must be given).
  * Any configuration a 2D context accepts is admitted: two or four Gauss
- * points, FP64 or FP32 gradient storage; slots of each such kind share their
- * own face launches, so a mix of kinds runs in one step.  Returns its slot.
+ * points, FP64 or FP32 gradient storage, conservative or characteristic
+ * variables; slots of each such kind share their own face launches, so a mix
+ * of kinds runs in one step.  Returns its slot.
  * CGKS_EBUSY: no free slot or no room in the arena; CGKS_ENONPHYS:
  * non-physical initial state; CGKS_EINVAL: bad configuration or dim != 2.  A
  * device pointer must be ready (its producer synchronized). */

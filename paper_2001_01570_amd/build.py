@@ -28,14 +28,40 @@ def hipcc() -> str:
 FLOPS_JSON = os.path.join(PKG, 'flops.json')
 
 
+def code_tokens(text: str) -> str:
+    """C/C++ source with comments removed and whitespace runs collapsed (string
+    and character literals kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in '"\'':
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == '\\' else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith('//', i):
+            j = text.find('\n', i)
+            i = n if j < 0 else j
+        elif text.startswith('/*', i):
+            j = text.find('*/', i + 2)
+            i = n if j < 0 else j + 2
+            out.append(' ')
+        else:
+            out.append(c)
+            i += 1
+    return ' '.join(''.join(out).split())
+
+
 def source_digest() -> str:
-    """Digest of the HIP sources: measured or tuned figures are valid only for
-    the kernels they were taken on."""
+    """Digest of the code of the HIP sources (comments and layout excluded):
+    measured or tuned figures are valid only for the kernels they were taken
+    on."""
     import hashlib
     h = hashlib.sha256()
     for path in (os.path.join(PKG, 'csrc', 'cgks.hip'), os.path.join(PKG, 'csrc', 'cgks_device.h')):
-        with open(path, 'rb') as f:
-            h.update(f.read())
+        with open(path, encoding='utf-8') as f:
+            h.update(code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 OPCOUNT_SRC = os.path.join(PKG, 'csrc', 'opcount.cpp')
 

@@ -332,9 +332,10 @@ __global__ __launch_bounds__(256) void k_scan(Geom G, Bufs B) {
 // for two blocks per CU (one block's reconstruction overlaps the other's point
 // evaluation).  Phase 1 reconstructs TF x (TT + 2 HALO) line segments (each
 // shifted by its own reference cell), with the cells' tangential gradients
-// carried across the face, into LDS; phase 2 runs one Gauss point per thread:
-// tangential fits, gas-kinetic evolution, Gauss average over the lanes of the
-// segment.
+// carried across the face, into LDS (CH: the WENO-Z states in characteristic
+// variables, from a second pass over the segments); phase 2 runs one Gauss
+// point per thread: tangential fits, gas-kinetic evolution, Gauss average
+// over the lanes of the segment.
 // Tile of this block when consecutive blocks go round-robin to the XCDs: each
 // XCD (its own L2) gets a contiguous run of tiles in row-major order, so the
 // stencil halos shared by neighbouring tiles are fetched into one L2.
