@@ -473,25 +473,36 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   // banks), a half-wave covers 16 segments along x.  x faces: the two points in
   // the two half-waves (within a half-wave, reads of lines 2 or 4 rows apart
   // would share LDS banks), a half-wave covers 32/TF rows of TF faces.
-  // With four points (M = 4) the groups are quarter-waves (x faces) or 4
-  // adjacent lanes (y faces): point gp = 2 pr + mirror, pr 0 the inner pair
-  // of nodes, 1 the outer; the mirrored point reads the lines in reverse.
-  constexpr int M = TL::M, NL = 2 * HALO + 1, QW = 64 / M;
-  int gp, fl, tl;
-  if (DIR == 0) {
-    const int lane = threadIdx.x & 63;
-    gp = lane / QW;
-    fl = lane % TF;
-    tl = (QW / TF) * (threadIdx.x >> 6) + (lane % QW) / TF;
+  // With four points (M = 4) waves 0-1 take the inner pair of nodes and waves
+  // 2-3 the outer pair (pr, the same for a whole wave, so that the node
+  // weights are scalar loads), each wave 32 segments with the mirror pair
+  // placed as with two points; point gp = 2 pr + mirror, the mirrored point
+  // reads the lines in reverse.
+  constexpr int M = TL::M, NL = 2 * HALO + 1;
+  int mirror, fl, tl, seg = 0, pr = 0;
+  if constexpr (M == 2) {
+    if (DIR == 0) {
+      const int lane = threadIdx.x & 63;
+      mirror = lane >> 5;
+      fl = lane % TF;
+      tl = (32 / TF) * (threadIdx.x >> 6) + (lane & 31) / TF;
+    } else {
+      mirror = threadIdx.x & 1;
+      tl = (threadIdx.x >> 1) % TT;
+      fl = (threadIdx.x >> 1) / TT;
+    }
   } else {
-    gp = threadIdx.x % M;
-    tl = (threadIdx.x / M) % TT;
-    fl = (threadIdx.x / M) / TT;
+    const int lane = threadIdx.x & 63;
+    pr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);
+    mirror = DIR == 0 ? lane >> 5 : lane & 1;
+    seg = 32 * ((threadIdx.x >> 6) & 1) + (DIR == 0 ? (lane & 31) : (lane >> 1));
+    if (DIR == 0) { fl = seg % TF; tl = seg / TF; }
+    else { tl = seg % TT; fl = seg / TT; }
   }
-  constexpr int PAIR = DIR == 0 ? QW : 1;   // lane distance of the two points of a pair
+  constexpr int PAIR = DIR == 0 ? 32 : 1;   // lane distance of the two points of a pair
   const int f = f0 + fl, tt = t0 + tl;
-  if (f > nn || tt >= nt) return;
-  const int mirror = gp & 1;
+  const bool live = f <= nn && tt < nt;
+  if (M == 2 && !live) return;
   const int lstride = DIR == 0 ? TF : 1;    // next stencil line in LDS
   const int lfirst = (DIR == 0 ? tl * TF + fl : fl * TH + tl) + (mirror ? (NL - 1) * lstride : 0);
   const int lstep = mirror ? -lstride : lstride;
@@ -502,32 +513,41 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
     return W[k];
   };
   constexpr int NO = STAGE == 1 ? 16 : 8;
-  double acc[NO];
-  int guard, nbad;
+  double acc[NO] = {};
+  int guard = 0, nbad = 0;
   const double inv_hn = DIR == 0 ? G.inv_dx : G.inv_dy, inv_ht = DIR == 0 ? G.inv_dy : G.inv_dx;
   const double dsg = mirror ? -1.0 : 1.0;
   if constexpr (M == 2) {
     face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[0], kHerm2[0], dsg, inv_hn, mirror ? -inv_ht : inv_ht,
                                     G.gas, dt, acc, guard, nbad);
   } else {
-    const int pr = gp >> 1;
-    face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[pr], kHerm4[pr], dsg, inv_hn,
-                                    mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad,
-                                    pr ? kGauss4Outer : kGauss4Inner);
+    if (live)
+      face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[pr], kHerm4[pr], dsg, inv_hn,
+                                      mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad,
+                                      pr ? kGauss4Outer : kGauss4Inner);
   }
   if (guard) atomicAdd(&sc->guard_w0, 1ull);
   if (nbad) atomicAdd(&sc->guard_weno, (unsigned long long)nbad);
 
-  // Gauss average over the lanes of the segment (each point weighted in
-  // face_point: the pair, then the two pairs); the first point's lane writes
+  // Gauss average over the points of the segment (each point weighted in
+  // face_point): the mirror pair by a lane exchange; with four points the
+  // outer pair's waves then hand their sums to the inner pair's through LDS
+  // (after every wave has finished reading the reconstruction).  The first
+  // point's lane writes.
 #pragma unroll
   for (int q = 0; q < NO; ++q) acc[q] += __shfl_xor(acc[q], PAIR, 64);
   if constexpr (M == 4) {
-    constexpr int PAIRS = DIR == 0 ? 32 : 2;
+    __syncthreads();
+    if (pr == 1 && mirror == 0 && live) {
 #pragma unroll
-    for (int q = 0; q < NO; ++q) acc[q] += __shfl_xor(acc[q], PAIRS, 64);
+      for (int q = 0; q < NO; ++q) lds[q][seg] = acc[q];
+    }
+    __syncthreads();
+    if (pr == 1 || !live) return;
+#pragma unroll
+    for (int q = 0; q < NO; ++q) acc[q] += lds[q][seg];
   }
-  if (gp) return;
+  if (mirror) return;
   double* F = DIR == 0 ? B.FX : B.FY;
   // x faces: [q][row][face] (nx+1 per row); y faces: [q][face][column] (nx per row)
   const size_t plane = DIR == 0 ? (size_t)G.ny * (G.nx + 1) : (size_t)(G.ny + 1) * G.nx;
