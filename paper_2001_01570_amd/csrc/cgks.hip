@@ -467,30 +467,24 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   }
   __syncthreads();
 
-  // phase 2: one Gauss point per thread (face_point); the second point reads
-  // the stencil lines in reverse order.  y faces: the two points of a segment
-  // in adjacent lanes (their reads of a line row coincide or fall in different
-  // banks), a half-wave covers 16 segments along x.  x faces: the two points in
-  // the two half-waves (within a half-wave, reads of lines 2 or 4 rows apart
-  // would share LDS banks), a half-wave covers 32/TF rows of TF faces.
-  // With four points (M = 4) waves 0-1 take the inner pair of nodes and waves
-  // 2-3 the outer pair (pr, the same for a whole wave, so that the node
-  // weights are scalar loads), each wave 32 segments with the mirror pair
-  // placed as with two points; point gp = 2 pr + mirror, the mirrored point
-  // reads the lines in reverse.
+  // phase 2: one Gauss point per thread (face_point); the mirrored point reads
+  // the stencil lines in reverse order.  Two points: waves 0-1 evaluate the
+  // first point of the 128 segments and waves 2-3 the mirrored one, so that
+  // the mirror sign and the line order are the same for a whole wave;
+  // consecutive lanes take consecutive segments (along the face within a
+  // row of TF faces for x faces, along the face for y faces), so their LDS
+  // reads are consecutive.  Four points: waves 0-1 take the inner pair of
+  // nodes and waves 2-3 the outer pair (pr, the same for a whole wave, so
+  // that the node weights are scalar loads), each wave 32 segments with the
+  // mirror pair in its two half-waves (x faces) or adjacent lanes (y faces);
+  // point gp = 2 pr + mirror.
   constexpr int M = TL::M, NL = 2 * HALO + 1;
   int mirror, fl, tl, seg = 0, pr = 0;
   if constexpr (M == 2) {
-    if (DIR == 0) {
-      const int lane = threadIdx.x & 63;
-      mirror = lane >> 5;
-      fl = lane % TF;
-      tl = (32 / TF) * (threadIdx.x >> 6) + (lane & 31) / TF;
-    } else {
-      mirror = threadIdx.x & 1;
-      tl = (threadIdx.x >> 1) % TT;
-      fl = (threadIdx.x >> 1) / TT;
-    }
+    mirror = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);
+    seg = threadIdx.x & 127;
+    if (DIR == 0) { fl = seg % TF; tl = seg / TF; }
+    else { tl = seg % TT; fl = seg / TT; }
   } else {
     const int lane = threadIdx.x & 63;
     pr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);
@@ -499,10 +493,9 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
     if (DIR == 0) { fl = seg % TF; tl = seg / TF; }
     else { tl = seg % TT; fl = seg / TT; }
   }
-  constexpr int PAIR = DIR == 0 ? 32 : 1;   // lane distance of the two points of a pair
+  constexpr int PAIR = DIR == 0 ? 32 : 1;   // four points: lane distance of the mirror pair
   const int f = f0 + fl, tt = t0 + tl;
   const bool live = f <= nn && tt < nt;
-  if (M == 2 && !live) return;
   const int lstride = DIR == 0 ? TF : 1;    // next stencil line in LDS
   const int lfirst = (DIR == 0 ? tl * TF + fl : fl * TH + tl) + (mirror ? (NL - 1) * lstride : 0);
   const int lstep = mirror ? -lstride : lstride;
@@ -518,8 +511,9 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   const double inv_hn = DIR == 0 ? G.inv_dx : G.inv_dy, inv_ht = DIR == 0 ? G.inv_dy : G.inv_dx;
   const double dsg = mirror ? -1.0 : 1.0;
   if constexpr (M == 2) {
-    face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[0], kHerm2[0], dsg, inv_hn, mirror ? -inv_ht : inv_ht,
-                                    G.gas, dt, acc, guard, nbad);
+    if (live)
+      face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[0], kHerm2[0], dsg, inv_hn,
+                                      mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad);
   } else {
     if (live)
       face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[pr], kHerm4[pr], dsg, inv_hn,
@@ -530,12 +524,25 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   if (nbad) atomicAdd(&sc->guard_weno, (unsigned long long)nbad);
 
   // Gauss average over the points of the segment (each point weighted in
-  // face_point): the mirror pair by a lane exchange; with four points the
-  // outer pair's waves then hand their sums to the inner pair's through LDS
-  // (after every wave has finished reading the reconstruction).  The first
-  // point's lane writes.
+  // face_point), once every wave has finished reading the reconstruction:
+  // two points, the mirrored point's waves hand their results to the first
+  // point's through LDS; four points, the mirror pairs are summed by a lane
+  // exchange and the outer pair's waves hand their sums to the inner pair's
+  // through LDS.  The first point's lane writes.
+  if constexpr (M == 2) {
+    __syncthreads();
+    if (mirror == 1 && live) {
 #pragma unroll
-  for (int q = 0; q < NO; ++q) acc[q] += __shfl_xor(acc[q], PAIR, 64);
+      for (int q = 0; q < NO; ++q) lds[q][seg] = acc[q];
+    }
+    __syncthreads();
+    if (mirror == 1 || !live) return;
+#pragma unroll
+    for (int q = 0; q < NO; ++q) acc[q] += lds[q][seg];
+  } else {
+#pragma unroll
+    for (int q = 0; q < NO; ++q) acc[q] += __shfl_xor(acc[q], PAIR, 64);
+  }
   if constexpr (M == 4) {
     __syncthreads();
     if (pr == 1 && mirror == 0 && live) {
