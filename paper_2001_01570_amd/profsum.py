@@ -2,6 +2,7 @@
 
     python -m paper_2001_01570_amd.profsum stats  KERNEL_STATS_CSV --cmd "..."
     python -m paper_2001_01570_amd.profsum fp64   COUNTER_CSV --nx N --ny N --cmd "..."
+    python -m paper_2001_01570_amd.profsum counters COUNTER_CSV --cmd "..."
     python -m paper_2001_01570_amd.profsum traffic FETCH_CSV WRITE_CSV --copy-mib M --nx N --ny N
                                                    --cmd-fetch "..." --cmd-write "..."
 
@@ -105,6 +106,20 @@ def cmd_fp64(a):
               + ' %14.4g %14.4g %7.3f' % (ex, alg, ex / alg if alg else float('nan')))
 
 
+def cmd_counters(a):
+    per = read_counters(a.csv)
+    print('# rocprofv3 counters per dispatch (mean over dispatches)')
+    print('# command: %s' % a.cmd)
+    names = sorted(set(c for k in per.values() for c in k))
+    print('%-10s ' % 'kernel' + ' '.join('%16s' % n.replace('SQ_', '')[:16] for n in names))
+    for full, cs in per.items():
+        k = short_name(full)
+        if k == COPY_KERNEL or not k:
+            continue
+        mean = {n: sum(v) / len(v) for n, v in cs.items()}
+        print('%-10s ' % k + ' '.join('%16.4g' % mean.get(n, float('nan')) for n in names))
+
+
 def cmd_traffic(a):
     fetch = read_counters(a.fetch)
     write = read_counters(a.write)
@@ -154,6 +169,10 @@ def main(argv=None):
     s.add_argument('--nx', type=int, default=1024)
     s.add_argument('--ny', type=int, default=1024)
     s.set_defaults(fn=cmd_fp64)
+    s = sub.add_parser('counters')
+    s.add_argument('csv')
+    s.add_argument('--cmd', required=True)
+    s.set_defaults(fn=cmd_counters)
     s = sub.add_parser('traffic')
     s.add_argument('fetch')
     s.add_argument('write')
