@@ -569,8 +569,10 @@ def _oblique_shock(M, beta, g=1.4):
     return rr, pr, theta, Mn2 / math.sin(beta - theta)
 
 
-def test_regular_shock_reflection_steady_state():
-    """Sec. 4.4 regular shock reflection (Mach 2.9, 29 degrees, 200 x 50):
+@pytest.mark.parametrize('rv', [0, 1], ids=['conservative', 'characteristic'])
+def test_regular_shock_reflection_steady_state(rv):
+    """Sec. 4.4 regular shock reflection (Mach 2.9, 29 degrees, 200 x 50),
+    with the WENO-Z states in conservative or characteristic variables:
     no guard fires; by t = 25 the field is steady except for a small unsteady
     patch where the wall meets the free outflow (the paper's own residue
     likewise stalls for this case); along y = 0.51 the plateaus match the
@@ -582,7 +584,7 @@ def test_regular_shock_reflection_steady_state():
     r2, _, th, M2 = _oblique_shock(2.9, b1)
     br = brentq(lambda b: _oblique_shock(M2, b)[2] - th, math.asin(1 / M2) + 1e-9, math.radians(60))
     r3 = r2 * _oblique_shock(M2, br)[0]
-    p = I.shock_reflection_2d(200, 50)
+    p = dataclasses.replace(I.shock_reflection_2d(200, 50), recon_vars=rv)
     s = solver(p)
     s.advance_to(25.0)
     r25 = s.state[0].copy()
@@ -602,7 +604,7 @@ def test_regular_shock_reflection_steady_state():
         return x[k] + 0.02 * (level - row[k]) / (row[k + 1] - row[k])
     x_inc = (1 - y) / math.tan(b1)
     x_ref = 1 / math.tan(b1) + y / math.tan(br - th)
-    say('shock reflection: plateaus', row[(x > 1.2) & (x < 2.6)].mean(), r2, row[(x > 3.2) & (x < 3.9)].mean(), r3,
+    say('shock reflection', p.recon_vars, ': plateaus', row[(x > 1.2) & (x < 2.6)].mean(), r2, row[(x > 3.2) & (x < 3.9)].mean(), r3,
         'crossings', crossing(0.5 * (1 + r2), 0.3, 1.5), x_inc, crossing(0.5 * (r2 + r3), 2.5, 3.5), x_ref)
     assert abs(crossing(0.5 * (1 + r2), 0.3, 1.5) - x_inc) < 0.01
     assert abs(crossing(0.5 * (r2 + r3), 2.5, 3.5) - x_ref) < 0.01
