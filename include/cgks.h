@@ -92,6 +92,15 @@ typedef struct {
                                 across; tile shape fixed)                            */
   int recon_vars;            /* CGKS_CONSERVATIVE (0, the default) or
                                 CGKS_CHARACTERISTIC, for the WENO-Z states           */
+  int side_slopes;           /* normal slopes of the two non-equilibrium sides in the
+                                kinetic evolution (Sec. 2.1).  0 (the default): the
+                                linear reconstruction's derivative at the face for
+                                both sides.  1 (1D only, with conservative
+                                variables; an evaluated variant): each side takes
+                                the derivative of its WENO-Z combination (the
+                                candidates' slopes with the same nonlinear weights);
+                                a side that falls back to its cell average takes the
+                                linear one                                          */
 } cgks_config;
 
 typedef struct {

@@ -118,12 +118,13 @@ class OracleError(RuntimeError):
 class Oracle:
     """The oracle solver for one problem (see paper_2001_01570_amd.inputs.Problem)."""
 
-    def __init__(self, prob, threads: int = 0, side_slopes: int = 0):
+    def __init__(self, prob, threads: int = 0, side_slopes=None):
         """side_slopes = 1 (1D): the evaluated variant whose non-equilibrium
-        sides take the WENO-weighted slopes of their candidates."""
+        sides take the WENO-weighted slopes of their candidates (default: the
+        problem's own setting)."""
         cfg = _Cfg()
-        cfg.side_slopes = int(side_slopes)
         d = prob.config_dict()
+        cfg.side_slopes = int(d.get('side_slopes', 0) if side_slopes is None else side_slopes)
         for k in ('dim', 'nx', 'ny'):
             setattr(cfg, k, int(d[k]))
         for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt', 'mu'):
@@ -286,6 +287,7 @@ def face_1d(prob, cells, dt, final=False):
     for k in ('x0', 'x1', 'y0', 'y1', 'gamma', 'cfl', 'weno_eps', 'tau_eps', 'tau_C', 'fixed_dt', 'mu'):
         setattr(cfg, k, float(d[k]))
     cfg.char_vars = int(d.get('recon_vars', 0))
+    cfg.side_slopes = int(d.get('side_slopes', 0))
     a = _vec(cells, 24)
     out = np.empty(12)
     g = (C.c_long * 2)()

@@ -70,6 +70,7 @@ struct Geom {
   double inflow[4][4];   // conservative inflow state per side
   Gas gas;
   int charv;             // WENO-Z states in characteristic variables
+  int sides;             // 1D: WENO-weighted slopes of the non-equilibrium sides
 };
 
 struct Params {          // written by the host before a batch of steps
@@ -720,19 +721,39 @@ __device__ __forceinline__ void faces1_body(const Geom& G, const Bufs& B, int f)
       in.Wr[k] = Wc[1][k] + wr[k];
     }
   }
+  // normal slopes of the two non-equilibrium sides: the linear
+  // reconstruction's, or (the evaluated variant) the WENO-weighted slopes of
+  // the candidates; a side that falls back to its cell average takes the
+  // linear slope
+  double Wln[3], Wrn[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Wln[k] = Wrn[k] = in.Wn[k];
+  if (G.sides) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double ref = Wc[1][k];
+      const double a = Wc[0][k] - ref, c = Wc[2][k] - ref, d = Wc[3][k] - ref;
+      const double A = h * Dc[0][k], Bq = h * Dc[1][k], C = h * Dc[2][k], D = h * Dc[3][k];
+      double sl, sr;
+      weno_left_s<true>(a, c, d, A, Bq, C, D, G.eps, &sl);
+      weno_left_s<true>(d - c, -c, a - c, -D, -C, -Bq, -A, G.eps, &sr);
+      Wln[k] = sl / h;
+      Wrn[k] = -sr / h;
+    }
+  }
   int gweno = 0;
   if (!admissible<3>(in.Wl, G.gas.gamma)) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) in.Wl[k] = Wc[1][k];
+    for (int k = 0; k < 3; ++k) { in.Wl[k] = Wc[1][k]; Wln[k] = in.Wn[k]; }
     ++gweno;
   }
   if (!admissible<3>(in.Wr, G.gas.gamma)) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) in.Wr[k] = Wc[2][k];
+    for (int k = 0; k < 3; ++k) { in.Wr[k] = Wc[2][k]; Wrn[k] = in.Wn[k]; }
     ++gweno;
   }
   PointOut<3> o;
-  gks_point<3, STAGE == 1>(in, G.gas, dt, o);
+  gks_point<3, STAGE == 1>(in, Wln, Wrn, G.gas, dt, o);
   if (o.guard) atomicAdd(&sc->guard_w0, 1ull);
   if (gweno) atomicAdd(&sc->guard_weno, (unsigned long long)gweno);
   const size_t plane = (size_t)G.nx + 1;
@@ -1037,6 +1058,8 @@ static int validate(const cgks_config* c) {
   const int gp = c->gauss_points ? c->gauss_points : 2;
   if (gp != 2 && !(gp == 4 && c->dim == 2)) return CGKS_EINVAL;
   if (c->recon_vars != CGKS_CONSERVATIVE && c->recon_vars != CGKS_CHARACTERISTIC) return CGKS_EINVAL;
+  if (c->side_slopes != 0 && (c->side_slopes != 1 || c->dim != 1 || c->recon_vars != CGKS_CONSERVATIVE))
+    return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
     if (c->bc[s] < 0 || c->bc[s] > 4) return CGKS_EINVAL;
     const int n = s < 2 ? c->nx : c->ny;
@@ -1063,6 +1086,7 @@ static void make_geom(const cgks_config& cfg, Geom& G) {
   G.inv_dy = 1.0 / G.dy;
   G.eps = cfg.weno_eps;
   G.charv = cfg.recon_vars == CGKS_CHARACTERISTIC;
+  G.sides = cfg.side_slopes == 1;
   G.gas = make_gas(cfg.gamma, cfg.dim, cfg.tau_eps, cfg.tau_C, cfg.mu);
   for (int s = 0; s < 4; ++s) {
     G.bc[s] = s < 2 * cfg.dim ? cfg.bc[s] : CGKS_PERIODIC;

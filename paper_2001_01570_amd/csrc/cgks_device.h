@@ -80,8 +80,15 @@ CGKS_HD __forceinline__ void p7_shifted(double a, double c, double d, double A, 
 //   quartic     beta = (k1 + k3/4)^2 + 13/3 (k2 + 63/130 k4)^2 + 781/20 k3^2 + 1421461/2275 k4^2
 // (exact integrals of sum_r (q^(r))^2; beta_1 from the cubic on Q_{i-1}, Q_i,
 // Q_{i+1}, Q'_{i-1}).
-CGKS_HD __forceinline__ double weno_left(double a, double c, double d, double A, double B,
-                                            double C, double D, double eps) {
+// SLOPE: also *slope = h times the derivative at x_{i+1/2} of the WENO
+// combination of the candidate polynomials (their slopes with the same
+// nonlinear weights; an evaluated variant of the non-equilibrium side
+// slopes).  The candidates' interface slopes, from their stencil conditions
+// (csrc/candidate_slopes.py): s0 = -3a - 2A, s1 = s3 = s4 = c,
+// s2 = c/2 + 3d/8 - D/4, s5 = 3a/2 + c/2 + A/2 + 3B/2, s6 = 2c - 3d/2 + 3C/2 + D/2.
+template <bool SLOPE>
+CGKS_HD __forceinline__ double weno_left_s(double a, double c, double d, double A, double B,
+                                           double C, double D, double eps, double* slope) {
   constexpr double S2 = 13.0 / 3.0, S3 = 781.0 / 20.0, S4 = 1421461.0 / 2275.0, L42 = 63.0 / 130.0;
   // candidate values q_k(x_{i+1/2}) with Q_i removed
   const double q0 = (-7.0 * a - 4.0 * A) * (1.0 / 6.0);
@@ -141,7 +148,20 @@ CGKS_HD __forceinline__ double weno_left(double a, double c, double d, double A,
   const double a6 = (17.0 / 49.0) * (P + z * l6);
   const double num = a0 * q0 + (a1 + a3) * q1 + a2 * q2 + a4 * q4 + a5 * q5 + a6 * q6;
   const double den = a0 + a1 + a2 + a3 + a4 + a5 + a6;
-  return num * recip(den);
+  const double iden = recip(den);
+  if constexpr (SLOPE) {
+    const double s0 = -3.0 * a - 2.0 * A;
+    const double s2 = 0.5 * c + 0.375 * d - 0.25 * D;
+    const double s5 = 1.5 * a + 0.5 * c + 0.5 * A + 1.5 * B;
+    const double s6 = 2.0 * c - 1.5 * d + 1.5 * C + 0.5 * D;
+    *slope = (a0 * s0 + (a1 + a3 + a4) * c + a2 * s2 + a5 * s5 + a6 * s6) * iden;
+  }
+  return num * iden;
+}
+
+CGKS_HD __forceinline__ double weno_left(double a, double c, double d, double A, double B,
+                                         double C, double D, double eps) {
+  return weno_left_s<false>(a, c, d, A, B, C, D, eps, nullptr);
 }
 
 // Full normal reconstruction of one component on one line.  Q[0..3] are the
@@ -918,8 +938,12 @@ CGKS_HD __forceinline__ void combine(const double* W0, const double* M2, const S
 // part for the flux): the collision time tau in exp(-t/tau), its pressure-jump
 // part in the Chapman-Enskog term.  The phases above in order; FULL = false
 // computes only what the second stage needs (Ft, Wtt).
+// Wln, Wrn: the normal slopes of the two non-equilibrium sides (the linear
+// reconstruction's in.Wn as the scheme reads it, or the WENO-weighted slopes
+// of the evaluated variant).
 template <int NC, bool FULL>
-CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, double dt, PointOut<NC>& out) {
+CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const double* Wln, const double* Wrn, const Gas& g,
+                                       double dt, PointOut<NC>& out) {
   // equilibrium from the linear reconstruction; the kinetic collision state
   // of the two sides if it is not admissible
   double W0[NC];
@@ -936,10 +960,15 @@ CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, doub
   const double tau = collision_time<NC>(in.Wl, in.Wr, W0, g, dt, tau_ce);
   SideSums<NC> sd;
   sd.zero();
-  side_terms<NC, FULL>(in.Wl, +1, in.Wn, in.Wt, g, sd);
-  side_terms<NC, FULL>(in.Wr, -1, in.Wn, in.Wt, g, sd);
+  side_terms<NC, FULL>(in.Wl, +1, Wln, in.Wt, g, sd);
+  side_terms<NC, FULL>(in.Wr, -1, Wrn, in.Wt, g, sd);
   equilibrium_terms<NC, FULL>(W0, in.Wn, in.Wt, g, tau_ce, M2, sd.D35, out.F);   // D35 = M3 - M5
   combine<NC, FULL>(W0, M2, sd, tau, dt, g, out.F, out);
+}
+
+template <int NC, bool FULL>
+CGKS_HD __forceinline__ void gks_point(const PointIn<NC>& in, const Gas& g, double dt, PointOut<NC>& out) {
+  gks_point<NC, FULL>(in, in.Wn, in.Wn, g, dt, out);
 }
 
 // ----------------------------------------------------------------------------

@@ -56,6 +56,7 @@ class Problem:
     mu: float = 0.0               # dynamic viscosity (0: Euler equations)
     gauss_points: int = 2         # 2D: Gauss points per face segment (2: quartic on 5 segments, 4: sextic on 7)
     recon_vars: int = 0           # variables of the WENO-Z states: 0 conservative, 1 characteristic
+    side_slopes: int = 0          # 1D: 1 = WENO-weighted slopes of the non-equilibrium sides (evaluated variant)
     exact: Optional[Callable[[float], np.ndarray]] = None   # t -> exact fields (cell averages)
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -78,7 +79,7 @@ class Problem:
                     inflow_prim=np.asarray(inflow, dtype=np.float64).tolist(),
                     weno_eps=self.weno_eps, tau_eps=self.tau_eps, tau_C=self.tau_C,
                     fixed_dt=self.fixed_dt, mu=self.mu, gauss_points=self.gauss_points,
-                    recon_vars=self.recon_vars)
+                    recon_vars=self.recon_vars, side_slopes=self.side_slopes)
 
 
 # ---------------------------------------------------------------- helpers

@@ -1,0 +1,102 @@
+"""The evaluated side-slope variant (side_slopes = 1, 1D): the two
+non-equilibrium sides take the WENO-weighted slopes of their candidate
+polynomials instead of the linear reconstruction's derivative.  The HIP
+path against the oracle with the same option: single steps (smooth flow,
+the Sec. 4.4 shock tube, a pressure-ratio-300 tube where the guards fire),
+whole runs with each side's own steps, and a pressure-ratio-800 tube that
+only this variant carries to its end time."""
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2001_01570_amd import inputs as I
+from tests.parity import field_errors, field_scales, scaled_errors
+from tests.test_gpu_parity_runs import _guard_case, own_dt_run
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def side(p):
+    return dataclasses.replace(p, side_slopes=1)
+
+
+# (name, problem, steps before, smallest change against the linear side slopes:
+# in smooth flow the WENO-weighted slopes approach the linear derivative and
+# enter with a weight of about tau/dt, so one step moves by rounding size)
+CASES = [
+    ('smooth_wave', lambda: I.sine_wave_1d(100, eps=0.2, t_end=2.0, cfl=0.3), 0, 1e-15),
+    ('shock_tube', lambda: I.shock_tube_1d(100), 6, 1e-10),
+    ('pressure_ratio_300', lambda: I.riemann_1d((1.0, 0.0, 30.0), (0.125, 0.0, 0.1), 100), 3, 1e-10),
+]
+
+
+@pytest.mark.parametrize('name,mk,before,min_change', CASES, ids=[c[0] for c in CASES])
+def test_single_step(name, mk, before, min_change):
+    """One step from the oracle's state after `before` steps: within 1e-12 of
+    the oracle's step with the same option, and different from the step
+    with the linear side slopes (the option is in effect)."""
+    from paper_2001_01570_amd.cgks import Solver
+    p = side(mk())
+    o = O.Oracle(p)
+    for _ in range(before):
+        o.step()
+    st, t, _ = o.get_state()
+    s = Solver(p)
+    s.set_state(st, t)
+    dt = s.step()
+    o.step(dt)
+    r = Solver(dataclasses.replace(p, side_slopes=0))
+    r.set_state(st, t)
+    r.step(dt)
+    e = field_errors(s.state, o.state)
+    change = (np.abs(s.state - r.state).max(axis=1) / field_scales(o.state)).max()
+    say(name, 'errors', e.max(), 'change against the linear side slopes', change)
+    assert e.max() < TOL, e
+    assert change > min_change
+
+
+def test_shock_tube_whole_run_each_side_its_own_dt():
+    p = side(I.shock_tube_1d(100))
+    s, o, _ = own_dt_run(p, t_end=0.16, threads=1)
+    err = scaled_errors(s.state, o.state, p.dx)
+    say('side slopes, shock tube to t = 0.16:', o.counters()['steps'], 'steps, scaled errors', err)
+    assert s.t == o.t == 0.16
+    assert err.max() < TOL, err
+
+
+def test_table1_row_12_with_the_variant():
+    """Table 1's N = 12 run (14,400 steps of dt = 0.5 dx^2 to t = 200): the
+    GPU run agrees with the oracle's to the rounding of that many steps, and
+    both land on the variant's own error (above the printed R3 value)."""
+    from paper_2001_01570_amd.cgks import Solver
+    n = 12
+    dx = 2.0 / n
+    p = side(I.sine_wave_1d(n, eps=1e-4, t_end=200.0, fixed_dt=0.5 * dx * dx))
+    s, o = Solver(p), O.Oracle(p, threads=1)
+    assert s.advance_to(200.0) == o.advance_to(200.0)
+    d = np.abs(s.state[0] - o.state[0]).max()
+    eg, eo = I.density_errors(s.state, p.exact(200.0)), I.density_errors(o.state, p.exact(200.0))
+    say('side slopes, Table 1 N = 12: GPU', eg, 'oracle', eo, 'max density difference', d)
+    assert d < 1e-12 * 1e-4 * 1e3
+    assert eg[0] == pytest.approx(eo[0], rel=1e-6)
+
+
+@pytest.mark.parametrize('pr', [300.0, 800.0])
+def test_strong_tubes_guard_counts_and_states(pr):
+    """Pressure ratios 300 and 800 (Sod-like, t = 0.1 / sqrt(p_L)): step by
+    step and over the run, the guard counts equal the oracle's and the
+    states meet the parity bar (or, near a vacuum, 3x the oracle's own
+    1-ulp spread)."""
+    L, R = (1.0, 0.0, pr / 10.0), (0.125, 0.0, 0.1)
+    t_end = 0.1 / math.sqrt(pr / 10.0)
+    _guard_case(side(I.riemann_1d(L, R, 100, t_end=t_end)), t_end=t_end, min_w0=0, min_weno=0)
