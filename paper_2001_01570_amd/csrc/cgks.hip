@@ -432,11 +432,18 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
         else { fl = s / TH; tl = s % TH; pos = fl * TH + tl; }
         const int f = f0 + fl, ta = t0 - HALO + tl;
         if (f > nn || ta > nt + HALO - 1) continue;
+        // the cells through the per-component boundary rule of the loop
+        // above: the array form (load_cell) compiled in this kernel gave wrong
+        // ghost values at no-slip walls normal to the face direction
         double Wc[4][4], Dc[4][4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const int i = DIR == 0 ? f - 2 + m : ta, j = DIR == 0 ? ta : f - 2 + m;
-          load_cell<4, GT>(S, G, i, j, DIR, Wc[m], Dc[m]);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            double gt_unused;
+            load_comp<GT>(S, G, i, j, DIR, k, Wc[m][k], Dc[m][k], gt_unused);
+          }
           if (DIR == 1) {
             double t = Wc[m][1]; Wc[m][1] = Wc[m][2]; Wc[m][2] = t;
             t = Dc[m][1]; Dc[m][1] = Dc[m][2]; Dc[m][2] = t;

@@ -86,6 +86,8 @@ def test_1d_shock_tube_whole_run_each_side_its_own_dt():
 CASES_2D = [
     ('shock_vortex_walls_inflow', lambda: I.shock_vortex_2d(64, 32, Rc=0.12), 3),
     ('expansion_near_vacuum', lambda: I.expansion_2d(32, 28, U=1.25, amp=0.1), 2),
+    ('viscous_shock_vortex_noslip', lambda: dataclasses.replace(I.shock_vortex_2d(48, 24, Rc=0.12), mu=1e-3,
+                                                                bc=(I.INFLOW, I.FREE, I.NOSLIP, I.NOSLIP)), 2),
 ]
 
 
@@ -108,6 +110,47 @@ def test_2d_forty_steps_each_side_its_own_dt(gp):
     say('2d characteristic 40 steps, gauss points', gp, 'dt rel', rel.max(), 'scaled errors', err)
     assert rel.max() < 1e-13
     assert err.max() < TOL, err
+
+
+def moving_pulse():
+    """The acoustic pulse carried by a mean flow (0.2, 0.1): both momenta
+    are non-zero next to every wall."""
+    p = I.acoustic_pulse_2d(40, seed=4, amp=0.05, half_width=0.3, ny=24)
+    f = p.fields
+    f[1] += 0.2 * f[0]
+    f[2] += 0.1 * f[0]
+    f[3] += 0.5 * 0.05 * f[0]
+    return p
+
+
+@pytest.mark.parametrize('gp', [2, 4])
+@pytest.mark.parametrize('walls', ['x', 'y', 'all'])
+def test_noslip_walls_repeatable_and_at_parity(walls, gp):
+    """No-slip walls mirror both momenta, so the ghost cells of a wall normal
+    to the face direction enter the characteristic projection with every
+    component changed: three contexts from one state give bitwise equal steps,
+    and each is within 1e-12 of the oracle's (a regression test: the ghost
+    values of that pass were once wrong and varied from run to run)."""
+    N, P = I.NOSLIP, I.PERIODIC
+    bc = {'x': (N, N, P, P), 'y': (P, P, N, N), 'all': (N, N, N, N)}[walls]
+    p = dataclasses.replace(moving_pulse(), recon_vars=1, bc=bc, gauss_points=gp)
+    say('characteristic variables, no-slip walls', walls, 'gauss points', gp)
+    o = O.Oracle(p, threads=8)
+    st, t, _ = o.get_state()
+    o.step(1e-3)
+    outs = []
+    for _ in range(3):
+        s = solver(p)
+        s.set_state(st, t)
+        s.step(1e-3)
+        assert s.counters()['guard_weno'] == o.counters()['guard_weno'] == 0
+        outs.append(s.state.copy())
+        s.close()
+    for x in outs[1:]:
+        assert np.array_equal(x, outs[0])
+    e = field_errors(outs[0], o.state)
+    say('no-slip', walls, gp, 'errors', e.max())
+    assert e.max() < TOL, e
 
 
 def test_2d_guards_fire_with_characteristic_variables():

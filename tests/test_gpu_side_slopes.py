@@ -37,6 +37,7 @@ CASES = [
     ('smooth_wave', lambda: I.sine_wave_1d(100, eps=0.2, t_end=2.0, cfl=0.3), 0, 1e-15),
     ('shock_tube', lambda: I.shock_tube_1d(100), 6, 1e-10),
     ('pressure_ratio_300', lambda: I.riemann_1d((1.0, 0.0, 30.0), (0.125, 0.0, 0.1), 100), 3, 1e-10),
+    ('shock_entropy_inflow', lambda: I.shock_entropy_1d(400, t_end=1.8), 4, 1e-10),
 ]
 
 
