@@ -153,6 +153,18 @@ def test_noslip_walls_repeatable_and_at_parity(walls, gp):
     assert e.max() < TOL, e
 
 
+@pytest.mark.parametrize('rv,steps', [(0, 30), (1, 12)], ids=['conservative', 'characteristic'])
+def test_guards_fire_next_to_noslip_walls(rv, steps):
+    """The flow leaves every wall (the 2D expansion with velocity 1.0 towards
+    the curve, no-slip walls on all sides): the gas thins out along the
+    walls, the equilibrium and WENO fallbacks fire there (the WENO fallback
+    takes the cells beside the face through the boundary rule), and the
+    guard counts and states follow the oracle step by step and over the run
+    (with characteristic variables the oracle meets a vacuum at step 13)."""
+    p = dataclasses.replace(I.expansion_2d(32, 28, U=-1.0, amp=0.1), bc=(I.NOSLIP,) * 4, recon_vars=rv)
+    _guard_case(p, steps=steps, min_w0=1, min_weno=1)
+
+
 def test_2d_guards_fire_with_characteristic_variables():
     """The curved expansion to near-vacuum: equilibrium and WENO fallbacks
     fire; the guard counts equal the oracle's step by step and over the run."""
