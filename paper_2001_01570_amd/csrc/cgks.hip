@@ -182,6 +182,33 @@ __device__ __forceinline__ void load_cell(const double* S, const Geom& G, int i,
   if constexpr (NC == 4) apply_rule<NC>(G, ky, 2 + sy, 1, dir, W, Gd);
 }
 
+// the boundary rules of one component k, x rule then y rule (kinds and sides
+// from src_index), on its value w and its gradients along dir (gn) and, with
+// TANG, along the other axis (gt)
+template <bool TANG>
+__device__ __forceinline__ void comp_rule(const Geom& G, int kx, int sx, int ky, int sy, int dir, int k,
+                                          double& w, double& gn, double& gt) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int kind = a == 0 ? kx : ky;
+    if (kind < 0 || kind == CGKS_PERIODIC) continue;
+    const int side = a == 0 ? sx : 2 + sy;
+    if (kind == CGKS_FREE) {
+      gn = 0.0;
+      if (TANG) gt = 0.0;
+    } else if (kind == CGKS_INFLOW) {
+      w = G.inflow[side][k];
+      gn = 0.0;
+      if (TANG) gt = 0.0;
+    } else {  // walls about axis a: the gradient along a has the opposite parity
+      const double par = wall_parity<4>(kind, a, k);
+      w *= par;
+      gn *= dir == a ? -par : par;
+      if (TANG) gt *= dir == a ? par : -par;
+    }
+  }
+}
+
 // one component k of W and of its gradients along dir (gn) and along the other
 // axis (gt) at cell (i, j), ghosts included (2D)
 template <class GT>
@@ -195,26 +222,7 @@ __device__ __forceinline__ void load_comp(const double* S, const Geom& G, int i,
   w = S[k * N + id];
   gn = grad_planes<GT>(S, N, 4)[(4 * dir + k) * N + id];
   gt = grad_planes<GT>(S, N, 4)[(4 * (1 - dir) + k) * N + id];
-  // rules applied to one component: x rule, then y rule
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int kind = a == 0 ? kx : ky;
-    if (kind < 0 || kind == CGKS_PERIODIC) continue;
-    const int side = a == 0 ? sx : 2 + sy;
-    if (kind == CGKS_FREE) {
-      gn = 0.0;
-      gt = 0.0;
-    } else if (kind == CGKS_INFLOW) {
-      w = G.inflow[side][k];
-      gn = 0.0;
-      gt = 0.0;
-    } else {  // walls about axis a: the gradient along a has the opposite parity
-      const double par = wall_parity<4>(kind, a, k);
-      w *= par;
-      gn *= dir == a ? -par : par;
-      gt *= dir == a ? par : -par;
-    }
-  }
+  comp_rule<true>(G, kx, sx, ky, sy, dir, k, w, gn, gt);
 }
 
 // the averages only (any storage of the gradients)
@@ -432,17 +440,37 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
         else { fl = s / TH; tl = s % TH; pos = fl * TH + tl; }
         const int f = f0 + fl, ta = t0 - HALO + tl;
         if (f > nn || ta > nt + HALO - 1) continue;
-        // the cells through the per-component boundary rule of the loop
-        // above: the array form (load_cell) compiled in this kernel gave wrong
-        // ghost values at no-slip walls normal to the face direction
+        // the 4 cells: source indices, loads, then the per-component rules of
+        // the loop above (the array form, load_cell, compiled in this kernel
+        // gave wrong ghost values at no-slip walls normal to the face
+        // direction)
         double Wc[4][4], Dc[4][4];
+        int kx[4], sx[4], ky[4], sy[4];
+        size_t id[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const int i = DIR == 0 ? f - 2 + m : ta, j = DIR == 0 ? ta : f - 2 + m;
+          sx[m] = 0;
+          sy[m] = 0;
+          const int si = src_index(i, G.nx, G.bc[0], G.bc[1], kx[m], sx[m]);
+          const int sj = src_index(j, G.ny, G.bc[2], G.bc[3], ky[m], sy[m]);
+          id[m] = (size_t)sj * G.nx + si;
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            double gt_unused;
-            load_comp<GT>(S, G, i, j, DIR, k, Wc[m][k], Dc[m][k], gt_unused);
+            Wc[m][k] = S[k * N + id[m]];
+            Dc[m][k] = grad_planes<GT>(S, N, 4)[(4 * DIR + k) * N + id[m]];
+          }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          if (!interior) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              double unused = 0.0;
+              comp_rule<false>(G, kx[m], sx[m], ky[m], sy[m], DIR, k, Wc[m][k], Dc[m][k], unused);
+            }
           }
           if (DIR == 1) {
             double t = Wc[m][1]; Wc[m][1] = Wc[m][2]; Wc[m][2] = t;
