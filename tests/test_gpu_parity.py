@@ -425,8 +425,9 @@ def test_largest_accepted_grid_single_step_sampled():
     del s, f
 
 
-def test_config4_full_size_single_step_sampled():
-    p = I.shock_vortex_2d(2048, 1024)
+@pytest.mark.parametrize('rv', [0, 1], ids=['conservative', 'characteristic'])
+def test_config4_full_size_single_step_sampled(rv):
+    p = dataclasses.replace(I.shock_vortex_2d(2048, 1024), recon_vars=rv)
     wins = [(0, 0), (508, 500), (254, 508), (2040, 1016), (1024, 0), (0, 1016), (250, 470)]
     say('config4 sampled windows', wins)
     worst, s = _sampled(p, wins)
@@ -527,8 +528,13 @@ def test_config4_inviscid_runs_to_its_end_time():
     assert abs(np.median(off)) <= 1.0 and np.abs(off).max() <= 12.0, off
 
 
-def test_viscous_shock_vortex_full_size_single_step_sampled():
-    p = I.viscous_shock_vortex_2d()
+@pytest.mark.parametrize('rv', [0, 1], ids=['conservative', 'characteristic'])
+def test_viscous_shock_vortex_full_size_single_step_sampled(rv):
+    """The paper's viscous case at its full 700 x 600 size (free outflow,
+    inflow, periodic in y): one GPU step, windows on the shock, the vortex,
+    the corners and the sides recomputed by the oracle; also with
+    characteristic variables."""
+    p = dataclasses.replace(I.viscous_shock_vortex_2d(), recon_vars=rv)
     # shock at x = 0 (column 500), vortex at (2, 0) (column 550, row 300)
     wins = [(496, 296), (546, 296), (540, 260), (0, 0), (692, 592), (300, 10)]
     say('viscous shock-vortex sampled windows', wins)
