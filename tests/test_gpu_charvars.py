@@ -199,15 +199,18 @@ def test_fp32_storage_single_step(gp):
 
 def test_batch_characteristic_kinds_equal_separate_contexts():
     """Characteristic slots of every Gauss-point count and storage next to
-    conservative ones in one batch: bitwise equal to separate contexts on
-    every replay, and one characteristic slot within 1e-12 of the oracle."""
+    conservative ones in one batch (walls, inflow, no-slip walls on every
+    side): bitwise equal to separate contexts on every replay, and one
+    characteristic slot within 1e-12 of the oracle."""
     from paper_2001_01570_amd.cgks import Batch, CGKS_FP32_STORAGE
     g4 = lambda p: dataclasses.replace(p, gauss_points=4)
     kinds = [(chv(I.shock_vortex_2d(64, 32, Rc=0.12)), 0),
              (chv(g4(I.acoustic_pulse_2d(37, seed=4, amp=0.05, half_width=0.3, ny=21))), 0),
              (chv(I.vortex_translation_2d(24)), CGKS_FP32_STORAGE),
              (chv(g4(I.shock_vortex_2d(40, 24, Rc=0.12))), CGKS_FP32_STORAGE),
-             (I.shock_vortex_2d(64, 32, Rc=0.12), 0)]
+             (I.shock_vortex_2d(64, 32, Rc=0.12), 0),
+             (chv(dataclasses.replace(moving_pulse(), bc=(I.NOSLIP,) * 4)), 0),
+             (chv(g4(dataclasses.replace(moving_pulse(), bc=(I.NOSLIP,) * 4))), 0)]
     say('characteristic batch', [(p.name, p.gauss_points, st, p.recon_vars) for p, st in kinds])
     b = Batch(1 * GiB, max_slots=8)
     slots = [b.admit_storage(p, st, max_steps=6) for p, st in kinds]
