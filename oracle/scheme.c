@@ -47,9 +47,10 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   if ((cfg->bc[0] == ORC_PERIODIC) != (cfg->bc[1] == ORC_PERIODIC)) return ORC_EINVAL;
   if (cfg->dim == 2 && (cfg->bc[2] == ORC_PERIODIC) != (cfg->bc[3] == ORC_PERIODIC)) return ORC_EINVAL;
   if (!(cfg->mu >= 0.0) || !isfinite(cfg->mu)) return ORC_EINVAL;
-  if (cfg->side_slopes != 0 && !(cfg->side_slopes == 1 && cfg->dim == 1)) return ORC_EINVAL;
-  if (cfg->char_vars != 0 && (cfg->char_vars != 1 || cfg->side_slopes)) return ORC_EINVAL;
   const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
+  /* the side-slope variant: 1D, or 2D with two Gauss points */
+  if (cfg->side_slopes != 0 && !(cfg->side_slopes == 1 && (cfg->dim == 1 || gp == 2))) return ORC_EINVAL;
+  if (cfg->char_vars != 0 && (cfg->char_vars != 1 || cfg->side_slopes)) return ORC_EINVAL;
   if (gp != 2 && !(gp == 4 && cfg->dim == 2)) return ORC_EINVAL;
   /* the 7-segment stencil reaches 3 cells across a side: a wall mirrors 3 cells */
   if (gp == 4)
@@ -311,7 +312,7 @@ typedef struct { long w0, weno; } guards_t;
  * of the three nearest segments as with two points. */
 static void face_eval(orc_ctx *c, double lines[7][5][4], double tg[7][2][4], const double *ref,
                       const double *Wleft, const double *Wright, double dt, int final, int rot, double ht,
-                      double (*sslope)[4], double *out, guards_t *gd) {
+                      double (*ss)[2][4], double *out, guards_t *gd) {
   const int dim = c->cfg.dim, nc = c->nc;
   const double gam = c->cfg.gamma;
   const int npts = c->npts, nl = c->nl;
@@ -383,10 +384,27 @@ static void face_eval(orc_ctx *c, double lines[7][5][4], double tg[7][2][4], con
       }
       W0[k] = ref[k] + W0d[k];
     }
-    /* side slopes of the evaluated variant (1D): the WENO-weighted ones; a
-     * side that falls back to the cell average takes the linear slope */
+    /* side slopes of the evaluated variant: the WENO-weighted slopes of each
+     * line (ss[l][side][k]), in 2D taken to the point like the normal
+     * derivative Wn (the quintic of the three nearest segments with the
+     * same tangential-derivative data); a side that falls back to the cell
+     * average takes the linear slope */
     double Wln[4], Wrn[4];
-    if (sslope) for (int k = 0; k < nc; ++k) { Wln[k] = sslope[0][k]; Wrn[k] = sslope[1][k]; }
+    if (ss) {
+      for (int k = 0; k < nc; ++k) {
+        if (dim == 2) {
+          double sl[3], sr[3], dn[3], r3[3];
+          for (int l = 0; l < 3; ++l) { sl[l] = ss[l][0][k]; sr[l] = ss[l][1][k]; dn[l] = ht * tg[l][1][k]; }
+          orc_hermite3(sl, dn, eta[g], r3);
+          Wln[k] = r3[0];
+          orc_hermite3(sr, dn, eta[g], r3);
+          Wrn[k] = r3[0];
+        } else {
+          Wln[k] = ss[0][0][k];
+          Wrn[k] = ss[0][1][k];
+        }
+      }
+    }
     /* inadmissible nonlinear states fall back to the adjacent cell average */
     if (!orc_admissible(dim, gam, Wl)) {
       for (int k = 0; k < nc; ++k) { Wl[k] = Wleft[k]; Wln[k] = Wn[k]; }
@@ -398,12 +416,12 @@ static void face_eval(orc_ctx *c, double lines[7][5][4], double tg[7][2][4], con
     }
     if (rot) {
       swap12(W0); swap12(Wn); swap12(Wt_); swap12(Wnn); swap12(Wnt); swap12(Wtt_);
-      swap12(Wl); swap12(Wr);
+      swap12(Wl); swap12(Wr); swap12(Wln); swap12(Wrn);
     }
     double F[4], Ft[4], Wt[4], Wtt[4], Nh[4], Nf[4], tau, W0u[4];
     const int fired = orc_gks_point_g(dim, gam, c->cfg.tau_eps, c->cfg.tau_C, c->cfg.mu, dt, W0, Wn, Wt_, Wnn,
                                       Wnt, Wtt_, Wl, Wr, F, Ft, Wt, Wtt, Nh, Nf, &tau, W0u,
-                                      sslope ? Wln : 0, sslope ? Wrn : 0);
+                                      ss ? Wln : 0, ss ? Wrn : 0);
     if (rot) { swap12(F); swap12(Ft); swap12(Wt); swap12(Wtt); swap12(Nh); swap12(Nf); swap12(W0u); }
     if (fired) { gd->w0++; for (int k = 0; k < nc; ++k) W0d[k] = W0u[k] - ref[k]; }
     const double wg = wgt[g];
@@ -437,7 +455,7 @@ void orc_face_1d(const orc_config *cfg, const double *cells, double dt, int fina
   orc_recon_init();
   const double h = (cfg->x1 - cfg->x0) / cfg->nx;
   double ref[4] = {0, 0, 0, 0}, Wlc[4] = {0, 0, 0, 0}, Wrc[4] = {0, 0, 0, 0};
-  double lines[7][5][4], tg[7][2][4], sslope[2][4] = {{0}};
+  double lines[7][5][4], tg[7][2][4], ss[1][2][4] = {{{0}}};
   memset(tg, 0, sizeof tg);
   double Q[4][4], D[4][4], Wm[4], o5[5][4];
   for (int k = 0; k < 3; ++k) {
@@ -449,11 +467,11 @@ void orc_face_1d(const orc_config *cfg, const double *cells, double dt, int fina
       D[k][m] = h * cells[(3 + k) * 4 + m];
     }
   }
-  line_all(cfg, 3, Q, D, h, Wm, 0, o5, cfg->side_slopes ? sslope : 0);
+  line_all(cfg, 3, Q, D, h, Wm, 0, o5, cfg->side_slopes ? ss[0] : 0);
   for (int q = 0; q < 5; ++q)
     for (int k = 0; k < 3; ++k) lines[0][q][k] = o5[q][k];
   guards_t gd = {0, 0};
-  face_eval(&c, lines, tg, ref, Wlc, Wrc, dt, final, 0, 1.0, cfg->side_slopes ? sslope : 0, out, &gd);
+  face_eval(&c, lines, tg, ref, Wlc, Wrc, dt, final, 0, 1.0, cfg->side_slopes ? ss : 0, out, &gd);
   guards[0] = gd.w0;
   guards[1] = gd.weno;
 }
@@ -467,8 +485,8 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
   for (int j = 0; j < ny; ++j) {
     guards_t gd = {0, 0};
     for (int f = 0; f <= nx; ++f) {
-      double ref[4], Wlc[4], Wrc[4], lines[7][5][4], tg[7][2][4], sslope[2][4];
-      const int side = dim == 1 && c->cfg.side_slopes;
+      double ref[4], Wlc[4], Wrc[4], lines[7][5][4], tg[7][2][4], ss[7][2][4];
+      const int side = c->cfg.side_slopes;
       for (int k = 0; k < nc; ++k) {
         ref[k] = fld(c, (double *)G, k)[gidx(c, f - 1, j)];
         Wlc[k] = ref[k];
@@ -486,7 +504,7 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
           }
           Wm[k] = 0.5 * (Gk[gidx(c, f - 1, jj)] + Gk[gidx(c, f, jj)]);
         }
-        line_all(&c->cfg, nc, Q, D, c->dx, Wm, 0, o5, side ? sslope : 0);
+        line_all(&c->cfg, nc, Q, D, c->dx, Wm, 0, o5, side ? ss[l] : 0);
         for (int k = 0; k < nc; ++k) {
           for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q][k];
           if (dim == 2) {
@@ -499,7 +517,7 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
         }
       }
       double *out = c->xf + ((size_t)j * (nx + 1) + f) * NF_FACE * nc;
-      face_eval(c, lines, tg, ref, Wlc, Wrc, dt, final, 0, c->dy, side ? sslope : 0, out, &gd);
+      face_eval(c, lines, tg, ref, Wlc, Wrc, dt, final, 0, c->dy, side ? ss : 0, out, &gd);
     }
     gw0 += gd.w0; gwe += gd.weno;
   }
@@ -509,7 +527,8 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
     for (int f = 0; f <= ny; ++f) {
       guards_t gd = {0, 0};
       for (int i = 0; i < nx; ++i) {
-        double ref[4], Wlc[4], Wrc[4], lines[7][5][4], tg[7][2][4];
+        double ref[4], Wlc[4], Wrc[4], lines[7][5][4], tg[7][2][4], ss[7][2][4];
+        const int side = c->cfg.side_slopes;
         for (int k = 0; k < nc; ++k) {
           ref[k] = fld(c, (double *)G, k)[gidx(c, i, f - 1)];
           Wlc[k] = ref[k];
@@ -526,7 +545,7 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
             }
             Wm[k] = 0.5 * (Gk[gidx(c, ii, f - 1)] + Gk[gidx(c, ii, f)]);
           }
-          line_all(&c->cfg, nc, Q, D, c->dy, Wm, 1, o5, 0);
+          line_all(&c->cfg, nc, Q, D, c->dy, Wm, 1, o5, side ? ss[l] : 0);
           for (int k = 0; k < nc; ++k) {
             double T[4], o2[2];
             for (int q = 0; q < 5; ++q) lines[l][q][k] = o5[q][k];
@@ -537,7 +556,7 @@ static void stage_faces(orc_ctx *c, const double *G, double dt, int final, guard
           }
         }
         double *out = c->yf + ((size_t)f * nx + i) * NF_FACE * nc;
-        face_eval(c, lines, tg, ref, Wlc, Wrc, dt, final, 1, c->dx, 0, out, &gd);
+        face_eval(c, lines, tg, ref, Wlc, Wrc, dt, final, 1, c->dx, side ? ss : 0, out, &gd);
       }
       gw0 += gd.w0; gwe += gd.weno;
     }
