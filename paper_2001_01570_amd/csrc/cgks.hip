@@ -70,7 +70,7 @@ struct Geom {
   double inflow[4][4];   // conservative inflow state per side
   Gas gas;
   int charv;             // WENO-Z states in characteristic variables
-  int sides;             // 1D: WENO-weighted slopes of the non-equilibrium sides
+  int sides;             // WENO-weighted slopes of the non-equilibrium sides (1D; 2D two points)
 };
 
 struct Params {          // written by the host before a batch of steps
@@ -362,7 +362,7 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 // Tile (bx, by) of the face grid of one direction: DIR 0 tiles (faces, rows),
 // DIR 1 tiles (columns, faces).
 // lds: the kernel's LDS tile, NQ rows of NSEG line segments.
-template <int DIR, int STAGE, class GT = double, class TL = Tile8x16, bool CH = false>
+template <int DIR, int STAGE, class GT = double, class TL = Tile8x16, bool CH = false, bool SS = false>
 __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx, int by,
                                             double (*lds)[TL::NSEG]) {
   constexpr int TF = TL::F, TT = TL::T, TH = TL::H, NSEG = TL::NSEG, HALO = TL::HALO;
@@ -421,6 +421,13 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
       if constexpr (!charv) {
         lds[3 * 4 + k][pos] = weno_left(a, c, d, A, Bq, C, D, G.eps);
         lds[4 * 4 + k][pos] = weno_left(d - c, -c, a - c, -D, -C, -Bq, -A, G.eps) + c;
+      }
+      if constexpr (SS) {   // the side slopes of the evaluated variant (h-scaled)
+        double sl, sr;
+        weno_left_s<true>(a, c, d, A, Bq, C, D, G.eps, &sl);
+        weno_left_s<true>(d - c, -c, a - c, -D, -C, -Bq, -A, G.eps, &sr);
+        lds[NQ + k][pos] = sl;
+        lds[NQ + 4 + k][pos] = -sr;
       }
       lds[20 + k][pos] = ref;
       // the cells' tangential gradient carried across the face by the cubic
@@ -548,8 +555,8 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   const double dsg = mirror ? -1.0 : 1.0;
   if constexpr (M == 2) {
     if (live)
-      face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[0], kHerm2[0], dsg, inv_hn,
-                                      mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad);
+      face_point<DIR, STAGE == 1, NL, SS>(get, right_cell, kTang7[0], kHerm2[0], dsg, inv_hn,
+                                          mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad);
   } else {
     if (live)
       face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[pr], kHerm4[pr], dsg, inv_hn,
@@ -599,12 +606,12 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   for (int q = 0; q < NO; ++q) F[q * plane + idx] = acc[q];
 }
 
-template <int DIR, int STAGE, class GT, class TL, bool CH>
+template <int DIR, int STAGE, class GT, class TL, bool CH, bool SS = false>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom G, Bufs B) {
-  __shared__ double lds[NQ][TL::NSEG];
+  __shared__ double lds[SS ? NQ + 8 : NQ][TL::NSEG];   // SS: 8 rows of side slopes
   int bx, by;
   xcd_tile(bx, by);
-  faces2_body<DIR, STAGE, GT, TL, CH>(G, B, bx, by, lds);
+  faces2_body<DIR, STAGE, GT, TL, CH, SS>(G, B, bx, by, lds);
 }
 
 // ---------------------------------------------------------------- 2D update
@@ -1093,7 +1100,8 @@ static int validate(const cgks_config* c) {
   const int gp = c->gauss_points ? c->gauss_points : 2;
   if (gp != 2 && !(gp == 4 && c->dim == 2)) return CGKS_EINVAL;
   if (c->recon_vars != CGKS_CONSERVATIVE && c->recon_vars != CGKS_CHARACTERISTIC) return CGKS_EINVAL;
-  if (c->side_slopes != 0 && (c->side_slopes != 1 || c->dim != 1 || c->recon_vars != CGKS_CONSERVATIVE))
+  if (c->side_slopes != 0 &&
+      (c->side_slopes != 1 || (c->dim == 2 && gp != 2) || c->recon_vars != CGKS_CONSERVATIVE))
     return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
     if (c->bc[s] < 0 || c->bc[s] > 4) return CGKS_EINVAL;
@@ -1325,28 +1333,33 @@ static void launch_step_on(const Geom& G, const Bufs& B, int gp, int storage, co
     auto faces = [&](auto dir, auto stage, auto gt, int kind) {
       constexpr int DIR = decltype(dir)::value, STAGE = decltype(stage)::value;
       using GT = decltype(gt);
-      auto go = [&](auto tl, auto ch) {
+      auto go = [&](auto tl, auto ch, auto ss) {
         using TL = decltype(tl);
-        constexpr bool CH = decltype(ch)::value;
+        constexpr bool CH = decltype(ch)::value, SS = decltype(ss)::value;
         const dim3 g = DIR == 0 ? dim3((G.nx + 1 + TL::F - 1) / TL::F, (G.ny + TL::T - 1) / TL::T)
                                 : dim3((G.nx + TL::T - 1) / TL::T, (G.ny + 1 + TL::F - 1) / TL::F);
-        run(kind, [&] { k_faces2<DIR, STAGE, GT, TL, CH><<<g, FACE_THREADS, 0, s>>>(G, B); });
+        run(kind, [&] { k_faces2<DIR, STAGE, GT, TL, CH, SS><<<g, FACE_THREADS, 0, s>>>(G, B); });
       };
       using CV = std::false_type;
       using CC = std::true_type;
+      using NS = std::false_type;
       if (gp == 4) {
-        if (G.charv) { if constexpr (DIR == 0) go(Tile4x16G4(), CC()); else go(Tile2x32G4(), CC()); }
-        else { if constexpr (DIR == 0) go(Tile4x16G4(), CV()); else go(Tile2x32G4(), CV()); }
+        if (G.charv) { if constexpr (DIR == 0) go(Tile4x16G4(), CC(), NS()); else go(Tile2x32G4(), CC(), NS()); }
+        else { if constexpr (DIR == 0) go(Tile4x16G4(), CV(), NS()); else go(Tile2x32G4(), CV(), NS()); }
         return;
       }
       if (G.charv) {   // characteristic variables: one tile shape per direction
-        if constexpr (DIR == 0) go(Tile4x32(), CC()); else go(Tile2x64(), CC());
+        if constexpr (DIR == 0) go(Tile4x32(), CC(), NS()); else go(Tile2x64(), CC(), NS());
+        return;
+      }
+      if (G.sides) {   // the side-slope variant: one tile shape per direction
+        if constexpr (DIR == 0) go(Tile4x32(), CV(), std::true_type()); else go(Tile2x64(), CV(), std::true_type());
         return;
       }
       switch (tiles[DIR]) {
-        case 1: go(Tile4x32(), CV()); break;
-        case 2: go(Tile2x64(), CV()); break;
-        default: go(Tile8x16(), CV()); break;
+        case 1: go(Tile4x32(), CV(), NS()); break;
+        case 2: go(Tile2x64(), CV(), NS()); break;
+        default: go(Tile8x16(), CV(), NS()); break;
       }
     };
     using D0 = std::integral_constant<int, 0>;
@@ -1811,7 +1824,7 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   if (!b || !fields || !slot) return CGKS_EINVAL;
   int rc = validate(cfg);
   if (rc) return rc;
-  if (cfg->dim != 2) return CGKS_EINVAL;
+  if (cfg->dim != 2 || cfg->side_slopes) return CGKS_EINVAL;
   if (!(t_end > 0.0) && max_steps <= 0) return CGKS_EINVAL;   // a request needs an end
   int k = 0;
   while (k < b->max_slots && b->info[k].used) ++k;

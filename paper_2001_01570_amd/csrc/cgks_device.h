@@ -1064,9 +1064,12 @@ struct TangEval {
   template <class Get> CGKS_HD __forceinline__ double Wtt(Get get, int k, const double* off) const {
     return herm_value<NL>(get, h.d2, h.d2d, k, 24 + k, off, dsg);
   }
-  template <class Get> CGKS_HD __forceinline__ double Wn(Get get, int k) const {
-    if constexpr (NL == 3) return herm_deriv<3>(get, h.v, h.vd, 4 + k, 28 + k, dsg);
-    else return tang_deriv<NL>(get, w7.v, 4 + k);
+  template <class Get> CGKS_HD __forceinline__ double Wn(Get get, int k) const { return Wn_of(get, 4 + k, k); }
+  // a normal derivative at the point from the line quantity q of component k
+  // (the linear reconstruction's, or a side slope of the evaluated variant)
+  template <class Get> CGKS_HD __forceinline__ double Wn_of(Get get, int q, int k) const {
+    if constexpr (NL == 3) return herm_deriv<3>(get, h.v, h.vd, q, 28 + k, dsg);
+    else return tang_deriv<NL>(get, w7.v, q);
   }
   template <class Get> CGKS_HD __forceinline__ double Wnt(Get get, int k) const {
     return herm_deriv<NL>(get, h.d1, h.d1d, 4 + k, 28 + k, dsg);
@@ -1135,7 +1138,7 @@ CGKS_HD __forceinline__ void face_accumulate(double* acc, const PointOut<NC>& o,
 // DIR 1 (y faces) rotates the momenta so that the normal one comes first.
 // acc receives this point's share wg of the Gauss average (face_accumulate
 // from zero); guard / nbad count the equilibrium and WENO fallbacks.
-template <int DIR, bool FULL, int NL, class Get, class Right>
+template <int DIR, bool FULL, int NL, bool SS = false, class Get, class Right>
 CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<7>& w7, const HermWT& h, double dsg,
                                         double inv_hn, double inv_ht, const Gas& gas, double dt, double* acc,
                                         int& guard, int& nbad, double wg = 0.5) {
@@ -1161,15 +1164,18 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<7>& w
     CGKS_BREAK();
   }
   nbad = 0;
+  bool bad_l = false, bad_r = false;
   if (!admissible<4>(Wl, gas.gamma)) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) Wl[k] = get(20 + k, NL / 2);
     ++nbad;
+    bad_l = true;
   }
   if (!admissible<4>(Wr, gas.gamma)) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) Wr[k] = right(k);
     ++nbad;
+    bad_r = true;
   }
   rot(Wl);
   rot(Wr);
@@ -1203,14 +1209,35 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<7>& w
   rot(Wn);
   rot(Wt);
 
+  // normal slopes of the two non-equilibrium sides: the linear
+  // reconstruction's Wn, or (SS, the evaluated variant) each line's
+  // WENO-weighted side slopes (LDS rows 32-35 left, 36-39 right, h-scaled)
+  // taken to the point like Wn; a side that fell back to its cell average
+  // takes Wn
+  double Wln[4], Wrn[4];
+  if constexpr (SS) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Wln[k] = te.Wn_of(get, 32 + k, k) * inv_hn;
+      Wrn[k] = te.Wn_of(get, 36 + k, k) * inv_hn;
+    }
+    rot(Wln);
+    rot(Wrn);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (bad_l) Wln[k] = Wn[k];
+      if (bad_r) Wrn[k] = Wn[k];
+    }
+  }
+
   // the two non-equilibrium sides (each phase's results are pinned before its
   // barrier so that its arithmetic stays in the phase)
   SideSums<4> sd;
   sd.zero();
-  side_terms<4, FULL>(Wl, +1, Wn, Wt, gas, sd);
+  side_terms<4, FULL>(Wl, +1, SS ? Wln : Wn, Wt, gas, sd);
   sd.pin<FULL>();
   CGKS_BREAK();
-  side_terms<4, FULL>(Wr, -1, Wn, Wt, gas, sd);
+  side_terms<4, FULL>(Wr, -1, SS ? Wrn : Wn, Wt, gas, sd);
   sd.pin<FULL>();
   CGKS_BREAK();
 

@@ -1,10 +1,13 @@
-"""The evaluated side-slope variant (side_slopes = 1, 1D): the two
-non-equilibrium sides take the WENO-weighted slopes of their candidate
-polynomials instead of the linear reconstruction's derivative.  The HIP
-path against the oracle with the same option: single steps (smooth flow,
-the Sec. 4.4 shock tube, a pressure-ratio-300 tube where the guards fire),
-whole runs with each side's own steps, and a pressure-ratio-800 tube that
-only this variant carries to its end time."""
+"""The evaluated side-slope variant (side_slopes = 1; 1D, and 2D with two
+Gauss points): the two non-equilibrium sides take the WENO-weighted slopes
+of their candidate polynomials instead of the linear reconstruction's
+derivative (in 2D each line's slopes taken to the Gauss point like the
+normal derivative).  The HIP path against the oracle with the same option:
+single steps (smooth flow, the Sec. 4.4 shock tube, a pressure-ratio-300
+tube where the guards fire; 2D shock-vortex with walls and inflow, a
+near-vacuum expansion, no-slip walls, FP32 gradient storage), whole runs
+with each side's own steps, runs where the guards fire, and a
+pressure-ratio-800 tube that only this variant carries to its end time."""
 import dataclasses
 import math
 import sys
@@ -101,3 +104,94 @@ def test_strong_tubes_guard_counts_and_states(pr):
     L, R = (1.0, 0.0, pr / 10.0), (0.125, 0.0, 0.1)
     t_end = 0.1 / math.sqrt(pr / 10.0)
     _guard_case(side(I.riemann_1d(L, R, 100, t_end=t_end)), t_end=t_end, min_w0=0, min_weno=0)
+
+
+def moving_pulse():
+    p = I.acoustic_pulse_2d(40, seed=4, amp=0.05, half_width=0.3, ny=24)
+    f = p.fields
+    f[1] += 0.2 * f[0]
+    f[2] += 0.1 * f[0]
+    f[3] += 0.5 * 0.05 * f[0]
+    return p
+
+
+CASES_2D = [
+    ('shock_vortex_walls_inflow', lambda: I.shock_vortex_2d(64, 32, Rc=0.12), 3, 1e-10),
+    ('expansion_near_vacuum', lambda: I.expansion_2d(32, 28, U=1.25, amp=0.1), 2, 1e-10),
+    ('viscous_shock_vortex_noslip', lambda: dataclasses.replace(I.shock_vortex_2d(48, 24, Rc=0.12), mu=1e-3,
+                                                                bc=(I.INFLOW, I.FREE, I.NOSLIP, I.NOSLIP)), 2, 1e-10),
+    ('moving_pulse_noslip', lambda: dataclasses.replace(moving_pulse(), bc=(I.NOSLIP,) * 4), 0, 1e-15),
+]
+
+
+def _step_pair_2d(p, before, storage=0):
+    from paper_2001_01570_amd.cgks import Solver
+    o = O.Oracle(p, threads=8)
+    for _ in range(before):
+        o.step()
+    st, t, _ = o.get_state()
+    if storage:
+        st[4:] = st[4:].astype(np.float32).astype(np.float64)
+        o.set_state(st, t)
+    s = Solver(p, storage=storage)
+    s.set_state(st, t)
+    dt = s.step()
+    o.step(dt)
+    r = Solver(dataclasses.replace(p, side_slopes=0), storage=storage)
+    r.set_state(st, t)
+    r.step(dt)
+    e = field_errors(s.state, o.state)
+    change = (np.abs(s.state - r.state).reshape(12, -1).max(axis=1) / field_scales(o.state)).max()
+    return e, change
+
+
+@pytest.mark.parametrize('name,mk,before,min_change', CASES_2D, ids=[c[0] for c in CASES_2D])
+def test_2d_single_step(name, mk, before, min_change):
+    """2D, two Gauss points: one step from the oracle's state after `before`
+    steps, within 1e-12 of the oracle's step with the same option, and
+    different from the step with the linear side slopes."""
+    p = side(mk())
+    say('2d side slopes single step', name, p.nx, p.ny)
+    e, change = _step_pair_2d(p, before)
+    say(name, 'errors', e.max(), 'change against the linear side slopes', change)
+    assert e.max() < TOL, e
+    assert change > min_change
+
+
+def test_2d_fp32_storage_single_step():
+    """FP32 gradient storage: the averages within 1e-8 of their field scale,
+    the gradients within their FP32 rounding (as for the other options)."""
+    from paper_2001_01570_amd.cgks import CGKS_FP32_STORAGE
+    e, change = _step_pair_2d(side(I.shock_vortex_2d(64, 32, Rc=0.12)), 3, CGKS_FP32_STORAGE)
+    say('2d side slopes, fp32 storage: averages', e[:4].max(), 'gradients', e[4:].max(), 'change', change)
+    assert e[:4].max() < 1e-8, e
+    assert e[4:].max() < 4 * 2.0 ** -24, e
+    assert change > 1e-10
+
+
+def test_2d_forty_steps_each_side_its_own_dt():
+    p = side(I.shock_vortex_2d(64, 32, Rc=0.12))
+    s, o, rel = own_dt_run(p, steps=40)
+    err = scaled_errors(s.state, o.state, p.dx, p.dy)
+    say('2d side slopes, 40 steps: dt rel', rel.max(), 'scaled errors', err)
+    assert rel.max() < 1e-13
+    assert err.max() < TOL, err
+
+
+def test_2d_guards_fire_with_the_variant():
+    """The curved expansion to near-vacuum: both fallbacks fire (a side that
+    falls back to its cell average takes the linear slope); guard counts
+    equal the oracle's step by step and over the run."""
+    _guard_case(side(I.expansion_2d(32, 28, U=1.25, amp=0.1)), steps=12, min_w0=1, min_weno=1)
+
+
+def test_2d_variant_refused_by_the_batch_and_with_four_points():
+    from paper_2001_01570_amd.cgks import Batch, CgksError, CGKS_EINVAL, Solver
+    b = Batch(1 << 28, max_slots=2)
+    with pytest.raises(CgksError) as ei:
+        b.admit(side(I.shock_vortex_2d(64, 32, Rc=0.12)), max_steps=1)
+    assert ei.value.code == CGKS_EINVAL
+    b.close()
+    with pytest.raises(CgksError) as ei:
+        Solver(side(dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), gauss_points=4)))
+    assert ei.value.code == CGKS_EINVAL
