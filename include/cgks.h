@@ -95,12 +95,15 @@ typedef struct {
   int side_slopes;           /* normal slopes of the two non-equilibrium sides in the
                                 kinetic evolution (Sec. 2.1).  0 (the default): the
                                 linear reconstruction's derivative at the face for
-                                both sides.  1 (1D only, with conservative
-                                variables; an evaluated variant): each side takes
-                                the derivative of its WENO-Z combination (the
-                                candidates' slopes with the same nonlinear weights);
-                                a side that falls back to its cell average takes the
-                                linear one                                          */
+                                both sides.  1 (an evaluated variant; 1D, or 2D with
+                                two Gauss points; conservative variables; contexts
+                                and cgks_step_noalloc, not the batch): each side
+                                takes the derivative of its WENO-Z combination (the
+                                candidates' slopes with the same nonlinear weights),
+                                in 2D per stencil line, taken to the Gauss point
+                                like the normal derivative; a side that falls back
+                                to its cell average takes the linear one.  Other
+                                values and combinations: CGKS_EINVAL               */
 } cgks_config;
 
 typedef struct {
