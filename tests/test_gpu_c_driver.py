@@ -32,6 +32,7 @@ def write_config(prob, path):
     ('diagonal_4_points', lambda: dataclasses.replace(I.diagonal_wave_2d(24), gauss_points=4), 10),
     ('shock_vortex_characteristic', lambda: dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), recon_vars=1), 12),
     ('shock_tube_side_slopes', lambda: dataclasses.replace(I.shock_tube_1d(100), side_slopes=1), 30),
+    ('shock_vortex_side_slopes', lambda: dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), side_slopes=1), 12),
 ])
 def test_c_driver_equals_the_binding(tmp_path, name, mk, steps):
     from paper_2001_01570_amd.cgks import Solver
