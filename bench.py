@@ -338,6 +338,9 @@ def main():
     ap.add_argument('--recon-vars', choices=('conservative', 'characteristic'), default='conservative',
                     help='variables of the WENO-Z states (the headline: conservative); the flop count covers '
                          'the conservative kernels only, so the roofline is left out for characteristic')
+    ap.add_argument('--side-slopes', action='store_true',
+                    help='the evaluated variant whose non-equilibrium sides take the WENO-weighted slopes of their '
+                         'candidates (two Gauss points); like characteristic variables, without the roofline')
     ap.add_argument('--fp32-storage', action='store_true',
                     help='instead: the same workload with FP32 storage of the gradients, and its error vs FP64')
     args = ap.parse_args()
@@ -375,6 +378,12 @@ def main():
     if charv:
         prob = dataclasses.replace(prob, recon_vars=1)
         workload += ', WENO-Z states in characteristic variables'
+    if args.side_slopes:
+        prob = dataclasses.replace(prob, side_slopes=1)
+        workload += ', WENO-weighted side slopes'
+    # the flop count covers the scheme as read with conservative variables:
+    # no roofline for the options
+    variant = charv or args.side_slopes
     fields = torch.from_numpy(prob.fields).to('cuda')
     torch.cuda.synchronize()
     s = Solver(prob, load_state=False)
@@ -425,7 +434,7 @@ def main():
     flops = load_flops()
     roof = None
     units_key = 'per_launch_units' if args.gauss_points == 2 else 'per_launch_units_4pt'
-    if flops is not None and name in flops.get(units_key, {}) and not charv:
+    if flops is not None and name in flops.get(units_key, {}) and not variant:
         unit = flops[units_key][name]
         nunits = launch_units(name, prob.nx, prob.ny)
         alg = unit['flops_per_unit'] * nunits
@@ -438,7 +447,7 @@ def main():
 
     # the whole step: algorithmic flops per cell and step times the rate
     step = None
-    if flops is not None and args.gauss_points == 2 and not charv:
+    if flops is not None and args.gauss_points == 2 and not variant:
         fc = flops['flops_per_cell_step']
         step = {'flops_per_cell_step': fc, 'tflops': fc * value / 1e12,
                 'frac_of_fp64_peak': fc * value / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
