@@ -38,11 +38,10 @@ typedef struct {
                                 3 segments with the tangential gradients) or 4 (sextic through
                                 7 segment averages, three ghost layers) */
   int side_slopes;           /* slopes of the two non-equilibrium sides: 0 the linear
-                                reconstruction's derivatives (the scheme as read); 1 (1D,
-                                or 2D with two Gauss points; an evaluated variant) the
-                                WENO-weighted derivatives of the candidate polynomials of
-                                each side, in 2D taken to the Gauss point like the normal
-                                derivative */
+                                reconstruction's derivatives (the scheme as read); 1 (an
+                                evaluated variant) the WENO-weighted derivatives of the
+                                candidate polynomials of each side, in 2D taken to the
+                                Gauss point like the normal derivative */
   int char_vars;             /* variables of the nonlinear (WENO-Z) reconstruction: 0
                                 conservative, 1 characteristic (Sec. 3.2: the eigenvectors
                                 of the normal flux Jacobian at the mean of the two cells

@@ -119,9 +119,9 @@ class Oracle:
     """The oracle solver for one problem (see paper_2001_01570_amd.inputs.Problem)."""
 
     def __init__(self, prob, threads: int = 0, side_slopes=None):
-        """side_slopes = 1 (1D, or 2D with two Gauss points): the evaluated
-        variant whose non-equilibrium sides take the WENO-weighted slopes of
-        their candidates (default: the problem's own setting)."""
+        """side_slopes = 1: the evaluated variant whose non-equilibrium sides
+        take the WENO-weighted slopes of their candidates (default: the
+        problem's own setting)."""
         cfg = _Cfg()
         d = prob.config_dict()
         cfg.side_slopes = int(d.get('side_slopes', 0) if side_slopes is None else side_slopes)

@@ -48,8 +48,7 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   if (cfg->dim == 2 && (cfg->bc[2] == ORC_PERIODIC) != (cfg->bc[3] == ORC_PERIODIC)) return ORC_EINVAL;
   if (!(cfg->mu >= 0.0) || !isfinite(cfg->mu)) return ORC_EINVAL;
   const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
-  /* the side-slope variant: 1D, or 2D with two Gauss points */
-  if (cfg->side_slopes != 0 && !(cfg->side_slopes == 1 && (cfg->dim == 1 || gp == 2))) return ORC_EINVAL;
+  if (cfg->side_slopes != 0 && cfg->side_slopes != 1) return ORC_EINVAL;
   if (cfg->char_vars != 0 && (cfg->char_vars != 1 || cfg->side_slopes)) return ORC_EINVAL;
   if (gp != 2 && !(gp == 4 && cfg->dim == 2)) return ORC_EINVAL;
   /* the 7-segment stencil reaches 3 cells across a side: a wall mirrors 3 cells */
@@ -386,18 +385,26 @@ static void face_eval(orc_ctx *c, double lines[7][5][4], double tg[7][2][4], con
     }
     /* side slopes of the evaluated variant: the WENO-weighted slopes of each
      * line (ss[l][side][k]), in 2D taken to the point like the normal
-     * derivative Wn (the quintic of the three nearest segments with the
-     * same tangential-derivative data); a side that falls back to the cell
-     * average takes the linear slope */
+     * derivative Wn (two points: the quintic of the three nearest segments
+     * with the same tangential-derivative data; four points: the sextic
+     * through the 7 segments); a side that falls back to the cell average
+     * takes the linear slope */
     double Wln[4], Wrn[4];
     if (ss) {
       for (int k = 0; k < nc; ++k) {
-        if (dim == 2) {
+        if (dim == 2 && nl == 3) {
           double sl[3], sr[3], dn[3], r3[3];
           for (int l = 0; l < 3; ++l) { sl[l] = ss[l][0][k]; sr[l] = ss[l][1][k]; dn[l] = ht * tg[l][1][k]; }
           orc_hermite3(sl, dn, eta[g], r3);
           Wln[k] = r3[0];
           orc_hermite3(sr, dn, eta[g], r3);
+          Wrn[k] = r3[0];
+        } else if (dim == 2) {
+          double sl[7], sr[7], r3[3];
+          for (int l = 0; l < nl; ++l) { sl[l] = ss[l][0][k]; sr[l] = ss[l][1][k]; }
+          orc_sextic(sl, eta[g], r3);
+          Wln[k] = r3[0];
+          orc_sextic(sr, eta[g], r3);
           Wrn[k] = r3[0];
         } else {
           Wln[k] = ss[0][0][k];
