@@ -95,9 +95,9 @@ typedef struct {
   int side_slopes;           /* normal slopes of the two non-equilibrium sides in the
                                 kinetic evolution (Sec. 2.1).  0 (the default): the
                                 linear reconstruction's derivative at the face for
-                                both sides.  1 (an evaluated variant; 1D, or 2D with
-                                two Gauss points; conservative variables; contexts
-                                and cgks_step_noalloc, not the batch): each side
+                                both sides.  1 (an evaluated variant; 1D or 2D, two
+                                or four Gauss points; conservative variables;
+                                contexts and cgks_step_noalloc, not the batch): each side
                                 takes the derivative of its WENO-Z combination (the
                                 candidates' slopes with the same nonlinear weights),
                                 in 2D per stencil line, taken to the Gauss point

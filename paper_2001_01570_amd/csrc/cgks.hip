@@ -70,7 +70,7 @@ struct Geom {
   double inflow[4][4];   // conservative inflow state per side
   Gas gas;
   int charv;             // WENO-Z states in characteristic variables
-  int sides;             // WENO-weighted slopes of the non-equilibrium sides (1D; 2D two points)
+  int sides;             // WENO-weighted slopes of the non-equilibrium sides
 };
 
 struct Params {          // written by the host before a batch of steps
@@ -559,9 +559,9 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
                                           mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad);
   } else {
     if (live)
-      face_point<DIR, STAGE == 1, NL>(get, right_cell, kTang7[pr], kHerm4[pr], dsg, inv_hn,
-                                      mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad,
-                                      pr ? kGauss4Outer : kGauss4Inner);
+      face_point<DIR, STAGE == 1, NL, SS>(get, right_cell, kTang7[pr], kHerm4[pr], dsg, inv_hn,
+                                          mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad,
+                                          pr ? kGauss4Outer : kGauss4Inner);
   }
   if (guard) atomicAdd(&sc->guard_w0, 1ull);
   if (nbad) atomicAdd(&sc->guard_weno, (unsigned long long)nbad);
@@ -1100,9 +1100,7 @@ static int validate(const cgks_config* c) {
   const int gp = c->gauss_points ? c->gauss_points : 2;
   if (gp != 2 && !(gp == 4 && c->dim == 2)) return CGKS_EINVAL;
   if (c->recon_vars != CGKS_CONSERVATIVE && c->recon_vars != CGKS_CHARACTERISTIC) return CGKS_EINVAL;
-  if (c->side_slopes != 0 &&
-      (c->side_slopes != 1 || (c->dim == 2 && gp != 2) || c->recon_vars != CGKS_CONSERVATIVE))
-    return CGKS_EINVAL;
+  if (c->side_slopes != 0 && (c->side_slopes != 1 || c->recon_vars != CGKS_CONSERVATIVE)) return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
     if (c->bc[s] < 0 || c->bc[s] > 4) return CGKS_EINVAL;
     const int n = s < 2 ? c->nx : c->ny;
@@ -1344,7 +1342,9 @@ static void launch_step_on(const Geom& G, const Bufs& B, int gp, int storage, co
       using CC = std::true_type;
       using NS = std::false_type;
       if (gp == 4) {
+        using SV = std::true_type;
         if (G.charv) { if constexpr (DIR == 0) go(Tile4x16G4(), CC(), NS()); else go(Tile2x32G4(), CC(), NS()); }
+        else if (G.sides) { if constexpr (DIR == 0) go(Tile4x16G4(), CV(), SV()); else go(Tile2x32G4(), CV(), SV()); }
         else { if constexpr (DIR == 0) go(Tile4x16G4(), CV(), NS()); else go(Tile2x32G4(), CV(), NS()); }
         return;
       }

@@ -105,8 +105,8 @@ def test_create_rejects_invalid_configurations_before_touching_the_device():
     assert rc(base, storage=7) == EINVAL
     assert rc(base, recon_vars=2) == EINVAL                       # conservative or characteristic
     assert rc(base, recon_vars=-1) == EINVAL
-    assert rc(base, side_slopes=1) != EINVAL                      # the side-slope variant: 1D, 2D two points
-    assert rc(dataclasses.replace(base, gauss_points=4), side_slopes=1) == EINVAL
+    assert rc(base, side_slopes=1) != EINVAL                      # the side-slope variant: 1D and 2D
+    assert rc(dataclasses.replace(base, gauss_points=4), side_slopes=1) != EINVAL
     assert rc(base, side_slopes=1, recon_vars=1) == EINVAL
     assert rc(I.sine_wave_1d(16), side_slopes=2) == EINVAL
     assert rc(I.sine_wave_1d(16), side_slopes=1, recon_vars=1) == EINVAL

@@ -69,6 +69,7 @@ def test_walls_inflow_viscous_and_four_points():
     _check(dataclasses.replace(I.shock_tube_1d(100), recon_vars=1))
     # the side-slope variant (2D: kernel instances of their own; 1D)
     _check(dataclasses.replace(I.shock_vortex_2d(64, 32), side_slopes=1))
+    _check(dataclasses.replace(I.shock_vortex_2d(48, 24), side_slopes=1, gauss_points=4))
     _check(dataclasses.replace(I.shock_tube_1d(100), side_slopes=1))
 
 
