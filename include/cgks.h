@@ -97,7 +97,7 @@ typedef struct {
                                 linear reconstruction's derivative at the face for
                                 both sides.  1 (an evaluated variant; 1D or 2D, two
                                 or four Gauss points; conservative variables;
-                                contexts and cgks_step_noalloc, not the batch): each side
+                                contexts, the batch and cgks_step_noalloc): each side
                                 takes the derivative of its WENO-Z combination (the
                                 candidates' slopes with the same nonlinear weights),
                                 in 2D per stencil line, taken to the Gauss point
@@ -227,7 +227,8 @@ int cgks_batch_create(size_t hbm_budget_bytes, int max_slots, void *hip_stream, 
  * max_steps (> 0) steps, whichever comes first (one of them must be given).
  * Any configuration a 2D context accepts is admitted: two or four Gauss
  * points, FP64 or FP32 gradient storage, conservative or characteristic
- * variables; slots of each such kind share their own face launches, so a mix
+ * variables, the side-slope variant; slots of each such kind share their own
+ * face launches, so a mix
  * of kinds runs in one step.  Returns its slot.
  * CGKS_EBUSY: no free slot or no room in the arena; CGKS_ENONPHYS:
  * non-physical initial state; CGKS_EINVAL: bad configuration or dim != 2.  A

@@ -932,10 +932,11 @@ struct SlotDev {
 // Slot kinds: the face kernels differ by Gauss points (bit 0: four),
 // gradient storage (bit 1: FP32) and the variables of the WENO-Z states
 // (bit 2: characteristic).
-enum { BK_G2 = 0, BK_G4 = 1, BK_G2_F32 = 2, BK_G4_F32 = 3, BK_CHAR = 4, BK_KINDS = 8 };
+enum { BK_G2 = 0, BK_G4 = 1, BK_G2_F32 = 2, BK_G4_F32 = 3, BK_CHAR = 4, BK_SIDE = 8, BK_KINDS = 16 };
 constexpr bool kind_g4(int kind) { return kind & 1; }
 constexpr bool kind_f32(int kind) { return kind & 2; }
 constexpr bool kind_char(int kind) { return kind & BK_CHAR; }
+constexpr bool kind_side(int kind) { return kind & BK_SIDE; }   // the side-slope variant
 
 // Running slots of one kind: work item i of a face direction belongs to the
 // k-th of them when pre[dir][k] <= i < pre[dir][k + 1] (face tiles).
@@ -989,11 +990,11 @@ __global__ void kb_end(const SlotDev* slots, const BatchTable* tab) {
 }
 
 // Face tiles of the slots of one kind (tile shape TL, gradient storage GT,
-// characteristic variables CH).
-template <int DIR, int STAGE, class GT, class TL, bool CH>
+// characteristic variables CH, side-slope variant SS).
+template <int DIR, int STAGE, class GT, class TL, bool CH, bool SS = false>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces(const SlotDev* slots,
                                                                             const BatchTable* tab, int kind) {
-  __shared__ double lds[NQ][TL::NSEG];
+  __shared__ double lds[SS ? NQ + 8 : NQ][TL::NSEG];
   const FaceList& L = tab->face[kind];
   const int n = L.n;
   const int* pre = L.pre[DIR];
@@ -1003,7 +1004,7 @@ __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces(cons
   const SlotDev& sd = slots[L.slot[k]];
   const int local = item - pre[k];
   const int w = sd.gw[DIR];
-  faces2_body<DIR, STAGE, GT, TL, CH>(sd.G, sd.B, local % w, local / w, lds);
+  faces2_body<DIR, STAGE, GT, TL, CH, SS>(sd.G, sd.B, local % w, local / w, lds);
 }
 
 template <int STAGE, class GT>
@@ -1824,7 +1825,7 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   if (!b || !fields || !slot) return CGKS_EINVAL;
   int rc = validate(cfg);
   if (rc) return rc;
-  if (cfg->dim != 2 || cfg->side_slopes) return CGKS_EINVAL;
+  if (cfg->dim != 2) return CGKS_EINVAL;
   if (!(t_end > 0.0) && max_steps <= 0) return CGKS_EINVAL;   // a request needs an end
   int k = 0;
   while (k < b->max_slots && b->info[k].used) ++k;
@@ -1835,7 +1836,7 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
   const int f32 = cfg->storage == CGKS_FP32_STORAGE;
   const int kind = (gp == 4 ? BK_G4 : BK_G2) | (f32 ? BK_G2_F32 : 0) |
-                   (cfg->recon_vars == CGKS_CHARACTERISTIC ? BK_CHAR : 0);
+                   (cfg->recon_vars == CGKS_CHARACTERISTIC ? BK_CHAR : 0) | (cfg->side_slopes ? BK_SIDE : 0);
   make_geom(*cfg, sd.G);
   const Geom& G = sd.G;
   const size_t N = (size_t)G.nx * G.ny;
@@ -1976,29 +1977,34 @@ static void launch_batch_step(cgks_batch* b) {
     for (int q = 0; q < BK_KINDS; ++q) {
       const int g = b->cap_f[q][DIR];
       if (!g) continue;
-      auto go = [&](auto gt, auto tl, auto ch) {
-        kb_faces<DIR, STAGE, decltype(gt), decltype(tl), decltype(ch)::value><<<g, FACE_THREADS, 0, s>>>(sl, t, q);
+      using F = std::false_type;
+      using T = std::true_type;
+      auto go = [&](auto gt, auto tl, auto ch, auto ss) {
+        kb_faces<DIR, STAGE, decltype(gt), decltype(tl), decltype(ch)::value, decltype(ss)::value>
+            <<<g, FACE_THREADS, 0, s>>>(sl, t, q);
       };
       // the tile shapes of kind_tile
-      auto go_ch = [&](auto ch) {
+      auto go_ch = [&](auto ch, auto ss) {
         if (kind_g4(q)) {
-          if (!kind_f32(q)) { if constexpr (DIR == 0) go(0.0, Tile4x16G4(), ch); else go(0.0, Tile2x32G4(), ch); }
-          else { if constexpr (DIR == 0) go(0.0f, Tile4x16G4(), ch); else go(0.0f, Tile2x32G4(), ch); }
+          if (!kind_f32(q)) { if constexpr (DIR == 0) go(0.0, Tile4x16G4(), ch, ss); else go(0.0, Tile2x32G4(), ch, ss); }
+          else { if constexpr (DIR == 0) go(0.0f, Tile4x16G4(), ch, ss); else go(0.0f, Tile2x32G4(), ch, ss); }
         } else if (kind_f32(q)) {
-          if constexpr (DIR == 0) go(0.0f, Tile4x32(), ch); else go(0.0f, Tile2x64(), ch);
+          if constexpr (DIR == 0) go(0.0f, Tile4x32(), ch, ss); else go(0.0f, Tile2x64(), ch, ss);
         } else {
-          if constexpr (DIR == 0) go(0.0, Tile4x32(), ch); else go(0.0, Tile2x64(), ch);
+          if constexpr (DIR == 0) go(0.0, Tile4x32(), ch, ss); else go(0.0, Tile2x64(), ch, ss);
         }
       };
       if (kind_char(q)) {
-        go_ch(std::true_type());
+        go_ch(T(), F());
+      } else if (kind_side(q)) {
+        go_ch(F(), T());
       } else if (q != BK_G2) {
-        go_ch(std::false_type());
+        go_ch(F(), F());
       } else {
         switch (b->tile[DIR]) {
-          case 1: go(0.0, Tile4x32(), std::false_type()); break;
-          case 2: go(0.0, Tile2x64(), std::false_type()); break;
-          default: go(0.0, Tile8x16(), std::false_type()); break;
+          case 1: go(0.0, Tile4x32(), F(), F()); break;
+          case 2: go(0.0, Tile2x64(), F(), F()); break;
+          default: go(0.0, Tile8x16(), F(), F()); break;
         }
       }
     }

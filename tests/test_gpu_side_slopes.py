@@ -190,10 +190,40 @@ def test_2d_guards_fire_with_the_variant():
     _guard_case(side(I.expansion_2d(32, 28, U=1.25, amp=0.1, gauss_points=4)), steps=8, min_w0=1, min_weno=1)
 
 
-def test_2d_variant_refused_by_the_batch():
-    from paper_2001_01570_amd.cgks import Batch, CgksError, CGKS_EINVAL
+def test_batch_side_slope_kinds_equal_separate_contexts():
+    """Side-slope slots of every Gauss-point count and storage next to
+    conservative and characteristic ones in one batch: bitwise equal to
+    separate contexts on every replay, and a side-slope slot within 1e-12 of
+    the oracle."""
+    from paper_2001_01570_amd.cgks import Batch, CGKS_FP32_STORAGE, Solver
+    g4 = lambda p: dataclasses.replace(p, gauss_points=4)
+    kinds = [(side(I.shock_vortex_2d(64, 32, Rc=0.12)), 0),
+             (side(g4(I.shock_vortex_2d(40, 24, Rc=0.12))), 0),
+             (side(I.expansion_2d(32, 28, U=1.0, amp=0.1)), CGKS_FP32_STORAGE),
+             (side(g4(dataclasses.replace(moving_pulse(), bc=(I.NOSLIP,) * 4))), CGKS_FP32_STORAGE),
+             (I.shock_vortex_2d(64, 32, Rc=0.12), 0),
+             (dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), recon_vars=1), 0)]
+    b = Batch(1 << 30, max_slots=8)
+    slots = [b.admit_storage(p, st, max_steps=6) for p, st in kinds]
+    refs = [Solver(p, storage=st) for p, st in kinds]
+    for rnd in range(2):
+        b.run(3)
+        for r in refs:
+            r.run_steps(3)
+        for (p, st), s, r in zip(kinds, slots, refs):
+            g = b.read(s)
+            e, te, ne = r.get_state()
+            assert b.poll(s)[2] == ne == 3 * (rnd + 1)
+            assert np.array_equal(g, e), (p.name, p.gauss_points, st, rnd, np.abs(g - e).max())
+    assert np.abs(b.read(slots[0]) - b.read(slots[4])).max() > 1e-8
+    b.close()
+    p = kinds[0][0]
+    o = O.Oracle(p, threads=8)
     b = Batch(1 << 28, max_slots=2)
-    with pytest.raises(CgksError) as ei:
-        b.admit(side(I.shock_vortex_2d(64, 32, Rc=0.12)), max_steps=1)
-    assert ei.value.code == CGKS_EINVAL
+    s = b.admit(p, max_steps=1)
+    b.run(1)
+    o.step(b.poll(s)[1])
+    e = field_errors(b.read(s), o.state)
+    say('side-slope batch slot vs oracle', e.max())
+    assert e.max() < TOL
     b.close()
