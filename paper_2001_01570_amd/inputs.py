@@ -56,7 +56,7 @@ class Problem:
     mu: float = 0.0               # dynamic viscosity (0: Euler equations)
     gauss_points: int = 2         # 2D: Gauss points per face segment (2: quartic on 5 segments, 4: sextic on 7)
     recon_vars: int = 0           # variables of the WENO-Z states: 0 conservative, 1 characteristic
-    side_slopes: int = 0          # 1D: 1 = WENO-weighted slopes of the non-equilibrium sides (evaluated variant)
+    side_slopes: int = 0          # 1 = WENO-weighted slopes of the non-equilibrium sides (evaluated variant)
     exact: Optional[Callable[[float], np.ndarray]] = None   # t -> exact fields (cell averages)
     meta: dict = dataclasses.field(default_factory=dict)
 

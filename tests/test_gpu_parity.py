@@ -210,7 +210,7 @@ def test_2d_multi_step_four_points(name, mk):
     assert err.max() < TOL, err
 
 
-def _tiny(nx, ny, kind, gp):
+def _tiny(nx, ny, kind, gp, **options):
     p = I.acoustic_pulse_2d(max(nx, ny), seed=3, amp=0.05, half_width=0.3, ny=max(nx, ny))
     f = np.ascontiguousarray(p.fields[:, :ny, :nx])
     f[1] += 0.2 * f[0]
@@ -218,11 +218,24 @@ def _tiny(nx, ny, kind, gp):
     bc = {'periodic': (I.PERIODIC,) * 4, 'walls': (I.WALL, I.WALL, I.PERIODIC, I.PERIODIC),
           'noslip': (I.NOSLIP,) * 4, 'inflow': (I.INFLOW, I.FREE, I.WALL, I.FREE)}[kind]
     q = I.Problem('tiny', 2, nx, ny, 0.0, nx * p.dx, 0.0, ny * p.dy, f, bc=bc,
-                  inflow_prim=((1.0, 0.3, 0.0, 0.7),) * 4, mu=0.01 if kind == 'noslip' else 0.0, gauss_points=gp)
-    say('tiny', nx, ny, kind, 'gauss points', gp)
+                  inflow_prim=((1.0, 0.3, 0.0, 0.7),) * 4, mu=0.01 if kind == 'noslip' else 0.0, gauss_points=gp,
+                  **options)
+    say('tiny', nx, ny, kind, 'gauss points', gp, options)
     e, dt, dtg = single_step(q)
     assert dtg == pytest.approx(dt, rel=1e-13)
     assert e.max() < TOL, e
+
+
+OPTIONS = [('characteristic', dict(recon_vars=1)), ('side_slopes', dict(side_slopes=1))]
+TINY_ALL = [t + (2,) for t in TINY] + [t + (4,) for t in TINY4]
+
+
+@pytest.mark.parametrize('option,kw', OPTIONS, ids=[o[0] for o in OPTIONS])
+@pytest.mark.parametrize('nx,ny,kind,gp', TINY_ALL, ids=['g%d_%dx%d-%s' % (t[3], t[0], t[1], t[2]) for t in TINY_ALL])
+def test_2d_degenerate_tiny_grids_with_options(nx, ny, kind, gp, option, kw):
+    """The tiny grids with characteristic variables and with the side-slope
+    variant (their kernel instances of their own), two and four points."""
+    _tiny(nx, ny, kind, gp, **kw)
 
 
 @pytest.mark.parametrize('name,mk', CASES_2D[:3] + VISCOUS, ids=[c[0] for c in CASES_2D[:3] + VISCOUS])
