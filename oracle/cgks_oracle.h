@@ -46,6 +46,12 @@ typedef struct {
                                 conservative, 1 characteristic (Sec. 3.2: the eigenvectors
                                 of the normal flux Jacobian at the mean of the two cells
                                 beside the face, per stencil line) */
+  int tang_weno;             /* tangential assembly of the WENO-Z states (2D, two Gauss
+                                points, conservative variables, linear side slopes; an
+                                evaluated variant): 0 as the linear quantities (the quintic
+                                of the three nearest segments); 1 a WENO-Z of the three
+                                average-interpolating quadratics on the five nearest
+                                segments (orc_tang_weno) */
 } orc_config;
 
 typedef struct orc_ctx orc_ctx;
@@ -143,6 +149,12 @@ void orc_flux_integral(int dim, double gamma, double tau, double tau_ce, double 
 void orc_sextic(const double *s, double eta, double *out3);
 /* The quadratic through 3 unit-cell averages s[0..2] (offsets -1..1), at eta. */
 void orc_quadratic3(const double *s, double eta, double *out3);
+/* Point value at the first Gauss node eta = -1/(2 sqrt 3) (unit segment
+ * width) from the averages s[0..4] of the segments -2..2: WENO-Z of the
+ * three average-interpolating quadratics on segments (-2..0), (-1..1),
+ * (0..2); the second node is reached by reversing s.  Test infrastructure:
+ * the tangential-WENO variant of the 2D assembly. */
+double orc_tang_weno(const double *s, double eps, double *cand, double *beta, double *weights);
 /* The quintic fixed by 3 unit-cell averages s[0..2] (offsets -1..1) and by the
  * averages of its derivative over the same cells, d[0..2] (for a unit cell the
  * average of the derivative is the difference of the end values), at eta:

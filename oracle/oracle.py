@@ -36,7 +36,7 @@ class _Cfg(C.Structure):
                 ('bc', C.c_int * 4), ('inflow_prim', (C.c_double * 4) * 4),
                 ('weno_eps', C.c_double), ('tau_eps', C.c_double), ('tau_C', C.c_double),
                 ('fixed_dt', C.c_double), ('mu', C.c_double), ('gauss_points', C.c_int),
-                ('side_slopes', C.c_int), ('char_vars', C.c_int)]
+                ('side_slopes', C.c_int), ('char_vars', C.c_int), ('tang_weno', C.c_int)]
 
 
 class _Counters(C.Structure):
@@ -94,6 +94,8 @@ def lib():
         L.orc_char_basis.restype = C.c_int
         L.orc_weno_char.argtypes = [C.c_int, C.c_double, C.c_double, D, D, D, D, D]
         L.orc_weno_char.restype = C.c_int
+        L.orc_tang_weno.argtypes = [D, C.c_double, D, D, D]
+        L.orc_tang_weno.restype = C.c_double
         _lib = L
     return _lib
 
@@ -131,6 +133,7 @@ class Oracle:
             setattr(cfg, k, float(d[k]))
         cfg.gauss_points = int(d.get('gauss_points', 2))
         cfg.char_vars = int(d.get('recon_vars', 0))
+        cfg.tang_weno = int(d.get('tang_weno', 0))
         for s in range(4):
             cfg.bc[s] = int(d['bc'][s])
             for q in range(4):
@@ -304,6 +307,15 @@ def char_basis(dim, gamma, W):
     if lib().orc_char_basis(int(dim), float(gamma), _p(_vec(W, nc)), _p(L_), _p(R_)) != 0:
         return None
     return L_.reshape(nc, nc), R_.reshape(nc, nc)
+
+
+def tang_weno(s, eps=1e-6, details=False):
+    """Point value at the first Gauss node -1/(2 sqrt 3) from the averages of
+    the segments -2..2 (the tangential-WENO variant); with details also the
+    three candidate values, indicators and normalised weights."""
+    cand, beta, w = np.empty(3), np.empty(3), np.empty(3)
+    v = lib().orc_tang_weno(_p(_vec(s, 5)), float(eps), _p(cand), _p(beta), _p(w))
+    return (v, cand, beta, w) if details else v
 
 
 def weno_char(dim, gamma, Wm, Q, D_, eps=1e-6):

@@ -267,3 +267,45 @@ void orc_cubic_face(const double *a, double *out2) {
   poly_eval(4, CUBIC_INV, a, 0.5, o);
   out2[0] = o[0]; out2[1] = o[1];
 }
+
+/* Tangential WENO-Z of the WENO-Z states (the evaluated variant tang_weno):
+ * each of the three quadratics has the segment averages A, B, C on the unit
+ * segments centred at c - 1, c, c + 1 (c = -1, 0, 1):
+ *   p(y) = B - (A - 2B + C)/24 + (C - A)/2 (y - c) + (A - 2B + C)/2 (y - c)^2,
+ * its smoothness on the centre segment is the Jiang-Shu indicator of the
+ * three averages, and the nonlinear weights have the form of the normal
+ * reconstruction's WENO-Z (eq. WENO-Z-w) with tau = |beta_0 - beta_2|.  The
+ * linear weights are the ones for which the combination equals the quartic
+ * through the five averages at eta = -1/(2 sqrt 3): solving the five
+ * coefficient equations gives 7/36 + sqrt(3)/1080, 11/18 and
+ * 7/36 - sqrt(3)/1080 (all positive). */
+double orc_tang_weno(const double *s, double eps, double *cand, double *beta, double *weights) {
+  const double eta = -0.5 / sqrt(3.0);
+  const double d[3] = {7.0 / 36.0 + sqrt(3.0) / 1080.0, 11.0 / 18.0, 7.0 / 36.0 - sqrt(3.0) / 1080.0};
+  double q[3], b[3], w[3];
+  for (int k = 0; k < 3; ++k) {
+    const double A = s[k], B = s[k + 1], C = s[k + 2], y = eta - (k - 1.0);
+    const double curv = A - 2.0 * B + C;
+    q[k] = B - curv / 24.0 + 0.5 * (C - A) * y + 0.5 * curv * y * y;
+  }
+  {
+    const double a0 = s[0] - 2.0 * s[1] + s[2], c0 = s[0] - 4.0 * s[1] + 3.0 * s[2];
+    const double a1 = s[1] - 2.0 * s[2] + s[3], c1 = s[1] - s[3];
+    const double a2 = s[2] - 2.0 * s[3] + s[4], c2 = 3.0 * s[2] - 4.0 * s[3] + s[4];
+    b[0] = 13.0 / 12.0 * a0 * a0 + 0.25 * c0 * c0;
+    b[1] = 13.0 / 12.0 * a1 * a1 + 0.25 * c1 * c1;
+    b[2] = 13.0 / 12.0 * a2 * a2 + 0.25 * c2 * c2;
+  }
+  const double tau = fabs(b[0] - b[2]);
+  double wsum = 0.0;
+  for (int k = 0; k < 3; ++k) { w[k] = d[k] * (1.0 + tau / (b[k] + eps)); wsum += w[k]; }
+  double v = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    w[k] /= wsum;
+    v += w[k] * q[k];
+    if (cand) cand[k] = q[k];
+    if (beta) beta[k] = b[k];
+    if (weights) weights[k] = w[k];
+  }
+  return v;
+}

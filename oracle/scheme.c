@@ -50,6 +50,8 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
   if (cfg->side_slopes != 0 && cfg->side_slopes != 1) return ORC_EINVAL;
   if (cfg->char_vars != 0 && (cfg->char_vars != 1 || cfg->side_slopes)) return ORC_EINVAL;
+  if (cfg->tang_weno != 0 && (cfg->tang_weno != 1 || cfg->dim != 2 || gp != 2 || cfg->char_vars || cfg->side_slopes))
+    return ORC_EINVAL;
   if (gp != 2 && !(gp == 4 && cfg->dim == 2)) return ORC_EINVAL;
   /* the 7-segment stencil reaches 3 cells across a side: a wall mirrors 3 cells */
   if (gp == 4)
@@ -64,7 +66,7 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   c->nf = cfg->dim == 2 ? 12 : 6;
   c->cfg.gauss_points = gp;
   c->npts = cfg->dim == 2 ? gp : 1;
-  c->nl = gp == 4 ? 7 : 3;
+  c->nl = gp == 4 ? 7 : (cfg->tang_weno ? 5 : 3);   /* tangential WENO: 5 segments */
   c->ng = gp == 4 ? 3 : 2;
   c->gx = c->cfg.nx + 2 * c->ng;
   c->gy = cfg->dim == 2 ? c->cfg.ny + 2 * c->ng : 1;
@@ -333,24 +335,37 @@ static void face_eval(orc_ctx *c, double lines[7][5][4], double tg[7][2][4], con
   for (int g = 0; g < npts; ++g) {
     double W0d[4], W0[4], Wn[4], Wt_[4], Wnn[4], Wnt[4], Wtt_[4], Wl[4], Wr[4];
     for (int k = 0; k < nc; ++k) {
-      if (dim == 2 && nl == 3) {
+      if (dim == 2 && (nl == 3 || nl == 5)) {
+        /* two points: the three nearest segments (with the tangential WENO
+         * variant, nl = 5, the middle three of the five) */
+        const int o = nl == 5;
         double s[3], d[3], dn[3], r3[3];
-        for (int l = 0; l < 3; ++l) { d[l] = ht * tg[l][0][k]; dn[l] = ht * tg[l][1][k]; }
-        for (int l = 0; l < 3; ++l) s[l] = lines[l][0][k];
+        for (int l = 0; l < 3; ++l) { d[l] = ht * tg[l + o][0][k]; dn[l] = ht * tg[l + o][1][k]; }
+        for (int l = 0; l < 3; ++l) s[l] = lines[l + o][0][k];
         orc_hermite3(s, d, eta[g], r3);
         W0d[k] = r3[0]; Wt_[k] = r3[1] / ht; Wtt_[k] = r3[2] / (ht * ht);
-        for (int l = 0; l < 3; ++l) s[l] = lines[l][1][k];
+        for (int l = 0; l < 3; ++l) s[l] = lines[l + o][1][k];
         orc_hermite3(s, dn, eta[g], r3);
         Wn[k] = r3[0]; Wnt[k] = r3[1] / ht;
-        for (int l = 0; l < 3; ++l) s[l] = lines[l][2][k];
+        for (int l = 0; l < 3; ++l) s[l] = lines[l + o][2][k];
         orc_quadratic3(s, eta[g], r3);
         Wnn[k] = r3[0];
-        for (int l = 0; l < 3; ++l) s[l] = lines[l][3][k];
-        orc_hermite3(s, d, eta[g], r3);
-        Wl[k] = ref[k] + r3[0];
-        for (int l = 0; l < 3; ++l) s[l] = lines[l][4][k];
-        orc_hermite3(s, d, eta[g], r3);
-        Wr[k] = ref[k] + r3[0];
+        if (nl == 5) {
+          /* tangential WENO-Z of the five segments' states at the node (the
+           * second node: the segments in reverse order) */
+          double s5[5];
+          for (int l = 0; l < 5; ++l) s5[l] = lines[g == 0 ? l : 4 - l][3][k];
+          Wl[k] = ref[k] + orc_tang_weno(s5, c->cfg.weno_eps, 0, 0, 0);
+          for (int l = 0; l < 5; ++l) s5[l] = lines[g == 0 ? l : 4 - l][4][k];
+          Wr[k] = ref[k] + orc_tang_weno(s5, c->cfg.weno_eps, 0, 0, 0);
+        } else {
+          for (int l = 0; l < 3; ++l) s[l] = lines[l][3][k];
+          orc_hermite3(s, d, eta[g], r3);
+          Wl[k] = ref[k] + r3[0];
+          for (int l = 0; l < 3; ++l) s[l] = lines[l][4][k];
+          orc_hermite3(s, d, eta[g], r3);
+          Wr[k] = ref[k] + r3[0];
+        }
       } else if (dim == 2) {
         double s[7], r3[3], d[3];
         for (int l = 0; l < nl; ++l) s[l] = lines[l][0][k];

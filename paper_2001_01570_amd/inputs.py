@@ -57,6 +57,7 @@ class Problem:
     gauss_points: int = 2         # 2D: Gauss points per face segment (2: quartic on 5 segments, 4: sextic on 7)
     recon_vars: int = 0           # variables of the WENO-Z states: 0 conservative, 1 characteristic
     side_slopes: int = 0          # 1 = WENO-weighted slopes of the non-equilibrium sides (evaluated variant)
+    tang_weno: int = 0            # 1 = tangential WENO-Z of the WENO-Z states (evaluated variant, 2D two points)
     exact: Optional[Callable[[float], np.ndarray]] = None   # t -> exact fields (cell averages)
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -79,7 +80,7 @@ class Problem:
                     inflow_prim=np.asarray(inflow, dtype=np.float64).tolist(),
                     weno_eps=self.weno_eps, tau_eps=self.tau_eps, tau_C=self.tau_C,
                     fixed_dt=self.fixed_dt, mu=self.mu, gauss_points=self.gauss_points,
-                    recon_vars=self.recon_vars, side_slopes=self.side_slopes)
+                    recon_vars=self.recon_vars, side_slopes=self.side_slopes, tang_weno=self.tang_weno)
 
 
 # ---------------------------------------------------------------- helpers
