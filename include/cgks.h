@@ -104,6 +104,15 @@ typedef struct {
                                 like the normal derivative; a side that falls back
                                 to its cell average takes the linear one.  Other
                                 values and combinations: CGKS_EINVAL               */
+  int tang_weno;             /* tangential assembly of the two WENO-Z states in 2D.
+                                0 (the default): the quintic of the three nearest
+                                face segments, as for the linear quantities.  1 (an
+                                evaluated variant; two Gauss points, conservative
+                                variables, side_slopes 0; contexts and
+                                cgks_step_noalloc, not the batch): a WENO-Z of the
+                                three quadratics on the five nearest segments'
+                                averages.  Other values and combinations:
+                                CGKS_EINVAL                                          */
 } cgks_config;
 
 typedef struct {

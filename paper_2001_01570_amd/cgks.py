@@ -27,7 +27,7 @@ class cgks_config(C.Structure):
                 ('bc', C.c_int * 4), ('inflow_prim', (C.c_double * 4) * 4),
                 ('weno_eps', C.c_double), ('tau_eps', C.c_double), ('tau_C', C.c_double),
                 ('fixed_dt', C.c_double), ('storage', C.c_int), ('mu', C.c_double), ('gauss_points', C.c_int),
-                ('recon_vars', C.c_int), ('side_slopes', C.c_int)]
+                ('recon_vars', C.c_int), ('side_slopes', C.c_int), ('tang_weno', C.c_int)]
 
 
 class cgks_counters_t(C.Structure):
@@ -117,6 +117,7 @@ def make_config(prob, storage: int = CGKS_FP64) -> cgks_config:
     cfg.gauss_points = int(d.get('gauss_points', 2))
     cfg.recon_vars = int(d.get('recon_vars', 0))
     cfg.side_slopes = int(d.get('side_slopes', 0))
+    cfg.tang_weno = int(d.get('tang_weno', 0))
     return cfg
 
 

@@ -34,7 +34,8 @@ namespace cgks {
 // reconstructed line segments per face segment) and in the width of the rows
 // they read and write; the shape is chosen per direction at run time (tuned).
 // M Gauss points per segment (one thread each); the tangential stencil has
-// 2 HALO + 1 lines (1: the three nearest segments with two points, 3: the
+// 2 HALO + 1 lines (1: the three nearest segments with two points, 2: five,
+// for the tangential-WENO variant, 3: the
 // sextic through 7 with four).
 template <int F_, int T_, int M_ = 2, int HALO_ = 1>
 struct Tile {
@@ -47,6 +48,9 @@ using Tile8x16 = Tile<8, 16>;
 using Tile4x32 = Tile<4, 32>;
 using Tile2x64 = Tile<2, 64>;
 constexpr int kTileShapes = 3;
+// two points with the 5-segment halo of the tangential-WENO variant
+using Tile4x32W = Tile<4, 32, 2, 2>;
+using Tile2x64W = Tile<2, 64, 2, 2>;
 // four Gauss points per segment with the 7-line stencil (x faces, y faces)
 using Tile4x16G4 = Tile<4, 16, 4, 3>;
 using Tile2x32G4 = Tile<2, 32, 4, 3>;
@@ -71,6 +75,7 @@ struct Geom {
   Gas gas;
   int charv;             // WENO-Z states in characteristic variables
   int sides;             // WENO-weighted slopes of the non-equilibrium sides
+  int tw;                // tangential WENO-Z of the WENO-Z states (two points)
 };
 
 struct Params {          // written by the host before a batch of steps
@@ -553,7 +558,29 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   int guard = 0, nbad = 0;
   const double inv_hn = DIR == 0 ? G.inv_dx : G.inv_dy, inv_ht = DIR == 0 ? G.inv_dy : G.inv_dx;
   const double dsg = mirror ? -1.0 : 1.0;
-  if constexpr (M == 2) {
+  if constexpr (M == 2 && HALO == 2) {
+    // the tangential-WENO variant: the nonlinear states from the 5 segments,
+    // the rest from the middle three as with the 3-segment halo
+    if (live) {
+      double tws[8];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double rj = get(20 + k, 2);
+        double sl[5], sr[5];
+#pragma unroll
+        for (int l = 0; l < 5; ++l) {
+          const double off = get(20 + k, l) - rj;
+          sl[l] = off + get(12 + k, l);
+          sr[l] = off + get(16 + k, l);
+        }
+        tws[k] = rj + tang_weno5(sl, G.eps);
+        tws[4 + k] = rj + tang_weno5(sr, G.eps);
+      }
+      auto get3 = [&](int q, int l) { return get(q, l + 1); };
+      face_point<DIR, STAGE == 1, 3, false, true>(get3, right_cell, kTang7[0], kHerm2[0], dsg, inv_hn,
+                                                  mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad, 0.5, tws);
+    }
+  } else if constexpr (M == 2) {
     if (live)
       face_point<DIR, STAGE == 1, NL, SS>(get, right_cell, kTang7[0], kHerm2[0], dsg, inv_hn,
                                           mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad);
@@ -1102,6 +1129,9 @@ static int validate(const cgks_config* c) {
   if (gp != 2 && !(gp == 4 && c->dim == 2)) return CGKS_EINVAL;
   if (c->recon_vars != CGKS_CONSERVATIVE && c->recon_vars != CGKS_CHARACTERISTIC) return CGKS_EINVAL;
   if (c->side_slopes != 0 && (c->side_slopes != 1 || c->recon_vars != CGKS_CONSERVATIVE)) return CGKS_EINVAL;
+  if (c->tang_weno != 0 && (c->tang_weno != 1 || c->dim != 2 || gp != 2 || c->recon_vars != CGKS_CONSERVATIVE ||
+                            c->side_slopes != 0))
+    return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
     if (c->bc[s] < 0 || c->bc[s] > 4) return CGKS_EINVAL;
     const int n = s < 2 ? c->nx : c->ny;
@@ -1129,6 +1159,7 @@ static void make_geom(const cgks_config& cfg, Geom& G) {
   G.eps = cfg.weno_eps;
   G.charv = cfg.recon_vars == CGKS_CHARACTERISTIC;
   G.sides = cfg.side_slopes == 1;
+  G.tw = cfg.tang_weno == 1;
   G.gas = make_gas(cfg.gamma, cfg.dim, cfg.tau_eps, cfg.tau_C, cfg.mu);
   for (int s = 0; s < 4; ++s) {
     G.bc[s] = s < 2 * cfg.dim ? cfg.bc[s] : CGKS_PERIODIC;
@@ -1351,6 +1382,10 @@ static void launch_step_on(const Geom& G, const Bufs& B, int gp, int storage, co
       }
       if (G.charv) {   // characteristic variables: one tile shape per direction
         if constexpr (DIR == 0) go(Tile4x32(), CC(), NS()); else go(Tile2x64(), CC(), NS());
+        return;
+      }
+      if (G.tw) {      // the tangential-WENO variant: the 5-segment halo
+        if constexpr (DIR == 0) go(Tile4x32W(), CV(), NS()); else go(Tile2x64W(), CV(), NS());
         return;
       }
       if (G.sides) {   // the side-slope variant: one tile shape per direction
@@ -1825,7 +1860,7 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   if (!b || !fields || !slot) return CGKS_EINVAL;
   int rc = validate(cfg);
   if (rc) return rc;
-  if (cfg->dim != 2) return CGKS_EINVAL;
+  if (cfg->dim != 2 || cfg->tang_weno) return CGKS_EINVAL;
   if (!(t_end > 0.0) && max_steps <= 0) return CGKS_EINVAL;   // a request needs an end
   int k = 0;
   while (k < b->max_slots && b->info[k].used) ++k;

@@ -1041,6 +1041,34 @@ CGKS_HD __forceinline__ double herm_deriv(Get get, const double* ws, const doubl
   return s + dsg * d;
 }
 
+// The tangential-WENO variant (two Gauss points): the value at the first node
+// eta = -1/(2 sqrt 3) (unit segment width; the mirrored node reads the
+// segments in reverse order) from the averages s[0..4] of the five nearest
+// segments: the three quadratics with the averages of segments (-2..0),
+// (-1..1), (0..2), evaluated at the node, combined with WENO-Z weights of
+// the normal reconstruction's form (tau = |beta_0 - beta_2|, Jiang-Shu
+// indicators of the three averages) whose linear part gives the quartic
+// through the five averages at the node.
+CGKS_HD __forceinline__ double tang_weno5(const double* s, double eps) {
+  constexpr double r3 = 1.7320508075688772935;   // sqrt(3)
+  // the quadratics at the node: centre segment value plus sqrt(3)/12 times
+  // a difference of the averages
+  const double q0 = s[2] + (r3 / 12.0) * (4.0 * s[1] - s[0] - 3.0 * s[2]);
+  const double q1 = s[2] + (r3 / 12.0) * (s[1] - s[3]);
+  const double q2 = s[2] + (r3 / 12.0) * (3.0 * s[2] - 4.0 * s[3] + s[4]);
+  const double a0 = s[0] - 2.0 * s[1] + s[2], c0 = s[0] - 4.0 * s[1] + 3.0 * s[2];
+  const double a1 = s[1] - 2.0 * s[2] + s[3], c1 = s[1] - s[3];
+  const double a2 = s[2] - 2.0 * s[3] + s[4], c2 = 3.0 * s[2] - 4.0 * s[3] + s[4];
+  const double b0 = (13.0 / 12.0) * a0 * a0 + 0.25 * c0 * c0;
+  const double b1 = (13.0 / 12.0) * a1 * a1 + 0.25 * c1 * c1;
+  const double b2 = (13.0 / 12.0) * a2 * a2 + 0.25 * c2 * c2;
+  const double tau = fabs(b0 - b2);
+  const double w0 = (7.0 / 36.0 + r3 / 1080.0) * (1.0 + tau * recip(b0 + eps));
+  const double w1 = (11.0 / 18.0) * (1.0 + tau * recip(b1 + eps));
+  const double w2 = (7.0 / 36.0 - r3 / 1080.0) * (1.0 + tau * recip(b2 + eps));
+  return (w0 * q0 + w1 * q1 + w2 * q2) * recip(w0 + w1 + w2);
+}
+
 // The point quantities of component k (h: quintic weights at this node; w7:
 // sextic weights, used when NL = 7).  Value-type results are deviations from
 // the middle line's reference.
@@ -1138,10 +1166,12 @@ CGKS_HD __forceinline__ void face_accumulate(double* acc, const PointOut<NC>& o,
 // DIR 1 (y faces) rotates the momenta so that the normal one comes first.
 // acc receives this point's share wg of the Gauss average (face_accumulate
 // from zero); guard / nbad count the equilibrium and WENO fallbacks.
-template <int DIR, bool FULL, int NL, bool SS = false, class Get, class Right>
+// TW (the tangential-WENO variant): the two nonlinear states come in tws
+// (Wl, Wr, unrotated) instead of from the quintic of the three segments.
+template <int DIR, bool FULL, int NL, bool SS = false, bool TW = false, class Get, class Right>
 CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<7>& w7, const HermWT& h, double dsg,
                                         double inv_hn, double inv_ht, const Gas& gas, double dt, double* acc,
-                                        int& guard, int& nbad, double wg = 0.5) {
+                                        int& guard, int& nbad, double wg = 0.5, const double* tws = nullptr) {
   const TangEval<NL> te{w7, h, dsg};
   auto rot = [](double* v) {
     if (DIR == 1) { const double t = v[1]; v[1] = v[2]; v[2] = t; }
@@ -1155,8 +1185,13 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<7>& w
   for (int k = 0; k < 4; ++k) {
     double off[NL];
     const double rj = tang_offsets<NL>(get, k, off);
-    Wl[k] = rj + te.side(get, 12 + k, k, off);
-    Wr[k] = rj + te.side(get, 16 + k, k, off);
+    if constexpr (TW) {
+      Wl[k] = tws[k];
+      Wr[k] = tws[4 + k];
+    } else {
+      Wl[k] = rj + te.side(get, 12 + k, k, off);
+      Wr[k] = rj + te.side(get, 16 + k, k, off);
+    }
     W0[k] = rj + te.W0(get, k, off);
     CGKS_PIN(Wl[k]);
     CGKS_PIN(Wr[k]);

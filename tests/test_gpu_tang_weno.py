@@ -1,0 +1,138 @@
+"""The tangential-WENO variant of the 2D assembly (tang_weno = 1, two Gauss
+points; an evaluated variant): the two WENO-Z states at each Gauss point
+come from a WENO-Z of the three average-interpolating quadratics on the
+five nearest face segments.  The HIP path (face kernels with a 5-segment
+halo) against the oracle with the same option: single steps with walls,
+inflow, no-slip walls, a near vacuum and a ragged grid, FP32 gradient
+storage, tiny grids, 40-step runs with each side's own steps, a run where
+both guards fire, the Mach 2 shock-vortex run whose WENO-state fallbacks
+the variant removes, and the configurations it refuses."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2001_01570_amd import inputs as I
+from tests.parity import field_errors, field_scales, scaled_errors
+from tests.test_gpu_parity import _tiny, TINY
+from tests.test_gpu_parity_runs import _guard_case, own_dt_run
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def tw(p):
+    return dataclasses.replace(p, tang_weno=1)
+
+
+def moving_pulse():
+    p = I.acoustic_pulse_2d(40, seed=4, amp=0.05, half_width=0.3, ny=24)
+    f = p.fields
+    f[1] += 0.2 * f[0]
+    f[2] += 0.1 * f[0]
+    f[3] += 0.5 * 0.05 * f[0]
+    return p
+
+
+CASES = [
+    ('shock_vortex_walls_inflow', lambda: I.shock_vortex_2d(64, 32, Rc=0.12), 3, 1e-10),
+    ('expansion_near_vacuum', lambda: I.expansion_2d(32, 28, U=1.25, amp=0.1), 2, 1e-10),
+    ('viscous_shock_vortex_noslip', lambda: dataclasses.replace(I.shock_vortex_2d(48, 24, Rc=0.12), mu=1e-3,
+                                                                bc=(I.INFLOW, I.FREE, I.NOSLIP, I.NOSLIP)), 2, 1e-10),
+    ('moving_pulse_noslip', lambda: dataclasses.replace(moving_pulse(), bc=(I.NOSLIP,) * 4), 0, 1e-12),
+    ('pulse_ragged', lambda: I.acoustic_pulse_2d(37, seed=4, amp=0.05, half_width=0.3, ny=21), 0, 1e-12),
+]
+
+
+def _step_pair(p, before, storage=0):
+    from paper_2001_01570_amd.cgks import Solver
+    o = O.Oracle(p, threads=8)
+    for _ in range(before):
+        o.step()
+    st, t, _ = o.get_state()
+    if storage:
+        st[4:] = st[4:].astype(np.float32).astype(np.float64)
+        o.set_state(st, t)
+    s = Solver(p, storage=storage)
+    s.set_state(st, t)
+    dt = s.step()
+    o.step(dt)
+    r = Solver(dataclasses.replace(p, tang_weno=0), storage=storage)
+    r.set_state(st, t)
+    r.step(dt)
+    e = field_errors(s.state, o.state)
+    change = (np.abs(s.state - r.state).reshape(12, -1).max(axis=1) / field_scales(o.state)).max()
+    return e, change
+
+
+@pytest.mark.parametrize('name,mk,before,min_change', CASES, ids=[c[0] for c in CASES])
+def test_single_step(name, mk, before, min_change):
+    p = tw(mk())
+    say('tangential WENO single step', name, p.nx, p.ny)
+    e, change = _step_pair(p, before)
+    say(name, 'errors', e.max(), 'change against the quintic states', change)
+    assert e.max() < TOL, e
+    assert change > min_change
+
+
+def test_fp32_storage_single_step():
+    from paper_2001_01570_amd.cgks import CGKS_FP32_STORAGE
+    e, change = _step_pair(tw(I.shock_vortex_2d(64, 32, Rc=0.12)), 3, CGKS_FP32_STORAGE)
+    say('tangential WENO, fp32 storage: averages', e[:4].max(), 'gradients', e[4:].max())
+    assert e[:4].max() < 1e-8, e
+    assert e[4:].max() < 4 * 2.0 ** -24, e
+
+
+@pytest.mark.parametrize('nx,ny,kind', TINY, ids=['%dx%d-%s' % t for t in TINY])
+def test_tiny_grids(nx, ny, kind):
+    """Grids smaller than the five-segment stencil (ghosts wrap onto or
+    mirror the same few cells)."""
+    _tiny(nx, ny, kind, 2, tang_weno=1)
+
+
+def test_forty_steps_each_side_its_own_dt():
+    p = tw(I.shock_vortex_2d(64, 32, Rc=0.12))
+    s, o, rel = own_dt_run(p, steps=40)
+    err = scaled_errors(s.state, o.state, p.dx, p.dy)
+    say('tangential WENO, 40 steps: dt rel', rel.max(), 'scaled errors', err)
+    assert rel.max() < 1e-13
+    assert err.max() < TOL, err
+
+
+def test_guards_fire_with_the_variant():
+    _guard_case(tw(I.expansion_2d(32, 28, U=1.25, amp=0.1)), steps=12, min_w0=1, min_weno=0)
+
+
+def test_mach2_shock_vortex_run_without_weno_fallbacks():
+    """M_s = 2, M_v = 0.5, 64 x 32, CFL 0.3 to t = 0.3 with each side's own
+    steps: equal step and guard counts, no WENO-state fallback (the scheme as
+    read takes 5 in the oracle), states within 1e-12."""
+    p = tw(I.shock_vortex_2d(64, 32, Ms=2.0, Mv=0.5, cfl=0.3))
+    s, o, _ = own_dt_run(p, t_end=0.3)
+    cs, co = s.counters(), o.counters()
+    say('tangential WENO, Mach 2 shock-vortex:', co['steps'], 'steps, guards GPU', cs['guard_w0'], cs['guard_weno'],
+        'oracle', co['guard_w0'], co['guard_weno'])
+    assert cs['steps'] == co['steps'] and cs['guard_weno'] == co['guard_weno'] == 0
+    assert cs['guard_w0'] == co['guard_w0']
+    err = scaled_errors(s.state, o.state, p.dx, p.dy)
+    assert err.max() < TOL, err
+
+
+def test_refused_by_the_batch_and_with_other_options():
+    from paper_2001_01570_amd.cgks import Batch, CgksError, CGKS_EINVAL, Solver
+    b = Batch(1 << 28, max_slots=2)
+    with pytest.raises(CgksError) as ei:
+        b.admit(tw(I.shock_vortex_2d(64, 32, Rc=0.12)), max_steps=1)
+    assert ei.value.code == CGKS_EINVAL
+    b.close()
+    for bad in (dict(gauss_points=4), dict(recon_vars=1), dict(side_slopes=1)):
+        with pytest.raises(CgksError) as ei:
+            Solver(dataclasses.replace(tw(I.shock_vortex_2d(32, 16, Rc=0.12)), **bad))
+        assert ei.value.code == CGKS_EINVAL

@@ -71,6 +71,8 @@ def test_walls_inflow_viscous_and_four_points():
     _check(dataclasses.replace(I.shock_vortex_2d(64, 32), side_slopes=1))
     _check(dataclasses.replace(I.shock_vortex_2d(48, 24), side_slopes=1, gauss_points=4))
     _check(dataclasses.replace(I.shock_tube_1d(100), side_slopes=1))
+    # the tangential-WENO variant (the 5-segment halo)
+    _check(dataclasses.replace(I.shock_vortex_2d(64, 32), tang_weno=1))
 
 
 def test_one_dimensional_and_fixed_step():
