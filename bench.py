@@ -341,6 +341,9 @@ def main():
     ap.add_argument('--side-slopes', action='store_true',
                     help='the evaluated variant whose non-equilibrium sides take the WENO-weighted slopes of their '
                          'candidates (two Gauss points); like characteristic variables, without the roofline')
+    ap.add_argument('--tang-weno', action='store_true',
+                    help='the evaluated variant whose WENO-Z states are assembled along the face by a tangential '
+                         'WENO-Z of five segments (two Gauss points); without the roofline')
     ap.add_argument('--fp32-storage', action='store_true',
                     help='instead: the same workload with FP32 storage of the gradients, and its error vs FP64')
     args = ap.parse_args()
@@ -381,9 +384,12 @@ def main():
     if args.side_slopes:
         prob = dataclasses.replace(prob, side_slopes=1)
         workload += ', WENO-weighted side slopes'
+    if args.tang_weno:
+        prob = dataclasses.replace(prob, tang_weno=1)
+        workload += ', tangential WENO-Z of the WENO-Z states'
     # the flop count covers the scheme as read with conservative variables:
     # no roofline for the options
-    variant = charv or args.side_slopes
+    variant = charv or args.side_slopes or args.tang_weno
     fields = torch.from_numpy(prob.fields).to('cuda')
     torch.cuda.synchronize()
     s = Solver(prob, load_state=False)
