@@ -108,8 +108,8 @@ typedef struct {
                                 0 (the default): the quintic of the three nearest
                                 face segments, as for the linear quantities.  1 (an
                                 evaluated variant; two Gauss points, conservative
-                                variables, side_slopes 0; contexts and
-                                cgks_step_noalloc, not the batch): a WENO-Z of the
+                                variables, side_slopes 0; contexts, the batch and
+                                cgks_step_noalloc): a WENO-Z of the
                                 three quadratics on the five nearest segments'
                                 averages.  Other values and combinations:
                                 CGKS_EINVAL                                          */
@@ -236,7 +236,7 @@ int cgks_batch_create(size_t hbm_budget_bytes, int max_slots, void *hip_stream, 
  * max_steps (> 0) steps, whichever comes first (one of them must be given).
  * Any configuration a 2D context accepts is admitted: two or four Gauss
  * points, FP64 or FP32 gradient storage, conservative or characteristic
- * variables, the side-slope variant; slots of each such kind share their own
+ * variables, the side-slope and tangential-WENO variants; slots of each such kind share their own
  * face launches, so a mix
  * of kinds runs in one step.  Returns its slot.
  * CGKS_EBUSY: no free slot or no room in the arena; CGKS_ENONPHYS:

@@ -959,11 +959,15 @@ struct SlotDev {
 // Slot kinds: the face kernels differ by Gauss points (bit 0: four),
 // gradient storage (bit 1: FP32) and the variables of the WENO-Z states
 // (bit 2: characteristic).
-enum { BK_G2 = 0, BK_G4 = 1, BK_G2_F32 = 2, BK_G4_F32 = 3, BK_CHAR = 4, BK_SIDE = 8, BK_KINDS = 16 };
+// bits 0-1: four points, FP32 storage; bits 2-3 (exclusive options):
+// characteristic variables, the side-slope variant, the tangential-WENO
+// variant (two points only)
+enum { BK_G2 = 0, BK_G4 = 1, BK_G2_F32 = 2, BK_G4_F32 = 3, BK_CHAR = 4, BK_SIDE = 8, BK_TW = 12, BK_KINDS = 16 };
 constexpr bool kind_g4(int kind) { return kind & 1; }
 constexpr bool kind_f32(int kind) { return kind & 2; }
-constexpr bool kind_char(int kind) { return kind & BK_CHAR; }
-constexpr bool kind_side(int kind) { return kind & BK_SIDE; }   // the side-slope variant
+constexpr bool kind_char(int kind) { return (kind & 12) == BK_CHAR; }
+constexpr bool kind_side(int kind) { return (kind & 12) == BK_SIDE; }
+constexpr bool kind_tw(int kind) { return (kind & 12) == BK_TW; }
 
 // Running slots of one kind: work item i of a face direction belongs to the
 // k-th of them when pre[dir][k] <= i < pre[dir][k + 1] (face tiles).
@@ -1860,7 +1864,7 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   if (!b || !fields || !slot) return CGKS_EINVAL;
   int rc = validate(cfg);
   if (rc) return rc;
-  if (cfg->dim != 2 || cfg->tang_weno) return CGKS_EINVAL;
+  if (cfg->dim != 2) return CGKS_EINVAL;
   if (!(t_end > 0.0) && max_steps <= 0) return CGKS_EINVAL;   // a request needs an end
   int k = 0;
   while (k < b->max_slots && b->info[k].used) ++k;
@@ -1871,7 +1875,8 @@ extern "C" int cgks_batch_admit(cgks_batch* b, const cgks_config* cfg, const dou
   const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
   const int f32 = cfg->storage == CGKS_FP32_STORAGE;
   const int kind = (gp == 4 ? BK_G4 : BK_G2) | (f32 ? BK_G2_F32 : 0) |
-                   (cfg->recon_vars == CGKS_CHARACTERISTIC ? BK_CHAR : 0) | (cfg->side_slopes ? BK_SIDE : 0);
+                   (cfg->recon_vars == CGKS_CHARACTERISTIC ? BK_CHAR : 0) | (cfg->side_slopes ? BK_SIDE : 0) |
+                   (cfg->tang_weno ? BK_TW : 0);
   make_geom(*cfg, sd.G);
   const Geom& G = sd.G;
   const size_t N = (size_t)G.nx * G.ny;
@@ -2033,6 +2038,9 @@ static void launch_batch_step(cgks_batch* b) {
         go_ch(T(), F());
       } else if (kind_side(q)) {
         go_ch(F(), T());
+      } else if (kind_tw(q)) {   // two points only: the 5-segment halo tiles
+        if (kind_f32(q)) { if constexpr (DIR == 0) go(0.0f, Tile4x32W(), F(), F()); else go(0.0f, Tile2x64W(), F(), F()); }
+        else { if constexpr (DIR == 0) go(0.0, Tile4x32W(), F(), F()); else go(0.0, Tile2x64W(), F(), F()); }
       } else if (q != BK_G2) {
         go_ch(F(), F());
       } else {

@@ -125,13 +125,44 @@ def test_mach2_shock_vortex_run_without_weno_fallbacks():
     assert err.max() < TOL, err
 
 
-def test_refused_by_the_batch_and_with_other_options():
-    from paper_2001_01570_amd.cgks import Batch, CgksError, CGKS_EINVAL, Solver
-    b = Batch(1 << 28, max_slots=2)
-    with pytest.raises(CgksError) as ei:
-        b.admit(tw(I.shock_vortex_2d(64, 32, Rc=0.12)), max_steps=1)
-    assert ei.value.code == CGKS_EINVAL
+def test_batch_slots_equal_separate_contexts():
+    """Tangential-WENO slots (both storages) beside the other kinds in one
+    batch: bitwise equal to separate contexts on every replay; one slot
+    within 1e-12 of the oracle."""
+    from paper_2001_01570_amd.cgks import Batch, CGKS_FP32_STORAGE, Solver
+    kinds = [(tw(I.shock_vortex_2d(64, 32, Rc=0.12)), 0),
+             (tw(dataclasses.replace(moving_pulse(), bc=(I.NOSLIP,) * 4)), CGKS_FP32_STORAGE),
+             (I.shock_vortex_2d(64, 32, Rc=0.12), 0),
+             (dataclasses.replace(I.shock_vortex_2d(48, 24, Rc=0.12), side_slopes=1), 0),
+             (dataclasses.replace(I.shock_vortex_2d(48, 24, Rc=0.12), recon_vars=1, gauss_points=4), 0)]
+    b = Batch(1 << 30, max_slots=8)
+    slots = [b.admit_storage(p, st, max_steps=6) for p, st in kinds]
+    refs = [Solver(p, storage=st) for p, st in kinds]
+    for rnd in range(2):
+        b.run(3)
+        for r in refs:
+            r.run_steps(3)
+        for (p, st), s, r in zip(kinds, slots, refs):
+            g = b.read(s)
+            e, te, ne = r.get_state()
+            assert b.poll(s)[2] == ne == 3 * (rnd + 1)
+            assert np.array_equal(g, e), (p.name, st, rnd, np.abs(g - e).max())
+    assert np.abs(b.read(slots[0]) - b.read(slots[2])).max() > 1e-8
     b.close()
+    p = kinds[0][0]
+    o = O.Oracle(p, threads=8)
+    b = Batch(1 << 28, max_slots=2)
+    s = b.admit(p, max_steps=1)
+    b.run(1)
+    o.step(b.poll(s)[1])
+    e = field_errors(b.read(s), o.state)
+    say('tangential-WENO batch slot vs oracle', e.max())
+    assert e.max() < TOL
+    b.close()
+
+
+def test_refused_with_other_options():
+    from paper_2001_01570_amd.cgks import CgksError, CGKS_EINVAL, Solver
     for bad in (dict(gauss_points=4), dict(recon_vars=1), dict(side_slopes=1)):
         with pytest.raises(CgksError) as ei:
             Solver(dataclasses.replace(tw(I.shock_vortex_2d(32, 16, Rc=0.12)), **bad))
