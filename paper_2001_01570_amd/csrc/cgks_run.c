@@ -5,7 +5,7 @@
  * CONFIG: one line of numbers, in order
  *   dim nx ny x0 x1 y0 y1 gamma cfl bc0 bc1 bc2 bc3
  *   inflow_prim (16 values, side-major) weno_eps tau_eps tau_C fixed_dt mu
- *   [gauss_points [recon_vars [side_slopes]]]  (optional; 2, CGKS_CONSERVATIVE and 0 when absent)
+ *   [gauss_points [recon_vars [side_slopes [tang_weno]]]]  (optional; 2, CGKS_CONSERVATIVE, 0 and 0 when absent)
  * STATE_IN / STATE_OUT: the fields as raw native doubles in the layout of
  * cgks.h (6*nx values in 1D, 12*ny*nx in 2D).  The state is loaded from host
  * memory, advanced STEPS steps of the configured rule on the null stream and
@@ -40,6 +40,7 @@ int main(int argc, char **argv) {
   if (ok && fscanf(f, "%d", &cfg.gauss_points) != 1) cfg.gauss_points = 2;
   else if (ok && fscanf(f, "%d", &cfg.recon_vars) != 1) cfg.recon_vars = CGKS_CONSERVATIVE;
   else if (ok && fscanf(f, "%d", &cfg.side_slopes) != 1) cfg.side_slopes = 0;
+  else if (ok && fscanf(f, "%d", &cfg.tang_weno) != 1) cfg.tang_weno = 0;
   fclose(f);
   if (!ok) { fprintf(stderr, "cgks_run: malformed configuration %s\n", argv[1]); return 1; }
   cfg.storage = CGKS_FP64;

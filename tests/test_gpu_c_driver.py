@@ -20,7 +20,7 @@ def write_config(prob, path):
     vals = [d['dim'], d['nx'], d['ny'], d['x0'], d['x1'], d['y0'], d['y1'], d['gamma'], d['cfl']] + list(d['bc'])
     vals += [v for side in d['inflow_prim'] for v in side]
     vals += [d['weno_eps'], d['tau_eps'], d['tau_C'], d['fixed_dt'], d['mu'], d['gauss_points'], d['recon_vars'],
-             d['side_slopes']]
+             d['side_slopes'], d['tang_weno']]
     with open(path, 'w') as f:
         f.write(' '.join(repr(float(v)) if isinstance(v, float) else str(v) for v in vals) + '\n')
 
@@ -33,6 +33,7 @@ def write_config(prob, path):
     ('shock_vortex_characteristic', lambda: dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), recon_vars=1), 12),
     ('shock_tube_side_slopes', lambda: dataclasses.replace(I.shock_tube_1d(100), side_slopes=1), 30),
     ('shock_vortex_side_slopes', lambda: dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), side_slopes=1), 12),
+    ('shock_vortex_tang_weno', lambda: dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), tang_weno=1), 12),
 ])
 def test_c_driver_equals_the_binding(tmp_path, name, mk, steps):
     from paper_2001_01570_amd.cgks import Solver
