@@ -438,9 +438,15 @@ def test_largest_accepted_grid_single_step_sampled():
     del s, f
 
 
-@pytest.mark.parametrize('rv', [0, 1], ids=['conservative', 'characteristic'])
-def test_config4_full_size_single_step_sampled(rv):
-    p = dataclasses.replace(I.shock_vortex_2d(2048, 1024), recon_vars=rv)
+FULL_OPTIONS = [('conservative', {}), ('characteristic', dict(recon_vars=1)), ('side_slopes', dict(side_slopes=1)),
+                ('side_slopes_four_points', dict(side_slopes=1, gauss_points=4)), ('tang_weno', dict(tang_weno=1))]
+
+
+@pytest.mark.parametrize('option,kw', FULL_OPTIONS, ids=[o[0] for o in FULL_OPTIONS])
+def test_config4_full_size_single_step_sampled(option, kw):
+    """The 2048 x 1024 shock-vortex workload (walls, inflow): one GPU step,
+    windows recomputed by the oracle; the scheme as read and each option."""
+    p = dataclasses.replace(I.shock_vortex_2d(2048, 1024), **kw)
     wins = [(0, 0), (508, 500), (254, 508), (2040, 1016), (1024, 0), (0, 1016), (250, 470)]
     say('config4 sampled windows', wins)
     worst, s = _sampled(p, wins)

@@ -44,7 +44,8 @@ def window_step(prob, fields, i0, j0, size, dt, ulp_seed=None):
     p = I.Problem('window', 2, len(ix), len(iy), 0.0, dx * len(ix), 0.0, dy * len(iy), patch,
                   bc=(xlo, xhi, ylo, yhi), inflow_prim=prob.inflow_prim, gamma=prob.gamma, cfl=prob.cfl,
                   weno_eps=prob.weno_eps, tau_eps=prob.tau_eps, tau_C=prob.tau_C, mu=prob.mu,
-                  gauss_points=prob.gauss_points, recon_vars=prob.recon_vars)
+                  gauss_points=prob.gauss_points, recon_vars=prob.recon_vars, side_slopes=prob.side_slopes,
+                  tang_weno=prob.tang_weno)
     o = O.Oracle(p, threads=4)
     for d in dts:
         o.step(d)
