@@ -6,7 +6,8 @@ halo) against the oracle with the same option: single steps with walls,
 inflow, no-slip walls, a near vacuum and a ragged grid, FP32 gradient
 storage, tiny grids, 40-step runs with each side's own steps, a run where
 both guards fire, the Mach 2 shock-vortex run whose WENO-state fallbacks
-the variant removes, and the configurations it refuses."""
+the variant removes, batch slots, the configurations it refuses, and which
+options carry the strong shock-vortex case."""
 import dataclasses
 import sys
 
@@ -167,3 +168,32 @@ def test_refused_with_other_options():
         with pytest.raises(CgksError) as ei:
             Solver(dataclasses.replace(tw(I.shock_vortex_2d(32, 16, Rc=0.12)), **bad))
         assert ei.value.code == CGKS_EINVAL
+
+
+@pytest.mark.parametrize('Ms,gp,kw,reaches', [
+    (2.0, 2, {}, False), (2.0, 2, dict(recon_vars=1), True), (2.0, 2, dict(tang_weno=1), True),
+    (2.5, 2, {}, False), (2.5, 2, dict(recon_vars=1), False), (2.5, 2, dict(side_slopes=1), False),
+    (2.5, 2, dict(tang_weno=1), True), (2.5, 4, {}, False), (2.5, 4, dict(recon_vars=1), True)],
+    ids=['Ms2-as_read', 'Ms2-characteristic', 'Ms2-tang_weno', 'Ms2.5-as_read', 'Ms2.5-characteristic',
+         'Ms2.5-side_slopes', 'Ms2.5-tang_weno', 'Ms2.5-g4-as_read', 'Ms2.5-g4-characteristic'])
+def test_strong_shock_vortex_which_options_carry_it(Ms, gp, kw, reaches):
+    """The shock-vortex case at 256 x 128 (M_v = 0.5, CFL 0.3) to t = 0.3 on
+    the GPU path: the scheme as read stops at a non-physical state for
+    M_s >= 2 (t = 0.17 at M_s = 2, 0.08 at 2.5); characteristic variables
+    carry M_s = 2 and, with four Gauss points, 2.5; with two points only the
+    tangential WENO carries M_s = 2.5 (characteristic variables stop at
+    t = 0.285, the side slopes at 0.037)."""
+    from paper_2001_01570_amd.cgks import CgksError, CGKS_ENONPHYS, Solver
+    p = dataclasses.replace(I.shock_vortex_2d(256, 128, Ms=Ms, Mv=0.5, cfl=0.3), gauss_points=gp, **kw)
+    s = Solver(p)
+    try:
+        s.advance_to(0.3)
+        ok = True
+    except CgksError as e:
+        assert e.code == CGKS_ENONPHYS
+        ok = False
+    say('shock-vortex M_s', Ms, 'gauss points', gp, kw, 'reaches t = 0.3' if ok else 'stops at t = %.3f' % s.t)
+    assert ok == reaches
+    if not ok:
+        assert s.t < 0.29
+    s.close()
