@@ -46,12 +46,11 @@ typedef struct {
                                 conservative, 1 characteristic (Sec. 3.2: the eigenvectors
                                 of the normal flux Jacobian at the mean of the two cells
                                 beside the face, per stencil line) */
-  int tang_weno;             /* tangential assembly of the WENO-Z states (2D, two Gauss
-                                points, conservative variables, linear side slopes; an
-                                evaluated variant): 0 as the linear quantities (the quintic
-                                of the three nearest segments); 1 a WENO-Z of the three
+  int tang_weno;             /* tangential assembly of the WENO-Z states (2D, conservative
+                                variables, linear side slopes; an evaluated variant): 0 as
+                                the linear quantities; 1 a WENO-Z of the three
                                 average-interpolating quadratics on the five nearest
-                                segments (orc_tang_weno) */
+                                segments (orc_tang_weno, orc_tang_weno_eta) */
 } orc_config;
 
 typedef struct orc_ctx orc_ctx;
@@ -155,6 +154,9 @@ void orc_quadratic3(const double *s, double eta, double *out3);
  * (0..2); the second node is reached by reversing s.  Test infrastructure:
  * the tangential-WENO variant of the 2D assembly. */
 double orc_tang_weno(const double *s, double eps, double *cand, double *beta, double *weights);
+/* The same at any node eta (the four-point nodes), linear weights from the
+ * quartic through the five averages. */
+double orc_tang_weno_eta(const double *s, double eta, double eps, double *cand, double *beta, double *weights);
 /* The quintic fixed by 3 unit-cell averages s[0..2] (offsets -1..1) and by the
  * averages of its derivative over the same cells, d[0..2] (for a unit cell the
  * average of the derivative is the difference of the end values), at eta:

@@ -96,6 +96,8 @@ def lib():
         L.orc_weno_char.restype = C.c_int
         L.orc_tang_weno.argtypes = [D, C.c_double, D, D, D]
         L.orc_tang_weno.restype = C.c_double
+        L.orc_tang_weno_eta.argtypes = [D, C.c_double, C.c_double, D, D, D]
+        L.orc_tang_weno_eta.restype = C.c_double
         _lib = L
     return _lib
 
@@ -315,6 +317,13 @@ def tang_weno(s, eps=1e-6, details=False):
     three candidate values, indicators and normalised weights."""
     cand, beta, w = np.empty(3), np.empty(3), np.empty(3)
     v = lib().orc_tang_weno(_p(_vec(s, 5)), float(eps), _p(cand), _p(beta), _p(w))
+    return (v, cand, beta, w) if details else v
+
+
+def tang_weno_eta(s, eta, eps=1e-6, details=False):
+    """tang_weno at any node eta (the four-point nodes)."""
+    cand, beta, w = np.empty(3), np.empty(3), np.empty(3)
+    v = lib().orc_tang_weno_eta(_p(_vec(s, 5)), float(eta), float(eps), _p(cand), _p(beta), _p(w))
     return (v, cand, beta, w) if details else v
 
 

@@ -309,3 +309,58 @@ double orc_tang_weno(const double *s, double eps, double *cand, double *beta, do
   }
   return v;
 }
+
+/* The same WENO-Z at any node eta in (-1/2, 1/2) (the four-point nodes): the
+ * linear weights follow from matching the quartic through the five averages
+ * at eta, whose weight of each average comes from the inverse of the 5 x 5
+ * matrix of the monomials' segment averages.  s_0 enters only the first
+ * quadratic and s_4 only the third, which fixes d_0 and d_2; s_1 then fixes
+ * d_1 (the other two equations hold by construction). */
+double orc_tang_weno_eta(const double *s, double eta, double eps, double *cand, double *beta, double *weights) {
+  double A[25], Ainv[25];
+  for (int m = 0; m < 5; ++m)
+    for (int p = 0; p < 5; ++p) {
+      const double lo = m - 2.5, hi = m - 1.5;
+      A[m * 5 + p] = (ipow(hi, p + 1) - ipow(lo, p + 1)) / (p + 1);
+    }
+  if (orc_invert(5, A, Ainv) != 0) return NAN;
+  double P[5];   /* weight of average i in the quartic at eta */
+  for (int i = 0; i < 5; ++i) {
+    P[i] = 0.0;
+    for (int p = 0; p < 5; ++p) P[i] += Ainv[p * 5 + i] * ipow(eta, p);
+  }
+  /* each quadratic's weights of its three averages (A, B, C) at eta */
+  double qa[3], qb[3], qc[3];
+  for (int k = 0; k < 3; ++k) {
+    const double y = eta - (k - 1.0), w2 = -1.0 / 24.0 + 0.5 * y * y;
+    qa[k] = w2 - 0.5 * y;
+    qb[k] = 1.0 - 2.0 * w2;
+    qc[k] = w2 + 0.5 * y;
+  }
+  double d[3];
+  d[0] = P[0] / qa[0];
+  d[2] = P[4] / qc[2];
+  d[1] = (P[1] - d[0] * qb[0]) / qa[1];
+  double q[3], b[3], w[3];
+  for (int k = 0; k < 3; ++k) q[k] = qa[k] * s[k] + qb[k] * s[k + 1] + qc[k] * s[k + 2];
+  {
+    const double a0 = s[0] - 2.0 * s[1] + s[2], c0 = s[0] - 4.0 * s[1] + 3.0 * s[2];
+    const double a1 = s[1] - 2.0 * s[2] + s[3], c1 = s[1] - s[3];
+    const double a2 = s[2] - 2.0 * s[3] + s[4], c2 = 3.0 * s[2] - 4.0 * s[3] + s[4];
+    b[0] = 13.0 / 12.0 * a0 * a0 + 0.25 * c0 * c0;
+    b[1] = 13.0 / 12.0 * a1 * a1 + 0.25 * c1 * c1;
+    b[2] = 13.0 / 12.0 * a2 * a2 + 0.25 * c2 * c2;
+  }
+  const double tau = fabs(b[0] - b[2]);
+  double wsum = 0.0;
+  for (int k = 0; k < 3; ++k) { w[k] = d[k] * (1.0 + tau / (b[k] + eps)); wsum += w[k]; }
+  double v = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    w[k] /= wsum;
+    v += w[k] * q[k];
+    if (cand) cand[k] = q[k];
+    if (beta) beta[k] = b[k];
+    if (weights) weights[k] = w[k];
+  }
+  return v;
+}

@@ -50,7 +50,7 @@ int orc_create(const orc_config *cfg, orc_ctx **out) {
   const int gp = cfg->gauss_points ? cfg->gauss_points : 2;
   if (cfg->side_slopes != 0 && cfg->side_slopes != 1) return ORC_EINVAL;
   if (cfg->char_vars != 0 && (cfg->char_vars != 1 || cfg->side_slopes)) return ORC_EINVAL;
-  if (cfg->tang_weno != 0 && (cfg->tang_weno != 1 || cfg->dim != 2 || gp != 2 || cfg->char_vars || cfg->side_slopes))
+  if (cfg->tang_weno != 0 && (cfg->tang_weno != 1 || cfg->dim != 2 || cfg->char_vars || cfg->side_slopes))
     return ORC_EINVAL;
   if (gp != 2 && !(gp == 4 && cfg->dim == 2)) return ORC_EINVAL;
   /* the 7-segment stencil reaches 3 cells across a side: a wall mirrors 3 cells */
@@ -385,12 +385,21 @@ static void face_eval(orc_ctx *c, double lines[7][5][4], double tg[7][2][4], con
         for (int l = 0; l < nl; ++l) s[l] = lines[l][2][k];
         orc_sextic(s, eta[g], r3);
         Wnn[k] = r3[0];
-        for (int l = 0; l < nl; ++l) s[l] = lines[l][3][k];
-        orc_sextic(s, eta[g], r3);
-        Wl[k] = ref[k] + r3[0];
-        for (int l = 0; l < nl; ++l) s[l] = lines[l][4][k];
-        orc_sextic(s, eta[g], r3);
-        Wr[k] = ref[k] + r3[0];
+        if (c->cfg.tang_weno) {
+          /* the tangential-WENO variant: the middle five of the seven segments */
+          double s5[5];
+          for (int l = 0; l < 5; ++l) s5[l] = lines[l + 1][3][k];
+          Wl[k] = ref[k] + orc_tang_weno_eta(s5, eta[g], c->cfg.weno_eps, 0, 0, 0);
+          for (int l = 0; l < 5; ++l) s5[l] = lines[l + 1][4][k];
+          Wr[k] = ref[k] + orc_tang_weno_eta(s5, eta[g], c->cfg.weno_eps, 0, 0, 0);
+        } else {
+          for (int l = 0; l < nl; ++l) s[l] = lines[l][3][k];
+          orc_sextic(s, eta[g], r3);
+          Wl[k] = ref[k] + r3[0];
+          for (int l = 0; l < nl; ++l) s[l] = lines[l][4][k];
+          orc_sextic(s, eta[g], r3);
+          Wr[k] = ref[k] + r3[0];
+        }
       } else {
         W0d[k] = lines[0][0][k]; Wn[k] = lines[0][1][k]; Wnn[k] = lines[0][2][k];
         Wl[k] = ref[k] + lines[0][3][k]; Wr[k] = ref[k] + lines[0][4][k];
