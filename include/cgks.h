@@ -107,9 +107,9 @@ typedef struct {
   int tang_weno;             /* tangential assembly of the two WENO-Z states in 2D.
                                 0 (the default): the quintic of the three nearest
                                 face segments, as for the linear quantities.  1 (an
-                                evaluated variant; two Gauss points, conservative
-                                variables, side_slopes 0; contexts, the batch and
-                                cgks_step_noalloc): a WENO-Z of the
+                                evaluated variant; two or four Gauss points,
+                                conservative variables, side_slopes 0; contexts,
+                                the batch and cgks_step_noalloc): a WENO-Z of the
                                 three quadratics on the five nearest segments'
                                 averages.  Other values and combinations:
                                 CGKS_EINVAL                                          */

@@ -367,7 +367,8 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 // Tile (bx, by) of the face grid of one direction: DIR 0 tiles (faces, rows),
 // DIR 1 tiles (columns, faces).
 // lds: the kernel's LDS tile, NQ rows of NSEG line segments.
-template <int DIR, int STAGE, class GT = double, class TL = Tile8x16, bool CH = false, bool SS = false>
+template <int DIR, int STAGE, class GT = double, class TL = Tile8x16, bool CH = false, bool SS = false,
+          bool TW = false>
 __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx, int by,
                                             double (*lds)[TL::NSEG]) {
   constexpr int TF = TL::F, TT = TL::T, TH = TL::H, NSEG = TL::NSEG, HALO = TL::HALO;
@@ -558,9 +559,10 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   int guard = 0, nbad = 0;
   const double inv_hn = DIR == 0 ? G.inv_dx : G.inv_dy, inv_ht = DIR == 0 ? G.inv_dy : G.inv_dx;
   const double dsg = mirror ? -1.0 : 1.0;
-  if constexpr (M == 2 && HALO == 2) {
+  if constexpr (M == 2 && TW) {
     // the tangential-WENO variant: the nonlinear states from the 5 segments,
     // the rest from the middle three as with the 3-segment halo
+    static_assert(HALO == 2, "the two-point tangential WENO needs the 5-segment tiles");
     if (live) {
       double tws[8];
 #pragma unroll
@@ -584,6 +586,29 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
     if (live)
       face_point<DIR, STAGE == 1, NL, SS>(get, right_cell, kTang7[0], kHerm2[0], dsg, inv_hn,
                                           mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad);
+  } else if constexpr (TW) {
+    // four points with the tangential WENO: the middle five of the seven
+    // segments at this wave's node
+    if (live) {
+      const TwNode node = pr ? kTwOuter : kTwInner;
+      double tws[8];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double rj = get(20 + k, 3);
+        double sl[5], sr[5];
+#pragma unroll
+        for (int l = 0; l < 5; ++l) {
+          const double off = get(20 + k, l + 1) - rj;
+          sl[l] = off + get(12 + k, l + 1);
+          sr[l] = off + get(16 + k, l + 1);
+        }
+        tws[k] = rj + tang_weno5_at(sl, G.eps, node);
+        tws[4 + k] = rj + tang_weno5_at(sr, G.eps, node);
+      }
+      face_point<DIR, STAGE == 1, NL, false, true>(get, right_cell, kTang7[pr], kHerm4[pr], dsg, inv_hn,
+                                                   mirror ? -inv_ht : inv_ht, G.gas, dt, acc, guard, nbad,
+                                                   pr ? kGauss4Outer : kGauss4Inner, tws);
+    }
   } else {
     if (live)
       face_point<DIR, STAGE == 1, NL, SS>(get, right_cell, kTang7[pr], kHerm4[pr], dsg, inv_hn,
@@ -633,12 +658,12 @@ __device__ __forceinline__ void faces2_body(const Geom& G, const Bufs& B, int bx
   for (int q = 0; q < NO; ++q) F[q * plane + idx] = acc[q];
 }
 
-template <int DIR, int STAGE, class GT, class TL, bool CH, bool SS = false>
+template <int DIR, int STAGE, class GT, class TL, bool CH, bool SS = false, bool TW = false>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void k_faces2(Geom G, Bufs B) {
   __shared__ double lds[SS ? NQ + 8 : NQ][TL::NSEG];   // SS: 8 rows of side slopes
   int bx, by;
   xcd_tile(bx, by);
-  faces2_body<DIR, STAGE, GT, TL, CH, SS>(G, B, bx, by, lds);
+  faces2_body<DIR, STAGE, GT, TL, CH, SS, TW>(G, B, bx, by, lds);
 }
 
 // ---------------------------------------------------------------- 2D update
@@ -1022,7 +1047,7 @@ __global__ void kb_end(const SlotDev* slots, const BatchTable* tab) {
 
 // Face tiles of the slots of one kind (tile shape TL, gradient storage GT,
 // characteristic variables CH, side-slope variant SS).
-template <int DIR, int STAGE, class GT, class TL, bool CH, bool SS = false>
+template <int DIR, int STAGE, class GT, class TL, bool CH, bool SS = false, bool TW = false>
 __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces(const SlotDev* slots,
                                                                             const BatchTable* tab, int kind) {
   __shared__ double lds[SS ? NQ + 8 : NQ][TL::NSEG];
@@ -1035,7 +1060,7 @@ __global__ __launch_bounds__(FACE_THREADS, FACE_WAVES(STAGE)) void kb_faces(cons
   const SlotDev& sd = slots[L.slot[k]];
   const int local = item - pre[k];
   const int w = sd.gw[DIR];
-  faces2_body<DIR, STAGE, GT, TL, CH, SS>(sd.G, sd.B, local % w, local / w, lds);
+  faces2_body<DIR, STAGE, GT, TL, CH, SS, TW>(sd.G, sd.B, local % w, local / w, lds);
 }
 
 template <int STAGE, class GT>
@@ -1133,7 +1158,7 @@ static int validate(const cgks_config* c) {
   if (gp != 2 && !(gp == 4 && c->dim == 2)) return CGKS_EINVAL;
   if (c->recon_vars != CGKS_CONSERVATIVE && c->recon_vars != CGKS_CHARACTERISTIC) return CGKS_EINVAL;
   if (c->side_slopes != 0 && (c->side_slopes != 1 || c->recon_vars != CGKS_CONSERVATIVE)) return CGKS_EINVAL;
-  if (c->tang_weno != 0 && (c->tang_weno != 1 || c->dim != 2 || gp != 2 || c->recon_vars != CGKS_CONSERVATIVE ||
+  if (c->tang_weno != 0 && (c->tang_weno != 1 || c->dim != 2 || c->recon_vars != CGKS_CONSERVATIVE ||
                             c->side_slopes != 0))
     return CGKS_EINVAL;
   for (int s = 0; s < 2 * c->dim; ++s) {
@@ -1367,39 +1392,40 @@ static void launch_step_on(const Geom& G, const Bufs& B, int gp, int storage, co
     auto faces = [&](auto dir, auto stage, auto gt, int kind) {
       constexpr int DIR = decltype(dir)::value, STAGE = decltype(stage)::value;
       using GT = decltype(gt);
-      auto go = [&](auto tl, auto ch, auto ss) {
+      auto go = [&](auto tl, auto ch, auto ss, auto tw) {
         using TL = decltype(tl);
-        constexpr bool CH = decltype(ch)::value, SS = decltype(ss)::value;
+        constexpr bool CH = decltype(ch)::value, SS = decltype(ss)::value, TW = decltype(tw)::value;
         const dim3 g = DIR == 0 ? dim3((G.nx + 1 + TL::F - 1) / TL::F, (G.ny + TL::T - 1) / TL::T)
                                 : dim3((G.nx + TL::T - 1) / TL::T, (G.ny + 1 + TL::F - 1) / TL::F);
-        run(kind, [&] { k_faces2<DIR, STAGE, GT, TL, CH, SS><<<g, FACE_THREADS, 0, s>>>(G, B); });
+        run(kind, [&] { k_faces2<DIR, STAGE, GT, TL, CH, SS, TW><<<g, FACE_THREADS, 0, s>>>(G, B); });
       };
       using CV = std::false_type;
       using CC = std::true_type;
       using NS = std::false_type;
       if (gp == 4) {
         using SV = std::true_type;
-        if (G.charv) { if constexpr (DIR == 0) go(Tile4x16G4(), CC(), NS()); else go(Tile2x32G4(), CC(), NS()); }
-        else if (G.sides) { if constexpr (DIR == 0) go(Tile4x16G4(), CV(), SV()); else go(Tile2x32G4(), CV(), SV()); }
-        else { if constexpr (DIR == 0) go(Tile4x16G4(), CV(), NS()); else go(Tile2x32G4(), CV(), NS()); }
+        if (G.charv) { if constexpr (DIR == 0) go(Tile4x16G4(), CC(), NS(), NS()); else go(Tile2x32G4(), CC(), NS(), NS()); }
+        else if (G.sides) { if constexpr (DIR == 0) go(Tile4x16G4(), CV(), SV(), NS()); else go(Tile2x32G4(), CV(), SV(), NS()); }
+        else if (G.tw) { if constexpr (DIR == 0) go(Tile4x16G4(), CV(), NS(), SV()); else go(Tile2x32G4(), CV(), NS(), SV()); }
+        else { if constexpr (DIR == 0) go(Tile4x16G4(), CV(), NS(), NS()); else go(Tile2x32G4(), CV(), NS(), NS()); }
         return;
       }
       if (G.charv) {   // characteristic variables: one tile shape per direction
-        if constexpr (DIR == 0) go(Tile4x32(), CC(), NS()); else go(Tile2x64(), CC(), NS());
+        if constexpr (DIR == 0) go(Tile4x32(), CC(), NS(), NS()); else go(Tile2x64(), CC(), NS(), NS());
         return;
       }
       if (G.tw) {      // the tangential-WENO variant: the 5-segment halo
-        if constexpr (DIR == 0) go(Tile4x32W(), CV(), NS()); else go(Tile2x64W(), CV(), NS());
+        if constexpr (DIR == 0) go(Tile4x32W(), CV(), NS(), std::true_type()); else go(Tile2x64W(), CV(), NS(), std::true_type());
         return;
       }
       if (G.sides) {   // the side-slope variant: one tile shape per direction
-        if constexpr (DIR == 0) go(Tile4x32(), CV(), std::true_type()); else go(Tile2x64(), CV(), std::true_type());
+        if constexpr (DIR == 0) go(Tile4x32(), CV(), std::true_type(), NS()); else go(Tile2x64(), CV(), std::true_type(), NS());
         return;
       }
       switch (tiles[DIR]) {
-        case 1: go(Tile4x32(), CV(), NS()); break;
-        case 2: go(Tile2x64(), CV(), NS()); break;
-        default: go(Tile8x16(), CV(), NS()); break;
+        case 1: go(Tile4x32(), CV(), NS(), NS()); break;
+        case 2: go(Tile2x64(), CV(), NS(), NS()); break;
+        default: go(Tile8x16(), CV(), NS(), NS()); break;
       }
     };
     using D0 = std::integral_constant<int, 0>;
@@ -2019,35 +2045,38 @@ static void launch_batch_step(cgks_batch* b) {
       if (!g) continue;
       using F = std::false_type;
       using T = std::true_type;
-      auto go = [&](auto gt, auto tl, auto ch, auto ss) {
-        kb_faces<DIR, STAGE, decltype(gt), decltype(tl), decltype(ch)::value, decltype(ss)::value>
-            <<<g, FACE_THREADS, 0, s>>>(sl, t, q);
+      auto go = [&](auto gt, auto tl, auto ch, auto ss, auto tw) {
+        kb_faces<DIR, STAGE, decltype(gt), decltype(tl), decltype(ch)::value, decltype(ss)::value,
+                 decltype(tw)::value><<<g, FACE_THREADS, 0, s>>>(sl, t, q);
       };
       // the tile shapes of kind_tile
       auto go_ch = [&](auto ch, auto ss) {
         if (kind_g4(q)) {
-          if (!kind_f32(q)) { if constexpr (DIR == 0) go(0.0, Tile4x16G4(), ch, ss); else go(0.0, Tile2x32G4(), ch, ss); }
-          else { if constexpr (DIR == 0) go(0.0f, Tile4x16G4(), ch, ss); else go(0.0f, Tile2x32G4(), ch, ss); }
+          if (!kind_f32(q)) { if constexpr (DIR == 0) go(0.0, Tile4x16G4(), ch, ss, F()); else go(0.0, Tile2x32G4(), ch, ss, F()); }
+          else { if constexpr (DIR == 0) go(0.0f, Tile4x16G4(), ch, ss, F()); else go(0.0f, Tile2x32G4(), ch, ss, F()); }
         } else if (kind_f32(q)) {
-          if constexpr (DIR == 0) go(0.0f, Tile4x32(), ch, ss); else go(0.0f, Tile2x64(), ch, ss);
+          if constexpr (DIR == 0) go(0.0f, Tile4x32(), ch, ss, F()); else go(0.0f, Tile2x64(), ch, ss, F());
         } else {
-          if constexpr (DIR == 0) go(0.0, Tile4x32(), ch, ss); else go(0.0, Tile2x64(), ch, ss);
+          if constexpr (DIR == 0) go(0.0, Tile4x32(), ch, ss, F()); else go(0.0, Tile2x64(), ch, ss, F());
         }
       };
       if (kind_char(q)) {
         go_ch(T(), F());
       } else if (kind_side(q)) {
         go_ch(F(), T());
-      } else if (kind_tw(q)) {   // two points only: the 5-segment halo tiles
-        if (kind_f32(q)) { if constexpr (DIR == 0) go(0.0f, Tile4x32W(), F(), F()); else go(0.0f, Tile2x64W(), F(), F()); }
-        else { if constexpr (DIR == 0) go(0.0, Tile4x32W(), F(), F()); else go(0.0, Tile2x64W(), F(), F()); }
+      } else if (kind_tw(q)) {   // two points: the 5-segment halo tiles; four: the four-point tiles
+        if (kind_g4(q)) {
+          if (kind_f32(q)) { if constexpr (DIR == 0) go(0.0f, Tile4x16G4(), F(), F(), T()); else go(0.0f, Tile2x32G4(), F(), F(), T()); }
+          else { if constexpr (DIR == 0) go(0.0, Tile4x16G4(), F(), F(), T()); else go(0.0, Tile2x32G4(), F(), F(), T()); }
+        } else if (kind_f32(q)) { if constexpr (DIR == 0) go(0.0f, Tile4x32W(), F(), F(), T()); else go(0.0f, Tile2x64W(), F(), F(), T()); }
+        else { if constexpr (DIR == 0) go(0.0, Tile4x32W(), F(), F(), T()); else go(0.0, Tile2x64W(), F(), F(), T()); }
       } else if (q != BK_G2) {
         go_ch(F(), F());
       } else {
         switch (b->tile[DIR]) {
-          case 1: go(0.0, Tile4x32(), F(), F()); break;
-          case 2: go(0.0, Tile2x64(), F(), F()); break;
-          default: go(0.0, Tile8x16(), F(), F()); break;
+          case 1: go(0.0, Tile4x32(), F(), F(), F()); break;
+          case 2: go(0.0, Tile2x64(), F(), F(), F()); break;
+          default: go(0.0, Tile8x16(), F(), F(), F()); break;
         }
       }
     }

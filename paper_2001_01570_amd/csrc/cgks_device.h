@@ -1069,6 +1069,36 @@ CGKS_HD __forceinline__ double tang_weno5(const double* s, double eps) {
   return (w0 * q0 + w1 * q1 + w2 * q2) * recip(w0 + w1 + w2);
 }
 
+// The same at a node eta of the four-point rule: the quadratics evaluated at
+// eta (y = eta - c for the segment centres c = -1, 0, 1) and the linear
+// weights of that node (from csrc/tang_weno_weights.py: the quartic through
+// the five averages at eta).
+struct TwNode { double eta, d0, d1, d2; };
+// first node of each mirror pair: inner -a, outer -b
+constexpr TwNode kTwInner = {-0.169990521792428132401, 0.128164158435505840028, 0.521969149850356295584,
+                             0.349866691714137864388};
+constexpr TwNode kTwOuter = {-0.430568155797026287612, 0.265842097477831923315, 0.611250490032248606455,
+                             0.122907412489919470230};
+CGKS_HD __forceinline__ double tang_weno5_at(const double* s, double eps, const TwNode& n) {
+  double q[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double y = n.eta - (k - 1.0), w2 = 0.5 * y * y - 1.0 / 24.0;
+    q[k] = (w2 - 0.5 * y) * s[k] + (1.0 - 2.0 * w2) * s[k + 1] + (w2 + 0.5 * y) * s[k + 2];
+  }
+  const double a0 = s[0] - 2.0 * s[1] + s[2], c0 = s[0] - 4.0 * s[1] + 3.0 * s[2];
+  const double a1 = s[1] - 2.0 * s[2] + s[3], c1 = s[1] - s[3];
+  const double a2 = s[2] - 2.0 * s[3] + s[4], c2 = 3.0 * s[2] - 4.0 * s[3] + s[4];
+  const double b0 = (13.0 / 12.0) * a0 * a0 + 0.25 * c0 * c0;
+  const double b1 = (13.0 / 12.0) * a1 * a1 + 0.25 * c1 * c1;
+  const double b2 = (13.0 / 12.0) * a2 * a2 + 0.25 * c2 * c2;
+  const double tau = fabs(b0 - b2);
+  const double w0 = n.d0 * (1.0 + tau * recip(b0 + eps));
+  const double w1 = n.d1 * (1.0 + tau * recip(b1 + eps));
+  const double wq = n.d2 * (1.0 + tau * recip(b2 + eps));
+  return (w0 * q[0] + w1 * q[1] + wq * q[2]) * recip(w0 + w1 + wq);
+}
+
 // The point quantities of component k (h: quintic weights at this node; w7:
 // sextic weights, used when NL = 7).  Value-type results are deviations from
 // the middle line's reference.

@@ -1,8 +1,9 @@
-"""The tangential-WENO variant of the 2D assembly (tang_weno = 1, two Gauss
-points; an evaluated variant): the two WENO-Z states at each Gauss point
-come from a WENO-Z of the three average-interpolating quadratics on the
-five nearest face segments.  The HIP path (face kernels with a 5-segment
-halo) against the oracle with the same option: single steps with walls,
+"""The tangential-WENO variant of the 2D assembly (tang_weno = 1; an
+evaluated variant): the two WENO-Z states at each Gauss point come from a
+WENO-Z of the three average-interpolating quadratics on the five nearest
+face segments.  The HIP path (two points: face kernels with a 5-segment
+halo; four points: the middle five of the seven segments) against the
+oracle with the same option: single steps with walls,
 inflow, no-slip walls, a near vacuum and a ragged grid, FP32 gradient
 storage, tiny grids, 40-step runs with each side's own steps, a run where
 both guards fire, the Mach 2 shock-vortex run whose WENO-state fallbacks
@@ -17,7 +18,7 @@ import pytest
 from oracle import oracle as O
 from paper_2001_01570_amd import inputs as I
 from tests.parity import field_errors, field_scales, scaled_errors
-from tests.test_gpu_parity import _tiny, TINY
+from tests.test_gpu_parity import _tiny, TINY, TINY4
 from tests.test_gpu_parity_runs import _guard_case, own_dt_run
 
 pytestmark = pytest.mark.gpu
@@ -73,33 +74,39 @@ def _step_pair(p, before, storage=0):
     return e, change
 
 
+@pytest.mark.parametrize('gp', [2, 4])
 @pytest.mark.parametrize('name,mk,before,min_change', CASES, ids=[c[0] for c in CASES])
-def test_single_step(name, mk, before, min_change):
-    p = tw(mk())
-    say('tangential WENO single step', name, p.nx, p.ny)
+def test_single_step(name, mk, before, min_change, gp):
+    p = tw(dataclasses.replace(mk(), gauss_points=gp))
+    say('tangential WENO single step', name, p.nx, p.ny, 'gauss points', gp)
     e, change = _step_pair(p, before)
     say(name, 'errors', e.max(), 'change against the quintic states', change)
     assert e.max() < TOL, e
     assert change > min_change
 
 
-def test_fp32_storage_single_step():
+@pytest.mark.parametrize('gp', [2, 4])
+def test_fp32_storage_single_step(gp):
     from paper_2001_01570_amd.cgks import CGKS_FP32_STORAGE
-    e, change = _step_pair(tw(I.shock_vortex_2d(64, 32, Rc=0.12)), 3, CGKS_FP32_STORAGE)
+    e, change = _step_pair(tw(dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), gauss_points=gp)), 3, CGKS_FP32_STORAGE)
     say('tangential WENO, fp32 storage: averages', e[:4].max(), 'gradients', e[4:].max())
     assert e[:4].max() < 1e-8, e
     assert e[4:].max() < 4 * 2.0 ** -24, e
 
 
-@pytest.mark.parametrize('nx,ny,kind', TINY, ids=['%dx%d-%s' % t for t in TINY])
-def test_tiny_grids(nx, ny, kind):
+TINY_TW = [t + (2,) for t in TINY] + [t + (4,) for t in TINY4]
+
+
+@pytest.mark.parametrize('nx,ny,kind,gp', TINY_TW, ids=['g%d_%dx%d-%s' % (t[3], t[0], t[1], t[2]) for t in TINY_TW])
+def test_tiny_grids(nx, ny, kind, gp):
     """Grids smaller than the five-segment stencil (ghosts wrap onto or
     mirror the same few cells)."""
-    _tiny(nx, ny, kind, 2, tang_weno=1)
+    _tiny(nx, ny, kind, gp, tang_weno=1)
 
 
-def test_forty_steps_each_side_its_own_dt():
-    p = tw(I.shock_vortex_2d(64, 32, Rc=0.12))
+@pytest.mark.parametrize('gp', [2, 4])
+def test_forty_steps_each_side_its_own_dt(gp):
+    p = tw(dataclasses.replace(I.shock_vortex_2d(64, 32, Rc=0.12), gauss_points=gp))
     s, o, rel = own_dt_run(p, steps=40)
     err = scaled_errors(s.state, o.state, p.dx, p.dy)
     say('tangential WENO, 40 steps: dt rel', rel.max(), 'scaled errors', err)
@@ -109,6 +116,7 @@ def test_forty_steps_each_side_its_own_dt():
 
 def test_guards_fire_with_the_variant():
     _guard_case(tw(I.expansion_2d(32, 28, U=1.25, amp=0.1)), steps=12, min_w0=1, min_weno=0)
+    _guard_case(tw(I.expansion_2d(32, 28, U=1.25, amp=0.1, gauss_points=4)), steps=8, min_w0=1, min_weno=0)
 
 
 def test_mach2_shock_vortex_run_without_weno_fallbacks():
@@ -133,6 +141,8 @@ def test_batch_slots_equal_separate_contexts():
     from paper_2001_01570_amd.cgks import Batch, CGKS_FP32_STORAGE, Solver
     kinds = [(tw(I.shock_vortex_2d(64, 32, Rc=0.12)), 0),
              (tw(dataclasses.replace(moving_pulse(), bc=(I.NOSLIP,) * 4)), CGKS_FP32_STORAGE),
+             (tw(dataclasses.replace(I.shock_vortex_2d(40, 24, Rc=0.12), gauss_points=4)), 0),
+             (tw(dataclasses.replace(I.shock_vortex_2d(40, 24, Rc=0.12), gauss_points=4)), CGKS_FP32_STORAGE),
              (I.shock_vortex_2d(64, 32, Rc=0.12), 0),
              (dataclasses.replace(I.shock_vortex_2d(48, 24, Rc=0.12), side_slopes=1), 0),
              (dataclasses.replace(I.shock_vortex_2d(48, 24, Rc=0.12), recon_vars=1, gauss_points=4), 0)]
@@ -148,7 +158,7 @@ def test_batch_slots_equal_separate_contexts():
             e, te, ne = r.get_state()
             assert b.poll(s)[2] == ne == 3 * (rnd + 1)
             assert np.array_equal(g, e), (p.name, st, rnd, np.abs(g - e).max())
-    assert np.abs(b.read(slots[0]) - b.read(slots[2])).max() > 1e-8
+    assert np.abs(b.read(slots[0]) - b.read(slots[4])).max() > 1e-8
     b.close()
     p = kinds[0][0]
     o = O.Oracle(p, threads=8)
@@ -164,7 +174,7 @@ def test_batch_slots_equal_separate_contexts():
 
 def test_refused_with_other_options():
     from paper_2001_01570_amd.cgks import CgksError, CGKS_EINVAL, Solver
-    for bad in (dict(gauss_points=4), dict(recon_vars=1), dict(side_slopes=1)):
+    for bad in (dict(recon_vars=1), dict(side_slopes=1)):
         with pytest.raises(CgksError) as ei:
             Solver(dataclasses.replace(tw(I.shock_vortex_2d(32, 16, Rc=0.12)), **bad))
         assert ei.value.code == CGKS_EINVAL
@@ -173,16 +183,19 @@ def test_refused_with_other_options():
 @pytest.mark.parametrize('Ms,gp,kw,reaches', [
     (2.0, 2, {}, False), (2.0, 2, dict(recon_vars=1), True), (2.0, 2, dict(tang_weno=1), True),
     (2.5, 2, {}, False), (2.5, 2, dict(recon_vars=1), False), (2.5, 2, dict(side_slopes=1), False),
-    (2.5, 2, dict(tang_weno=1), True), (2.5, 4, {}, False), (2.5, 4, dict(recon_vars=1), True)],
+    (2.5, 2, dict(tang_weno=1), True), (2.5, 4, {}, False), (2.5, 4, dict(recon_vars=1), True),
+    (2.5, 4, dict(tang_weno=1), True), (3.0, 2, dict(tang_weno=1), False), (3.0, 4, dict(recon_vars=1), False)],
     ids=['Ms2-as_read', 'Ms2-characteristic', 'Ms2-tang_weno', 'Ms2.5-as_read', 'Ms2.5-characteristic',
-         'Ms2.5-side_slopes', 'Ms2.5-tang_weno', 'Ms2.5-g4-as_read', 'Ms2.5-g4-characteristic'])
+         'Ms2.5-side_slopes', 'Ms2.5-tang_weno', 'Ms2.5-g4-as_read', 'Ms2.5-g4-characteristic',
+         'Ms2.5-g4-tang_weno', 'Ms3-tang_weno', 'Ms3-g4-characteristic'])
 def test_strong_shock_vortex_which_options_carry_it(Ms, gp, kw, reaches):
     """The shock-vortex case at 256 x 128 (M_v = 0.5, CFL 0.3) to t = 0.3 on
     the GPU path: the scheme as read stops at a non-physical state for
     M_s >= 2 (t = 0.17 at M_s = 2, 0.08 at 2.5); characteristic variables
-    carry M_s = 2 and, with four Gauss points, 2.5; with two points only the
-    tangential WENO carries M_s = 2.5 (characteristic variables stop at
-    t = 0.285, the side slopes at 0.037)."""
+    carry M_s = 2 and, with four Gauss points, 2.5; the tangential WENO
+    carries M_s = 2.5 with two and four points (with two, characteristic
+    variables stop at t = 0.285, the side slopes at 0.037); at M_s = 3 every
+    option stops (t < 0.14)."""
     from paper_2001_01570_amd.cgks import CgksError, CGKS_ENONPHYS, Solver
     p = dataclasses.replace(I.shock_vortex_2d(256, 128, Ms=Ms, Mv=0.5, cfl=0.3), gauss_points=gp, **kw)
     s = Solver(p)
