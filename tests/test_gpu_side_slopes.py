@@ -227,3 +227,14 @@ def test_batch_side_slope_kinds_equal_separate_contexts():
     say('side-slope batch slot vs oracle', e.max())
     assert e.max() < TOL
     b.close()
+
+
+@pytest.mark.parametrize('gp', [2, 4])
+def test_guards_fire_next_to_noslip_walls(gp):
+    """The flow leaves every no-slip wall (the 2D expansion with velocity 1.0
+    towards the curve): both fallbacks fire along the walls (the WENO
+    fallback takes the cells beside the face through the boundary rule);
+    guard counts and states follow the oracle step by step and over 30
+    steps."""
+    p = side(dataclasses.replace(I.expansion_2d(32, 28, U=-1.0, amp=0.1, gauss_points=gp), bc=(I.NOSLIP,) * 4))
+    _guard_case(p, steps=30, min_w0=1, min_weno=1)
