@@ -1277,32 +1277,28 @@ CGKS_HD __forceinline__ void face_point(Get get, Right right, const TangWT<7>& w
   // normal slopes of the two non-equilibrium sides: the linear
   // reconstruction's Wn, or (SS, the evaluated variant) each line's
   // WENO-weighted side slopes (LDS rows 32-35 left, 36-39 right, h-scaled)
-  // taken to the point like Wn; a side that fell back to its cell average
-  // takes Wn
-  double Wln[4], Wrn[4];
-  if constexpr (SS) {
+  // taken to the point like Wn, one side at a time; a side that fell back
+  // to its cell average takes Wn
+  double Wsn[4];
+  auto side_slope = [&](int row0, bool bad) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      Wln[k] = te.Wn_of(get, 32 + k, k) * inv_hn;
-      Wrn[k] = te.Wn_of(get, 36 + k, k) * inv_hn;
-    }
-    rot(Wln);
-    rot(Wrn);
+    for (int k = 0; k < 4; ++k) Wsn[k] = te.Wn_of(get, row0 + k, k) * inv_hn;
+    rot(Wsn);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (bad_l) Wln[k] = Wn[k];
-      if (bad_r) Wrn[k] = Wn[k];
-    }
-  }
+    for (int k = 0; k < 4; ++k)
+      if (bad) Wsn[k] = Wn[k];
+  };
 
   // the two non-equilibrium sides (each phase's results are pinned before its
   // barrier so that its arithmetic stays in the phase)
   SideSums<4> sd;
   sd.zero();
-  side_terms<4, FULL>(Wl, +1, SS ? Wln : Wn, Wt, gas, sd);
+  if constexpr (SS) side_slope(32, bad_l);
+  side_terms<4, FULL>(Wl, +1, SS ? Wsn : Wn, Wt, gas, sd);
   sd.pin<FULL>();
   CGKS_BREAK();
-  side_terms<4, FULL>(Wr, -1, SS ? Wrn : Wn, Wt, gas, sd);
+  if constexpr (SS) side_slope(36, bad_r);
+  side_terms<4, FULL>(Wr, -1, SS ? Wsn : Wn, Wt, gas, sd);
   sd.pin<FULL>();
   CGKS_BREAK();
 
